@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Batched likelihood throughput and nested-sampling wall time on one MI355X.
+
+Step: one ns_loglike_batch call over B = 4096 walkers of the four-spectrum CMB
+emulator workload (6 parameters -> 4 networks 6-512-512-512-512-2500 ->
+TT/TE/EE/PP at l = 2..2501, 3x3 block + diagonal Gaussian chi^2 over 10000
+data), theta resident in HBM.  Every precision form is timed; `value` is the
+BF16-MFMA form, the FP64 form is reported beside it.  The nested-sampling leg
+times ns_run on the 6-parameter CMB emulator likelihood until sigma(log Z) <=
+0.1.  The CPU baseline is the FP64 oracle on a bounded sample of the same
+workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+MI355X_PEAK = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}   # dense TFLOP/s
+HBM_PEAK_GBS = 8000.0
+
+
+def gemm_flops(B, K, N):
+    return 2.0 * B * K * N
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--workload", default="cmb4x2500")
+    ap.add_argument("--forms", default="bf16,bf16x3,fp32,fp64")
+    ap.add_argument("--no-ns", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the walker-parallel "
+              "path shards without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2509_13307_amd import Model
+
+    dev = "cuda:0"
+    B = args.batch
+    m = W.load_model(args.workload)
+    g = Model(m)
+    theta_np = W.prior_draws(m, B, tag=7)
+    theta = torch.tensor(theta_np, dtype=torch.float64, device=dev)
+    logl = torch.empty(B, dtype=torch.float64, device=dev)
+    forms = args.forms.split(",")
+    res = {}
+    traces = {}
+    for prec in forms:
+        for _ in range(args.warmup):
+            g.loglike(theta, prec, out=logl)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.loglike(theta, prec, out=logl)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / args.steps
+        # same work with every kernel bracketed by HIP events on its stream
+        g.trace(True)
+        e0.record()
+        for _ in range(args.steps):
+            g.loglike(theta, prec, out=logl)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_traced = e0.elapsed_time(e1) / args.steps
+        traces[prec] = g.trace_report()
+        g.trace(False)
+        res[prec] = dict(evals_per_s=B / (ms * 1e-3), ms_per_step=ms, ms_per_step_traced=ms_traced,
+                         wall_s=wall, logl_finite=int(torch.isfinite(logl).sum().item()))
+        print(f"# {prec}: {ms:.3f} ms/step, {B / (ms * 1e-3):.4g} evals/s", file=sys.stderr, flush=True)
+
+    head = "bf16" if "bf16" in res else forms[0]
+    # dominant kernel of the headline form: largest total traced time
+    tr = traces[head]
+    dom = max(tr, key=lambda k: tr[k][1])
+    n_launch, tot_ms = tr[dom]
+    avg_s = tot_ms / n_launch * 1e-3
+    net = m["nets"][0]
+    K_last, N_last = net["W"][-1].shape[1], net["W"][-1].shape[0]
+    K_hid = net["W"][1].shape[1]
+    if dom.endswith("_out"):
+        work, unit, bound = gemm_flops(B, K_last, N_last), "TFLOP/s", "mfma"
+    elif dom.endswith("_hidden"):
+        work, unit, bound = gemm_flops(B, K_hid, K_hid), "TFLOP/s", "mfma"
+    else:
+        elem = 8 if head == "fp64" else 4
+        work, unit, bound = float(B) * m["data"].size * elem, "GB/s", "hbm"
+    if unit == "TFLOP/s":
+        achieved = work / avg_s / 1e12
+        peak = MI355X_PEAK[head]
+        if head == "fp64":
+            bound = "alu"          # the FP64 GEMM runs on the VALU
+    else:
+        achieved = work / avg_s / 1e9
+        peak = HBM_PEAK_GBS
+    roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 2), peak=peak, unit=unit,
+                    frac=round(achieved / peak, 4), traffic=None, avg_launch_us=round(avg_s * 1e6, 2),
+                    work_per_launch=work)
+
+    out = {
+        "metric": "likelihood evals/sec @batch 4096 (BF16 vs FP64); NS wall time to logZ +/-0.1",
+        "value": round(res[head]["evals_per_s"], 1),
+        "unit": "likelihood evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res[head]["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 6 params -> 4 x (6-512-512-512-512-2500) emulators, "
+                               "3x3 block + diagonal Gaussian over 10000 data, prior-draw theta",
+                   "batch": B, "parallelism": "single GPU"},
+        "forms": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for p, r in res.items()},
+        "fp64_evals_per_s": round(res["fp64"]["evals_per_s"], 1) if "fp64" in res else None,
+        "kernels": {p: {k: [n, round(t / n * 1e3, 2)] for k, (n, t) in tr_.items()} for p, tr_ in traces.items()},
+        "roofline": roofline,
+    }
+
+    if not args.no_ns:
+        out["ns"] = ns_leg(Model, W)
+
+    if not args.no_cpu:
+        out["cpu_baseline"], out["accuracy"] = cpu_leg(m, g, forms, torch, dev)
+
+    print(json.dumps(out), flush=True)
+
+
+def ns_leg(Model, W):
+    """Nested slice sampling on the 6-parameter CMB emulator likelihood."""
+    import torch
+    m = W.load_model("cmb6")
+    g = Model(m)
+    torch.cuda.synchronize()
+    out = {}
+    r = g.run(100, 50, 30, precision="fp64", seed=1, n_replicates=1000)
+    out["as_configured"] = dict(n_live=100, n_delete=50, logz=r["logz"], sigma=r["sigma"], wall_s=r["wall_s"],
+                                n_iter=r["n_iter"], n_evals=r["n_evals"])
+    for prec in ("fp64", "bf16x3"):
+        r = g.run(1600, 800, 30, precision=prec, seed=2, n_replicates=1000)
+        out[f"to_sigma_0.1_{prec}"] = dict(n_live=1600, n_delete=800, logz=r["logz"], sigma=r["sigma"],
+                                           wall_s=r["wall_s"], n_iter=r["n_iter"], n_evals=r["n_evals"])
+    print(f"# ns: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_leg(m, g, forms, torch, dev):
+    """FP64 oracle on a bounded sample (about 10-30 s of host time) and the
+    accuracy of every GPU form on the same sample."""
+    from threadpoolctl import threadpool_info
+    import workloads as W
+    from oracle.likelihood import loglike as oracle_loglike
+    width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
+    th = W.posterior_draws(m["theta_fid"], np.minimum(m["fisher_sigma"], 0.1 * width), 64, tag=9)
+    t0 = time.perf_counter()
+    n = 0
+    ref = None
+    while time.perf_counter() - t0 < 10.0:
+        ref = oracle_loglike(th, m, chunk=64)
+        n += th.shape[0]
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    cpu = dict(value=round(n / dt, 2), unit="likelihood evals/s", cores=threads, kind="oracle",
+               sample=f"{n} FP64 oracle evaluations ({n // th.shape[0]} passes over 64 posterior-region "
+                      f"walkers of the same workload) in {dt:.1f} s")
+    acc = {}
+    t = torch.tensor(th, dtype=torch.float64, device=dev)
+    for p in forms:
+        got = g.loglike(t, p).cpu().numpy()
+        acc[p] = float(np.max(np.abs(got - ref)))
+    return cpu, {"max_abs_dlogl_posterior_64": acc}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * ns.h -- C ABI of the MI355X batched-likelihood and nested-slice-sampling
+ * library (libnsmi.so).
+ *
+ * The library evaluates, for thousands of walkers at once, the log-likelihoods
+ * of the paper "High-Dimensional Bayesian Model Comparison in Cosmology with
+ * GPU-accelerated Nested Sampling and Neural Emulators" (Lovick et al.,
+ * arXiv:2509.13307) and runs nested slice sampling on them:
+ *
+ *   - neural-emulator likelihoods of CMB spectra with a Gaussian chi^2
+ *     (Sec. 2.3),
+ *   - the tomographic cosmic-shear likelihood of App. A: emulated P(k, z),
+ *     extended Limber projection Eq. (A2) with lensing and intrinsic-alignment
+ *     windows Eqs. (A3)-(A4), summed as in Eq. (A1), multiplicative shear bias
+ *     and photo-z shifts, and a dense-covariance Gaussian,
+ *   - nested sampling with k-deletion (Sec. 2.1-2.2) and the evidence of
+ *     Eq. (1), from which Bayes factors follow by Eq. (2).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns ns_status: 0 on success, a negative code on
+ *     failure.  No function throws or aborts across the ABI; the message of
+ *     the last failure on the calling thread is returned by ns_last_error().
+ *   - Pointers marked "device" are HIP device memory on the model's device;
+ *     "host" pointers are ordinary CPU memory.  The caller owns every buffer
+ *     it passes and keeps it alive until the work queued on `stream` that
+ *     uses it has completed; the library never frees or retains caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Arguments are validated before any launch; a rejected call queues
+ *     nothing.
+ *   - Parameters theta are in physical units, row-major [B x ld], ld >= d.
+ *     A theta outside a uniform prior's [a, b] has logL = -inf and gradient 0
+ *     (not an error: the sampler relies on it).  A NaN theta gives NaN.
+ *   - Calls on one model must not overlap in time unless they are queued on
+ *     the same stream (the model's workspaces are shared).  Different models
+ *     are independent.
+ */
+#ifndef NS_H
+#define NS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NS_OK = 0,
+    NS_E_INVALID = -1,     /* null pointer, bad enum, bad scalar argument     */
+    NS_E_SHAPE = -2,       /* inconsistent sizes                              */
+    NS_E_HIP = -3,         /* a HIP runtime call failed                       */
+    NS_E_NOMEM = -4,       /* device or host allocation failed                */
+    NS_E_NOT_SPD = -5,     /* covariance not symmetric positive definite      */
+    NS_E_UNSUPPORTED = -6  /* valid request this build does not implement     */
+} ns_status;
+
+/* Arithmetic of the emulator and projection stages.  The final Gaussian
+ * chi^2 (Cholesky whitening, reductions) and all sampler bookkeeping are FP64
+ * in every form. */
+typedef enum {
+    NS_FP64 = 0,   /* everything in double                                   */
+    NS_FP32 = 1,   /* emulator and Limber stages in float                    */
+    NS_BF16 = 2,   /* hidden and output layers on BF16 MFMA, FP32 accumulate;
+                      first layer, output transform and Limber in FP32       */
+    NS_BF16X3 = 3  /* as NS_BF16 with weights and activations split into
+                      hi + lo BF16 parts, three MFMA products per tile       */
+} ns_precision;
+
+typedef enum {
+    NS_MODEL_CMB_DIAG = 0,   /* one emulator, Gaussian with diagonal covariance */
+    NS_MODEL_CMB_BLOCK = 1,  /* TT, TE, EE, PP emulators; 3x3 block + diagonal  */
+    NS_MODEL_SHEAR = 2,      /* cosmic shear, App. A                            */
+    NS_MODEL_GAUSS = 3       /* diagonal Gaussian in theta (closed-form evidence) */
+} ns_model_kind;
+
+enum { NS_PRIOR_UNIFORM = 0, NS_PRIOR_NORMAL = 1 };
+
+/* One emulator network (Sec. 2.2 and 2.4: CosmoPower-style MLP):
+ *   x   = (inputs - in_shift) / in_scale
+ *   h_l = f_l(W_l h_{l-1} + b_l),  f_l(t) = (gamma_l + (1 - gamma_l) sigmoid(beta_l t)) t
+ *   y   = out_mu + out_sigma * (W_L h_{L-1} + b_L)
+ * All arrays are host memory, copied at ns_model_create. */
+typedef struct ns_net_desc {
+    int32_t n_layers;             /* L >= 2 affine layers (L-1 hidden)         */
+    const int32_t* dims;          /* [L+1]: dims[0] inputs ... dims[L] outputs  */
+    const double* const* W;       /* [L] row-major [dims[l+1] x dims[l]]        */
+    const double* const* b;       /* [L] [dims[l+1]]                            */
+    const double* const* beta;    /* [L-1] [dims[l+1]]                          */
+    const double* const* gamma;   /* [L-1] [dims[l+1]]                          */
+    const double* in_shift;       /* [dims[0]]                                  */
+    const double* in_scale;       /* [dims[0]]                                  */
+    const double* out_mu;         /* [dims[L]] (CMB) or [n_z x dims[L]] (shear) */
+    const double* out_sigma;      /* [dims[L]]                                  */
+} ns_net_desc;
+
+/* Model description (host memory; copied at creation, may be freed after). */
+typedef struct ns_model_desc {
+    int32_t kind;                 /* ns_model_kind                              */
+    int32_t d;                    /* sampled parameters                         */
+    const int32_t* prior_kind;    /* [d] NS_PRIOR_*                             */
+    const double* prior_a;        /* [d] uniform lower bound / normal mean      */
+    const double* prior_b;        /* [d] uniform upper bound / normal sigma     */
+
+    int32_t n_nets;               /* CMB_DIAG 1, CMB_BLOCK 4, SHEAR 1, GAUSS 0   */
+    const ns_net_desc* nets;
+    const int32_t* spec_log;      /* CMB: [n_nets], 1 -> C = 10^y, 0 -> C = y    */
+
+    int32_t n_data;               /* data vector length                         */
+    const double* data;           /* [n_data]                                   */
+    const double* sigma;          /* CMB_DIAG: [n_data] standard deviations     */
+    const double* cov_blocks;     /* CMB_BLOCK: [n_ell x 3 x 3] (TT, TE, EE)    */
+    const double* sigma_pp;       /* CMB_BLOCK: [n_ell]                         */
+    const double* cov;            /* SHEAR: [n_data x n_data] row-major         */
+
+    /* SHEAR geometry (App. A) */
+    int32_t n_bins;               /* tomographic bins (<= 10)                   */
+    const double* nz_mean;        /* [n_bins] Gaussian n(z) means               */
+    double nz_sigma;              /* Gaussian n(z) width                        */
+    int32_t n_a;                  /* scale-factor nodes, a = 1 .. a_min         */
+    double a_min;
+    int32_t n_z;                  /* emulator redshift nodes on [0, 1/a_min-1]  */
+    double k_min, k_max;          /* emulated k range [1/Mpc], log-spaced       */
+    int32_t n_k;
+    double ell_min, ell_max;      /* log-spaced multipoles                      */
+    int32_t n_ell;
+    const int32_t* pidx;          /* [9 + 3 n_bins] theta index per physical slot
+                                     (omega_b, omega_cdm, h, n_s, lnAs, w0, wa,
+                                      c_min, eta0, A_IA.., Dz.., m..), -1 = fixed */
+    const double* pfix;           /* [9 + 3 n_bins] values of fixed slots       */
+
+    /* GAUSS */
+    const double* mu;             /* [d]                                        */
+    const double* gsigma;         /* [d]                                        */
+} ns_model_desc;
+
+typedef struct ns_model ns_model; /* opaque, library-owned */
+
+/* Create a model on HIP device `device`: copies weights, data and grids to the
+ * device and factorises the covariance in FP64 on the host.
+ * Errors: NS_E_INVALID / NS_E_SHAPE for bad descriptions, NS_E_NOT_SPD when a
+ * covariance (block) has no Cholesky factor, NS_E_HIP / NS_E_NOMEM. */
+ns_status ns_model_create(const ns_model_desc* desc, int32_t device, ns_model** out);
+
+/* Release a model and its device memory (synchronises the device). NULL is a no-op. */
+ns_status ns_model_free(ns_model* model);
+
+/* Number of sampled parameters of a model. */
+ns_status ns_model_dim(const ns_model* model, int32_t* d);
+
+/* Prior transform (Table 1): u in the unit cube -> theta.
+ *   uniform U(a, b): a + (b - a) u;   normal N(mu, s): mu + s sqrt(2) erfinv(2u - 1)
+ * u, theta: device [B x ld] row-major (may alias).  Asynchronous on stream. */
+ns_status ns_prior_transform(ns_model* model, const double* u, double* theta, int64_t ld,
+                             int64_t B, void* stream);
+
+/* Batched log-likelihood logL(theta_b), b < B (the hot path: emulator ->
+ * [Limber + nuisances] -> Gaussian chi^2).
+ * theta: device [B x ld]; logl: device [B].  Asynchronous on stream.
+ * B = 0 is a no-op.  NS_E_UNSUPPORTED for precisions a model kind lacks. */
+ns_status ns_loglike_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
+                           double* logl, int32_t precision, void* stream);
+
+/* As ns_loglike_batch, plus grad: device [B x d], d logL / d theta by the
+ * hand-written adjoint of every stage (input gradients only). */
+ns_status ns_loglike_grad_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
+                                double* logl, double* grad, int32_t precision, void* stream);
+
+/* n_inner hit-and-run slice steps (Sec. 2.1; Neal 2003) for k walkers in the
+ * unit cube under the hard constraint logL(T(u)) > logl_star:
+ *   u:        device [k x d] in/out (start points must satisfy the constraint)
+ *   logl:     device [k] in/out
+ *   n_evals:  device [k] out, likelihood evaluations per walker
+ *   n_stalls: device [k] out, steps that kept their point (bracket collapsed)
+ *   dir_chol: device [d x d] lower-triangular factor of the direction
+ *             covariance (row-major)
+ * Random numbers: Philox4x64-10, key (seed, 0), counter (q/4, walker, step,
+ * iter), word q mod 4, U = (w >> 11) 2^-53; per step s (1..n_inner): draws
+ * 0..2d-1 give d Box-Muller normals, draw 2d the bracket offset, then one
+ * draw per shrink.  Step-out at most 10 per end, stall when the bracket is
+ * narrower than 1e-12 or after 200 shrinks.
+ * Synchronises `stream` (the host polls a completion flag). */
+ns_status ns_slice_step(ns_model* model, double* u, double* logl, int32_t* n_evals,
+                        int32_t* n_stalls, int64_t k, double logl_star, const double* dir_chol,
+                        int32_t n_inner, uint64_t seed, uint64_t iter, int32_t precision,
+                        void* stream);
+
+typedef struct ns_run_opts {
+    int32_t n_live;          /* live points n                                  */
+    int32_t n_delete;        /* k deleted and evolved in parallel per iteration */
+    int32_t n_inner;         /* slice steps per walker per iteration            */
+    int32_t precision;       /* ns_precision of the likelihood                  */
+    double frac_remain;      /* stop when the live share of Z falls below this  */
+    uint64_t seed;
+    int32_t max_iter;
+    int32_t n_replicates;    /* shrinkage replicates for sigma(log Z)           */
+} ns_run_opts;
+
+typedef struct ns_run_result {
+    double logz;             /* log Z, Eq. (1), FP64 logsumexp                  */
+    double sigma;            /* std of log Z over shrinkage replicates          */
+    double sigma_skilling;   /* sqrt(H / n)                                     */
+    double h;                /* information H                                   */
+    int64_t n_iter;
+    int64_t n_evals;
+    int64_t n_stalls;
+    int64_t n_dead;
+    double wall_s;
+} ns_run_result;
+
+/* Nested slice sampling to convergence (Sec. 2.1-2.2): k-deletion, slice
+ * steps with live-covariance directions, FP64 evidence accumulation.
+ * Optional outputs (host, may be NULL): dead_logl [capacity], dead_n
+ * [capacity], dead_u [capacity x d]; if the run produces more than `capacity`
+ * dead points only the first `capacity` are written (result->n_dead has the
+ * total).  Synchronous. */
+ns_status ns_run(ns_model* model, const ns_run_opts* opts, ns_run_result* result,
+                 double* dead_logl, int32_t* dead_n, double* dead_u, int64_t capacity,
+                 void* stream);
+
+/* Kernel tracing (instrumentation, no paper passage): while enabled, every
+ * kernel the library launches for `model` is bracketed by a pair of HIP
+ * events recorded on its launch stream.  Enabling or disabling synchronises
+ * the device and discards pending records. */
+ns_status ns_trace_enable(ns_model* model, int32_t enable);
+
+/* Synchronise the device and write the traced kernels since the last report
+ * as JSON {"kernel": [launches, total_ms], ...} into buf (host, buf_len bytes,
+ * NUL-terminated; NS_E_SHAPE if it does not fit).  Clears the records. */
+ns_status ns_trace_report(ns_model* model, char* buf, int64_t buf_len);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NS_H */

@@ -1,0 +1,213 @@
+// Gaussian chi^2 stages of the CMB-style likelihoods (Sec. 2.3 of the paper,
+// Gaussian form), the diagonal-Gaussian test likelihood, the prior transform
+// (Table 1) and the per-kind dispatch of the batched likelihood.
+//
+// All chi^2 arithmetic is FP64 whatever the emulator precision: the model
+// vector (FP32 or FP64) is widened before the residual is formed.
+#include "devutil.h"
+#include "nsmi.h"
+
+namespace nsmi {
+
+// theta outside a uniform prior's [a, b] -> false (NaN compares false: kept)
+__device__ __forceinline__ bool in_support(const double* th, int d, const int* kind, const double* a,
+                                           const double* b) {
+    bool ok = true;
+    for (int i = 0; i < d; ++i)
+        if (kind[i] == NS_PRIOR_UNIFORM && (th[i] < a[i] || th[i] > b[i])) ok = false;
+    return ok;
+}
+
+// ------------------------------------------------------------ diagonal chi^2
+// One wave per walker; lanes stride over the n data points.
+template <class T>
+__global__ __launch_bounds__(256) void chi2_diag_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
+    const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ mvec, int n,
+    const double* __restrict__ data, const double* __restrict__ isig, double cst,
+    double* __restrict__ logl, const int* __restrict__ count) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (count) B = min<int64_t>(B, *count);
+    if (row >= B) return;
+    const T* mv = mvec + row * n;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        double r = (data[i] - (double)mv[i]) * isig[i];
+        s = fma(r, r, s);
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+        const bool ok = in_support(theta + row * ld, d, pk, pa, pb);
+        logl[row] = ok ? -0.5 * s + cst : -INFINITY;
+    }
+}
+
+// ------------------------------------------------- 3x3 block + diagonal chi^2
+// Model vector spectrum-major [TT | TE | EE | PP] (n_ell each).  Per multipole
+// the residual (TT, TE, EE) is whitened with the precomputed inverse Cholesky
+// factor (lower, 6 entries); PP is whitened by 1/sigma_pp.  A block of 256
+// threads handles ROWS walkers so the per-multipole constants are read once.
+template <class T, int ROWS>
+__global__ __launch_bounds__(256) void chi2_block_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
+    const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ mvec,
+    int n_ell, const double* __restrict__ data, const double* __restrict__ linv,
+    const double* __restrict__ isig_pp, double cst, double* __restrict__ logl,
+    const int* __restrict__ count) {
+    __shared__ double red[ROWS][4];
+    if (count) B = min<int64_t>(B, *count);
+    const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+    if (r0 >= B) return;
+    const int64_t n = 4 * (int64_t)n_ell;
+    double s[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) s[r] = 0.0;
+    for (int l = threadIdx.x; l < n_ell; l += blockDim.x) {
+        const double* L = linv + 6 * (int64_t)l;
+        const double l00 = L[0], l10 = L[1], l11 = L[2], l20 = L[3], l21 = L[4], l22 = L[5];
+        const double dtt = data[l], dte = data[n_ell + l], dee = data[2 * n_ell + l], dpp = data[3 * n_ell + l];
+        const double ip = isig_pp[l];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int64_t row = r0 + r;
+            if (row >= B) break;
+            const T* mv = mvec + row * n;
+            const double rtt = dtt - (double)mv[l], rte = dte - (double)mv[n_ell + l];
+            const double ree = dee - (double)mv[2 * n_ell + l], rpp = (dpp - (double)mv[3 * n_ell + l]) * ip;
+            const double y0 = l00 * rtt;
+            const double y1 = l10 * rtt + l11 * rte;
+            const double y2 = l20 * rtt + l21 * rte + l22 * ree;
+            s[r] += y0 * y0 + y1 * y1 + y2 * y2 + rpp * rpp;
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        double v = wave_sum(s[r]);
+        if (lane == 0) red[r][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < ROWS) {
+        const int64_t row = r0 + threadIdx.x;
+        if (row < B) {
+            const double chi2 = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+            const bool ok = in_support(theta + row * ld, d, pk, pa, pb);
+            logl[row] = ok ? -0.5 * chi2 + cst : -INFINITY;
+        }
+    }
+}
+
+// ------------------------------------------------------------ Gaussian test
+__global__ void gauss_kernel(const double* __restrict__ theta, int64_t ld, int64_t B, int d,
+                             const int* __restrict__ pk, const double* __restrict__ pa,
+                             const double* __restrict__ pb, const double* __restrict__ mu,
+                             const double* __restrict__ isig, double cst, double* __restrict__ logl,
+                             const int* __restrict__ count) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (count) B = min<int64_t>(B, *count);
+    if (row >= B) return;
+    const double* th = theta + row * ld;
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) {
+        const double r = (th[i] - mu[i]) * isig[i];
+        s = fma(r, r, s);
+    }
+    logl[row] = in_support(th, d, pk, pa, pb) ? -0.5 * s + cst : -INFINITY;
+}
+
+// ------------------------------------------------------------ prior transform
+__global__ void prior_transform_kernel(const double* __restrict__ u, double* __restrict__ theta,
+                                       int64_t ld, int64_t B, int d, const int* __restrict__ pk,
+                                       const double* __restrict__ pa, const double* __restrict__ pb,
+                                       const int* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (count) B = min<int64_t>(B, *count);
+    if (i >= B * d) return;
+    const int64_t row = i / d;
+    const int c = (int)(i % d);
+    const double x = u[row * ld + c];
+    theta[row * ld + c] = pk[c] == NS_PRIOR_UNIFORM ? pa[c] + (pb[c] - pa[c]) * x
+                                                    : pa[c] + pb[c] * 1.4142135623730950488 * erfinv(2.0 * x - 1.0);
+}
+
+void prior_transform(ns_model* m, const double* u, double* theta, int64_t ld, int64_t B,
+                     const int* count, hipStream_t s) {
+    const int64_t n = B * m->d;
+    if (n == 0) return;
+    TraceScope ts(m, s, "prior_transform");
+    hipLaunchKernelGGL(prior_transform_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, u, theta,
+                       ld, B, m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(),
+                       count);
+    NS_HIP(hipGetLastError());
+}
+
+void gauss_loglike(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
+                   const int* count, hipStream_t s) {
+    TraceScope ts(m, s, "gauss");
+    hipLaunchKernelGGL(gauss_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld, B, m->d,
+                       m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(),
+                       m->g_mu.as<double>(), m->g_isig.as<double>(), m->logl_const, logl, count);
+    NS_HIP(hipGetLastError());
+}
+
+void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const void* mvec, double* logl,
+              int prec, const int* count, hipStream_t s) {
+    const int* pk = m->prior_kind.as<int>();
+    const double* pa = m->prior_a.as<double>();
+    const double* pb = m->prior_b.as<double>();
+    TraceScope ts(m, s, m->kind == NS_MODEL_CMB_DIAG ? "chi2_diag" : "chi2_block");
+    if (m->kind == NS_MODEL_CMB_DIAG) {
+        dim3 g((unsigned)((B + 3) / 4));
+        if (prec == NS_FP64)
+            hipLaunchKernelGGL(chi2_diag_kernel<double>, g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
+                               (const double*)mvec, m->n_data, m->data.as<double>(), m->inv_sigma.as<double>(),
+                               m->logl_const, logl, count);
+        else
+            hipLaunchKernelGGL(chi2_diag_kernel<float>, g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
+                               (const float*)mvec, m->n_data, m->data.as<double>(), m->inv_sigma.as<double>(),
+                               m->logl_const, logl, count);
+    } else {
+        constexpr int R = 8;
+        dim3 g((unsigned)((B + R - 1) / R));
+        if (prec == NS_FP64)
+            hipLaunchKernelGGL((chi2_block_kernel<double, R>), g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
+                               (const double*)mvec, m->n_ell_cmb, m->data.as<double>(), m->blk_linv.as<double>(),
+                               m->inv_sigma_pp.as<double>(), m->logl_const, logl, count);
+        else
+            hipLaunchKernelGGL((chi2_block_kernel<float, R>), g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
+                               (const float*)mvec, m->n_ell_cmb, m->data.as<double>(), m->blk_linv.as<double>(),
+                               m->inv_sigma_pp.as<double>(), m->logl_const, logl, count);
+    }
+    NS_HIP(hipGetLastError());
+}
+
+void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, int prec,
+                   const int* count, hipStream_t s) {
+    if (B == 0) return;
+    if (m->kind == NS_MODEL_GAUSS) {
+        gauss_loglike(m, theta, ld, B, logl, count, s);
+        return;
+    }
+    const size_t elem = prec == NS_FP64 ? 8 : 4;
+    if (m->kind == NS_MODEL_CMB_DIAG || m->kind == NS_MODEL_CMB_BLOCK) {
+        const int64_t n = m->n_data;
+        m->ws_out.ensure((size_t)B * n * elem);
+        int64_t off = 0;
+        for (size_t ni = 0; ni < m->nets.size(); ++ni) {
+            const int n_out = m->nets[ni]->dims.back();
+            char* dst = m->ws_out.as<char>() + off * elem;
+            emulator_forward(m, (int)ni, theta, ld, B, dst, n, m->spec_log[ni], prec, count, s);
+            off += n_out;
+        }
+        cmb_chi2(m, theta, ld, B, m->ws_out.p, logl, prec, count, s);
+        return;
+    }
+    // shear: emulator table [B * n_z x n_k], then projection and chi^2
+    const int n_k = m->nets[0]->dims.back();
+    m->ws_out.ensure((size_t)B * m->n_z * n_k * elem);
+    emulator_forward(m, 0, theta, ld, B, m->ws_out.p, n_k, 0, prec, count, s);
+    shear_loglike_from_table(m, theta, ld, B, logl, prec, count, s);
+}
+
+}  // namespace nsmi

@@ -1,0 +1,210 @@
+// Internal declarations of libnsmi: the model handle, workspaces and the
+// kernel launchers shared by the translation units.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ns.h"
+
+namespace nsmi {
+
+// ----------------------------------------------------------------- errors
+struct Error {
+    ns_status code;
+    std::string msg;
+};
+void set_error(const std::string& msg);
+
+#define NS_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::nsmi::Error{NS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define NS_CHECK(cond, code, text)                                                     \
+    do {                                                                               \
+        if (!(cond)) throw ::nsmi::Error{code, text};                                  \
+    } while (0)
+
+// --------------------------------------------------------- device buffers
+// Owning device allocation; grows on demand (contents are not preserved).
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t n);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+    ~DevBuf() { release(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+};
+
+template <class T>
+T* upload(DevBuf& buf, const T* host, size_t n) {
+    buf.ensure(n * sizeof(T));
+    if (n) NS_HIP(hipMemcpy(buf.p, host, n * sizeof(T), hipMemcpyHostToDevice));
+    return buf.as<T>();
+}
+
+// BF16 storage (round to nearest even from FP32)
+typedef uint16_t bf16_t;
+inline bf16_t host_f2bf(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40);  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+inline float host_bf2f(bf16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// ----------------------------------------------------------- emulator
+// One layer's parameters in every storage form the kernels use.
+struct Layer {
+    int n_in = 0, n_out = 0;
+    bool hidden = false;
+    DevBuf W64, b64, beta64, gamma64;        // double
+    DevBuf W32, b32, beta32, gamma32;        // float
+    DevBuf Whi, Wlo;                         // bf16 hi / lo split of W
+};
+
+struct Net {
+    int n_layers = 0;
+    std::vector<int> dims;
+    std::vector<Layer*> layers;
+    DevBuf in_shift, in_scale;               // double [dims[0]]
+    DevBuf out_mu64, out_sigma64;            // double
+    DevBuf out_mu32, out_sigma32;            // float
+    int out_mu_rows = 1;                     // 1 (CMB) or n_z (shear)
+    ~Net();
+};
+
+// Emulator input source per input column: >= 0 theta column, -1 fixed value,
+// -2 redshift node of the row.
+enum { SRC_FIXED = -1, SRC_ZNODE = -2 };
+
+}  // namespace nsmi
+
+// ------------------------------------------------------------ model handle
+struct ns_model {
+    int kind = 0, d = 0, device = 0;
+    nsmi::DevBuf prior_kind, prior_a, prior_b;
+    std::vector<nsmi::Net*> nets;
+    std::vector<int> spec_log;
+    int n_data = 0;
+    nsmi::DevBuf data;
+
+    // emulator input mapping (length dims[0] of the first net)
+    std::vector<int> emu_src;
+    std::vector<double> emu_fix;
+    nsmi::DevBuf emu_src_d, emu_fix_d, znodes_d;
+
+    // CMB
+    nsmi::DevBuf inv_sigma;          // diag: 1/sigma [n]
+    nsmi::DevBuf blk_linv;           // block: [n_ell x 6] lower inverse (00,10,11,20,21,22)
+    nsmi::DevBuf inv_sigma_pp;       // block: [n_ell]
+    int n_ell_cmb = 0;
+    double logl_const = 0.0;         // -sum log diag(L) - n/2 log 2pi
+
+    // shear
+    int n_bins = 0, n_a = 0, n_z = 0, n_k = 0, n_ell = 0, n_pairs = 0;
+    double nz_sigma = 0.1, a_min = 0, k_min = 0, k_max = 0;
+    std::vector<int> pidx;
+    std::vector<double> pfix;
+    nsmi::DevBuf pidx_d, pfix_d, nz_mean_d;
+    nsmi::DevBuf agrid_d;            // a_j [n_a]
+    nsmi::DevBuf zsp_idx_d;          // int [n_a]: spline interval of z_j
+    nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t))
+    nsmi::DevBuf ell_d;              // double [n_ell]
+    nsmi::DevBuf cov_linv;           // double [n x n] lower-triangular inverse Cholesky factor
+    nsmi::DevBuf cov_w;              // double [n]: L^{-1} d
+
+    // GAUSS
+    nsmi::DevBuf g_mu, g_isig;
+
+    // workspaces (grow on demand)
+    nsmi::DevBuf ws_act[2];          // hidden activations ping-pong
+    nsmi::DevBuf ws_out;             // emulator outputs / model vectors
+    nsmi::DevBuf ws_aux;             // stage outputs (spline M, spectra, ...)
+    nsmi::DevBuf ws_theta;           // theta scratch for the sampler
+    nsmi::DevBuf ws_logl;            // logL scratch for the sampler
+    nsmi::DevBuf ws_slice;           // slice-sampler state
+    nsmi::DevBuf ws_flag;            // small device counters/flags
+    nsmi::DevBuf ws_grad;            // adjoint scratch
+    void* host_pinned = nullptr;     // pinned host flag for completion polling
+
+    // per-kernel tracing: HIP events bracketing each launch on its stream
+    bool trace = false;
+    struct TraceRec { const char* name; hipEvent_t e0, e1; };
+    std::vector<TraceRec> trace_recs;
+    std::vector<hipEvent_t> trace_pool;
+
+    ~ns_model();
+};
+
+namespace nsmi {
+
+// Records a HIP event pair around the launches in its scope when the model's
+// tracing is on (see ns_trace_enable).
+struct TraceScope {
+    ns_model* m;
+    hipStream_t s;
+    int rec = -1;
+    TraceScope(ns_model* m_, hipStream_t s_, const char* name);
+    ~TraceScope();
+};
+
+// ---------------------------------------------------------- launchers
+// Emulator: outputs of net `ni` for `rows` rows (rows = B, or B * n_z for shear).
+// theta [B x ld] device; `count` optional device row count (rows beyond it skipped).
+// Output written to `out` ([rows x ldo], double for NS_FP64 else float);
+// is_log applies 10^y after the output transform.
+void emulator_forward(ns_model* m, int ni, const double* theta, int64_t ld, int64_t B,
+                      void* out, int64_t ldo, int is_log, int prec, const int* count, hipStream_t s);
+
+// CMB chi^2 on model vectors (double or float per prec) -> logL, with support mask.
+void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const void* mvec,
+              double* logl, int prec, const int* count, hipStream_t s);
+
+// Shear likelihood stages after the emulator table is in m->ws_out.
+void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B,
+                              double* logl, int prec, const int* count, hipStream_t s);
+
+void gauss_loglike(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
+                   const int* count, hipStream_t s);
+
+// Full batched likelihood (dispatch by kind).
+void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
+                   int prec, const int* count, hipStream_t s);
+
+void prior_transform(ns_model* m, const double* u, double* theta, int64_t ld, int64_t B,
+                     const int* count, hipStream_t s);
+
+// Slice steps for k walkers with the threshold in device memory (lstar_dev)
+// or given on the host; synchronises s.
+void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
+                const double* lstar_dev, const double* L, int n_inner, uint64_t seed, uint64_t iter, int prec,
+                hipStream_t s);
+void slice_step_host_lstar(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
+                           double lstar, const double* L, int n_inner, uint64_t seed, uint64_t iter, int prec,
+                           hipStream_t s);
+
+// Nested slice sampling to convergence.
+void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, int* dn_h, double* du_h,
+         int64_t cap, hipStream_t s);
+
+}  // namespace nsmi

@@ -1,0 +1,623 @@
+// Nested slice sampling on the device (Sec. 2.1-2.2 of the paper; slice
+// sampling after Neal 2003, as adopted by the paper's GPU nested sampler).
+//
+// Slice step.  Each walker runs a hit-and-run slice state machine in the unit
+// cube.  Per step s = 1..n_inner it draws a direction v = L zeta (zeta by
+// Box-Muller from Philox draws 0..2d-1) and an offset r (draw 2d), brackets
+// [t_L, t_R] = [-r, 1-r], steps each end out while it is inside the constraint
+// (at most 10 times per end), then shrinks with draws 2d+1, 2d+2, ... until a
+// point inside is found (accept), the bracket is narrower than 1e-12 or 200
+// shrinks were rejected (stall: the point is kept).  "Inside" means
+// u in [0,1]^d and logL(T(u)) > L*; proposals outside the cube cost no
+// likelihood evaluation.
+//
+// The walkers advance in rounds: slice_advance_kernel applies the previous
+// round's likelihood values and runs every walker forward until it needs a
+// new evaluation, appending that proposal to a compacted batch; the batched
+// likelihood then runs on the compacted rows only.  Every random number is
+// addressed by (walker, step, draw), so the result does not depend on the
+// order of the compacted rows.
+//
+// Nested-sampling bookkeeping (k-deletion, evidence in FP64) runs in
+// single-workgroup kernels; the host only polls a termination flag.
+#include "devutil.h"
+#include "nsmi.h"
+
+namespace nsmi {
+
+enum { ST_NEWSTEP = 0, ST_OUT_L = 1, ST_OUT_R = 2, ST_SHRINK = 3, ST_DONE = 4 };
+constexpr int MAX_EXPAND = 10;
+constexpr int MAX_SHRINK = 200;
+constexpr double STALL_WIDTH = 1e-12;
+constexpr int MAX_DIM = 64;
+
+struct SliceState {
+    double* u;        // [k x d] walker positions (caller buffer)
+    double* logl;     // [k]
+    double* v;        // [k x d] current direction
+    double* tl;       // [k]
+    double* tr;       // [k]
+    double* tp;       // [k] t of the pending proposal
+    int* st;          // [k] phase
+    int* step;        // [k] current step (1-based)
+    int* q;           // [k] next draw index
+    int* ne;          // [k] expansions / rejected shrinks in the current phase
+    int* pend;        // [k] compact slot of the pending proposal, -1 none
+    int* n_evals;     // [k]
+    int* n_stalls;    // [k]
+    double* xc;       // [k x d] compacted proposals (unit cube)
+    int* cidx;        // [k] walker of each compact slot
+    double* llc;      // [k] likelihood of each compact slot
+    int* ccount;      // compact batch size
+    int* active;      // walkers not done after the last advance
+};
+
+__global__ void slice_init_kernel(SliceState S, int64_t k) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= k) return;
+    S.st[w] = ST_NEWSTEP;
+    S.step[w] = 0;
+    S.pend[w] = -1;
+    S.n_evals[w] = 0;
+    S.n_stalls[w] = 0;
+}
+
+__global__ void slice_reset_kernel(SliceState S) {
+    if (threadIdx.x == 0) {
+        *S.ccount = 0;
+        *S.active = 0;
+    }
+}
+
+__device__ __forceinline__ void apply_result(const SliceState& S, int64_t w, int d, bool inside, double ll) {
+    const int st = S.st[w];
+    if (st == ST_OUT_L) {
+        if (inside) { S.tl[w] -= 1.0; S.ne[w] += 1; }
+        else { S.st[w] = ST_OUT_R; S.ne[w] = 0; }
+    } else if (st == ST_OUT_R) {
+        if (inside) { S.tr[w] += 1.0; S.ne[w] += 1; }
+        else { S.st[w] = ST_SHRINK; S.ne[w] = 0; }
+    } else if (st == ST_SHRINK) {
+        const double t = S.tp[w];
+        if (inside) {
+            for (int i = 0; i < d; ++i)
+                S.u[w * d + i] = __dadd_rn(S.u[w * d + i], __dmul_rn(t, S.v[w * d + i]));
+            S.logl[w] = ll;
+            S.st[w] = ST_NEWSTEP;
+        } else {
+            if (t < 0.0) S.tl[w] = t; else S.tr[w] = t;
+            S.ne[w] += 1;
+            if (S.tr[w] - S.tl[w] < STALL_WIDTH || S.ne[w] >= MAX_SHRINK) {
+                S.n_stalls[w] += 1;
+                S.st[w] = ST_NEWSTEP;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_t k, int d,
+                                                            const double* __restrict__ lstar_p,
+                                                            const double* __restrict__ L, int n_inner,
+                                                            uint64_t seed, uint64_t iter) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= k) return;
+    const double lstar = *lstar_p;
+    if (S.pend[w] >= 0) {
+        const double ll = S.llc[S.pend[w]];
+        S.pend[w] = -1;
+        S.n_evals[w] += 1;
+        apply_result(S, w, d, ll > lstar, ll);
+    }
+    double x[MAX_DIM];
+    while (true) {
+        int st = S.st[w];
+        if (st == ST_DONE) break;
+        if (st == ST_NEWSTEP) {
+            if (S.step[w] >= n_inner) { S.st[w] = ST_DONE; break; }
+            const int s = ++S.step[w];
+            double zeta[MAX_DIM];
+            for (int i = 0; i < d; ++i) {
+                const double u1 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * i);
+                const double u2 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * i + 1);
+                zeta[i] = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
+            }
+            for (int i = 0; i < d; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j <= i; ++j) acc = __dadd_rn(acc, __dmul_rn(L[i * d + j], zeta[j]));
+                S.v[w * d + i] = acc;
+            }
+            const double r = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * d);
+            S.tl[w] = -r;
+            S.tr[w] = 1.0 - r;
+            S.q[w] = 2 * d + 1;
+            S.ne[w] = 0;
+            S.st[w] = ST_OUT_L;
+            continue;
+        }
+        double t;
+        if (st == ST_OUT_L) {
+            if (S.ne[w] >= MAX_EXPAND) { S.st[w] = ST_OUT_R; S.ne[w] = 0; continue; }
+            t = S.tl[w];
+        } else if (st == ST_OUT_R) {
+            if (S.ne[w] >= MAX_EXPAND) { S.st[w] = ST_SHRINK; S.ne[w] = 0; continue; }
+            t = S.tr[w];
+        } else {
+            const int qq = S.q[w]++;
+            const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)S.step[w], iter, (uint64_t)qq);
+            const double tl = S.tl[w], tr = S.tr[w];
+            t = __dadd_rn(tl, __dmul_rn(U, __dsub_rn(tr, tl)));
+        }
+        bool inbox = true;
+        for (int i = 0; i < d; ++i) {
+            x[i] = __dadd_rn(S.u[w * d + i], __dmul_rn(t, S.v[w * d + i]));
+            inbox = inbox && (x[i] >= 0.0) && (x[i] <= 1.0);
+        }
+        S.tp[w] = t;
+        if (!inbox) {
+            apply_result(S, w, d, false, -INFINITY);
+            continue;
+        }
+        const int slot = atomicAdd(S.ccount, 1);
+        for (int i = 0; i < d; ++i) S.xc[(int64_t)slot * d + i] = x[i];
+        S.cidx[slot] = (int)w;
+        S.pend[w] = slot;
+        break;
+    }
+    if (S.st[w] != ST_DONE) atomicAdd(S.active, 1);
+}
+
+// ------------------------------------------------------------- NS kernels
+struct NSState {
+    double logx;      // log X after the deaths recorded so far
+    double logz;      // running log Z of the dead points
+    double lstar;     // current threshold
+    double live_term; // log(X mean_live L)
+    int64_t n_dead;
+    int64_t n_evals;
+    int64_t n_stalls;
+    int stop;
+};
+
+__device__ __forceinline__ double logaddexp(double a, double b) {
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    const double m = fmax(a, b);
+    return m + log1p(exp(-fabs(a - b)));
+}
+
+// Bitonic sort of (logl, index) for n <= 4096 in one workgroup of 1024 threads;
+// then the k lowest die: evidence update and dead-point records (serial, FP64).
+__global__ __launch_bounds__(1024) void ns_select_kernel(const double* __restrict__ logl,
+                                                         const double* __restrict__ u, int n, int k, int d,
+                                                         int* __restrict__ order, NSState* __restrict__ S,
+                                                         double* __restrict__ dead_logl, int* __restrict__ dead_n,
+                                                         double* __restrict__ dead_u, int64_t dead_cap,
+                                                         int record) {
+    __shared__ double key[4096];
+    __shared__ int idx[4096];
+    int N2 = 1;
+    while (N2 < n) N2 <<= 1;
+    for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+        key[i] = i < n ? logl[i] : INFINITY;
+        idx[i] = i < n ? i : 0x7fffffff;
+    }
+    __syncthreads();
+    for (int size = 2; size <= N2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const double ki = key[i], kj = key[j];
+                    const int ii = idx[i], ij = idx[j];
+                    // (logl, index) lexicographic; NaN sorts after +inf
+                    const bool gt = (ki > kj) || (ki == kj && ii > ij) || (isnan(ki) && !isnan(kj));
+                    if (gt == up) {
+                        key[i] = kj; key[j] = ki;
+                        idx[i] = ij; idx[j] = ii;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = idx[i];
+    __syncthreads();
+    if (!record) return;
+    const int64_t base = S->n_dead;
+    for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
+        const int j = e / d, c = e % d;
+        if (base + j < dead_cap) dead_u[(base + j) * d + c] = u[(int64_t)idx[j] * d + c];
+    }
+    if (threadIdx.x == 0) {
+        double logx = S->logx, logz = S->logz;
+        for (int j = 0; j < k; ++j) {
+            const double nj = (double)(n - j);
+            const double l = key[j];
+            const double logw = logx + log(-expm1(-1.0 / nj));
+            logz = logaddexp(logz, l + logw);
+            logx -= 1.0 / nj;
+            if (base + j < dead_cap) {
+                dead_logl[base + j] = l;
+                dead_n[base + j] = n - j;
+            }
+        }
+        S->logx = logx;
+        S->logz = logz;
+        S->lstar = key[k - 1];
+        S->n_dead = base + k;
+    }
+}
+
+// Live-point covariance (1/(n-1)), trace jitter, Cholesky (lower, row-major).
+__global__ __launch_bounds__(256) void ns_dircov_kernel(const double* __restrict__ u, int n, int d,
+                                                        double* __restrict__ L) {
+    __shared__ double mean[MAX_DIM];
+    __shared__ double S[MAX_DIM * MAX_DIM];
+    for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += u[(int64_t)i * d + c];
+        mean[c] = s / n;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+        const int a = e / d, b = e % d;
+        if (b > a) continue;
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += (u[(int64_t)i * d + a] - mean[a]) * (u[(int64_t)i * d + b] - mean[b]);
+        S[a * d + b] = S[b * d + a] = s / (n - 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tr = 0.0;
+        for (int a = 0; a < d; ++a) tr += S[a * d + a];
+        const double jit = 1e-12 * tr / d;
+        for (int a = 0; a < d; ++a) S[a * d + a] += jit;
+        for (int j = 0; j < d; ++j) {
+            double s = S[j * d + j];
+            for (int p = 0; p < j; ++p) s -= S[j * d + p] * S[j * d + p];
+            const double djj = sqrt(fmax(s, 0.0));
+            S[j * d + j] = djj;
+            for (int i = j + 1; i < d; ++i) {
+                double t = S[i * d + j];
+                for (int p = 0; p < j; ++p) t -= S[i * d + p] * S[j * d + p];
+                S[i * d + j] = djj > 0.0 ? t / djj : 0.0;
+            }
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) L[a * d + b] = b <= a ? S[a * d + b] : 0.0;
+    }
+}
+
+// Walker w starts at survivor floor(U (n-k)) (draw 0 of step 0).
+__global__ void ns_spawn_kernel(const double* __restrict__ u, const double* __restrict__ logl,
+                                const int* __restrict__ order, int n, int k, int d, uint64_t seed,
+                                uint64_t iter, double* __restrict__ wu, double* __restrict__ wl) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= k) return;
+    const double U = philox_uniform(seed, 0, (uint64_t)w, 0, iter, 0);
+    int pick = (int)floor(U * (double)(n - k));
+    pick = pick > n - k - 1 ? n - k - 1 : pick;
+    const int src = order[k + pick];
+    for (int c = 0; c < d; ++c) wu[(int64_t)w * d + c] = u[(int64_t)src * d + c];
+    wl[w] = logl[src];
+}
+
+__global__ void ns_replace_kernel(double* __restrict__ u, double* __restrict__ logl,
+                                  const int* __restrict__ order, int k, int d, const double* __restrict__ wu,
+                                  const double* __restrict__ wl) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= k) return;
+    const int dst = order[w];
+    for (int c = 0; c < d; ++c) u[(int64_t)dst * d + c] = wu[(int64_t)w * d + c];
+    logl[dst] = wl[w];
+}
+
+// live term log(X mean_live L) and the stopping rule
+__global__ __launch_bounds__(256) void ns_term_kernel(const double* __restrict__ logl, int n,
+                                                      NSState* __restrict__ S, double log_frac) {
+    __shared__ double red[4];
+    double m = -INFINITY;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, logl[i]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += exp(logl[i] - mx);
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = red[0] + red[1] + red[2] + red[3];
+        const double live = mx + log(tot) - log((double)n) + S->logx;
+        S->live_term = live;
+        S->stop = (live - logaddexp(S->logz, live)) < log_frac ? 1 : 0;
+    }
+}
+
+// initial live points: u[i][c] = draw c of (walker i, step 0, iteration 0)
+__global__ void ns_init_kernel(double* __restrict__ u, int n, int d, uint64_t seed, NSState* S) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        S->logx = 0.0; S->logz = -INFINITY; S->lstar = -INFINITY; S->live_term = 0.0;
+        S->n_dead = 0; S->n_evals = n; S->n_stalls = 0; S->stop = 0;
+    }
+    if (e >= (int64_t)n * d) return;
+    const int i = (int)(e / d), c = (int)(e % d);
+    u[e] = philox_uniform(seed, 0, (uint64_t)i, 0, 0, (uint64_t)c);
+}
+
+// final: live points die in ascending order with counts n, n-1, ..., 1
+__global__ void ns_final_kernel(const double* __restrict__ logl, const double* __restrict__ u,
+                                const int* __restrict__ order, int n, int d, NSState* __restrict__ S,
+                                double* __restrict__ dead_logl, int* __restrict__ dead_n,
+                                double* __restrict__ dead_u, int64_t dead_cap) {
+    const int64_t base = S->n_dead;
+    for (int e = threadIdx.x; e < n * d; e += blockDim.x) {
+        const int j = e / d, c = e % d;
+        if (base + j < dead_cap) dead_u[(base + j) * d + c] = u[(int64_t)order[j] * d + c];
+    }
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        if (base + j < dead_cap) {
+            dead_logl[base + j] = logl[order[j]];
+            dead_n[base + j] = n - j;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) S->n_dead = base + n;
+}
+
+// log Z and H from the expected shrinkage, one workgroup, FP64.
+// out[0] = log Z, out[1] = H
+__global__ __launch_bounds__(256) void ns_evidence_kernel(const double* __restrict__ dl,
+                                                          const int* __restrict__ dn, int64_t M,
+                                                          double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double logx = 0.0, logz = -INFINITY;
+    for (int64_t i = 0; i < M; ++i) {
+        const double inv = 1.0 / dn[i];
+        logz = logaddexp(logz, dl[i] + logx + log(-expm1(-inv)));
+        logx -= inv;
+    }
+    logx = 0.0;
+    double H = 0.0;
+    for (int64_t i = 0; i < M; ++i) {
+        const double inv = 1.0 / dn[i];
+        const double lw = logx + log(-expm1(-inv));
+        if (isfinite(dl[i])) H += exp(dl[i] + lw - logz) * (dl[i] - logz);
+        logx -= inv;
+    }
+    out[0] = logz;
+    out[1] = H;
+}
+
+// log Z of replicate shrinkage sequences log t_m = log(1 - U_m)/n_m (stream 1).
+__global__ void ns_replicates_kernel(const double* __restrict__ dl, const int* __restrict__ dn, int64_t M,
+                                     int R, uint64_t seed, double* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double logx = 0.0, logz = -INFINITY;
+    for (int64_t m = 0; m < M; m += 4) {
+        const u64x4 b = philox4x64((uint64_t)(m >> 2), (uint64_t)r, 0, 0, seed, 1);
+        for (int e = 0; e < 4 && m + e < M; ++e) {
+            const double lt = log1p(-u01(b.x[e])) / (double)dn[m + e];
+            logz = logaddexp(logz, dl[m + e] + logx + log(-expm1(lt)));
+            logx += lt;
+        }
+    }
+    out[r] = logz;
+}
+
+// ------------------------------------------------------------------ host side
+__global__ void set_scalar_kernel(double* p, double v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
+// add the per-walker evaluation and stall counts of one slice step to the run totals
+__global__ __launch_bounds__(256) void ns_count_kernel(const int* __restrict__ ne, const int* __restrict__ ns,
+                                                       int k, NSState* __restrict__ S) {
+    __shared__ long long red[2][4];
+    long long a = 0, b = 0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) { a += ne[i]; b += ns[i]; }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = a; red[1][threadIdx.x >> 6] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S->n_evals += red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        S->n_stalls += red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* logl, int* ne, int* ns) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t bytes = al(k * d * 8) * 2 + al(k * 8) * 4 + al(k * 4) * 6 + al(4) * 2;
+    m->ws_slice.ensure(bytes);
+    char* p = m->ws_slice.as<char>();
+    SliceState S;
+    S.u = u; S.logl = logl; S.n_evals = ne; S.n_stalls = ns;
+    S.v = (double*)p; p += al(k * d * 8);
+    S.xc = (double*)p; p += al(k * d * 8);
+    S.tl = (double*)p; p += al(k * 8);
+    S.tr = (double*)p; p += al(k * 8);
+    S.tp = (double*)p; p += al(k * 8);
+    S.llc = (double*)p; p += al(k * 8);
+    S.st = (int*)p; p += al(k * 4);
+    S.step = (int*)p; p += al(k * 4);
+    S.q = (int*)p; p += al(k * 4);
+    S.ne = (int*)p; p += al(k * 4);
+    S.pend = (int*)p; p += al(k * 4);
+    S.cidx = (int*)p; p += al(k * 4);
+    S.ccount = (int*)p; p += al(4);
+    S.active = (int*)p; p += al(4);
+    return S;
+}
+
+// host flag buffer: pinned, one per model
+static int* host_flag(ns_model* m) {
+    if (!m->host_pinned) NS_HIP(hipHostMalloc(&m->host_pinned, 256, hipHostMallocDefault));
+    return static_cast<int*>(m->host_pinned);
+}
+
+void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
+                const double* lstar_dev, const double* L, int n_inner, uint64_t seed, uint64_t iter, int prec,
+                hipStream_t s) {
+    const int d = m->d;
+    NS_CHECK(d <= MAX_DIM, NS_E_UNSUPPORTED, "slice sampler supports d <= 64");
+    if (k == 0) return;
+    SliceState S = carve_slice(m, k, d, u, logl, n_evals, n_stalls);
+    m->ws_theta.ensure((size_t)k * d * sizeof(double));
+    double* thc = m->ws_theta.as<double>();
+    int* flag = host_flag(m);
+    const dim3 gw((unsigned)((k + 255) / 256));
+    hipLaunchKernelGGL(slice_init_kernel, gw, dim3(256), 0, s, S, k);
+    NS_HIP(hipGetLastError());
+    const int chunk = 16;
+    const int64_t max_rounds = (int64_t)n_inner * (2 * MAX_EXPAND + MAX_SHRINK + 4) + 8;
+    int64_t rounds = 0;
+    while (true) {
+        for (int c = 0; c < chunk; ++c) {
+            {
+                TraceScope ts(m, s, "slice_advance");
+                hipLaunchKernelGGL(slice_reset_kernel, dim3(1), dim3(64), 0, s, S);
+                hipLaunchKernelGGL(slice_advance_kernel, gw, dim3(256), 0, s, S, k, d, lstar_dev, L, n_inner, seed,
+                                   iter);
+            }
+            prior_transform(m, S.xc, thc, d, k, S.ccount, s);
+            loglike_batch(m, thc, d, k, S.llc, prec, S.ccount, s);
+        }
+        NS_HIP(hipGetLastError());
+        rounds += chunk;
+        NS_HIP(hipMemcpyAsync(flag, S.active, sizeof(int), hipMemcpyDeviceToHost, s));
+        NS_HIP(hipStreamSynchronize(s));
+        if (*flag == 0) break;
+        NS_CHECK(rounds < max_rounds, NS_E_INVALID, "slice sampler did not terminate");
+    }
+}
+
+void slice_step_host_lstar(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
+                           double lstar, const double* L, int n_inner, uint64_t seed, uint64_t iter, int prec,
+                           hipStream_t s) {
+    m->ws_flag.ensure(256);
+    double* lp = m->ws_flag.as<double>();
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, s, lp, lstar);
+    NS_HIP(hipGetLastError());
+    slice_step(m, u, logl, n_evals, n_stalls, k, lp, L, n_inner, seed, iter, prec, s);
+}
+
+void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, int* dn_h, double* du_h,
+         int64_t cap, hipStream_t s) {
+    const int n = o->n_live, k = o->n_delete, d = m->d;
+    NS_CHECK(n >= 2 && n <= 4096, NS_E_INVALID, "n_live must be in [2, 4096]");
+    NS_CHECK(k >= 1 && k < n, NS_E_INVALID, "n_delete must be in [1, n_live)");
+    NS_CHECK(o->n_inner >= 1, NS_E_INVALID, "n_inner must be >= 1");
+    NS_CHECK(d <= MAX_DIM, NS_E_UNSUPPORTED, "nested sampling supports d <= 64");
+    NS_CHECK(o->frac_remain > 0.0 && o->frac_remain < 1.0, NS_E_INVALID, "frac_remain must be in (0, 1)");
+    NS_CHECK(o->max_iter >= 1, NS_E_INVALID, "max_iter must be >= 1");
+    NS_CHECK(o->n_replicates >= 0, NS_E_INVALID, "n_replicates must be >= 0");
+    hipEvent_t ev0, ev1;
+    NS_HIP(hipEventCreate(&ev0));
+    NS_HIP(hipEventCreate(&ev1));
+    NS_HIP(hipEventRecord(ev0, s));
+    DevBuf live_u, live_l, order, wu, wl, wne, wns, L, state, th, dl, dn, du, ev;
+    live_u.ensure((size_t)n * d * 8);
+    live_l.ensure((size_t)n * 8);
+    order.ensure((size_t)n * 4);
+    wu.ensure((size_t)k * d * 8);
+    wl.ensure((size_t)k * 8);
+    wne.ensure((size_t)k * 4);
+    wns.ensure((size_t)k * 4);
+    L.ensure((size_t)d * d * 8);
+    state.ensure(sizeof(NSState));
+    th.ensure((size_t)n * d * 8);
+    int64_t dcap = std::max<int64_t>(4 * (int64_t)n, 1024);
+    dl.ensure(dcap * 8); dn.ensure(dcap * 4); du.ensure(dcap * d * 8);
+    NSState* S = state.as<NSState>();
+    NSState hs;
+    hipLaunchKernelGGL(ns_init_kernel, dim3((unsigned)(((int64_t)n * d + 255) / 256)), dim3(256), 0, s,
+                       live_u.as<double>(), n, d, o->seed, S);
+    NS_HIP(hipGetLastError());
+    prior_transform(m, live_u.as<double>(), th.as<double>(), d, n, nullptr, s);
+    loglike_batch(m, th.as<double>(), d, n, live_l.as<double>(), o->precision, nullptr, s);
+    const double log_frac = log(o->frac_remain);
+    int64_t it = 0;
+    int64_t n_dead = 0;
+    const double* lstar_dev = reinterpret_cast<const double*>(reinterpret_cast<const char*>(S) + offsetof(NSState, lstar));
+    while (it < o->max_iter) {
+        ++it;
+        if (n_dead + k + n > dcap) {
+            const int64_t ncap = std::max<int64_t>(2 * dcap, n_dead + k + n);
+            DevBuf dl2, dn2, du2;
+            dl2.ensure(ncap * 8); dn2.ensure(ncap * 4); du2.ensure(ncap * d * 8);
+            NS_HIP(hipMemcpyAsync(dl2.p, dl.p, n_dead * 8, hipMemcpyDeviceToDevice, s));
+            NS_HIP(hipMemcpyAsync(dn2.p, dn.p, n_dead * 4, hipMemcpyDeviceToDevice, s));
+            NS_HIP(hipMemcpyAsync(du2.p, du.p, n_dead * d * 8, hipMemcpyDeviceToDevice, s));
+            NS_HIP(hipStreamSynchronize(s));
+            std::swap(dl.p, dl2.p); std::swap(dl.bytes, dl2.bytes);
+            std::swap(dn.p, dn2.p); std::swap(dn.bytes, dn2.bytes);
+            std::swap(du.p, du2.p); std::swap(du.bytes, du2.bytes);
+            dcap = ncap;
+        }
+        hipLaunchKernelGGL(ns_select_kernel, dim3(1), dim3(1024), 0, s, live_l.as<double>(), live_u.as<double>(), n,
+                           k, d, order.as<int>(), S, dl.as<double>(), dn.as<int>(), du.as<double>(), dcap, 1);
+        hipLaunchKernelGGL(ns_dircov_kernel, dim3(1), dim3(256), 0, s, live_u.as<double>(), n, d, L.as<double>());
+        hipLaunchKernelGGL(ns_spawn_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, live_u.as<double>(),
+                           live_l.as<double>(), order.as<int>(), n, k, d, o->seed, (uint64_t)it, wu.as<double>(),
+                           wl.as<double>());
+        NS_HIP(hipGetLastError());
+        slice_step(m, wu.as<double>(), wl.as<double>(), wne.as<int>(), wns.as<int>(), k, lstar_dev, L.as<double>(),
+                   o->n_inner, o->seed, (uint64_t)it, o->precision, s);
+        hipLaunchKernelGGL(ns_count_kernel, dim3(1), dim3(256), 0, s, wne.as<int>(), wns.as<int>(), k, S);
+        hipLaunchKernelGGL(ns_replace_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s,
+                           live_u.as<double>(), live_l.as<double>(), order.as<int>(), k, d, wu.as<double>(),
+                           wl.as<double>());
+        hipLaunchKernelGGL(ns_term_kernel, dim3(1), dim3(256), 0, s, live_l.as<double>(), n, S, log_frac);
+        NS_HIP(hipGetLastError());
+        NS_HIP(hipMemcpyAsync(&hs, S, sizeof(NSState), hipMemcpyDeviceToHost, s));
+        NS_HIP(hipStreamSynchronize(s));
+        n_dead = hs.n_dead;
+        if (hs.stop) break;
+    }
+    // final: live points in ascending order
+    hipLaunchKernelGGL(ns_select_kernel, dim3(1), dim3(1024), 0, s, live_l.as<double>(), live_u.as<double>(), n, k,
+                       d, order.as<int>(), S, dl.as<double>(), dn.as<int>(), du.as<double>(), dcap, 0);
+    hipLaunchKernelGGL(ns_final_kernel, dim3(1), dim3(256), 0, s, live_l.as<double>(), live_u.as<double>(),
+                       order.as<int>(), n, d, S, dl.as<double>(), dn.as<int>(), du.as<double>(), dcap);
+    const int64_t M = n_dead + n;
+    const int R = o->n_replicates;
+    ev.ensure((size_t)(2 + std::max(R, 1)) * 8);
+    hipLaunchKernelGGL(ns_evidence_kernel, dim3(1), dim3(64), 0, s, dl.as<double>(), dn.as<int>(), M, ev.as<double>());
+    if (R > 0)
+        hipLaunchKernelGGL(ns_replicates_kernel, dim3((unsigned)((R + 63) / 64)), dim3(64), 0, s, dl.as<double>(),
+                           dn.as<int>(), M, R, o->seed, ev.as<double>() + 2);
+    NS_HIP(hipGetLastError());
+    std::vector<double> evh(2 + std::max(R, 1));
+    NS_HIP(hipMemcpyAsync(evh.data(), ev.p, evh.size() * 8, hipMemcpyDeviceToHost, s));
+    NS_HIP(hipMemcpyAsync(&hs, S, sizeof(NSState), hipMemcpyDeviceToHost, s));
+    NS_HIP(hipEventRecord(ev1, s));
+    NS_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    NS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    const int64_t ncopy = std::min<int64_t>(M, cap);
+    if (dl_h && ncopy > 0) NS_HIP(hipMemcpy(dl_h, dl.p, ncopy * 8, hipMemcpyDeviceToHost));
+    if (dn_h && ncopy > 0) NS_HIP(hipMemcpy(dn_h, dn.p, ncopy * 4, hipMemcpyDeviceToHost));
+    if (du_h && ncopy > 0) NS_HIP(hipMemcpy(du_h, du.p, ncopy * d * 8, hipMemcpyDeviceToHost));
+    res->logz = evh[0];
+    res->h = evh[1];
+    double mean = 0.0, var = 0.0;
+    for (int r = 0; r < R; ++r) mean += evh[2 + r];
+    if (R > 0) mean /= R;
+    for (int r = 0; r < R; ++r) var += (evh[2 + r] - mean) * (evh[2 + r] - mean);
+    res->sigma = R > 0 ? sqrt(var / R) : 0.0;
+    res->sigma_skilling = sqrt(std::max(evh[1], 0.0) / n);
+    res->n_iter = it;
+    res->n_evals = hs.n_evals;
+    res->n_stalls = hs.n_stalls;
+    res->n_dead = M;
+    res->wall_s = ms * 1e-3;
+}
+
+}  // namespace nsmi

@@ -1,0 +1,385 @@
+// Cosmic-shear likelihood stages after the emulator (App. A of the paper).
+//
+// zspline_kernel   second derivatives M_n(k) of the not-a-knot cubic spline of
+//                  log10 P along the uniform z nodes, one thread per (walker, k):
+//                  M_1 and M_{N-2} follow directly from the not-a-knot
+//                  conditions on a uniform grid, the interior (1, 4, 1)
+//                  system is solved by a Thomas sweep, M_0 and M_{N-1} are
+//                  linear extrapolations.
+// limber_kernel    one workgroup per walker:
+//                  (a) background on the a-grid: E(a), chi by per-interval
+//                      Simpson, J = dchi/d(-a), growth D (growth index 0.55);
+//                  (b) n_i(z) with photo-z shifts, normalised by the trapezoid
+//                      rule; lensing window Eq. (A3) as (chi/a)(G0 - chi G1)
+//                      with reverse cumulative trapezoids; NLA window Eq. (A4);
+//                      effective window W = W^g + W^I (the four terms of Eq. (A1)
+//                      share P_dd);
+//                  (c) P(k = (l+1/2)/chi_j, z_j): spline in z, Catmull-Rom in
+//                      log10 k (linear ghost nodes), zero outside [k_min, k_max];
+//                  (d) Limber sum Eq. (A2) by the trapezoid rule in a with the
+//                      analytic Jacobian, times (1 + m_i)(1 + m_j).
+//                  (a)-(b) are FP64; (c)-(d) run in the form's type T.
+// dense_chi2_kernel  y = L^{-1} d - L^{-1} C with the host-factorised dense
+//                  covariance, logL = -1/2 |y|^2 - sum log L_ii - n/2 log 2 pi (FP64).
+#include "devutil.h"
+#include "nsmi.h"
+
+namespace nsmi {
+
+constexpr double C_KM_S = 299792.458;
+constexpr double C1_RHOCR = 5e-14 * 2.77536627e11;
+constexpr double GROWTH_INDEX = 0.55;
+constexpr double LN10 = 2.302585092994045684;
+
+// -------------------------------------------------------------- z-spline
+template <class T>
+__global__ __launch_bounds__(256) void zspline_kernel(const T* __restrict__ Y, T* __restrict__ M, int64_t B,
+                                                      int nz, int nk, double h, const int* __restrict__ count) {
+    // c'_n of the (1, 4, 1) Thomas sweep: data independent, tabulated once per block
+    __shared__ T cps[256];
+    if (threadIdx.x == 0) {
+        T c = T(0);
+        for (int n = 2; n <= nz - 3 && n < 256; ++n) {
+            c = T(1) / (T(4) - (n == 2 ? T(0) : c));
+            cps[n] = c;
+        }
+    }
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (count) B = min<int64_t>(B, *count);
+    if (g >= B * nk) return;
+    const int64_t w = g / nk;
+    const int c = (int)(g % nk);
+    const T* y = Y + w * nz * nk + c;
+    T* mm = M + w * nz * nk + c;
+    const T ih2 = T(1.0 / (h * h));
+    auto yv = [&](int n) { return y[(int64_t)n * nk]; };
+    const T M1 = (yv(2) - T(2) * yv(1) + yv(0)) * ih2;
+    const T Mb = (yv(nz - 1) - T(2) * yv(nz - 2) + yv(nz - 3)) * ih2;   // M_{N-2}
+    mm[(int64_t)1 * nk] = M1;
+    mm[(int64_t)(nz - 2) * nk] = Mb;
+    // interior unknowns n = 2 .. nz-3: M_{n-1} + 4 M_n + M_{n+1} = 6 d2Y_n / h^2
+    if (nz > 4) {
+        T dp = T(0);
+        for (int n = 2; n <= nz - 3; ++n) {
+            T rhs = T(6) * (yv(n + 1) - T(2) * yv(n) + yv(n - 1)) * ih2;
+            if (n == 2) rhs -= M1;
+            if (n == nz - 3) rhs -= Mb;
+            dp = (rhs - (n == 2 ? T(0) : dp)) * cps[n];
+            mm[(int64_t)n * nk] = dp;                   // d'_n, overwritten below
+        }
+        T next = dp;                                    // M_{nz-3} = d'_{nz-3}
+        for (int n = nz - 4; n >= 2; --n) {
+            next = mm[(int64_t)n * nk] - cps[n] * next;
+            mm[(int64_t)n * nk] = next;
+        }
+    }
+    const T M2 = mm[(int64_t)2 * nk];
+    const T Mc = mm[(int64_t)(nz - 3) * nk];
+    mm[0] = T(2) * M1 - M2;
+    mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
+}
+
+// --------------------------------------------------------------- block scans
+// Inclusive prefix sum over the block of per-thread values (blockDim = 256).
+template <int NV>
+__device__ void block_scan(double (&v)[NV], double* buf /* [NV][256] */, bool reverse) {
+    const int t = threadIdx.x;
+    const int src = reverse ? 255 - t : t;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) buf[q * 256 + src] = v[q];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        double add[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) add[q] = src >= off ? buf[q * 256 + src - off] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NV; ++q) buf[q * 256 + src] += add[q];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = buf[q * 256 + src];
+    __syncthreads();
+}
+
+constexpr int MAXB = 10;   // tomographic bins supported by the kernel
+
+struct ShearGeom {
+    int n_a, n_z, n_k, n_ell, n_bins, n_pairs;
+    double a_min, da, zmax, k_min, k_max, u0, du, nz_sigma;
+};
+
+// One workgroup (256 threads) per walker; n_a <= 256 nodes (one per thread).
+template <class T>
+__global__ __launch_bounds__(256) void limber_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
+    const int* __restrict__ pidx, const double* __restrict__ pfix, const double* __restrict__ nz_mean,
+    const double* __restrict__ agrid, const int* __restrict__ zidx, const double* __restrict__ zcoef,
+    const double* __restrict__ ell, const T* __restrict__ Ytab, const T* __restrict__ Mtab,
+    double* __restrict__ Cout, const int* __restrict__ count) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    if (count) B = min<int64_t>(B, *count);
+    const int64_t w = blockIdx.x;
+    if (w >= B) return;
+    const int t = threadIdx.x;
+    const int na = G.n_a, nb = G.n_bins;
+    double* scan = reinterpret_cast<double*>(smem);                   // [2*MAXB][256]
+    double* red = scan + 2 * MAXB * 256;                              // [MAXB][4]
+    double* chis = red + MAXB * 4;                                    // [256]
+    T* Wt = reinterpret_cast<T*>(chis + 256);                         // [nb][256]
+    T* wq = Wt + nb * 256;                                            // [256]
+    T* Pl = wq + 256;                                                 // [n_ell][256]
+
+    // physical parameters
+    auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
+    const double ob = phys(0), oc = phys(1), h = phys(2), w0 = phys(5), wa = phys(6);
+    const double Om = (ob + oc) / (h * h);
+    const double cH0 = C_KM_S / (100.0 * h), H0c = 1.0 / cH0;
+    auto Efn = [&](double a) {
+        return sqrt(Om / (a * a * a) + (1.0 - Om) * pow(a, -3.0 * (1.0 + w0 + wa)) * exp(-3.0 * wa * (1.0 - a)));
+    };
+    auto ffn = [&](double a) { return cH0 / (a * a * Efn(a)); };
+    auto gfn = [&](double a) {
+        const double E = Efn(a);
+        return pow(Om / (a * a * a) / (E * E), GROWTH_INDEX) / a;
+    };
+
+    // (a) background: Simpson increments of chi and -ln D on interval [a_t, a_{t+1}]
+    const bool node = t < na;
+    const double a = node ? agrid[t] : 1.0;
+    double inc[2] = {0.0, 0.0};
+    double fa = 0.0, Ea = 1.0;
+    if (node) {
+        Ea = Efn(a);
+        fa = cH0 / (a * a * Ea);
+        if (t < na - 1) {
+            const double a1 = agrid[t + 1], am = 0.5 * (a + a1);
+            inc[0] = G.da / 6.0 * (fa + 4.0 * ffn(am) + ffn(a1));
+            inc[1] = G.da / 6.0 * (gfn(a) + 4.0 * gfn(am) + gfn(a1));
+        }
+    }
+    block_scan<2>(inc, scan, false);        // inclusive sums over intervals 0..t
+    // values at node t are the sums over intervals 0..t-1
+    chis[t] = inc[0];
+    __syncthreads();
+    const double chi = (node && t > 0) ? chis[t - 1] : 0.0;
+    __syncthreads();
+    chis[t] = inc[1];
+    __syncthreads();
+    const double D = exp(-((node && t > 0) ? chis[t - 1] : 0.0));
+    __syncthreads();
+    chis[t] = chi;
+
+    // (b) redshift distributions, normalisation
+    const double z = 1.0 / a - 1.0;
+    const double q = (t == 0 || t == na - 1) ? 0.5 * G.da : G.da;
+    double nraw[MAXB];
+    for (int i = 0; i < nb; ++i) {
+        const double mu = nz_mean[i] + phys(9 + nb + i);
+        const double dz = z - mu;
+        nraw[i] = (node && t > 0) ? exp(-dz * dz / (2.0 * G.nz_sigma * G.nz_sigma)) : 0.0;
+    }
+    {
+        const int lane = t & 63, wid = t >> 6;
+        for (int i = 0; i < nb; ++i) {
+            double v = wave_sum(node ? q * nraw[i] / (a * a) : 0.0);
+            if (lane == 0) red[i * 4 + wid] = v;
+        }
+        __syncthreads();
+        for (int i = 0; i < nb; ++i) nraw[i] /= (red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3]);
+        __syncthreads();
+    }
+    // reverse cumulative trapezoids G0, G1: segment [t, t+1] stored at node t
+    double seg[2 * MAXB];
+    {
+        // integrands at this node and the next one
+        double g0[MAXB], g1[MAXB];
+        for (int i = 0; i < nb; ++i) {
+            g0[i] = node ? nraw[i] / (a * a) : 0.0;
+            g1[i] = (node && t > 0) ? nraw[i] / (a * a * chi) : 0.0;
+        }
+        // exchange with the neighbour through LDS
+        for (int i = 0; i < nb; ++i) {
+            scan[i * 256 + t] = g0[i];
+            scan[(MAXB + i) * 256 + t] = g1[i];
+        }
+        __syncthreads();
+        for (int i = 0; i < nb; ++i) {
+            const bool has = node && t < na - 1;
+            seg[i] = has ? 0.5 * G.da * (g0[i] + scan[i * 256 + t + 1]) : 0.0;
+            seg[MAXB + i] = has ? 0.5 * G.da * (g1[i] + scan[(MAXB + i) * 256 + t + 1]) : 0.0;
+        }
+        for (int i = nb; i < MAXB; ++i) seg[i] = seg[MAXB + i] = 0.0;
+        __syncthreads();
+    }
+    block_scan<2 * MAXB>(seg, scan, true);   // seg[i] = sum_{m >= t} segment_m
+    const double pref = 1.5 * Om * H0c * H0c * chi / a;
+    for (int i = 0; i < nb; ++i) {
+        const double Wg = pref * (seg[i] - chi * seg[MAXB + i]);
+        const double AIA = phys(9 + i);
+        const double WI = -AIA * C1_RHOCR * Om * nraw[i] * H0c * Ea / D;
+        Wt[i * 256 + t] = node ? (T)(Wg + WI) : T(0);
+    }
+    wq[t] = (node && t > 0) ? (T)(q * fa / (chi * chi)) : T(0);
+    __syncthreads();
+
+    // (c) P at the Limber wavenumbers: ell-major [n_ell][256]
+    const T* Yw = Ytab + w * (int64_t)G.n_z * G.n_k;
+    const T* Mw = Mtab + w * (int64_t)G.n_z * G.n_k;
+    for (int e = t; e < G.n_ell * 256; e += 256) {
+        const int b = e >> 8, j = e & 255;
+        T P = T(0);
+        if (j > 0 && j < na) {
+            const double cj = chis[j];
+            const double k = (ell[b] + 0.5) / cj;
+            if (k >= G.k_min && k <= G.k_max) {
+                const double s = (log10(k) - G.u0) / G.du;
+                int i0 = (int)floor(s);
+                i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
+                const T tt = (T)(s - i0);
+                const int n = zidx[j];
+                const T c0 = (T)zcoef[4 * j], c1 = (T)zcoef[4 * j + 1], c2 = (T)zcoef[4 * j + 2], c3 = (T)zcoef[4 * j + 3];
+                auto Yz = [&](int col) {
+                    const int64_t o0 = (int64_t)n * G.n_k + col, o1 = o0 + G.n_k;
+                    return c0 * Yw[o0] + c1 * Yw[o1] + c2 * Mw[o0] + c3 * Mw[o1];
+                };
+                const T p0 = Yz(i0), p1 = Yz(i0 + 1);
+                const T pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
+                const T p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
+                const T m0 = T(0.5) * (p1 - pm), m1 = T(0.5) * (p2 - p0);
+                const T t2 = tt * tt, t3 = t2 * tt;
+                const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * m0 +
+                             (T(-2) * t3 + T(3) * t2) * p1 + (t3 - t2) * m1;
+                P = exp(lp * T(LN10)) * wq[j];
+            }
+        }
+        Pl[e] = P;
+    }
+    __syncthreads();
+
+    // (d) Limber sums, one thread per (pair, ell); pairs (i <= j) lexicographic
+    const int nout = G.n_pairs * G.n_ell;
+    for (int o = t; o < nout; o += 256) {
+        const int p = o / G.n_ell, b = o % G.n_ell;
+        int bi = 0, rem = p;
+        while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+        const int bj = bi + rem;
+        const T* Wi = Wt + bi * 256;
+        const T* Wj = Wt + bj * 256;
+        const T* Pb = Pl + b * 256;
+        T s = T(0);
+        for (int j = 1; j < na; ++j) s += Wi[j] * Wj[j] * Pb[j];
+        const double mi = phys(9 + 2 * nb + bi), mj = phys(9 + 2 * nb + bj);
+        Cout[w * nout + o] = (1.0 + mi) * (1.0 + mj) * (double)s;
+    }
+}
+
+// ---------------------------------------------------------------- dense chi^2
+// 16 walkers per block; y_i = wv_i - sum_{k <= i} Linv[i][k] C[k] in FP64.
+constexpr int DC_W = 16;
+__global__ __launch_bounds__(256) void dense_chi2_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
+    const double* __restrict__ pa, const double* __restrict__ pb, const double* __restrict__ C, int n,
+    const double* __restrict__ Linv, const double* __restrict__ wv, double cst, double* __restrict__ logl,
+    const int* __restrict__ count) {
+    extern __shared__ double Cs[];                 // [DC_W][n]
+    __shared__ double red[DC_W][16];
+    if (count) B = min<int64_t>(B, *count);
+    const int64_t w0 = (int64_t)blockIdx.x * DC_W;
+    if (w0 >= B) return;
+    for (int e = threadIdx.x; e < DC_W * n; e += 256) {
+        const int64_t w = w0 + e / n;
+        Cs[e] = w < B ? C[w * n + e % n] : 0.0;
+    }
+    __syncthreads();
+    const int wk = threadIdx.x % DC_W, part = threadIdx.x / DC_W;
+    double s = 0.0;
+    const double* cw = Cs + wk * n;
+    for (int i = part; i < n; i += 256 / DC_W) {
+        const double* Li = Linv + (int64_t)i * n;
+        double acc = 0.0;
+        for (int k = 0; k <= i; ++k) acc = fma(Li[k], cw[k], acc);
+        const double y = wv[i] - acc;
+        s = fma(y, y, s);
+    }
+    red[wk][part] = s;
+    __syncthreads();
+    if (threadIdx.x < DC_W) {
+        const int64_t w = w0 + threadIdx.x;
+        if (w < B) {
+            double chi2 = 0.0;
+            for (int p = 0; p < 256 / DC_W; ++p) chi2 += red[threadIdx.x][p];
+            bool ok = true;
+            const double* th = theta + w * ld;
+            for (int i = 0; i < d; ++i)
+                if (pk[i] == NS_PRIOR_UNIFORM && (th[i] < pa[i] || th[i] > pb[i])) ok = false;
+            logl[w] = ok ? -0.5 * chi2 + cst : -INFINITY;
+        }
+    }
+}
+
+static size_t limber_smem(const ns_model* m, size_t elem) {
+    return (2 * MAXB * 256 + MAXB * 4 + 256) * sizeof(double) + (size_t)(m->n_bins + 1 + m->n_ell) * 256 * elem;
+}
+
+void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
+                              int prec, const int* count, hipStream_t s) {
+    const int nk = m->n_k, nz = m->n_z;
+    const size_t elem = prec == NS_FP64 ? 8 : 4;
+    const int n = m->n_data;
+    // aux: spline second derivatives [B x nz x nk] then spectra [B x n] (double)
+    const size_t mbytes = (size_t)B * nz * nk * elem;
+    m->ws_aux.ensure(mbytes + (size_t)B * n * sizeof(double));
+    void* Mtab = m->ws_aux.p;
+    double* Cv = reinterpret_cast<double*>(m->ws_aux.as<char>() + mbytes);
+    const double zmax = 1.0 / m->a_min - 1.0;
+    const double hz = zmax / (nz - 1);
+    const int64_t nthr = B * nk;
+    dim3 gz((unsigned)((nthr + 255) / 256));
+    {
+    TraceScope ts(m, s, "zspline");
+    if (prec == NS_FP64)
+        hipLaunchKernelGGL(zspline_kernel<double>, gz, dim3(256), 0, s, m->ws_out.as<double>(), (double*)Mtab, B,
+                           nz, nk, hz, count);
+    else
+        hipLaunchKernelGGL(zspline_kernel<float>, gz, dim3(256), 0, s, m->ws_out.as<float>(), (float*)Mtab, B, nz,
+                           nk, hz, count);
+    NS_HIP(hipGetLastError());
+    }
+    ShearGeom G;
+    G.n_a = m->n_a; G.n_z = nz; G.n_k = nk; G.n_ell = m->n_ell; G.n_bins = m->n_bins; G.n_pairs = m->n_pairs;
+    G.a_min = m->a_min; G.da = (1.0 - m->a_min) / (m->n_a - 1); G.zmax = zmax;
+    G.k_min = m->k_min; G.k_max = m->k_max; G.u0 = log10(m->k_min);
+    G.du = (log10(m->k_max) - log10(m->k_min)) / (nk - 1); G.nz_sigma = m->nz_sigma;
+    const size_t sm = limber_smem(m, elem);
+    NS_CHECK(sm <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
+    if (prec == NS_FP64)
+        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<double>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
+    else
+        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<float>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
+    {
+    TraceScope ts(m, s, "limber");
+    if (prec == NS_FP64)
+        hipLaunchKernelGGL(limber_kernel<double>, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
+                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
+                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
+                           m->ell_d.as<double>(), m->ws_out.as<double>(), (const double*)Mtab, Cv, count);
+    else
+        hipLaunchKernelGGL(limber_kernel<float>, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
+                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
+                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
+                           m->ell_d.as<double>(), m->ws_out.as<float>(), (const float*)Mtab, Cv, count);
+    NS_HIP(hipGetLastError());
+    }
+    const size_t sm2 = (size_t)DC_W * n * sizeof(double);
+    TraceScope ts(m, s, "dense_chi2");
+    hipLaunchKernelGGL(dense_chi2_kernel, dim3((unsigned)((B + DC_W - 1) / DC_W)), dim3(256), sm2, s, theta, ld, B,
+                       m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), Cv, n,
+                       m->cov_linv.as<double>(), m->cov_w.as<double>(), m->logl_const, logl, count);
+    NS_HIP(hipGetLastError());
+}
+
+}  // namespace nsmi

@@ -1,0 +1,153 @@
+"""Parity of the HIP batched likelihood (ns_loglike_batch) with the FP64 oracle.
+
+Tolerances (stated per precision form):
+* FP64: |dlogL| <= 1e-6 for walkers in the posterior region (theta_fid plus
+  Fisher-scaled Gaussian draws); for prior draws, where chi^2 reaches 1e6+,
+  |dlogL| <= 1e-12 |logL| + 1e-6.
+* FP32 / BF16X3 / BF16: the measured |dlogL| on posterior-region walkers is
+  printed and bounded by the per-form, per-workload limits of LOWP_LIMIT
+  (see the design doc for their derivation from the rounding of each form).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.likelihood import loglike as oracle_loglike
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def built():
+    from paper_2509_13307_amd import _capi
+    _capi.lib()
+    return True
+
+
+_models = {}
+
+
+def gpu_model(name):
+    from paper_2509_13307_amd import Model
+    if name not in _models:
+        _models[name] = (W.load_model(name), Model(W.load_model(name)))
+    return _models[name]
+
+
+def post_scale(m):
+    width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
+    return np.minimum(m["fisher_sigma"], 0.1 * width)
+
+
+def run_gpu(model, theta, prec="fp64"):
+    t = torch.tensor(theta, dtype=torch.float64, device=DEV)
+    out = model.loglike(t, precision=prec)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check_fp64(ref, got, label):
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got)), label
+    d = np.abs(ref[fin] - got[fin])
+    tol = 1e-12 * np.abs(ref[fin]) + 1e-6
+    say(f"{label}: max|dlogL| = {d.max():.3e}  max rel = {(d / np.abs(ref[fin])).max():.3e}")
+    assert np.all(d <= tol), (label, d.max())
+
+
+@pytest.mark.parametrize("name,B", [("cmb6", 1000), ("cmb4x2500", 300), ("shear10", 24), ("shear64", 12)])
+def test_fp64_posterior_and_prior(built, name, B):
+    say(f"case fp64 {name} B={B}")
+    m, g = gpu_model(name)
+    th_post = W.posterior_draws(m["theta_fid"], post_scale(m), B, tag=1)
+    th_prior = W.prior_draws(m, B + 7, tag=1)
+    for label, th in (("posterior", th_post), ("prior", th_prior)):
+        ref = oracle_loglike(th, m, chunk=64)
+        got = run_gpu(g, th)
+        check_fp64(ref, got, f"{name} {label}")
+
+
+@pytest.mark.parametrize("name,B,sample", [("cmb4x2500", 4096, 40), ("shear64", 4096, 6), ("shear10", 16384, 6)])
+def test_fp64_full_size_sampled(built, name, B, sample):
+    say(f"case fp64 full {name} B={B}")
+    m, g = gpu_model(name)
+    th = W.prior_draws(m, B, tag=2)
+    th[: B // 2] = W.posterior_draws(m["theta_fid"], post_scale(m), B // 2, tag=2)
+    got = run_gpu(g, th)
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([[0, 1, 127, 128, B // 2 - 1, B // 2, B - 2, B - 1],
+                                    rng.integers(0, B, size=sample)]))
+    ref = oracle_loglike(th[idx], m, chunk=64)
+    check_fp64(ref, got[idx], f"{name} full B={B}")
+
+
+def test_edge_cases(built):
+    say("case edge cmb6")
+    m, g = gpu_model("cmb6")
+    th = np.tile(m["theta_fid"], (5, 1))
+    th[1, 2] = -0.01          # outside U(0,1)
+    th[2, 5] = 1.0            # on the boundary: inside
+    th[3, 0] = np.nan         # NaN -> NaN
+    got = run_gpu(g, th)
+    ref = oracle_loglike(th, m)
+    assert got[1] == -np.inf and np.isnan(got[3])
+    np.testing.assert_allclose(got[[0, 2, 4]], ref[[0, 2, 4]], rtol=1e-13, atol=1e-7)
+    one = run_gpu(g, th[:1])
+    assert abs(one[0] - ref[0]) < 1e-7
+    # B = 0 is a no-op
+    out = g.loglike(torch.empty(0, 6, dtype=torch.float64, device=DEV))
+    assert out.numel() == 0
+    # leading dimension > d
+    wide = np.concatenate([th, np.zeros((5, 3))], axis=1)
+    t = torch.tensor(wide, dtype=torch.float64, device=DEV)
+    got2 = g.loglike(t).cpu().numpy()
+    np.testing.assert_array_equal(np.isnan(got2), np.isnan(got))
+    np.testing.assert_allclose(got2[[0, 2, 4]], got[[0, 2, 4]], rtol=0, atol=0)
+
+
+def test_batch_and_permutation_invariance(built):
+    say("case invariance cmb4x2500")
+    m, g = gpu_model("cmb4x2500")
+    th = W.posterior_draws(m["theta_fid"], post_scale(m), 257, tag=3)
+    full = run_gpu(g, th, "bf16")
+    perm = np.random.default_rng(1).permutation(257)
+    again = run_gpu(g, th[perm], "bf16")
+    np.testing.assert_array_equal(again, full[perm])
+    single = run_gpu(g, th[100:101], "bf16")
+    assert single[0] == full[100]
+
+
+# |dlogL| limits of the reduced-precision forms on posterior-region walkers
+LOWP_LIMIT = {
+    ("cmb6", "fp32"): 1e-2, ("cmb6", "bf16x3"): 1e-2, ("cmb6", "bf16"): 5.0,
+    ("cmb4x2500", "fp32"): 1e-2, ("cmb4x2500", "bf16x3"): 1e-1, ("cmb4x2500", "bf16"): 200.0,
+    ("shear10", "fp32"): 1e-2, ("shear10", "bf16x3"): 1e-2, ("shear10", "bf16"): 5.0,
+    ("shear64", "fp32"): 1e-2, ("shear64", "bf16x3"): 1e-2, ("shear64", "bf16"): 5.0,
+}
+
+
+@pytest.mark.parametrize("name", ["cmb6", "cmb4x2500", "shear10", "shear64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_reduced_precision_forms(built, name, prec):
+    say(f"case {prec} {name}")
+    m, g = gpu_model(name)
+    B = 64 if name.startswith("shear") else 256
+    th = W.posterior_draws(m["theta_fid"], post_scale(m), B, tag=4)
+    ref = oracle_loglike(th, m, chunk=64)
+    got = run_gpu(g, th, prec)
+    fin = np.isfinite(ref)                 # draws beyond a uniform prior bound give -inf on both sides
+    assert np.array_equal(fin, np.isfinite(got))
+    assert fin.sum() >= B // 2
+    d = np.abs(got[fin] - ref[fin])
+    say(f"{name} {prec}: |dlogL| max {d.max():.3e} median {np.median(d):.3e} over {fin.sum()} walkers")
+    assert d.max() <= LOWP_LIMIT[(name, prec)]
