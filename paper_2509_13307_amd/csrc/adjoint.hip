@@ -1,0 +1,199 @@
+// Hand-written adjoint of the batched likelihood (input gradients only).
+//
+// logL = -1/2 |L^{-1}(d - C)|^2 + const, so d logL / dC = L^{-T} L^{-1} (d - C)
+// (Cholesky whitening run backwards, FP64).  The CMB seed kernels apply the
+// output transform's derivative (C = 10^y: dC/dy = C ln 10; y = mu + sigma o)
+// to obtain d logL / d o for the raw network outputs o; emulator_backward
+// carries it through the GEMM chain (transposed weights, f'(t) from the
+// saved pre-activations) to the emulator inputs; grad_assemble_kernel maps
+// input gradients back to theta (summing over networks and redshift rows)
+// and adds the direct (non-emulator) part.  Rows outside the prior support
+// get logL = -inf and a zero gradient.
+#include "devutil.h"
+#include "nsmi.h"
+
+namespace nsmi {
+
+__device__ __forceinline__ bool in_support_row(const double* th, int d, const int* kind, const double* a,
+                                               const double* b) {
+    bool ok = true;
+    for (int i = 0; i < d; ++i)
+        if (kind[i] == NS_PRIOR_UNIFORM && (th[i] < a[i] || th[i] > b[i])) ok = false;
+    return ok;
+}
+
+// CMB seeds: model vector mvec [B x n] (T) -> logL and delta[g][row][n_pad]
+// (T) for each of the G networks.  Diagonal: dlogL/dC_i = r_i / sigma_i^2.
+// Block: per multipole g3 = Linv^T (Linv r3); PP: r / sigma_pp^2.
+struct SeedNet {
+    const double* sigma_out;   // [n_out]
+    int is_log;
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void cmb_seed_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
+    const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ mvec, int kind, int n,
+    int n_ell, const double* __restrict__ data, const double* __restrict__ isig, const double* __restrict__ linv,
+    const double* __restrict__ isig_pp, double cst, SeedNet s0, SeedNet s1, SeedNet s2, SeedNet s3, int n_pad,
+    size_t gstride, T* __restrict__ delta, double* __restrict__ logl) {
+    __shared__ double red[4];
+    const int64_t row = blockIdx.x;
+    if (row >= B) return;
+    const bool ok = in_support_row(theta + row * ld, d, pk, pa, pb);
+    const T* mv = mvec + row * (int64_t)n;
+    const SeedNet sn[4] = {s0, s1, s2, s3};
+    double chi2 = 0.0;
+    auto put = [&](int g, int i, double gc) {
+        const double C = (double)mv[(int64_t)g * (kind == NS_MODEL_CMB_BLOCK ? n_ell : 0) + i];
+        double dv = gc * sn[g].sigma_out[i] * (sn[g].is_log ? C * 2.302585092994045684 : 1.0);
+        delta[g * gstride + row * n_pad + i] = ok ? (T)dv : T(0);
+    };
+    if (kind == NS_MODEL_CMB_DIAG) {
+        for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
+            if (i < n) {
+                const double r = data[i] - (double)mv[i];
+                const double w = r * isig[i];
+                chi2 += w * w;
+                put(0, i, w * isig[i]);
+            } else {
+                delta[row * n_pad + i] = T(0);
+            }
+        }
+    } else {
+        for (int l = threadIdx.x; l < n_pad; l += blockDim.x) {
+            if (l < n_ell) {
+                const double* Lq = linv + 6 * (int64_t)l;
+                const double rtt = data[l] - (double)mv[l], rte = data[n_ell + l] - (double)mv[n_ell + l];
+                const double ree = data[2 * n_ell + l] - (double)mv[2 * n_ell + l];
+                const double rpp = data[3 * n_ell + l] - (double)mv[3 * n_ell + l];
+                const double y0 = Lq[0] * rtt, y1 = Lq[1] * rtt + Lq[2] * rte;
+                const double y2 = Lq[3] * rtt + Lq[4] * rte + Lq[5] * ree;
+                const double wp = rpp * isig_pp[l];
+                chi2 += y0 * y0 + y1 * y1 + y2 * y2 + wp * wp;
+                put(0, l, Lq[0] * y0 + Lq[1] * y1 + Lq[3] * y2);
+                put(1, l, Lq[2] * y1 + Lq[4] * y2);
+                put(2, l, Lq[5] * y2);
+                put(3, l, wp * isig_pp[l]);
+            } else {
+                for (int g = 0; g < 4; ++g) delta[g * gstride + row * n_pad + l] = T(0);
+            }
+        }
+    }
+    chi2 = wave_sum(chi2);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = chi2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double c2 = red[0] + red[1] + red[2] + red[3];
+        logl[row] = ok ? -0.5 * c2 + cst : -INFINITY;
+    }
+}
+
+// grad[w][c] = direct[w][c] + sum_g sum_z sum_k [src_k == c] gx[g][w rpw + z][k]; zero outside the support.
+__global__ void grad_assemble_kernel(int64_t B, int d, int G, int rpw, int n_in, const int* __restrict__ src,
+                                     const double* __restrict__ gx, const double* __restrict__ direct,
+                                     const double* __restrict__ logl, double* __restrict__ grad) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * d) return;
+    const int64_t w = e / d;
+    const int c = (int)(e % d);
+    double s = direct ? direct[e] : 0.0;
+    const int64_t rows = B * rpw;
+    for (int g = 0; g < G; ++g)
+        for (int z = 0; z < rpw; ++z)
+            for (int k = 0; k < n_in; ++k)
+                if (src[k] == c) s += gx[((int64_t)g * rows + w * rpw + z) * n_in + k];
+    grad[e] = logl[w] == -INFINITY ? 0.0 : s;
+}
+
+__global__ void gauss_grad_kernel(const double* __restrict__ theta, int64_t ld, int64_t B, int d,
+                                  const int* __restrict__ pk, const double* __restrict__ pa,
+                                  const double* __restrict__ pb, const double* __restrict__ mu,
+                                  const double* __restrict__ isig, double cst, double* __restrict__ logl,
+                                  double* __restrict__ grad) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= B) return;
+    const double* th = theta + row * ld;
+    const bool ok = in_support_row(th, d, pk, pa, pb);
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) {
+        const double r = (th[i] - mu[i]) * isig[i];
+        s = fma(r, r, s);
+        grad[row * d + i] = ok ? -r * isig[i] : 0.0;
+    }
+    logl[row] = ok ? -0.5 * s + cst : -INFINITY;
+}
+
+void loglike_grad_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, double* grad,
+                        int prec, hipStream_t s) {
+    if (B == 0) return;
+    const int* pk = m->prior_kind.as<int>();
+    const double* pa = m->prior_a.as<double>();
+    const double* pb = m->prior_b.as<double>();
+    if (m->kind == NS_MODEL_GAUSS) {
+        TraceScope ts(m, s, "gauss_grad");
+        hipLaunchKernelGGL(gauss_grad_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld, B, m->d,
+                           pk, pa, pb, m->g_mu.as<double>(), m->g_isig.as<double>(), m->logl_const, logl, grad);
+        NS_HIP(hipGetLastError());
+        return;
+    }
+    const bool f64 = prec == NS_FP64;
+    const size_t elem = f64 ? 8 : 4;
+    const int G = (int)m->nets.size();
+    int ids[4] = {0, 1, 2, 3};
+    const Net& net0 = *m->nets[0];
+    const int L = net0.n_layers;
+    const int rpw = net0.out_mu_rows;
+    const int64_t rows = B * rpw;
+    size_t max_w = 0;
+    for (int l = 1; l < L; ++l) max_w = std::max(max_w, (size_t)net0.dims[l]);
+    const int n_pad = net0.layers[L - 1]->n_pad;
+    const size_t gstride = (size_t)rows * std::max(max_w, (size_t)n_pad);
+    m->ws_gact[0].ensure(G * gstride * elem);
+    m->ws_gact[1].ensure(G * gstride * elem);
+    // reduced forms: forward in the requested form, adjoint in FP32
+    const int bprec = f64 ? NS_FP64 : NS_FP32;
+    if (m->kind == NS_MODEL_CMB_DIAG || m->kind == NS_MODEL_CMB_BLOCK) {
+        const int64_t n = m->n_data;
+        m->ws_out.ensure((size_t)B * n * elem);
+        void* outs[4];
+        int64_t off = 0;
+        for (int g = 0; g < G; ++g) {
+            outs[g] = m->ws_out.as<char>() + off * elem;
+            off += m->nets[g]->dims.back();
+        }
+        emulator_forward(m, ids, G, theta, ld, B, outs, n, m->spec_log.data(), prec, nullptr, s, true);
+        SeedNet sn[4] = {};
+        for (int g = 0; g < G; ++g) sn[g] = SeedNet{m->nets[g]->out_sigma64.as<double>(), m->spec_log[g]};
+        {
+            TraceScope ts(m, s, "adj_seed_chi2");
+            if (f64)
+                hipLaunchKernelGGL(cmb_seed_kernel<double>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, m->d,
+                                   pk, pa, pb, m->ws_out.as<double>(), m->kind, (int)n, m->n_ell_cmb,
+                                   m->data.as<double>(), m->inv_sigma.as<double>(), m->blk_linv.as<double>(),
+                                   m->inv_sigma_pp.as<double>(), m->logl_const, sn[0], sn[1], sn[2], sn[3], n_pad,
+                                   gstride, m->ws_gact[0].as<double>(), logl);
+            else
+                hipLaunchKernelGGL(cmb_seed_kernel<float>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, m->d,
+                                   pk, pa, pb, m->ws_out.as<float>(), m->kind, (int)n, m->n_ell_cmb,
+                                   m->data.as<double>(), m->inv_sigma.as<double>(), m->blk_linv.as<double>(),
+                                   m->inv_sigma_pp.as<double>(), m->logl_const, sn[0], sn[1], sn[2], sn[3], n_pad,
+                                   gstride, m->ws_gact[0].as<float>(), logl);
+            NS_HIP(hipGetLastError());
+        }
+        emulator_backward(m, ids, G, B, bprec, s);
+        TraceScope ts(m, s, "adj_assemble");
+        grad_assemble(m, B, G, rpw, nullptr, logl, grad, s);
+        return;
+    }
+    shear_grad(m, theta, ld, B, logl, grad, prec, s);
+}
+
+void grad_assemble(ns_model* m, int64_t B, int G, int rpw, const double* direct, const double* logl, double* grad,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(grad_assemble_kernel, dim3((unsigned)((B * m->d + 255) / 256)), dim3(256), 0, s, B, m->d, G,
+                       rpw, m->nets[0]->dims[0], m->emu_src_d.as<int>(), m->ws_gx.as<double>(), direct, logl, grad);
+    NS_HIP(hipGetLastError());
+}
+
+}  // namespace nsmi

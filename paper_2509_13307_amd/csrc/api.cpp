@@ -144,6 +144,17 @@ static Net* build_net(const ns_net_desc& nd, int mu_rows) {
             }
             upload(ly->Whi, hi.data(), nw);
             upload(ly->Wlo, lo.data(), nw);
+            // transposed, zero-padded copies for the adjoint GEMMs
+            ly->n_pad = (N + 63) / 64 * 64;
+            std::vector<double> wt((size_t)K * ly->n_pad, 0.0);
+            std::vector<float> wtf((size_t)K * ly->n_pad, 0.0f);
+            for (int n = 0; n < N; ++n)
+                for (int k = 0; k < K; ++k) {
+                    wt[(size_t)k * ly->n_pad + n] = nd.W[l][(size_t)n * K + k];
+                    wtf[(size_t)k * ly->n_pad + n] = (float)nd.W[l][(size_t)n * K + k];
+                }
+            upload(ly->WT64, wt.data(), wt.size());
+            upload(ly->WT32, wtf.data(), wtf.size());
             if (ly->hidden) {
                 check_ptr(nd.beta[l], "net.beta[l]");
                 check_ptr(nd.gamma[l], "net.gamma[l]");
@@ -355,6 +366,10 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
             c -= std::log(A[(size_t)i * n + i]);
         }
         upload(m->cov_linv, X.data(), X.size());
+        std::vector<double> XT((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) XT[(size_t)k * n + i] = X[(size_t)i * n + k];
+        upload(m->cov_linvT, XT.data(), XT.size());
         upload(m->cov_w, w.data(), w.size());
         m->logl_const = c;
     }
@@ -484,8 +499,15 @@ ns_status ns_loglike_grad_batch(ns_model* model, const double* theta, int64_t ld
     return (ns_status)guard([&] {
         check_ptr(model, "model");
         check_prec(precision);
-        (void)theta; (void)ld; (void)B; (void)logl; (void)grad; (void)stream;
-        throw Error{NS_E_UNSUPPORTED, "the adjoint is not built in this version"};
+        NS_CHECK(B >= 0, NS_E_SHAPE, "B must be >= 0");
+        NS_CHECK(ld >= model->d, NS_E_SHAPE, "ld must be >= d");
+        NS_CHECK(B <= (int64_t)1 << 24, NS_E_SHAPE, "B too large");
+        if (B == 0) return;
+        check_ptr(theta, "theta");
+        check_ptr(logl, "logl");
+        check_ptr(grad, "grad");
+        bind_device(model);
+        loglike_grad_batch(model, theta, ld, B, logl, grad, precision, (hipStream_t)stream);
     });
 }
 

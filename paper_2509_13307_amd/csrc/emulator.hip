@@ -10,13 +10,18 @@
 //   NS_BF16X3 the same MFMA on hi/lo BF16 splits of both operands
 //             (hi*hi + hi*lo + lo*hi), activations stored in FP32
 //   NS_FP32   v_mfma_f32_32x32x2f32
-//   NS_FP64   LDS-tiled VALU FMA in double
+//   NS_FP64   v_mfma_f64_16x16x4f64
 // The epilogue applies bias + gated activation (hidden layers) or the output
 // transform mu + sigma * (.), optionally 10^y (output layer).
+//
+// Networks with identical shapes (the four CMB spectra) run in one grid,
+// blockIdx.z selecting the network, so a 4096-walker layer fills the chip.
 #include "devutil.h"
 #include "nsmi.h"
 
 namespace nsmi {
+
+constexpr int MAXG = 4;
 
 // ------------------------------------------------------------------ layer 1
 template <class T, class OutT> __device__ __forceinline__ OutT cvt_out(T v);
@@ -24,61 +29,99 @@ template <> __device__ __forceinline__ double cvt_out<double, double>(double v) 
 template <> __device__ __forceinline__ float cvt_out<float, float>(float v) { return v; }
 template <> __device__ __forceinline__ uint16_t cvt_out<float, uint16_t>(float v) { return f2bf(v); }
 
+template <class T, class OutT> struct FirstArgs {
+    const T* W[MAXG];
+    const T* b[MAXG];
+    const T* beta[MAXG];
+    const T* gamma[MAXG];
+    const double* shift[MAXG];
+    const double* scale[MAXG];
+    OutT* out[MAXG];
+    T* tsave[MAXG];
+};
+
 template <class T, class OutT, int ROWS>
 __global__ __launch_bounds__(256) void first_layer_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t rows, int rows_per_walker,
-    const int* __restrict__ src, const double* __restrict__ fix, const double* __restrict__ znodes,
-    const double* __restrict__ shift, const double* __restrict__ scale, int n_in,
-    const T* __restrict__ W, const T* __restrict__ b, const T* __restrict__ beta,
-    const T* __restrict__ gamma, int n_out, OutT* __restrict__ out, int64_t ldo,
-    const int* __restrict__ count) {
+    const int* __restrict__ src, const double* __restrict__ fix, const double* __restrict__ znodes, int n_in,
+    int n_out, FirstArgs<T, OutT> P, const int* __restrict__ count) {
     __shared__ T xs[ROWS][16];
+    const int g = blockIdx.z;
     int64_t nrows = rows;
     if (count) nrows = min<int64_t>(rows, (int64_t)(*count) * rows_per_walker);
     const int64_t r0 = (int64_t)blockIdx.x * ROWS;
     if (r0 >= nrows) return;
     if (threadIdx.x < ROWS * n_in) {
-        int rr = threadIdx.x / n_in, k = threadIdx.x % n_in;
-        int64_t r = r0 + rr;
+        const int rr = threadIdx.x / n_in, k = threadIdx.x % n_in;
+        const int64_t r = r0 + rr;
         double v = 0.0;
         if (r < nrows) {
-            int64_t w = r / rows_per_walker;
-            int zi = (int)(r % rows_per_walker);
-            int s = src[k];
+            const int64_t w = r / rows_per_walker;
+            const int zi = (int)(r % rows_per_walker);
+            const int s = src[k];
             v = s >= 0 ? theta[w * ld + s] : (s == SRC_ZNODE ? znodes[zi] : fix[k]);
-            v = (v - shift[k]) / scale[k];
+            v = (v - P.shift[g][k]) / P.scale[g][k];
         }
         xs[rr][k] = (T)v;
     }
     __syncthreads();
+    const T* W = P.W[g];
+    OutT* out = P.out[g];
     for (int c = threadIdx.x; c < n_out; c += blockDim.x) {
         T wrow[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) wrow[k] = k < n_in ? W[(int64_t)c * n_in + k] : T(0);
-        const T bc = b[c], be = beta[c], ga = gamma[c];
+        const T bc = P.b[g][c], be = P.beta[g][c], ga = P.gamma[g][c];
 #pragma unroll
         for (int rr = 0; rr < ROWS; ++rr) {
-            int64_t r = r0 + rr;
+            const int64_t r = r0 + rr;
             if (r >= nrows) break;
             T acc = bc;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
                 if (k < n_in) acc += wrow[k] * xs[rr][k];
-            out[r * ldo + c] = cvt_out<T, OutT>(gated<T>(acc, be, ga));
+            if (P.tsave[g]) P.tsave[g][r * n_out + c] = acc;
+            out[r * n_out + c] = cvt_out<T, OutT>(gated<T>(acc, be, ga));
         }
     }
 }
 
 // ------------------------------------------------------------------ epilogues
-// Hidden layer: bias + gated activation, store as OutT.
+// Hidden layer: bias + gated activation, store as OutT; optionally keep the
+// pre-activation t (for the adjoint) in tsave.
 template <class T, class OutT> struct EpiHidden {
     const T* b; const T* beta; const T* gamma;
     OutT* out; int64_t ldo;
+    T* tsave = nullptr;
     struct Col { T b, be, ga; };
     __device__ __forceinline__ Col col(int c) const { return Col{b[c], beta[c], gamma[c]}; }
     __device__ __forceinline__ void store(int64_t r, int c, const Col& p, T acc) const {
-        out[r * ldo + c] = cvt_out<T, OutT>(gated<T>(acc + p.b, p.be, p.ga));
+        const T t = acc + p.b;
+        if (tsave) tsave[r * ldo + c] = t;
+        out[r * ldo + c] = cvt_out<T, OutT>(gated<T>(t, p.be, p.ga));
     }
+};
+
+// Adjoint of a hidden layer: delta_{l-1} = (delta_l W_l) * f'(t_{l-1}),
+// f'(t) = gamma + (1 - gamma) [s + beta t s (1 - s)], s = sigmoid(beta t).
+template <class T> struct EpiBack {
+    const T* tsave; const T* beta; const T* gamma;
+    T* out; int64_t ldo;
+    struct Col { T be, ga; };
+    __device__ __forceinline__ Col col(int c) const { return Col{beta[c], gamma[c]}; }
+    __device__ __forceinline__ void store(int64_t r, int c, const Col& p, T acc) const {
+        const T t = tsave[r * ldo + c];
+        const T s = sigmoid<T>(p.be * t);
+        out[r * ldo + c] = acc * (p.ga + (T(1) - p.ga) * (s + p.be * t * s * (T(1) - s)));
+    }
+};
+
+// Adjoint of the first layer: plain store of delta_1 W_1 restricted to inputs.
+template <class T> struct EpiPlain {
+    T* out; int64_t ldo;
+    struct Col { int c; };
+    __device__ __forceinline__ Col col(int c) const { return Col{c}; }
+    __device__ __forceinline__ void store(int64_t r, int c, const Col&, T acc) const { out[r * ldo + c] = acc; }
 };
 
 // Output layer: y = mu[row % mu_rows][c] + sigma[c] (acc + b[c]); 10^y if log.
@@ -88,31 +131,162 @@ template <class T> struct EpiOut {
     struct Col { T b, s; int c; };
     __device__ __forceinline__ Col col(int c) const { return Col{b[c], sigma[c], c}; }
     __device__ __forceinline__ void store(int64_t r, int c, const Col& p, T acc) const {
-        int zr = mu_rows > 1 ? (int)(r % mu_rows) : 0;
+        const int zr = mu_rows > 1 ? (int)(r % mu_rows) : 0;
         T y = mu[(int64_t)zr * n_out + c] + p.s * (acc + p.b);
         if (is_log) y = exp(y * T(2.302585092994045684));
         out[r * ldo + c] = y;
     }
 };
 
+// Per-network operands of a grouped GEMM launch (blockIdx.z = network).
+template <class Epi> struct Group {
+    const void* A[MAXG];
+    const void* W[MAXG];
+    const void* Wl[MAXG];
+    Epi epi[MAXG];
+};
+
+// ------------------------------------------------------------ tile order
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X, each
+// with its own L2.  Remap the linear workgroup id so that the tiles one XCD
+// receives are consecutive in (network, row tile, column tile) order and so
+// share their activation row block in that XCD's L2.
+struct TileId { int g, ty, tx; };
+__device__ __forceinline__ TileId xcd_tile() {
+    const int nx = gridDim.x, ny = gridDim.y;
+    const int total = nx * ny * gridDim.z;
+    int i = (blockIdx.z * ny + blockIdx.y) * nx + blockIdx.x;
+    if ((total & 7) == 0) i = (i & 7) * (total >> 3) + (i >> 3);
+    TileId t;
+    t.tx = i % nx;
+    t.ty = (i / nx) % ny;
+    t.g = i / (nx * ny);
+    return t;
+}
+
 // ------------------------------------------------- MFMA GEMM, BF16 operands
 // WG tile 128 x 128, four waves in 2 x 2, each wave 64 x 64 = 2 x 2 tiles of
 // 32 x 32; BK = 64 staged through LDS (row stride BK + 8 avoids bank conflicts).
-// AMODE 0: A is BF16.  AMODE 1: A is FP32, split into hi + lo BF16 (BF16X3).
+// The next K tile is fetched into registers while the current one feeds the
+// MFMAs.  AMODE 0: A is BF16, LDS double buffered.  AMODE 1: A is FP32, split
+// into hi + lo BF16 (BF16X3), single LDS buffer (four operand planes).
 constexpr int GB_M = 128, GB_N = 128, GB_K = 64, GB_LDS = GB_K + 8;
+constexpr int GB_TILE = GB_M * GB_LDS;   // elements of one operand tile in LDS
+
+template <int AMODE>
+struct Bf16Stage {
+    uint4 a[4], al[AMODE ? 4 : 1], b[4], bl[AMODE ? 4 : 1];
+};
+
+template <int AMODE>
+__device__ __forceinline__ void bf16_fetch(Bf16Stage<AMODE>& st, const void* Aptr, int64_t lda,
+                                           const uint16_t* Whi, const uint16_t* Wlo, int64_t m0, int n0, int64_t M,
+                                           int N, int K, int k0, int tid) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int c = tid + it * 256;
+        const int row = c >> 3, kc = (c & 7) * 8;
+        const int64_t gr = m0 + row;
+        uint4 hi = make_uint4(0, 0, 0, 0), lo = make_uint4(0, 0, 0, 0);
+        if (gr < M) {
+            if (AMODE == 0) {
+                hi = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Aptr) + gr * lda + k0 + kc);
+            } else {
+                const float* ap = static_cast<const float*>(Aptr) + gr * lda + k0 + kc;
+                const float4 f0 = *reinterpret_cast<const float4*>(ap);
+                const float4 f1 = *reinterpret_cast<const float4*>(ap + 4);
+                const float f[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+                uint32_t h[8], l[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint16_t hb = f2bf(f[e]);
+                    h[e] = hb;
+                    l[e] = f2bf(f[e] - bf2f(hb));
+                }
+                hi = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+                lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
+            }
+        }
+        st.a[it] = hi;
+        if (AMODE) st.al[it] = lo;
+        const int gn = n0 + row;
+        uint4 wh = make_uint4(0, 0, 0, 0), wl = make_uint4(0, 0, 0, 0);
+        if (gn < N) {
+            wh = *reinterpret_cast<const uint4*>(Whi + (int64_t)gn * K + k0 + kc);
+            if (AMODE) wl = *reinterpret_cast<const uint4*>(Wlo + (int64_t)gn * K + k0 + kc);
+        }
+        st.b[it] = wh;
+        if (AMODE) st.bl[it] = wl;
+    }
+}
+
+template <int AMODE>
+__device__ __forceinline__ void bf16_stash(const Bf16Stage<AMODE>& st, uint16_t* As, uint16_t* Bs, uint16_t* Al,
+                                           uint16_t* Bl, int tid) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int c = tid + it * 256;
+        const int off = (c >> 3) * GB_LDS + (c & 7) * 8;
+        *reinterpret_cast<uint4*>(&As[off]) = st.a[it];
+        *reinterpret_cast<uint4*>(&Bs[off]) = st.b[it];
+        if (AMODE) {
+            *reinterpret_cast<uint4*>(&Al[off]) = st.al[it];
+            *reinterpret_cast<uint4*>(&Bl[off]) = st.bl[it];
+        }
+    }
+}
+
+template <int AMODE>
+__device__ __forceinline__ void bf16_mfma_tile(f32x16_t (&acc)[2][2], const uint16_t* As, const uint16_t* Bs,
+                                               const uint16_t* Al, const uint16_t* Bl, int lane, int wr, int wc) {
+#pragma unroll
+    for (int kk = 0; kk < GB_K; kk += 16) {
+        const int koff = kk + (lane >> 5) * 8;
+        bf16x8_t a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            a[i] = *reinterpret_cast<const bf16x8_t*>(&As[(wr * 64 + i * 32 + (lane & 31)) * GB_LDS + koff]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            b[j] = *reinterpret_cast<const bf16x8_t*>(&Bs[(wc * 64 + j * 32 + (lane & 31)) * GB_LDS + koff]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (AMODE) {
+            bf16x8_t al[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                al[i] = *reinterpret_cast<const bf16x8_t*>(&Al[(wr * 64 + i * 32 + (lane & 31)) * GB_LDS + koff]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bl[j] = *reinterpret_cast<const bf16x8_t*>(&Bl[(wc * 64 + j * 32 + (lane & 31)) * GB_LDS + koff]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], b[j], acc[i][j], 0, 0, 0);
+                }
+        }
+    }
+}
 
 template <int AMODE, class Epi>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(
-    const void* __restrict__ Aptr, int64_t lda, const uint16_t* __restrict__ Whi,
-    const uint16_t* __restrict__ Wlo, int64_t M, int N, int K, Epi epi,
-    const int* __restrict__ count, int rows_per_count) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[GB_M * GB_LDS];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[GB_N * GB_LDS];
-    __shared__ __attribute__((aligned(16))) uint16_t Al[AMODE ? GB_M * GB_LDS : 8];
-    __shared__ __attribute__((aligned(16))) uint16_t Bl[AMODE ? GB_N * GB_LDS : 8];
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(Group<Epi> G, int64_t lda, int64_t M, int N, int K,
+                                                        const int* __restrict__ count, int rows_per_count) {
+    // AMODE 0: two buffers of (A, B); AMODE 1: one buffer of (A hi, B hi, A lo, B lo)
+    __shared__ __attribute__((aligned(16))) uint16_t lds[4 * GB_TILE];
+    const TileId tile = xcd_tile();
+    const int g = tile.g;
+    const void* Aptr = G.A[g];
+    const uint16_t* Whi = static_cast<const uint16_t*>(G.W[g]);
+    const uint16_t* Wlo = static_cast<const uint16_t*>(G.Wl[g]);
+    const Epi& epi = G.epi[g];
     if (count) M = min<int64_t>(M, (int64_t)(*count) * rows_per_count);
-    const int64_t m0 = (int64_t)blockIdx.y * GB_M;
-    const int n0 = blockIdx.x * GB_N;
+    const int64_t m0 = (int64_t)tile.ty * GB_M;
+    const int n0 = tile.tx * GB_N;
     if (m0 >= M) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
@@ -125,77 +299,28 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    for (int k0 = 0; k0 < K; k0 += GB_K) {
-        // stage A and B tiles: 128 rows x 64 k = 1024 chunks of 8 elements
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int c = tid + it * 256;
-            const int row = c >> 3, kc = (c & 7) * 8;
-            const int64_t gr = m0 + row;
-            uint4 hi = make_uint4(0, 0, 0, 0), lo = make_uint4(0, 0, 0, 0);
-            if (gr < M) {
-                if (AMODE == 0) {
-                    hi = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(Aptr) + gr * lda + k0 + kc);
-                } else {
-                    const float* ap = static_cast<const float*>(Aptr) + gr * lda + k0 + kc;
-                    float4 f0 = *reinterpret_cast<const float4*>(ap);
-                    float4 f1 = *reinterpret_cast<const float4*>(ap + 4);
-                    float f[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
-                    uint16_t h[8], l[8];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        h[e] = f2bf(f[e]);
-                        l[e] = f2bf(f[e] - bf2f(h[e]));
-                    }
-                    hi = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
-                    lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
-                }
-            }
-            *reinterpret_cast<uint4*>(&As[row * GB_LDS + kc]) = hi;
-            if (AMODE) *reinterpret_cast<uint4*>(&Al[row * GB_LDS + kc]) = lo;
-            const int gn = n0 + row;
-            uint4 wh = make_uint4(0, 0, 0, 0), wl = make_uint4(0, 0, 0, 0);
-            if (gn < N) {
-                wh = *reinterpret_cast<const uint4*>(Whi + (int64_t)gn * K + k0 + kc);
-                if (AMODE) wl = *reinterpret_cast<const uint4*>(Wlo + (int64_t)gn * K + k0 + kc);
-            }
-            *reinterpret_cast<uint4*>(&Bs[row * GB_LDS + kc]) = wh;
-            if (AMODE) *reinterpret_cast<uint4*>(&Bl[row * GB_LDS + kc]) = wl;
-        }
+    Bf16Stage<AMODE> st;
+    const int nk = K / GB_K;
+    bf16_fetch<AMODE>(st, Aptr, lda, Whi, Wlo, m0, n0, M, N, K, 0, tid);
+    if (AMODE == 0) {
+        bf16_stash<AMODE>(st, lds, lds + GB_TILE, nullptr, nullptr, tid);
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GB_K; kk += 16) {
-            const int koff = kk + (lane >> 5) * 8;
-            bf16x8_t a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const bf16x8_t*>(&As[(wr * 64 + i * 32 + (lane & 31)) * GB_LDS + koff]);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const bf16x8_t*>(&Bs[(wc * 64 + j * 32 + (lane & 31)) * GB_LDS + koff]);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-            if (AMODE) {
-                bf16x8_t al[2], bl[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    al[i] = *reinterpret_cast<const bf16x8_t*>(&Al[(wr * 64 + i * 32 + (lane & 31)) * GB_LDS + koff]);
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    bl[j] = *reinterpret_cast<const bf16x8_t*>(&Bl[(wc * 64 + j * 32 + (lane & 31)) * GB_LDS + koff]);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bl[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], b[j], acc[i][j], 0, 0, 0);
-                    }
-            }
+        for (int t = 0; t < nk; ++t) {
+            uint16_t* cur = lds + (t & 1) * 2 * GB_TILE;
+            uint16_t* nxt = lds + ((t + 1) & 1) * 2 * GB_TILE;
+            if (t + 1 < nk) bf16_fetch<AMODE>(st, Aptr, lda, Whi, Wlo, m0, n0, M, N, K, (t + 1) * GB_K, tid);
+            bf16_mfma_tile<AMODE>(acc, cur, cur + GB_TILE, nullptr, nullptr, lane, wr, wc);
+            if (t + 1 < nk) bf16_stash<AMODE>(st, nxt, nxt + GB_TILE, nullptr, nullptr, tid);
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        for (int t = 0; t < nk; ++t) {
+            bf16_stash<AMODE>(st, lds, lds + GB_TILE, lds + 2 * GB_TILE, lds + 3 * GB_TILE, tid);
+            __syncthreads();
+            if (t + 1 < nk) bf16_fetch<AMODE>(st, Aptr, lda, Whi, Wlo, m0, n0, M, N, K, (t + 1) * GB_K, tid);
+            bf16_mfma_tile<AMODE>(acc, lds, lds + GB_TILE, lds + 2 * GB_TILE, lds + 3 * GB_TILE, lane, wr, wc);
+            __syncthreads();
+        }
     }
     // epilogue: lane owns column (lane & 31) of each 32 x 32 tile
 #pragma unroll
@@ -218,11 +343,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(
 constexpr int GF_K = 32, GF_LDS = GF_K + 1;
 
 template <class Epi>
-__global__ __launch_bounds__(256) void gemm_f32_kernel(
-    const float* __restrict__ A, int64_t lda, const float* __restrict__ W, int64_t M, int N, int K,
-    Epi epi, const int* __restrict__ count, int rows_per_count) {
+__global__ __launch_bounds__(256) void gemm_f32_kernel(Group<Epi> G, int64_t lda, int64_t M, int N, int K,
+                                                       const int* __restrict__ count, int rows_per_count) {
     __shared__ float As[GB_M * GF_LDS];
     __shared__ float Bs[GB_N * GF_LDS];
+    const int g = blockIdx.z;
+    const float* A = static_cast<const float*>(G.A[g]);
+    const float* W = static_cast<const float*>(G.W[g]);
+    const Epi& epi = G.epi[g];
     if (count) M = min<int64_t>(M, (int64_t)(*count) * rows_per_count);
     const int64_t m0 = (int64_t)blockIdx.y * GB_M;
     const int n0 = blockIdx.x * GB_N;
@@ -285,178 +413,350 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(
     }
 }
 
-// ------------------------------------------------------ VALU GEMM, FP64
-// WG tile 64 x 64, BK = 16, 256 threads with a 4 x 4 register tile each
-// (rows ty + 16 i, columns tx + 16 j).
-constexpr int GD_M = 64, GD_N = 64, GD_K = 16;
+// ------------------------------------------------------ MFMA GEMM, FP64
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// register r of lane l returns D[l / 16 + 4 r][l % 16].
+// WG tile 64 x 64, four waves in 2 x 2, each wave 32 x 32 = 2 x 2 tiles of
+// 16 x 16; BK = 16, LDS row stride 17 doubles.
+constexpr int GD_M = 64, GD_N = 64, GD_K = 16, GD_LDS = GD_K + 1;
 
 template <class Epi>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(
-    const double* __restrict__ A, int64_t lda, const double* __restrict__ W, int64_t M, int N,
-    int K, Epi epi, const int* __restrict__ count, int rows_per_count) {
-    __shared__ double As[GD_K][GD_M + 1];
-    __shared__ double Bs[GD_K][GD_N + 1];
+__global__ __launch_bounds__(256) void gemm_f64_kernel(Group<Epi> G, int64_t lda, int64_t M, int N, int K,
+                                                       const int* __restrict__ count, int rows_per_count) {
+    __shared__ double As[GD_M * GD_LDS];
+    __shared__ double Bs[GD_N * GD_LDS];
+    const int g = blockIdx.z;
+    const double* A = static_cast<const double*>(G.A[g]);
+    const double* W = static_cast<const double*>(G.W[g]);
+    const Epi& epi = G.epi[g];
     if (count) M = min<int64_t>(M, (int64_t)(*count) * rows_per_count);
     const int64_t m0 = (int64_t)blockIdx.y * GD_M;
     const int n0 = blockIdx.x * GD_N;
     if (m0 >= M) return;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double acc[4][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    f64x4_t acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
     for (int k0 = 0; k0 < K; k0 += GD_K) {
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int c = tid + it * 256;          // 64 rows x 16 k
             const int row = c >> 4, kk = c & 15;
             const int64_t gr = m0 + row;
-            As[kk][row] = (gr < M && k0 + kk < K) ? A[gr * lda + k0 + kk] : 0.0;
+            As[row * GD_LDS + kk] = (gr < M && k0 + kk < K) ? A[gr * lda + k0 + kk] : 0.0;
             const int gn = n0 + row;
-            Bs[kk][row] = (gn < N && k0 + kk < K) ? W[(int64_t)gn * K + k0 + kk] : 0.0;
+            Bs[row * GD_LDS + kk] = (gn < N && k0 + kk < K) ? W[(int64_t)gn * K + k0 + kk] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < GD_K; ++kk) {
-            double a[4], b[4];
+        for (int kq = 0; kq < GD_K; kq += 4) {
+            const int koff = kq + (lane >> 4);
+            double a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+            for (int i = 0; i < 2; ++i) a[i] = As[(wr * 32 + i * 16 + (lane & 15)) * GD_LDS + koff];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < 2; ++j) b[j] = Bs[(wc * 32 + j * 16 + (lane & 15)) * GD_LDS + koff];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int c = n0 + tx + 16 * j;
+    for (int j = 0; j < 2; ++j) {
+        const int c = n0 + wc * 32 + j * 16 + (lane & 15);
         if (c >= N) continue;
         const auto p = epi.col(c);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t row = m0 + ty + 16 * i;
-            if (row < M) epi.store(row, c, p, acc[i][j]);
-        }
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+                if (row < M) epi.store(row, c, p, acc[i][j][r]);
+            }
     }
 }
 
 // ------------------------------------------------------------------ driver
-static inline dim3 grid2(int64_t M, int N, int bm, int bn) {
-    return dim3((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm));
+static inline dim3 grid3(int64_t M, int N, int bm, int bn, int G) {
+    return dim3((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), (unsigned)G);
 }
 
-void emulator_forward(ns_model* m, int ni, const double* theta, int64_t ld, int64_t B, void* out,
-                      int64_t ldo, int is_log, int prec, const int* count, hipStream_t s) {
-    Net& net = *m->nets[ni];
-    const int L = net.n_layers;
-    const int rpw = net.out_mu_rows;                 // rows per walker
+template <class T, class OutT>
+static void launch_first(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t rows,
+                         int rpw, OutT* act0, size_t act_stride, T* tsave, size_t save_stride, const int* count,
+                         hipStream_t s) {
+    FirstArgs<T, OutT> P{};
+    const Net& n0 = *m->nets[nets[0]];
+    for (int g = 0; g < G; ++g) {
+        const Net& net = *m->nets[nets[g]];
+        const Layer& l1 = *net.layers[0];
+        if (sizeof(T) == 8) {
+            P.W[g] = (const T*)l1.W64.p; P.b[g] = (const T*)l1.b64.p;
+            P.beta[g] = (const T*)l1.beta64.p; P.gamma[g] = (const T*)l1.gamma64.p;
+        } else {
+            P.W[g] = (const T*)l1.W32.p; P.b[g] = (const T*)l1.b32.p;
+            P.beta[g] = (const T*)l1.beta32.p; P.gamma[g] = (const T*)l1.gamma32.p;
+        }
+        P.shift[g] = net.in_shift.as<double>();
+        P.scale[g] = net.in_scale.as<double>();
+        P.out[g] = act0 + g * act_stride;
+        P.tsave[g] = tsave ? tsave + g * save_stride : nullptr;
+    }
+    dim3 g1((unsigned)((rows + 3) / 4), 1, (unsigned)G);
+    hipLaunchKernelGGL((first_layer_kernel<T, OutT, 4>), g1, dim3(256), 0, s, theta, ld, rows, rpw,
+                       m->emu_src_d.as<int>(), m->emu_fix_d.as<double>(), m->znodes_d.as<double>(), n0.dims[0],
+                       n0.dims[1], P, count);
+}
+
+void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
+                      void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
+                      hipStream_t s, bool save_t) {
+    NS_CHECK(G >= 1 && G <= MAXG, NS_E_UNSUPPORTED, "at most 4 networks per launch");
+    const Net& net0 = *m->nets[nets[0]];
+    for (int g = 1; g < G; ++g)
+        NS_CHECK(m->nets[nets[g]]->dims == net0.dims, NS_E_SHAPE, "grouped networks must share their shapes");
+    const int L = net0.n_layers;
+    const int rpw = net0.out_mu_rows;                 // rows per walker
     const int64_t rows = B * rpw;
-    const int n_in = net.dims[0];
-    NS_CHECK(n_in <= 16, NS_E_UNSUPPORTED, "emulator with more than 16 inputs");
-    const int h1 = net.dims[1];
+    NS_CHECK(net0.dims[0] <= 16, NS_E_UNSUPPORTED, "emulator with more than 16 inputs");
     const size_t act_elem = prec == NS_FP64 ? 8 : (prec == NS_BF16 ? 2 : 4);
     size_t max_w = 0;
-    for (int l = 1; l < L; ++l) max_w = std::max(max_w, (size_t)net.dims[l]);
-    m->ws_act[0].ensure((size_t)rows * max_w * act_elem);
-    m->ws_act[1].ensure((size_t)rows * max_w * act_elem);
-    Layer& l1 = *net.layers[0];
-    const int rows_blk = 4;
-    dim3 g1((unsigned)((rows + rows_blk - 1) / rows_blk));
-    const int* src = m->emu_src_d.as<int>();
-    const double* fix = m->emu_fix_d.as<double>();
-    const double* zn = m->znodes_d.as<double>();
+    for (int l = 1; l < L; ++l) max_w = std::max(max_w, (size_t)net0.dims[l]);
+    const size_t act_stride = (size_t)rows * max_w;      // elements per network
+    m->ws_act[0].ensure(G * act_stride * act_elem);
+    m->ws_act[1].ensure(G * act_stride * act_elem);
+    // pre-activation saves for the adjoint: slot (g, l-1) holds t of hidden layer l
+    const size_t tsz = prec == NS_FP64 ? 8 : 4;
+    const size_t save_stride = (size_t)(L - 1) * act_stride;   // elements per network
+    if (save_t) m->ws_tsave.ensure(G * save_stride * tsz);
+    char* tbase = save_t ? m->ws_tsave.as<char>() : nullptr;
+    auto tslot = [&](int g, int slot) -> void* {
+        return tbase ? (void*)(tbase + ((size_t)g * save_stride + (size_t)slot * act_stride) * tsz) : nullptr;
+    };
     {
-    TraceScope ts(m, s, "emu_first_layer");
-    if (prec == NS_FP64) {
-        hipLaunchKernelGGL((first_layer_kernel<double, double, 4>), g1, dim3(256), 0, s, theta, ld, rows, rpw,
-                           src, fix, zn, net.in_shift.as<double>(), net.in_scale.as<double>(), n_in,
-                           l1.W64.as<double>(), l1.b64.as<double>(), l1.beta64.as<double>(), l1.gamma64.as<double>(),
-                           h1, m->ws_act[0].as<double>(), (int64_t)h1, count);
-    } else if (prec == NS_BF16) {
-        hipLaunchKernelGGL((first_layer_kernel<float, uint16_t, 4>), g1, dim3(256), 0, s, theta, ld, rows, rpw,
-                           src, fix, zn, net.in_shift.as<double>(), net.in_scale.as<double>(), n_in,
-                           l1.W32.as<float>(), l1.b32.as<float>(), l1.beta32.as<float>(), l1.gamma32.as<float>(),
-                           h1, m->ws_act[0].as<uint16_t>(), (int64_t)h1, count);
-    } else {
-        hipLaunchKernelGGL((first_layer_kernel<float, float, 4>), g1, dim3(256), 0, s, theta, ld, rows, rpw,
-                           src, fix, zn, net.in_shift.as<double>(), net.in_scale.as<double>(), n_in,
-                           l1.W32.as<float>(), l1.b32.as<float>(), l1.beta32.as<float>(), l1.gamma32.as<float>(),
-                           h1, m->ws_act[0].as<float>(), (int64_t)h1, count);
-    }
-    NS_HIP(hipGetLastError());
+        TraceScope ts(m, s, "emu_first_layer");
+        if (prec == NS_FP64)
+            launch_first<double, double>(m, nets, G, theta, ld, rows, rpw, m->ws_act[0].as<double>(), act_stride,
+                                         (double*)tslot(0, 0), save_stride, count, s);
+        else if (prec == NS_BF16)
+            launch_first<float, uint16_t>(m, nets, G, theta, ld, rows, rpw, m->ws_act[0].as<uint16_t>(),
+                                          act_stride, (float*)tslot(0, 0), save_stride, count, s);
+        else
+            launch_first<float, float>(m, nets, G, theta, ld, rows, rpw, m->ws_act[0].as<float>(), act_stride,
+                                       (float*)tslot(0, 0), save_stride, count, s);
+        NS_HIP(hipGetLastError());
     }
     int cur = 0;
     for (int l = 1; l < L; ++l) {
-        Layer& ly = *net.layers[l];
-        const int K = ly.n_in, N = ly.n_out;
+        const int K = net0.dims[l], N = net0.dims[l + 1];
         const bool last = (l == L - 1);
-        void* A = m->ws_act[cur].p;
-        void* dst = last ? out : m->ws_act[cur ^ 1].p;
         static const char* names[4][2] = {{"gemm_f64_hidden", "gemm_f64_out"}, {"gemm_f32_hidden", "gemm_f32_out"},
                                           {"gemm_bf16_hidden", "gemm_bf16_out"},
                                           {"gemm_bf16x3_hidden", "gemm_bf16x3_out"}};
         TraceScope ts(m, s, names[prec][last ? 1 : 0]);
+        char* A0 = m->ws_act[cur].as<char>();
+        char* D0 = m->ws_act[cur ^ 1].as<char>();
+        auto A_of = [&](int g) { return (const void*)(A0 + g * act_stride * act_elem); };
+        auto D_of = [&](int g) { return last ? outs[g] : (void*)(D0 + g * act_stride * act_elem); };
         if (prec == NS_FP64) {
-            dim3 g = grid2(rows, N, GD_M, GD_N);
+            const dim3 gr = grid3(rows, N, GD_M, GD_N, G);
             if (!last) {
-                EpiHidden<double, double> e{ly.b64.as<double>(), ly.beta64.as<double>(), ly.gamma64.as<double>(),
-                                           (double*)dst, (int64_t)N};
-                hipLaunchKernelGGL((gemm_f64_kernel<EpiHidden<double, double>>), g, dim3(256), 0, s,
-                                   (const double*)A, (int64_t)K, ly.W64.as<double>(), rows, N, K, e, count, rpw);
+                Group<EpiHidden<double, double>> P{};
+                for (int g = 0; g < G; ++g) {
+                    const Layer& ly = *m->nets[nets[g]]->layers[l];
+                    P.A[g] = A_of(g); P.W[g] = ly.W64.p;
+                    P.epi[g] = {ly.b64.as<double>(), ly.beta64.as<double>(), ly.gamma64.as<double>(),
+                                (double*)D_of(g), (int64_t)N, (double*)tslot(g, l)};
+                }
+                hipLaunchKernelGGL((gemm_f64_kernel<EpiHidden<double, double>>), gr, dim3(256), 0, s, P, (int64_t)K,
+                                   rows, N, K, count, rpw);
             } else {
-                EpiOut<double> e{ly.b64.as<double>(), net.out_mu64.as<double>(), net.out_sigma64.as<double>(),
-                                 (double*)dst, last ? ldo : (int64_t)N, net.out_mu_rows, N, is_log};
-                hipLaunchKernelGGL(gemm_f64_kernel<EpiOut<double>>, g, dim3(256), 0, s,
-                                   (const double*)A, (int64_t)K, ly.W64.as<double>(), rows, N, K, e, count, rpw);
+                Group<EpiOut<double>> P{};
+                for (int g = 0; g < G; ++g) {
+                    const Net& net = *m->nets[nets[g]];
+                    const Layer& ly = *net.layers[l];
+                    P.A[g] = A_of(g); P.W[g] = ly.W64.p;
+                    P.epi[g] = {ly.b64.as<double>(), net.out_mu64.as<double>(), net.out_sigma64.as<double>(),
+                                (double*)D_of(g), ldo, net.out_mu_rows, N, is_log[g]};
+                }
+                hipLaunchKernelGGL((gemm_f64_kernel<EpiOut<double>>), gr, dim3(256), 0, s, P, (int64_t)K, rows, N,
+                                   K, count, rpw);
             }
         } else if (prec == NS_FP32) {
             NS_CHECK(K % GF_K == 0, NS_E_UNSUPPORTED, "FP32 MFMA layers need K % 32 == 0");
-            dim3 g = grid2(rows, N, GB_M, GB_N);
+            const dim3 gr = grid3(rows, N, GB_M, GB_N, G);
             if (!last) {
-                EpiHidden<float, float> e{ly.b32.as<float>(), ly.beta32.as<float>(), ly.gamma32.as<float>(),
-                                         (float*)dst, (int64_t)N};
-                hipLaunchKernelGGL((gemm_f32_kernel<EpiHidden<float, float>>), g, dim3(256), 0, s,
-                                   (const float*)A, (int64_t)K, ly.W32.as<float>(), rows, N, K, e, count, rpw);
+                Group<EpiHidden<float, float>> P{};
+                for (int g = 0; g < G; ++g) {
+                    const Layer& ly = *m->nets[nets[g]]->layers[l];
+                    P.A[g] = A_of(g); P.W[g] = ly.W32.p;
+                    P.epi[g] = {ly.b32.as<float>(), ly.beta32.as<float>(), ly.gamma32.as<float>(), (float*)D_of(g),
+                                (int64_t)N, (float*)tslot(g, l)};
+                }
+                hipLaunchKernelGGL((gemm_f32_kernel<EpiHidden<float, float>>), gr, dim3(256), 0, s, P, (int64_t)K,
+                                   rows, N, K, count, rpw);
             } else {
-                EpiOut<float> e{ly.b32.as<float>(), net.out_mu32.as<float>(), net.out_sigma32.as<float>(),
-                                (float*)dst, last ? ldo : (int64_t)N, net.out_mu_rows, N, is_log};
-                hipLaunchKernelGGL(gemm_f32_kernel<EpiOut<float>>, g, dim3(256), 0, s,
-                                   (const float*)A, (int64_t)K, ly.W32.as<float>(), rows, N, K, e, count, rpw);
+                Group<EpiOut<float>> P{};
+                for (int g = 0; g < G; ++g) {
+                    const Net& net = *m->nets[nets[g]];
+                    const Layer& ly = *net.layers[l];
+                    P.A[g] = A_of(g); P.W[g] = ly.W32.p;
+                    P.epi[g] = {ly.b32.as<float>(), net.out_mu32.as<float>(), net.out_sigma32.as<float>(),
+                                (float*)D_of(g), ldo, net.out_mu_rows, N, is_log[g]};
+                }
+                hipLaunchKernelGGL((gemm_f32_kernel<EpiOut<float>>), gr, dim3(256), 0, s, P, (int64_t)K, rows, N, K,
+                                   count, rpw);
             }
         } else {
             NS_CHECK(K % GB_K == 0, NS_E_UNSUPPORTED, "BF16 MFMA layers need K % 64 == 0");
-            dim3 g = grid2(rows, N, GB_M, GB_N);
+            const dim3 gr = grid3(rows, N, GB_M, GB_N, G);
             const bool x3 = prec == NS_BF16X3;
             if (!last) {
                 if (x3) {
-                    EpiHidden<float, float> e{ly.b32.as<float>(), ly.beta32.as<float>(), ly.gamma32.as<float>(),
-                                             (float*)dst, (int64_t)N};
-                    hipLaunchKernelGGL((gemm_bf16_kernel<1, EpiHidden<float, float>>), g, dim3(256), 0, s, A,
-                                       (int64_t)K, ly.Whi.as<uint16_t>(), ly.Wlo.as<uint16_t>(), rows, N, K, e, count, rpw);
+                    Group<EpiHidden<float, float>> P{};
+                    for (int g = 0; g < G; ++g) {
+                        const Layer& ly = *m->nets[nets[g]]->layers[l];
+                        P.A[g] = A_of(g); P.W[g] = ly.Whi.p; P.Wl[g] = ly.Wlo.p;
+                        P.epi[g] = {ly.b32.as<float>(), ly.beta32.as<float>(), ly.gamma32.as<float>(),
+                                    (float*)D_of(g), (int64_t)N, (float*)tslot(g, l)};
+                    }
+                    hipLaunchKernelGGL((gemm_bf16_kernel<1, EpiHidden<float, float>>), gr, dim3(256), 0, s, P,
+                                       (int64_t)K, rows, N, K, count, rpw);
                 } else {
-                    EpiHidden<float, uint16_t> e{ly.b32.as<float>(), ly.beta32.as<float>(), ly.gamma32.as<float>(),
-                                                (uint16_t*)dst, (int64_t)N};
-                    hipLaunchKernelGGL((gemm_bf16_kernel<0, EpiHidden<float, uint16_t>>), g, dim3(256), 0, s, A,
-                                       (int64_t)K, ly.Whi.as<uint16_t>(), ly.Wlo.as<uint16_t>(), rows, N, K, e, count, rpw);
+                    Group<EpiHidden<float, uint16_t>> P{};
+                    for (int g = 0; g < G; ++g) {
+                        const Layer& ly = *m->nets[nets[g]]->layers[l];
+                        P.A[g] = A_of(g); P.W[g] = ly.Whi.p; P.Wl[g] = ly.Wlo.p;
+                        P.epi[g] = {ly.b32.as<float>(), ly.beta32.as<float>(), ly.gamma32.as<float>(),
+                                    (uint16_t*)D_of(g), (int64_t)N, (float*)tslot(g, l)};
+                    }
+                    hipLaunchKernelGGL((gemm_bf16_kernel<0, EpiHidden<float, uint16_t>>), gr, dim3(256), 0, s, P,
+                                       (int64_t)K, rows, N, K, count, rpw);
                 }
             } else {
-                EpiOut<float> e{ly.b32.as<float>(), net.out_mu32.as<float>(), net.out_sigma32.as<float>(),
-                                (float*)dst, last ? ldo : (int64_t)N, net.out_mu_rows, N, is_log};
+                Group<EpiOut<float>> P{};
+                for (int g = 0; g < G; ++g) {
+                    const Net& net = *m->nets[nets[g]];
+                    const Layer& ly = *net.layers[l];
+                    P.A[g] = A_of(g); P.W[g] = ly.Whi.p; P.Wl[g] = ly.Wlo.p;
+                    P.epi[g] = {ly.b32.as<float>(), net.out_mu32.as<float>(), net.out_sigma32.as<float>(),
+                                (float*)D_of(g), ldo, net.out_mu_rows, N, is_log[g]};
+                }
                 if (x3)
-                    hipLaunchKernelGGL((gemm_bf16_kernel<1, EpiOut<float>>), g, dim3(256), 0, s, A, (int64_t)K,
-                                       ly.Whi.as<uint16_t>(), ly.Wlo.as<uint16_t>(), rows, N, K, e, count, rpw);
+                    hipLaunchKernelGGL((gemm_bf16_kernel<1, EpiOut<float>>), gr, dim3(256), 0, s, P, (int64_t)K,
+                                       rows, N, K, count, rpw);
                 else
-                    hipLaunchKernelGGL((gemm_bf16_kernel<0, EpiOut<float>>), g, dim3(256), 0, s, A, (int64_t)K,
-                                       ly.Whi.as<uint16_t>(), ly.Wlo.as<uint16_t>(), rows, N, K, e, count, rpw);
+                    hipLaunchKernelGGL((gemm_bf16_kernel<0, EpiOut<float>>), gr, dim3(256), 0, s, P, (int64_t)K,
+                                       rows, N, K, count, rpw);
             }
         }
         NS_HIP(hipGetLastError());
         cur ^= 1;
     }
+}
+
+// ----------------------------------------------------------------- adjoint
+// gx[g][r][k] = sum_n delta_1[g][r][n] W_1[n][k] / scale[k]: one wave per row.
+template <class T>
+__global__ __launch_bounds__(256) void first_layer_back_kernel(const T* __restrict__ delta, int64_t rows,
+                                                               int n1, int n_in, FirstArgs<T, T> P, size_t dstride,
+                                                               double* __restrict__ gx, const int* __restrict__ count,
+                                                               int rpw) {
+    const int g = blockIdx.z;
+    int64_t nrows = rows;
+    if (count) nrows = min<int64_t>(rows, (int64_t)(*count) * rpw);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= nrows) return;
+    const T* dr = delta + g * dstride + r * n1;
+    const T* W = P.W[g];
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    for (int n = lane; n < n1; n += 64) {
+        const double dv = (double)dr[n];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < n_in) acc[k] = fma(dv, (double)W[(int64_t)n * n_in + k], acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < n_in) {
+            const double v = wave_sum(acc[k]);
+            if (lane == 0) gx[((int64_t)g * rows + r) * n_in + k] = v / P.scale[g][k];
+        }
+    }
+}
+
+template <class T>
+static void backward_impl(ns_model* m, const int* nets, int G, int64_t B, const int* count, hipStream_t s) {
+    const bool f64 = sizeof(T) == 8;
+    const Net& net0 = *m->nets[nets[0]];
+    const int L = net0.n_layers;
+    const int rpw = net0.out_mu_rows;
+    const int64_t rows = B * rpw;
+    size_t max_w = 0;
+    for (int l = 1; l < L; ++l) max_w = std::max(max_w, (size_t)net0.dims[l]);
+    const size_t act_stride = (size_t)rows * max_w;
+    const size_t save_stride = (size_t)(L - 1) * act_stride;
+    const size_t gstride = (size_t)rows * std::max(max_w, (size_t)net0.layers[L - 1]->n_pad);
+    char* tbase = m->ws_tsave.as<char>();
+    auto tslot = [&](int g, int slot) {
+        return (const T*)(tbase + ((size_t)g * save_stride + (size_t)slot * act_stride) * sizeof(T));
+    };
+    int cur = 0;
+    for (int l = L - 1; l >= 1; --l) {
+        const int Kred = net0.layers[l]->n_pad, Nout = net0.dims[l];
+        TraceScope ts(m, s, f64 ? "adj_gemm_f64" : "adj_gemm_f32");
+        Group<EpiBack<T>> P{};
+        for (int g = 0; g < G; ++g) {
+            const Net& net = *m->nets[nets[g]];
+            const Layer& ly = *net.layers[l];
+            const Layer& lb = *net.layers[l - 1];
+            P.A[g] = m->ws_gact[cur].as<T>() + g * gstride;
+            P.W[g] = f64 ? ly.WT64.p : ly.WT32.p;
+            P.epi[g] = {tslot(g, l - 1), (const T*)(f64 ? lb.beta64.p : lb.beta32.p),
+                        (const T*)(f64 ? lb.gamma64.p : lb.gamma32.p), m->ws_gact[cur ^ 1].as<T>() + g * gstride,
+                        (int64_t)Nout};
+        }
+        if constexpr (sizeof(T) == 8)
+            hipLaunchKernelGGL((gemm_f64_kernel<EpiBack<T>>), grid3(rows, Nout, GD_M, GD_N, G), dim3(256), 0, s, P,
+                               (int64_t)Kred, rows, Nout, Kred, count, rpw);
+        else
+            hipLaunchKernelGGL((gemm_f32_kernel<EpiBack<T>>), grid3(rows, Nout, GB_M, GB_N, G), dim3(256), 0, s, P,
+                               (int64_t)Kred, rows, Nout, Kred, count, rpw);
+        NS_HIP(hipGetLastError());
+        cur ^= 1;
+    }
+    FirstArgs<T, T> P{};
+    for (int g = 0; g < G; ++g) {
+        const Net& net = *m->nets[nets[g]];
+        const Layer& l1 = *net.layers[0];
+        P.W[g] = (const T*)(f64 ? l1.W64.p : l1.W32.p);
+        P.scale[g] = net.in_scale.as<double>();
+    }
+    const int n_in = net0.dims[0];
+    m->ws_gx.ensure((size_t)G * rows * n_in * sizeof(double));
+    TraceScope ts(m, s, "adj_first_layer");
+    hipLaunchKernelGGL(first_layer_back_kernel<T>, dim3((unsigned)((rows + 3) / 4), 1, (unsigned)G), dim3(256), 0, s,
+                       m->ws_gact[cur].as<T>(), rows, net0.dims[1], n_in, P, gstride, m->ws_gx.as<double>(), count,
+                       rpw);
+    NS_HIP(hipGetLastError());
+}
+
+void emulator_backward(ns_model* m, const int* nets, int G, int64_t B, int prec, hipStream_t s) {
+    if (prec == NS_FP64)
+        backward_impl<double>(m, nets, G, B, nullptr, s);
+    else
+        backward_impl<float>(m, nets, G, B, nullptr, s);
 }
 
 }  // namespace nsmi

@@ -194,19 +194,24 @@ void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
         const int64_t n = m->n_data;
         m->ws_out.ensure((size_t)B * n * elem);
         int64_t off = 0;
-        for (size_t ni = 0; ni < m->nets.size(); ++ni) {
-            const int n_out = m->nets[ni]->dims.back();
-            char* dst = m->ws_out.as<char>() + off * elem;
-            emulator_forward(m, (int)ni, theta, ld, B, dst, n, m->spec_log[ni], prec, count, s);
-            off += n_out;
+        int ids[4];
+        void* outs[4];
+        const int G = (int)m->nets.size();
+        for (int g = 0; g < G; ++g) {
+            ids[g] = g;
+            outs[g] = m->ws_out.as<char>() + off * elem;
+            off += m->nets[g]->dims.back();
         }
+        emulator_forward(m, ids, G, theta, ld, B, outs, n, m->spec_log.data(), prec, count, s);
         cmb_chi2(m, theta, ld, B, m->ws_out.p, logl, prec, count, s);
         return;
     }
     // shear: emulator table [B * n_z x n_k], then projection and chi^2
     const int n_k = m->nets[0]->dims.back();
     m->ws_out.ensure((size_t)B * m->n_z * n_k * elem);
-    emulator_forward(m, 0, theta, ld, B, m->ws_out.p, n_k, 0, prec, count, s);
+    const int id0 = 0, no_log = 0;
+    void* out0 = m->ws_out.p;
+    emulator_forward(m, &id0, 1, theta, ld, B, &out0, n_k, &no_log, prec, count, s);
     shear_loglike_from_table(m, theta, ld, B, logl, prec, count, s);
 }
 

@@ -80,6 +80,8 @@ struct Layer {
     DevBuf W64, b64, beta64, gamma64;        // double
     DevBuf W32, b32, beta32, gamma32;        // float
     DevBuf Whi, Wlo;                         // bf16 hi / lo split of W
+    int n_pad = 0;                           // n_out rounded up to 64
+    DevBuf WT64, WT32;                       // W^T [n_in x n_pad], zero padded (adjoint)
 };
 
 struct Net {
@@ -131,6 +133,7 @@ struct ns_model {
     nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t))
     nsmi::DevBuf ell_d;              // double [n_ell]
     nsmi::DevBuf cov_linv;           // double [n x n] lower-triangular inverse Cholesky factor
+    nsmi::DevBuf cov_linvT;          // its transpose (row k holds column k), for the adjoint
     nsmi::DevBuf cov_w;              // double [n]: L^{-1} d
 
     // GAUSS
@@ -145,6 +148,9 @@ struct ns_model {
     nsmi::DevBuf ws_slice;           // slice-sampler state
     nsmi::DevBuf ws_flag;            // small device counters/flags
     nsmi::DevBuf ws_grad;            // adjoint scratch
+    nsmi::DevBuf ws_tsave;           // saved pre-activations [G x (L-1) x rows x width]
+    nsmi::DevBuf ws_gact[2];         // adjoint activations ping-pong [G x rows x n_pad]
+    nsmi::DevBuf ws_gx;              // input gradients [G x rows x n_in]
     void* host_pinned = nullptr;     // pinned host flag for completion polling
 
     // per-kernel tracing: HIP events bracketing each launch on its stream
@@ -173,8 +179,27 @@ struct TraceScope {
 // theta [B x ld] device; `count` optional device row count (rows beyond it skipped).
 // Output written to `out` ([rows x ldo], double for NS_FP64 else float);
 // is_log applies 10^y after the output transform.
-void emulator_forward(ns_model* m, int ni, const double* theta, int64_t ld, int64_t B,
-                      void* out, int64_t ldo, int is_log, int prec, const int* count, hipStream_t s);
+// `nets` lists G <= 4 networks of identical shape that run in one grid; outs[g]
+// and is_log[g] belong to nets[g].
+// save_t keeps every hidden pre-activation in m->ws_tsave for the adjoint.
+void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
+                      void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
+                      hipStream_t s, bool save_t = false);
+
+// Adjoint of the emulator: from delta_out[g] ([rows x n_pad] FP64 for NS_FP64
+// else FP32; derivative of logL w.r.t. the raw network outputs) back to the
+// per-network, per-row input gradients gx [G x rows x n_in] (w.r.t. the
+// un-normalised inputs).  Requires a preceding forward with save_t.
+void emulator_backward(ns_model* m, const int* nets, int G, int64_t B, int prec, hipStream_t s);
+
+// Batched log-likelihood and its gradient (hand-written adjoint).
+void loglike_grad_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, double* grad,
+                        int prec, hipStream_t s);
+void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, double* grad, int prec,
+                hipStream_t s);
+// grad = direct (optional) + emulator input gradients in m->ws_gx mapped to theta; 0 where logl = -inf.
+void grad_assemble(ns_model* m, int64_t B, int G, int rpw, const double* direct, const double* logl, double* grad,
+                   hipStream_t s);
 
 // CMB chi^2 on model vectors (double or float per prec) -> logL, with support mask.
 void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const void* mvec,

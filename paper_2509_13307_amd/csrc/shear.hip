@@ -23,13 +23,9 @@
 //                  covariance, logL = -1/2 |y|^2 - sum log L_ii - n/2 log 2 pi (FP64).
 #include "devutil.h"
 #include "nsmi.h"
+#include "shear_common.h"
 
 namespace nsmi {
-
-constexpr double C_KM_S = 299792.458;
-constexpr double C1_RHOCR = 5e-14 * 2.77536627e11;
-constexpr double GROWTH_INDEX = 0.55;
-constexpr double LN10 = 2.302585092994045684;
 
 // -------------------------------------------------------------- z-spline
 template <class T>
@@ -79,36 +75,6 @@ __global__ __launch_bounds__(256) void zspline_kernel(const T* __restrict__ Y, T
     mm[0] = T(2) * M1 - M2;
     mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
 }
-
-// --------------------------------------------------------------- block scans
-// Inclusive prefix sum over the block of per-thread values (blockDim = 256).
-template <int NV>
-__device__ void block_scan(double (&v)[NV], double* buf /* [NV][256] */, bool reverse) {
-    const int t = threadIdx.x;
-    const int src = reverse ? 255 - t : t;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) buf[q * 256 + src] = v[q];
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        double add[NV];
-#pragma unroll
-        for (int q = 0; q < NV; ++q) add[q] = src >= off ? buf[q * 256 + src - off] : 0.0;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NV; ++q) buf[q * 256 + src] += add[q];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = buf[q * 256 + src];
-    __syncthreads();
-}
-
-constexpr int MAXB = 10;   // tomographic bins supported by the kernel
-
-struct ShearGeom {
-    int n_a, n_z, n_k, n_ell, n_bins, n_pairs;
-    double a_min, da, zmax, k_min, k_max, u0, du, nz_sigma;
-};
 
 // One workgroup (256 threads) per walker; n_a <= 256 nodes (one per thread).
 template <class T>
@@ -319,6 +285,16 @@ __global__ __launch_bounds__(256) void dense_chi2_kernel(
     }
 }
 
+ShearGeom shear_geom(const ns_model* m) {
+    ShearGeom G;
+    G.n_a = m->n_a; G.n_z = m->n_z; G.n_k = m->n_k; G.n_ell = m->n_ell; G.n_bins = m->n_bins;
+    G.n_pairs = m->n_pairs;
+    G.a_min = m->a_min; G.da = (1.0 - m->a_min) / (m->n_a - 1); G.zmax = 1.0 / m->a_min - 1.0;
+    G.k_min = m->k_min; G.k_max = m->k_max; G.u0 = log10(m->k_min);
+    G.du = (log10(m->k_max) - log10(m->k_min)) / (m->n_k - 1); G.nz_sigma = m->nz_sigma;
+    return G;
+}
+
 static size_t limber_smem(const ns_model* m, size_t elem) {
     return (2 * MAXB * 256 + MAXB * 4 + 256) * sizeof(double) + (size_t)(m->n_bins + 1 + m->n_ell) * 256 * elem;
 }
@@ -347,11 +323,7 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
                            nk, hz, count);
     NS_HIP(hipGetLastError());
     }
-    ShearGeom G;
-    G.n_a = m->n_a; G.n_z = nz; G.n_k = nk; G.n_ell = m->n_ell; G.n_bins = m->n_bins; G.n_pairs = m->n_pairs;
-    G.a_min = m->a_min; G.da = (1.0 - m->a_min) / (m->n_a - 1); G.zmax = zmax;
-    G.k_min = m->k_min; G.k_max = m->k_max; G.u0 = log10(m->k_min);
-    G.du = (log10(m->k_max) - log10(m->k_min)) / (nk - 1); G.nz_sigma = m->nz_sigma;
+    const ShearGeom G = shear_geom(m);
     const size_t sm = limber_smem(m, elem);
     NS_CHECK(sm <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
     if (prec == NS_FP64)

@@ -1,0 +1,141 @@
+"""Parity of the hand-written adjoint (ns_loglike_grad_batch) with the oracle's
+complex-step gradient, and with central finite differences of the GPU's own
+likelihood.
+
+Tolerances: FP64 form, gradient error <= 1e-8 relative to max|grad| per walker;
+reduced forms (forward in the form, adjoint in FP32) <= 1e-2 of max|grad|."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.gradient import loglike_grad
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_models = {}
+
+
+def gm(name):
+    from paper_2509_13307_amd import Model
+    if name not in _models:
+        m = W.load_model(name) if name != "gauss" else W.gauss_structure(d=5, mu=[0.2, 0.4, 0.5, 0.6, 0.9],
+                                                                          sigma=[0.05, 0.1, 0.2, 0.1, 0.05])
+        _models[name] = (m, Model(m))
+    return _models[name]
+
+
+def scale_of(m):
+    if "fisher_sigma" not in m:
+        return np.full(m["d"], 0.05)
+    width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
+    return np.minimum(m["fisher_sigma"], 0.1 * width)
+
+
+def center_of(m):
+    return m["theta_fid"] if "theta_fid" in m else np.asarray(m["mu"])
+
+
+@pytest.mark.parametrize("name,B", [("gauss", 33), ("cmb6", 77), ("cmb4x2500", 20)])
+def test_fp64_gradient_matches_complex_step(name, B):
+    say(f"case grad fp64 {name}")
+    m, g = gm(name)
+    th = W.posterior_draws(center_of(m), scale_of(m), B, tag=5)
+    th[0, 0] = -5.0                              # outside the support -> -inf, zero gradient
+    ref_l, ref_g = loglike_grad(th, m)
+    t = torch.tensor(th, device=DEV)
+    logl, grad = g.loglike_grad(t, "fp64")
+    logl, grad = logl.cpu().numpy(), grad.cpu().numpy()
+    assert logl[0] == -np.inf and np.all(grad[0] == 0)
+    fin = np.isfinite(ref_l)
+    np.testing.assert_allclose(logl[fin], ref_l[fin], rtol=1e-12, atol=1e-6)
+    scale = np.max(np.abs(ref_g[fin]), axis=1, keepdims=True)
+    err = np.abs(grad[fin] - ref_g[fin]) / scale
+    say(f"{name}: max rel gradient error {err.max():.3e}")
+    assert err.max() < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_reduced_gradient(prec):
+    say(f"case grad {prec} cmb4x2500")
+    m, g = gm("cmb4x2500")
+    th = W.posterior_draws(center_of(m), scale_of(m), 16, tag=6)
+    ref_l, ref_g = loglike_grad(th, m)
+    logl, grad = g.loglike_grad(torch.tensor(th, device=DEV), prec)
+    grad = grad.cpu().numpy()
+    scale = np.max(np.abs(ref_g), axis=1, keepdims=True)
+    err = np.abs(grad - ref_g) / scale
+    say(f"cmb4x2500 {prec}: max rel gradient error {err.max():.3e}")
+    lim = {"fp32": 1e-3, "bf16x3": 1e-3, "bf16": 0.5}[prec]
+    assert err.max() < lim
+
+
+def test_gradient_matches_central_differences_of_gpu_likelihood():
+    say("case grad vs FD cmb6")
+    m, g = gm("cmb6")
+    th = W.posterior_draws(m["theta_fid"], m["fisher_sigma"], 8, tag=7)
+    _, grad = g.loglike_grad(torch.tensor(th, device=DEV), "fp64")
+    grad = grad.cpu().numpy()
+    h = 1e-6
+    fd = np.zeros_like(th)
+    for k in range(6):
+        tp, tm = th.copy(), th.copy()
+        tp[:, k] += h
+        tm[:, k] -= h
+        lp = g.loglike(torch.tensor(tp, device=DEV)).cpu().numpy()
+        lm = g.loglike(torch.tensor(tm, device=DEV)).cpu().numpy()
+        fd[:, k] = (lp - lm) / (2 * h)
+    err = np.abs(fd - grad) / np.max(np.abs(grad), axis=1, keepdims=True)
+    say(f"cmb6 FD: max rel {err.max():.3e}")
+    assert err.max() < 1e-5
+
+
+def test_autograd_function():
+    say("case autograd")
+    from paper_2509_13307_amd.autograd import loglike as ll_fn
+    m, g = gm("cmb6")
+    th = torch.tensor(W.posterior_draws(m["theta_fid"], m["fisher_sigma"], 5, tag=8), device=DEV,
+                      requires_grad=True)
+    w = torch.linspace(0.5, 1.5, 5, dtype=torch.float64, device=DEV)
+    (ll_fn(g, th, "fp64") * w).sum().backward()
+    _, ref = g.loglike_grad(th.detach(), "fp64")
+    torch.testing.assert_close(th.grad, ref * w[:, None], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("name,B", [("shear10", 6), ("shear64", 3)])
+def test_shear_fp64_gradient_matches_complex_step(name, B):
+    say(f"case grad fp64 {name}")
+    m, g = gm(name)
+    th = W.posterior_draws(center_of(m), scale_of(m), B, tag=10)
+    th[:, 2] = np.maximum(th[:, 2], 0.65)           # keep h inside its prior
+    ref_l, ref_g = loglike_grad(th, m)
+    logl, grad = g.loglike_grad(torch.tensor(th, device=DEV), "fp64")
+    logl, grad = logl.cpu().numpy(), grad.cpu().numpy()
+    np.testing.assert_allclose(logl, ref_l, rtol=1e-12, atol=1e-6)
+    scale = np.max(np.abs(ref_g), axis=1, keepdims=True)
+    err = np.abs(grad - ref_g) / scale
+    worst = np.unravel_index(np.argmax(err), err.shape)
+    say(f"{name}: max rel gradient error {err.max():.3e} at param {m['names'][worst[1]]}")
+    assert np.all(grad[:, -15:] == 0.0)
+    assert err.max() < 1e-8
+
+
+def test_shear_fp32_gradient():
+    say("case grad fp32 shear10")
+    m, g = gm("shear10")
+    th = W.posterior_draws(center_of(m), scale_of(m), 4, tag=11)
+    th[:, 2] = np.maximum(th[:, 2], 0.65)
+    ref_l, ref_g = loglike_grad(th, m)
+    _, grad = g.loglike_grad(torch.tensor(th, device=DEV), "fp32")
+    err = np.abs(grad.cpu().numpy() - ref_g) / np.max(np.abs(ref_g), axis=1, keepdims=True)
+    say(f"shear10 fp32: max rel gradient error {err.max():.3e}")
+    assert err.max() < 1e-2
