@@ -115,6 +115,7 @@ SIGNATURES = [
                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("ns_trace_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ns_trace_report", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    ("ns_tuning_report", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
     ("ns_last_error", ctypes.c_char_p, []),
 ]
 

@@ -120,6 +120,17 @@ static Net* build_net(const ns_net_desc& nd, int mu_rows) {
         NS_CHECK(net->dims[0] <= 16, NS_E_UNSUPPORTED, "emulator supports <= 16 inputs");
         for (int l = 1; l < nd.n_layers; ++l)
             NS_CHECK(net->dims[l] % 64 == 0, NS_E_UNSUPPORTED, "hidden widths must be multiples of 64 (MFMA tiles)");
+        net->fused = fused_shape(net->dims);
+        const int H = net->dims[1];
+        const int n_out_net = net->dims.back();
+        const size_t fcols = (size_t)(n_out_net + H - 1) / H * H;
+        std::vector<bf16_t> fh, fl;
+        std::vector<float> fv;
+        if (net->fused) {
+            fh.assign((size_t)(nd.n_layers - 2) * H * H + fcols * H, 0);
+            fl.assign(fh.size(), 0);
+            fv.assign((size_t)(nd.n_layers - 2) * 3 * H + n_out_net, 0.0f);
+        }
         for (int l = 0; l < nd.n_layers; ++l) {
             Layer* ly = new Layer();
             net->layers.push_back(ly);
@@ -144,6 +155,37 @@ static Net* build_net(const ns_net_desc& nd, int mu_rows) {
             }
             upload(ly->Whi, hi.data(), nw);
             upload(ly->Wlo, lo.data(), nw);
+            if (net->fused && l >= 1) {
+                // fragment order: block (nt, kc) of 64 lanes x 8 inputs; lane q holds
+                // unit 32 nt + q % 32, inputs 16 kc + 8 (q / 32) + i
+                const int KC = K / 16;
+                const size_t base = (size_t)(l - 1) * H * H;
+                const int n_cols = ly->hidden ? H : (int)fcols;
+                for (int nt = 0; nt < n_cols / 32; ++nt)
+                    for (int kc = 0; kc < KC; ++kc)
+                        for (int q = 0; q < 64; ++q) {
+                            const int n = nt * 32 + q % 32;
+                            if (n >= N) continue;
+                            for (int i = 0; i < 8; ++i) {
+                                const size_t src = (size_t)n * K + kc * 16 + 8 * (q / 32) + i;
+                                const size_t dst = base + (((size_t)nt * KC + kc) * 64 + q) * 8 + i;
+                                fh[dst] = hi[src];
+                                fl[dst] = lo[src];
+                            }
+                        }
+                float* v = fv.data() + (size_t)(l - 1) * 3 * H;
+                if (ly->hidden) {
+                    check_ptr(nd.beta[l], "net.beta[l]");
+                    check_ptr(nd.gamma[l], "net.gamma[l]");
+                }
+                for (int i = 0; i < N; ++i) {
+                    v[i] = bf[i];
+                    if (ly->hidden) {
+                        v[H + i] = (float)nd.beta[l][i];
+                        v[2 * H + i] = (float)nd.gamma[l][i];
+                    }
+                }
+            }
             // transposed, zero-padded copies for the adjoint GEMMs
             ly->n_pad = (N + 63) / 64 * 64;
             std::vector<double> wt((size_t)K * ly->n_pad, 0.0);
@@ -165,6 +207,11 @@ static Net* build_net(const ns_net_desc& nd, int mu_rows) {
                 upload(ly->beta32, be.data(), (size_t)N);
                 upload(ly->gamma32, ga.data(), (size_t)N);
             }
+        }
+        if (net->fused) {
+            upload(net->Wf, fh.data(), fh.size());
+            upload(net->Wfl, fl.data(), fl.size());
+            upload(net->fvec, fv.data(), fv.size());
         }
         const int n_in = net->dims[0], n_out = net->dims.back();
         upload(net->in_shift, nd.in_shift, (size_t)n_in);
@@ -301,6 +348,7 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         m->n_pairs = nb * (nb + 1) / 2;
         m->nz_sigma = D->nz_sigma; m->a_min = D->a_min; m->k_min = D->k_min; m->k_max = D->k_max;
         NS_CHECK(D->n_data == m->n_pairs * D->n_ell, NS_E_SHAPE, "n_data must be n_pairs * n_ell");
+        NS_CHECK(D->n_data <= 1024, NS_E_UNSUPPORTED, "shear data vector longer than 1024");
         NS_CHECK(n_in == 8, NS_E_SHAPE, "shear emulator takes 8 inputs");
         NS_CHECK(m->nets[0]->dims.back() == D->n_k, NS_E_SHAPE, "shear emulator must output n_k values");
         const int nphys = 9 + 3 * nb;
@@ -352,6 +400,9 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         for (int b = 0; b < D->n_ell; ++b)
             ell[b] = std::pow(10.0, D->n_ell > 1 ? l0 + b * (l1 - l0) / (D->n_ell - 1) : l0);
         upload(m->ell_d, ell.data(), ell.size());
+        std::vector<double> lell(D->n_ell);
+        for (int b = 0; b < D->n_ell; ++b) lell[b] = std::log10(ell[b] + 0.5);
+        upload(m->lell_d, lell.data(), lell.size());
         // dense covariance: L^{-1} and the whitened data
         const int n = D->n_data;
         std::vector<double> A(D->cov, D->cov + (size_t)n * n);
@@ -370,6 +421,16 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < n; ++k) XT[(size_t)k * n + i] = X[(size_t)i * n + k];
         upload(m->cov_linvT, XT.data(), XT.size());
+        const int n16 = (n + 15) / 16 * 16, kc_all = n16 / 4;
+        std::vector<double> XF((size_t)n16 * n16, 0.0);
+        for (int nt = 0; nt < n16 / 16; ++nt)
+            for (int kc = 0; kc < kc_all; ++kc)
+                for (int q = 0; q < 64; ++q) {
+                    const int row = 16 * nt + q % 16, col = 4 * kc + q / 16;
+                    if (row < n && col < n)
+                        XF[((size_t)nt * kc_all + kc) * 64 + q] = X[(size_t)row * n + col];
+                }
+        upload(m->cov_linv_frag, XF.data(), XF.size());
         upload(m->cov_w, w.data(), w.size());
         m->logl_const = c;
     }
@@ -420,6 +481,8 @@ ns_model::~ns_model() {
         (void)hipEventDestroy(r.e1);
     }
     for (auto e : trace_pool) (void)hipEventDestroy(e);
+    if (graph_stream) (void)hipStreamDestroy(graph_stream);
+    if (graph_event) (void)hipEventDestroy(graph_event);
 }
 
 using namespace nsmi;
@@ -588,6 +651,16 @@ ns_status ns_trace_report(ns_model* model, char* buf, int64_t buf_len) {
         }
         js += "}";
         NS_CHECK((int64_t)js.size() < buf_len, NS_E_SHAPE, "trace report buffer too small");
+        memcpy(buf, js.c_str(), js.size() + 1);
+    });
+}
+
+ns_status ns_tuning_report(ns_model* model, char* buf, int64_t buf_len) {
+    return (ns_status)guard([&] {
+        check_ptr(model, "model");
+        check_ptr(buf, "buf");
+        const std::string js = bf16_tuning_report(model);
+        NS_CHECK((int64_t)js.size() < buf_len, NS_E_SHAPE, "tuning report buffer too small");
         memcpy(buf, js.c_str(), js.size() + 1);
     });
 }

@@ -12,16 +12,35 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4_t;
 
 // round-to-nearest-even float -> bf16 bits
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// FP32 -> BF16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Low BF16 part of the split v = hi + lo, hi = f2bf(v): lo = f2bf(v - hi) with
+// the subtraction kept apart from whatever product produced v (a fused
+// multiply-subtract would see the unrounded product instead of v).
+__device__ __forceinline__ uint16_t bf16_lo(float v, uint16_t hi) {
+#pragma clang fp contract(off)
+    return f2bf(v - bf2f(hi));
+}
+
 template <class T> __device__ __forceinline__ T sigmoid(T u) { return T(1) / (T(1) + exp(-u)); }
-template <> __device__ __forceinline__ float sigmoid<float>(float u) { return 1.0f / (1.0f + __expf(-u)); }
+// FP32: hardware exp2 and reciprocal (about 1 ulp each)
+template <> __device__ __forceinline__ float sigmoid<float>(float u) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u * -1.44269504088896341f));
+}
+// 10^y (output transform of log10-emulated spectra)
+template <class T> __device__ __forceinline__ T exp10_of(T y) { return exp(y * T(2.302585092994045684)); }
+// FP32: 10^y = 2^(p_hi + p_lo) with p_hi = fl(y log2 10) and p_lo its rounding
+// residual (plus the residual of log2 10 itself), so that the argument
+// rounding (up to |y log2 10| 2^-24) does not reach the result; then
+// 2^p_lo = 1 + p_lo ln 2 to first order (|p_lo| < 1e-5)
+template <> __device__ __forceinline__ float exp10_of<float>(float y) {
+    const float c_hi = 3.321928024291992f, c_lo = 7.059536955011936e-08f;
+    const float p_hi = y * c_hi;
+    const float p_lo = fmaf(y, c_hi, -p_hi) + y * c_lo;
+    return __builtin_amdgcn_exp2f(p_hi) * fmaf(p_lo, 0.6931471824645996f, 1.0f);
+}
 
 // gated activation (gamma + (1 - gamma) sigmoid(beta t)) t
 template <class T> __device__ __forceinline__ T gated(T t, T beta, T gamma) {

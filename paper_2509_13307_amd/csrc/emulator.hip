@@ -17,6 +17,7 @@
 // Networks with identical shapes (the four CMB spectra) run in one grid,
 // blockIdx.z selecting the network, so a 4096-walker layer fills the chip.
 #include "devutil.h"
+#include "gemm_bf16.h"
 #include "nsmi.h"
 
 namespace nsmi {
@@ -40,48 +41,66 @@ template <class T, class OutT> struct FirstArgs {
     T* tsave[MAXG];
 };
 
-template <class T, class OutT, int ROWS>
+// One workgroup per block of FL_ROWS rows.  The normalised inputs of the
+// block are computed once per row into LDS; thread t owns CPT consecutive
+// units (its CPT x n_in weights held in registers) for every
+// (256 / (n_out / CPT))-th row of the block.  Each unit's sum runs in input
+// order starting from the bias, whatever the thread mapping.
+constexpr int FL_ROWS = 64;
+
+template <class T, class OutT, int NI, int CPT>
 __global__ __launch_bounds__(256) void first_layer_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t rows, int rows_per_walker,
     const int* __restrict__ src, const double* __restrict__ fix, const double* __restrict__ znodes, int n_in,
     int n_out, FirstArgs<T, OutT> P, const int* __restrict__ count) {
-    __shared__ T xs[ROWS][16];
+    __shared__ T xs[FL_ROWS][NI];
     const int g = blockIdx.z;
     int64_t nrows = rows;
     if (count) nrows = min<int64_t>(rows, (int64_t)(*count) * rows_per_walker);
-    const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+    const int64_t r0 = (int64_t)blockIdx.x * FL_ROWS;
     if (r0 >= nrows) return;
-    if (threadIdx.x < ROWS * n_in) {
-        const int rr = threadIdx.x / n_in, k = threadIdx.x % n_in;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < FL_ROWS * NI; e += 256) {
+        const int rr = e / NI, k = e % NI;
         const int64_t r = r0 + rr;
-        double v = 0.0;
-        if (r < nrows) {
+        T v = T(0);
+        if (k < n_in && r < nrows) {
             const int64_t w = r / rows_per_walker;
             const int zi = (int)(r % rows_per_walker);
             const int s = src[k];
-            v = s >= 0 ? theta[w * ld + s] : (s == SRC_ZNODE ? znodes[zi] : fix[k]);
-            v = (v - P.shift[g][k]) / P.scale[g][k];
+            const double t = s >= 0 ? theta[w * ld + s] : (s == SRC_ZNODE ? znodes[zi] : fix[k]);
+            v = (T)((t - P.shift[g][k]) / P.scale[g][k]);
         }
-        xs[rr][k] = (T)v;
+        xs[rr][k] = v;
     }
     __syncthreads();
+    const int groups = n_out / CPT;
+    const int rpi = 256 / groups;                      // rows per pass of the workgroup
+    if (tid >= groups * rpi) return;
+    const int c0 = (tid % groups) * CPT;
+    T wr[CPT][NI], bb[CPT], be[CPT], ga[CPT];
     const T* W = P.W[g];
-    OutT* out = P.out[g];
-    for (int c = threadIdx.x; c < n_out; c += blockDim.x) {
-        T wrow[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) wrow[k] = k < n_in ? W[(int64_t)c * n_in + k] : T(0);
-        const T bc = P.b[g][c], be = P.beta[g][c], ga = P.gamma[g][c];
+    for (int j = 0; j < CPT; ++j) {
+        bb[j] = P.b[g][c0 + j];
+        be[j] = P.beta[g][c0 + j];
+        ga[j] = P.gamma[g][c0 + j];
 #pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr) {
-            const int64_t r = r0 + rr;
-            if (r >= nrows) break;
-            T acc = bc;
+        for (int k = 0; k < NI; ++k) wr[j][k] = k < n_in ? W[(c0 + j) * n_in + k] : T(0);
+    }
+    for (int rr = tid / groups; rr < FL_ROWS; rr += rpi) {
+        const int64_t r = r0 + rr;
+        if (r >= nrows) break;
+        OutT* out = P.out[g] + r * n_out + c0;
+        T* ts = P.tsave[g] ? P.tsave[g] + r * n_out + c0 : nullptr;
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k < n_in) acc += wrow[k] * xs[rr][k];
-            if (P.tsave[g]) P.tsave[g][r * n_out + c] = acc;
-            out[r * n_out + c] = cvt_out<T, OutT>(gated<T>(acc, be, ga));
+        for (int j = 0; j < CPT; ++j) {
+            T acc = bb[j];
+#pragma unroll
+            for (int k = 0; k < NI; ++k)
+                if (k < n_in) acc += wr[j][k] * xs[rr][k];
+            if (ts) ts[j] = acc;
+            out[j] = cvt_out<T, OutT>(gated<T>(acc, be[j], ga[j]));
         }
     }
 }
@@ -128,41 +147,16 @@ template <class T> struct EpiPlain {
 template <class T> struct EpiOut {
     const T* b; const T* mu; const T* sigma;
     T* out; int64_t ldo; int mu_rows; int n_out; int is_log;
-    struct Col { T b, s; int c; };
-    __device__ __forceinline__ Col col(int c) const { return Col{b[c], sigma[c], c}; }
+    struct Col { T b, s, mu0; int c; };
+    __device__ __forceinline__ Col col(int c) const { return Col{b[c], sigma[c], mu[c], c}; }
     __device__ __forceinline__ void store(int64_t r, int c, const Col& p, T acc) const {
-        const int zr = mu_rows > 1 ? (int)(r % mu_rows) : 0;
-        T y = mu[(int64_t)zr * n_out + c] + p.s * (acc + p.b);
-        if (is_log) y = exp(y * T(2.302585092994045684));
+        const T m = mu_rows > 1 ? mu[(int64_t)(r % mu_rows) * n_out + c] : p.mu0;
+        T y = m + p.s * (acc + p.b);
+        if (is_log) y = exp10_of<T>(y);
         out[r * ldo + c] = y;
     }
 };
 
-// Per-network operands of a grouped GEMM launch (blockIdx.z = network).
-template <class Epi> struct Group {
-    const void* A[MAXG];
-    const void* W[MAXG];
-    const void* Wl[MAXG];
-    Epi epi[MAXG];
-};
-
-// ------------------------------------------------------------ tile order
-// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X, each
-// with its own L2.  Remap the linear workgroup id so that the tiles one XCD
-// receives are consecutive in (network, row tile, column tile) order and so
-// share their activation row block in that XCD's L2.
-struct TileId { int g, ty, tx; };
-__device__ __forceinline__ TileId xcd_tile() {
-    const int nx = gridDim.x, ny = gridDim.y;
-    const int total = nx * ny * gridDim.z;
-    int i = (blockIdx.z * ny + blockIdx.y) * nx + blockIdx.x;
-    if ((total & 7) == 0) i = (i & 7) * (total >> 3) + (i >> 3);
-    TileId t;
-    t.tx = i % nx;
-    t.ty = (i / nx) % ny;
-    t.g = i / (nx * ny);
-    return t;
-}
 
 // ------------------------------------------------- MFMA GEMM, BF16 operands
 // WG tile 128 x 128, four waves in 2 x 2, each wave 64 x 64 = 2 x 2 tiles of
@@ -201,7 +195,7 @@ __device__ __forceinline__ void bf16_fetch(Bf16Stage<AMODE>& st, const void* Apt
                 for (int e = 0; e < 8; ++e) {
                     const uint16_t hb = f2bf(f[e]);
                     h[e] = hb;
-                    l[e] = f2bf(f[e] - bf2f(hb));
+                    l[e] = bf16_lo(f[e], hb);
                 }
                 hi = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
                 lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
@@ -484,6 +478,89 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Group<Epi> G, int64_t lda
     }
 }
 
+// ------------------------------------------------------ BF16 tile autotuner
+// Candidate tile configurations of gemm_bf16_t.  All of them accumulate each
+// output over K in the same order, so the choice never changes a result; the
+// fastest one for a (layer kind, M, N, K, networks) key is measured on the
+// device at first use (outside stream capture) and kept in the model.
+template <class Epi>
+using Bf16Launch = void (*)(const Group<Epi>&, int64_t, int, int, int, const int*, int, hipStream_t);
+
+template <int BM, int BN, int BK, int WM, int WN, int NB, class Epi>
+static void bf16_launch(const Group<Epi>& P, int64_t M, int N, int K, int G, const int* count, int rpw,
+                        hipStream_t s) {
+    const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)G);
+    hipLaunchKernelGGL((gemm_bf16_t<BM, BN, BK, WM, WN, NB, Epi>), grid, dim3(64 * WM * WN), 0, s, P, (int64_t)K, M,
+                       N, K, count, rpw);
+}
+
+static const char* const BF16_CFG_NAMES[] = {"128x128x64 waves 2x2 lds x1", "128x128x64 waves 2x2 lds x2",
+                                            "128x128x64 waves 4x2 lds x2", "128x128x32 waves 2x2 lds x2"};
+constexpr int BF16_NCFG = 4;
+
+template <class Epi>
+static Bf16Launch<Epi> bf16_candidate(int i) {
+    switch (i) {
+        case 0: return bf16_launch<128, 128, 64, 2, 2, 1, Epi>;
+        case 1: return bf16_launch<128, 128, 64, 2, 2, 2, Epi>;
+        case 2: return bf16_launch<128, 128, 64, 4, 2, 2, Epi>;
+        default: return bf16_launch<128, 128, 32, 2, 2, 2, Epi>;
+    }
+}
+
+template <class Epi>
+static void launch_bf16_tuned(ns_model* m, int kind, const Group<Epi>& P, int64_t M, int N, int K, int G,
+                              const int* count, int rpw, hipStream_t s) {
+    const auto key = std::make_tuple(kind, M, N, K, G);
+    auto it = m->tune.find(key);
+    int best = 0;
+    if (it != m->tune.end()) {
+        best = it->second;
+    } else {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        NS_HIP(hipStreamIsCapturing(s, &cs));
+        if (cs == hipStreamCaptureStatusNone && !m->trace && getenv("NSMI_NO_AUTOTUNE") == nullptr) {
+            hipEvent_t e0, e1;
+            NS_HIP(hipEventCreate(&e0));
+            NS_HIP(hipEventCreate(&e1));
+            float best_ms = 1e30f;
+            for (int c = 0; c < BF16_NCFG; ++c) {
+                const auto fn = bf16_candidate<Epi>(c);
+                fn(P, M, N, K, G, count, rpw, s);
+                NS_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 3; ++r) fn(P, M, N, K, G, count, rpw, s);
+                NS_HIP(hipEventRecord(e1, s));
+                NS_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                NS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) { best_ms = ms; best = c; }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            m->tune[key] = best;
+        }
+    }
+    bf16_candidate<Epi>(best)(P, M, N, K, G, count, rpw, s);
+}
+
+std::string bf16_tuning_report(const ns_model* m) {
+    std::string js = "{";
+    bool first = true;
+    for (const auto& kv : m->tune) {
+        char tmp[256];
+        const int kind = std::get<0>(kv.first);
+        static const char* kinds[6] = {"bf16_hidden", "bf16_out", "fused_bf16", "fused_bf16x3", "fused_bf16",
+                                       "fused_bf16x3"};
+        const char* cfg = kind < 2 ? BF16_CFG_NAMES[kv.second] : fused_cfg_name(kind >= 4, kind & 1, kv.second);
+        snprintf(tmp, sizeof tmp, "%s\"%s M=%lld N=%d K=%d networks=%d\": \"%s\"", first ? "" : ", ", kinds[kind],
+                 (long long)std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                 std::get<4>(kv.first), cfg);
+        js += tmp;
+        first = false;
+    }
+    return js + "}";
+}
+
 // ------------------------------------------------------------------ driver
 static inline dim3 grid3(int64_t M, int N, int bm, int bn, int G) {
     return dim3((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), (unsigned)G);
@@ -510,10 +587,19 @@ static void launch_first(ns_model* m, const int* nets, int G, const double* thet
         P.out[g] = act0 + g * act_stride;
         P.tsave[g] = tsave ? tsave + g * save_stride : nullptr;
     }
-    dim3 g1((unsigned)((rows + 3) / 4), 1, (unsigned)G);
-    hipLaunchKernelGGL((first_layer_kernel<T, OutT, 4>), g1, dim3(256), 0, s, theta, ld, rows, rpw,
-                       m->emu_src_d.as<int>(), m->emu_fix_d.as<double>(), m->znodes_d.as<double>(), n0.dims[0],
-                       n0.dims[1], P, count);
+    const int n_out = n0.dims[1], n_in = n0.dims[0];
+    constexpr int CPT = sizeof(T) == 8 ? 4 : 8;
+    NS_CHECK(n_out % CPT == 0 && n_out / CPT <= 256, NS_E_UNSUPPORTED,
+             "first hidden width must be a multiple of 8 and at most 1024");
+    dim3 g1((unsigned)((rows + FL_ROWS - 1) / FL_ROWS), 1, (unsigned)G);
+    if (n_in <= 8)
+        hipLaunchKernelGGL((first_layer_kernel<T, OutT, 8, CPT>), g1, dim3(256), 0, s, theta, ld, rows, rpw,
+                           m->emu_src_d.as<int>(), m->emu_fix_d.as<double>(), m->znodes_d.as<double>(), n_in, n_out,
+                           P, count);
+    else
+        hipLaunchKernelGGL((first_layer_kernel<T, OutT, 16, CPT>), g1, dim3(256), 0, s, theta, ld, rows, rpw,
+                           m->emu_src_d.as<int>(), m->emu_fix_d.as<double>(), m->znodes_d.as<double>(), n_in, n_out,
+                           P, count);
 }
 
 void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
@@ -527,6 +613,9 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
     const int rpw = net0.out_mu_rows;                 // rows per walker
     const int64_t rows = B * rpw;
     NS_CHECK(net0.dims[0] <= 16, NS_E_UNSUPPORTED, "emulator with more than 16 inputs");
+    if (!save_t && getenv("NSMI_NO_FUSED_MLP") == nullptr &&
+        emulator_forward_fused(m, nets, G, theta, ld, B, outs, ldo, is_log, prec, count, s))
+        return;
     const size_t act_elem = prec == NS_FP64 ? 8 : (prec == NS_BF16 ? 2 : 4);
     size_t max_w = 0;
     for (int l = 1; l < L; ++l) max_w = std::max(max_w, (size_t)net0.dims[l]);
@@ -638,8 +727,7 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
                         P.epi[g] = {ly.b32.as<float>(), ly.beta32.as<float>(), ly.gamma32.as<float>(),
                                     (uint16_t*)D_of(g), (int64_t)N, (float*)tslot(g, l)};
                     }
-                    hipLaunchKernelGGL((gemm_bf16_kernel<0, EpiHidden<float, uint16_t>>), gr, dim3(256), 0, s, P,
-                                       (int64_t)K, rows, N, K, count, rpw);
+                    launch_bf16_tuned(m, 0, P, rows, N, K, G, count, rpw, s);
                 }
             } else {
                 Group<EpiOut<float>> P{};
@@ -654,8 +742,7 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
                     hipLaunchKernelGGL((gemm_bf16_kernel<1, EpiOut<float>>), gr, dim3(256), 0, s, P, (int64_t)K,
                                        rows, N, K, count, rpw);
                 else
-                    hipLaunchKernelGGL((gemm_bf16_kernel<0, EpiOut<float>>), gr, dim3(256), 0, s, P, (int64_t)K,
-                                       rows, N, K, count, rpw);
+                    launch_bf16_tuned(m, 1, P, rows, N, K, G, count, rpw, s);
             }
         }
         NS_HIP(hipGetLastError());

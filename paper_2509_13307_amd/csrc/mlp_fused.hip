@@ -1,0 +1,373 @@
+// Whole-network emulator forward in one kernel for the BF16-operand forms
+// (NS_BF16 and the split form NS_BF16X3), Sec. 2.2 and 2.4 of the paper.
+//
+// One workgroup owns a block of R = 32 RT rows of one network.  The block's
+// activations stay in LDS (BF16; hi and lo planes for the split form) from
+// the first layer to the output layer.  Weights are never staged: each GEMM
+// layer's weights are stored at model creation in MFMA fragment order (one
+// 1 KB block per 32 output units x 16 inputs, lane l holding the 8 inputs
+// 8 (l / 32) .. + 7 of unit l % 32), so a wave fetches the B operand of one
+// v_mfma_f32_32x32x16_bf16 with a single coalesced 16-byte-per-lane load
+// straight into registers, P K-steps ahead of its use.  No weight element is
+// used by two waves of a workgroup, so LDS staging would bring no reuse.
+//
+// Wave w of NW = H / 64 owns output units [64 w, 64 w + 64) of each H-wide
+// column block: 2 column tiles x RT row tiles of 32 x 32.  Layer 1
+// (n_in <= 16 inputs) runs on the VALU in FP32.  Every output sees exactly
+// the arithmetic of the layer-by-layer path (same K order, same per-
+// accumulator MFMA sequence hi*hi, hi*lo, lo*hi, same epilogues), so both
+// paths give identical results.  The split residual v - hi is an explicitly
+// rounded subtraction: contracted with the activation's last multiply it
+// would see the unrounded product, which the stored FP32 value of the
+// layer-by-layer path does not.
+#include "devutil.h"
+#include "nsmi.h"
+
+namespace nsmi {
+
+constexpr int FM_MAXHID = 6;   // hidden GEMM layers supported
+
+struct FusedNet {
+    const float* W1; const float* b1; const float* be1; const float* ga1;   // first layer (FP32)
+    const double* shift; const double* scale;
+    const uint16_t* Wf;    // fragment-ordered BF16 hi weights of GEMM layers 2..L, layer l at l H^2
+    const uint16_t* Wfl;   // ... lo parts (split form)
+    const float* vec;      // hidden layer l: b, beta, gamma at l 3H + {0, H, 2H}; output bias after them
+    const float* mu; const float* sigma;
+    float* out; int is_log;
+};
+
+struct FusedArgs {
+    FusedNet net[4];
+    int n_hidden;        // hidden GEMM layers (network layers - 2)
+    int n_in, N_out, mu_rows;
+    int64_t ldo;
+};
+
+bool fused_shape(const std::vector<int>& dims) {
+    const int L = (int)dims.size() - 1;
+    if (L < 3 || L - 2 > FM_MAXHID || dims[0] > 16) return false;
+    const int H = dims[1];
+    if (H != 128 && H != 512) return false;
+    for (int l = 1; l < L; ++l)
+        if (dims[l] != H) return false;
+    return true;
+}
+
+template <int H, int RT, bool X3, int P, int CT>
+__global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t rows, int rows_per_walker, const int* __restrict__ src,
+    const double* __restrict__ fix, const double* __restrict__ znodes, FusedArgs A, const int* __restrict__ count) {
+    constexpr int WC = 32 * CT;            // output units per wave and column block
+    constexpr int NT = 64 * (H / WC);      // threads: one wave per WC units
+    constexpr int R = 32 * RT;             // rows per workgroup
+    constexpr int HS = H + 8;              // LDS row stride of an activation plane (elements)
+    constexpr int KC = H / 16;             // K steps of one GEMM layer
+    static_assert(KC % P == 0, "prefetch depth must divide the K steps");
+    extern __shared__ __attribute__((aligned(16))) uint16_t fm_lds[];
+    uint16_t* hs = fm_lds;                 // [R][HS] hi (or only) plane
+    uint16_t* hl = fm_lds + R * HS;        // [R][HS] lo plane (split form)
+    __shared__ float xs[R][16];
+    __shared__ int zrow[R];                // redshift-node index of each row (row mod mu_rows)
+    __shared__ int rowo[R];                // output offset of each row (row ldo), -1 beyond the live rows
+
+    // XCD-aware order: each XCD receives a contiguous run of (network, row block)
+    const int nrb = gridDim.x, total = nrb * gridDim.y;
+    int lin = blockIdx.y * nrb + blockIdx.x;
+    if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
+    const int g = lin / nrb, rb = lin % nrb;
+    const FusedNet& N = A.net[g];
+    int64_t nrows = rows;
+    if (count) nrows = min<int64_t>(rows, (int64_t)(*count) * rows_per_walker);
+    const int64_t r0 = (int64_t)rb * R;
+    if (r0 >= nrows) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n_in = A.n_in, n_hidden = A.n_hidden, N_out = A.N_out;
+    const int nvalid = (int)min<int64_t>(R, nrows - r0);   // live rows of this block
+    if (tid < R) {
+        zrow[tid] = A.mu_rows > 1 ? (int)((r0 + tid) % A.mu_rows) : 0;
+        rowo[tid] = tid < nvalid ? tid * (int)A.ldo : -1;
+    }
+
+    // ---- layer 1 into LDS (FP32 VALU, the arithmetic of the layer-by-layer path)
+    for (int e = tid; e < R * n_in; e += NT) {
+        const int rr = e / n_in, k = e % n_in;
+        const int64_t r = r0 + rr;
+        float v = 0.0f;
+        if (r < nrows) {
+            const int64_t w = r / rows_per_walker;
+            const int zi = (int)(r % rows_per_walker);
+            const int s = src[k];
+            const double t = s >= 0 ? theta[w * ld + s] : (s == SRC_ZNODE ? znodes[zi] : fix[k]);
+            v = (float)((t - N.shift[k]) / N.scale[k]);
+        }
+        xs[rr][k] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < R * H; e += NT) {
+        const int rr = e / H, c = e % H;
+        float acc = N.b1[c];
+        for (int k = 0; k < n_in; ++k) acc += N.W1[c * n_in + k] * xs[rr][k];
+        const float v = gated<float>(acc, N.be1[c], N.ga1[c]);
+        const uint16_t hi = f2bf(v);
+        hs[rr * HS + c] = hi;
+        if (X3) hl[rr * HS + c] = bf16_lo(v, hi);
+    }
+    __syncthreads();
+
+    // ---- GEMM stages: hidden layers, then the output layer's H-wide column
+    // blocks; stage s = (segment s / KC, K step s % KC).  Loads and MFMAs are
+    // unconditional (stages past the end re-read the last one, waves without
+    // a live unit in an output block compute on valid addresses and store
+    // nothing), so the weight prefetch stays in flight across iterations.
+    const int ncb = (N_out + H - 1) / H;
+    const int S = (n_hidden + ncb) * KC;
+    constexpr int TILE = KC * 64 * 8;                  // elements of one 32-unit column tile of a layer
+    auto frag = [&](int s) -> size_t {
+        s = min(s, S - 1);
+        const int seg = s / KC, kc = s - seg * KC;
+        const bool hid = seg < n_hidden;
+        int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
+        if (!hid && nb >= N_out) nb = 0;
+        return (size_t)min(seg, n_hidden) * H * H + (size_t)(nb / 32) * TILE + ((size_t)kc * 64 + lane) * 8;
+    };
+    bf16x8_t rh[P][CT], rl[P][CT];
+    auto fetch = [&](int s, bf16x8_t (&bh)[CT], bf16x8_t (&bl)[CT]) {
+        const size_t off = frag(s);
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            bh[j] = *reinterpret_cast<const bf16x8_t*>(N.Wf + off + (size_t)j * TILE);
+            if (X3) bl[j] = *reinterpret_cast<const bf16x8_t*>(N.Wfl + off + (size_t)j * TILE);
+        }
+    };
+    f32x16_t acc[RT][CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < P; ++u) fetch(u, rh[u], rl[u]);
+    // the compiler may issue these first loads in any order; waiting for them
+    // here keeps that order out of the K-step loop's load accounting
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+
+    // one segment (layer or output column block) per iteration; the K steps
+    // run in their own loop, so no epilogue path joins the steady state
+    for (int seg = 0; seg < n_hidden + ncb; ++seg) {
+        const bool hid = seg < n_hidden;
+        const int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
+        for (int kc0 = 0; kc0 < KC; kc0 += P) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                // slot u feeds this step's MFMAs first and is then refilled with
+                // the stage P steps ahead: no register copies, loads stay in flight
+                const int kc = kc0 + u;
+                const bf16x8_t (&bh)[CT] = rh[u];
+                const bf16x8_t (&bl)[CT] = rl[u];
+                const int koff = kc * 16 + (lane >> 5) * 8;
+                bf16x8_t ah[RT], al[RT];
+#pragma unroll
+                for (int i = 0; i < RT; ++i) {
+                    ah[i] = *reinterpret_cast<const bf16x8_t*>(&hs[(i * 32 + (lane & 31)) * HS + koff]);
+                    if (X3) al[i] = *reinterpret_cast<const bf16x8_t*>(&hl[(i * 32 + (lane & 31)) * HS + koff]);
+                }
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+#pragma unroll
+                    for (int j = 0; j < CT; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                if (X3) {
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+#pragma unroll
+                        for (int j = 0; j < CT; ++j) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                        }
+                }
+                fetch(seg * KC + kc + P, rh[u], rl[u]);
+            }
+        }
+        // ---- epilogue of a finished segment
+        if (hid) {
+            const float* vb = N.vec + (size_t)seg * 3 * H;
+            __syncthreads();                               // every wave done reading this layer's input
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                const int c = wave * WC + j * 32 + (lane & 31);
+                const float bb = vb[c], be = vb[H + c], ga = vb[2 * H + c];
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
+                        const float v = gated<float>(acc[i][j][r] + bb, be, ga);
+                        const uint16_t hi = f2bf(v);
+                        hs[row * HS + c] = hi;
+                        if (X3) hl[row * HS + c] = bf16_lo(v, hi);
+                    }
+            }
+            __syncthreads();                               // next layer's input complete
+        } else if (nb < N_out) {
+            const float* bo = N.vec + (size_t)n_hidden * 3 * H;
+            const bool zdep = A.mu_rows > 1, is_log = N.is_log;
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                const int c = nb + j * 32 + (lane & 31);
+                if (c >= N_out) continue;
+                const float bb = bo[c], sg = N.sigma[c], mu0 = N.mu[c];
+                float* ob = N.out + r0 * A.ldo + c;
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        // row offsets come from LDS: kept in registers they would
+                        // hold 64-bit addresses live across the whole stage loop
+                        const int lr = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
+                        const int ro = rowo[lr];
+                        if (ro < 0) continue;
+                        const float m = zdep ? N.mu[zrow[lr] * N_out + c] : mu0;
+                        float y = m + sg * (acc[i][j][r] + bb);
+                        if (is_log) y = exp10_of<float>(y);
+                        ob[ro] = y;
+                    }
+            }
+        }
+        // drain this segment's loads here (vmcnt(0) only), so that the next
+        // K-step loop starts with nothing but the weight prefetch in flight and
+        // its waits can count just those loads
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int j = 0; j < CT; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    }
+}
+
+template <int H, int RT, bool X3, int P, int CT>
+static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, int64_t ld, int64_t rows, int rpw,
+                         int G, const int* count, hipStream_t s) {
+    constexpr int R = 32 * RT;
+    constexpr int NT = 64 * (H / (32 * CT));
+    const size_t smem = (size_t)(X3 ? 2 : 1) * R * (H + 8) * sizeof(uint16_t);
+    const auto kern = mlp_fused_kernel<H, RT, X3, P, CT>;
+    const int bit = (H == 512 ? 16 : 0) + (X3 ? 8 : 0) + (CT == 1 ? 4 : 0) + (P == 2 ? 0 : (P == 4 ? 1 : 2));
+    if (smem > 64 * 1024 && !(m->fused_attr_set & (1u << bit))) {
+        NS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        m->fused_attr_set |= 1u << bit;
+    }
+    const dim3 grid((unsigned)((rows + R - 1) / R), (unsigned)G);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), smem, s, theta, ld, rows, rpw, m->emu_src_d.as<int>(),
+                       m->emu_fix_d.as<double>(), m->znodes_d.as<double>(), A, count);
+}
+
+// Candidate launch shapes (64-row blocks): waves of 32 or 64 output units,
+// 2-8 K steps of weight prefetch.  All candidates give identical results.
+using FusedLaunch = void (*)(ns_model*, const FusedArgs&, const double*, int64_t, int64_t, int, int, const int*,
+                             hipStream_t);
+struct FusedCfg { FusedLaunch fn; const char* name; };
+constexpr int FUSED_NCFG = 4;
+static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
+    {   // H = 128
+        {{launch_fused<128, 2, false, 4, 2>, "fused 2 waves x 64 units, prefetch 4"},
+         {launch_fused<128, 2, false, 8, 2>, "fused 2 waves x 64 units, prefetch 8"},
+         {launch_fused<128, 2, false, 4, 1>, "fused 4 waves x 32 units, prefetch 4"},
+         {launch_fused<128, 2, false, 8, 1>, "fused 4 waves x 32 units, prefetch 8"}},
+        {{launch_fused<128, 2, true, 2, 2>, "fused split 2 waves x 64 units, prefetch 2"},
+         {launch_fused<128, 2, true, 4, 2>, "fused split 2 waves x 64 units, prefetch 4"},
+         {launch_fused<128, 2, true, 2, 1>, "fused split 4 waves x 32 units, prefetch 2"},
+         {launch_fused<128, 2, true, 4, 1>, "fused split 4 waves x 32 units, prefetch 4"}},
+    },
+    {   // H = 512
+        {{launch_fused<512, 2, false, 4, 2>, "fused 8 waves x 64 units, prefetch 4"},
+         {launch_fused<512, 2, false, 8, 2>, "fused 8 waves x 64 units, prefetch 8"},
+         {launch_fused<512, 2, false, 4, 1>, "fused 16 waves x 32 units, prefetch 4"},
+         {launch_fused<512, 2, false, 8, 1>, "fused 16 waves x 32 units, prefetch 8"}},
+        {{launch_fused<512, 2, true, 2, 2>, "fused split 8 waves x 64 units, prefetch 2"},
+         {launch_fused<512, 2, true, 4, 2>, "fused split 8 waves x 64 units, prefetch 4"},
+         {launch_fused<512, 2, true, 2, 1>, "fused split 16 waves x 32 units, prefetch 2"},
+         {launch_fused<512, 2, true, 4, 1>, "fused split 16 waves x 32 units, prefetch 4"}},
+    },
+};
+
+const char* fused_cfg_name(int h512, int x3, int c) { return FUSED_CFGS[h512][x3][c].name; }
+
+// Returns false (and launches nothing) when the networks have no fragment-
+// ordered weights (shape outside fused_shape) or the form is not BF16-operand.
+bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
+                            void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
+                            hipStream_t s) {
+    if (prec != NS_BF16 && prec != NS_BF16X3) return false;
+    const Net& n0 = *m->nets[nets[0]];
+    if (!n0.fused) return false;
+    const bool x3 = prec == NS_BF16X3;
+    const int L = n0.n_layers;
+    const int H = n0.dims[1];
+    FusedArgs A{};
+    A.n_hidden = L - 2;
+    A.n_in = n0.dims[0];
+    A.N_out = n0.dims[L];
+    A.mu_rows = n0.out_mu_rows;
+    A.ldo = ldo;
+    for (int g = 0; g < G; ++g) {
+        const Net& net = *m->nets[nets[g]];
+        FusedNet& F = A.net[g];
+        const Layer& l1 = *net.layers[0];
+        F.W1 = l1.W32.as<float>(); F.b1 = l1.b32.as<float>(); F.be1 = l1.beta32.as<float>(); F.ga1 = l1.gamma32.as<float>();
+        F.shift = net.in_shift.as<double>();
+        F.scale = net.in_scale.as<double>();
+        F.Wf = net.Wf.as<uint16_t>();
+        F.Wfl = net.Wfl.as<uint16_t>();
+        F.vec = net.fvec.as<float>();
+        F.mu = net.out_mu32.as<float>(); F.sigma = net.out_sigma32.as<float>();
+        F.out = static_cast<float*>(outs[g]);
+        F.is_log = is_log[g];
+    }
+    const int rpw = n0.out_mu_rows;
+    const int64_t rows = B * rpw;
+    // launch shape: measured once per (form, rows, outputs, width, networks),
+    // outside stream capture and tracing
+    const int h512 = H == 512;
+    const FusedCfg* cfgs = FUSED_CFGS[h512][x3];
+    const auto key = std::make_tuple(2 + (int)x3 + 2 * h512, rows, A.N_out, H, G);
+    int best = 0;
+    auto it = m->tune.find(key);
+    const char* forced = getenv("NSMI_FUSED_CFG");      // pin one candidate (tests of every shape)
+    if (forced != nullptr) {
+        best = std::min(std::max(atoi(forced), 0), FUSED_NCFG - 1);
+    } else if (it != m->tune.end()) {
+        best = it->second;
+    } else {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        NS_HIP(hipStreamIsCapturing(s, &cs));
+        if (cs == hipStreamCaptureStatusNone && !m->trace && getenv("NSMI_NO_AUTOTUNE") == nullptr) {
+            hipEvent_t e0, e1;
+            NS_HIP(hipEventCreate(&e0));
+            NS_HIP(hipEventCreate(&e1));
+            float best_ms = 1e30f;
+            for (int c = 0; c < FUSED_NCFG; ++c) {
+                cfgs[c].fn(m, A, theta, ld, rows, rpw, G, count, s);
+                NS_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 3; ++r) cfgs[c].fn(m, A, theta, ld, rows, rpw, G, count, s);
+                NS_HIP(hipEventRecord(e1, s));
+                NS_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                NS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) { best_ms = ms; best = c; }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            m->tune[key] = best;
+        }
+    }
+    TraceScope ts(m, s, x3 ? "mlp_fused_bf16x3" : "mlp_fused_bf16");
+    cfgs[best].fn(m, A, theta, ld, rows, rpw, G, count, s);
+    NS_HIP(hipGetLastError());
+    return true;
+}
+
+}  // namespace nsmi

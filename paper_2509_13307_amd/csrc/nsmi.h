@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ns.h"
@@ -92,6 +94,13 @@ struct Net {
     DevBuf out_mu64, out_sigma64;            // double
     DevBuf out_mu32, out_sigma32;            // float
     int out_mu_rows = 1;                     // 1 (CMB) or n_z (shear)
+    // One-kernel BF16 forward (networks that pass fused_shape): BF16 hi / lo
+    // weights of GEMM layers 2..L in MFMA fragment order, one 1 KB block per
+    // (32 units, 16 inputs), layer l (0-based) at element l H^2, output units
+    // zero padded to a multiple of H; fvec holds b, beta, gamma of each hidden
+    // GEMM layer (3H floats each) followed by the output bias.
+    bool fused = false;
+    DevBuf Wf, Wfl, fvec;
     ~Net();
 };
 
@@ -132,8 +141,11 @@ struct ns_model {
     nsmi::DevBuf zsp_idx_d;          // int [n_a]: spline interval of z_j
     nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t))
     nsmi::DevBuf ell_d;              // double [n_ell]
+    nsmi::DevBuf lell_d;             // double [n_ell]: log10(l + 1/2)
     nsmi::DevBuf cov_linv;           // double [n x n] lower-triangular inverse Cholesky factor
     nsmi::DevBuf cov_linvT;          // its transpose (row k holds column k), for the adjoint
+    nsmi::DevBuf cov_linv_frag;      // L^{-1} in FP64-MFMA B-fragment order: [n16/16][n16/4][64],
+                                     // lane q of block (nt, kc) = L^{-1}[16 nt + q % 16][4 kc + q / 16]
     nsmi::DevBuf cov_w;              // double [n]: L^{-1} d
 
     // GAUSS
@@ -152,6 +164,13 @@ struct ns_model {
     nsmi::DevBuf ws_gact[2];         // adjoint activations ping-pong [G x rows x n_pad]
     nsmi::DevBuf ws_gx;              // input gradients [G x rows x n_in]
     void* host_pinned = nullptr;     // pinned host flag for completion polling
+    hipStream_t graph_stream = nullptr;  // stream the captured slice-step graphs replay on
+    hipEvent_t graph_event = nullptr;
+    bool shear_attr_set = false;     // hipFuncSetAttribute done for the Limber kernels
+    bool chi2_attr_set = false;      // ... and for the dense chi^2 kernel (n > 496)
+    unsigned fused_attr_set = 0;     // ... and per instance of the one-kernel emulator
+    // BF16 tile / fused launch-shape choice per (kind, M, N, K, networks), measured at first use
+    std::map<std::tuple<int, int64_t, int, int, int>, int> tune;
 
     // per-kernel tracing: HIP events bracketing each launch on its stream
     bool trace = false;
@@ -186,6 +205,16 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
                       void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
                       hipStream_t s, bool save_t = false);
 
+// Network shapes the one-kernel BF16-operand forward supports: 3..8 layers,
+// <= 16 inputs, every hidden width equal to 128 or 512.
+bool fused_shape(const std::vector<int>& dims);
+// Whole-network forward in one kernel for NS_BF16 / NS_BF16X3 (activations
+// resident in LDS); returns false without launching when the form or the
+// network shape does not fit it.
+bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
+                            void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
+                            hipStream_t s);
+
 // Adjoint of the emulator: from delta_out[g] ([rows x n_pad] FP64 for NS_FP64
 // else FP32; derivative of logL w.r.t. the raw network outputs) back to the
 // per-network, per-row input gradients gx [G x rows x n_in] (w.r.t. the
@@ -218,6 +247,12 @@ void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
 
 void prior_transform(ns_model* m, const double* u, double* theta, int64_t ld, int64_t B,
                      const int* count, hipStream_t s);
+
+// Name of candidate c of the one-kernel forward (width 512 or 128, split form or not).
+const char* fused_cfg_name(int h512, int x3, int c);
+
+// JSON of the BF16 tile configurations the autotuner chose so far.
+std::string bf16_tuning_report(const ns_model* m);
 
 // Slice steps for k walkers with the threshold in device memory (lstar_dev)
 // or given on the host; synchronises s.

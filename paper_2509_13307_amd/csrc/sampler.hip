@@ -476,24 +476,55 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
     const int chunk = 16;
     const int64_t max_rounds = (int64_t)n_inner * (2 * MAX_EXPAND + MAX_SHRINK + 4) + 8;
     int64_t rounds = 0;
-    while (true) {
+    auto rounds_chunk = [&](hipStream_t st) {
         for (int c = 0; c < chunk; ++c) {
             {
-                TraceScope ts(m, s, "slice_advance");
-                hipLaunchKernelGGL(slice_reset_kernel, dim3(1), dim3(64), 0, s, S);
-                hipLaunchKernelGGL(slice_advance_kernel, gw, dim3(256), 0, s, S, k, d, lstar_dev, L, n_inner, seed,
+                TraceScope ts(m, st, "slice_advance");
+                hipLaunchKernelGGL(slice_reset_kernel, dim3(1), dim3(64), 0, st, S);
+                hipLaunchKernelGGL(slice_advance_kernel, gw, dim3(256), 0, st, S, k, d, lstar_dev, L, n_inner, seed,
                                    iter);
             }
-            prior_transform(m, S.xc, thc, d, k, S.ccount, s);
-            loglike_batch(m, thc, d, k, S.llc, prec, S.ccount, s);
+            prior_transform(m, S.xc, thc, d, k, S.ccount, st);
+            loglike_batch(m, thc, d, k, S.llc, prec, S.ccount, st);
         }
         NS_HIP(hipGetLastError());
+    };
+    // First chunk eagerly on the caller's stream (sizes every workspace); the
+    // following chunks replay one captured graph of `chunk` rounds on the
+    // model's own stream, which is ordered after the caller's work.
+    const bool graphs = !m->trace && getenv("NSMI_NO_GRAPH") == nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t run = s;
+    while (true) {
+        if (rounds == 0 || !graphs) {
+            rounds_chunk(run);
+        } else {
+            if (!exec) {
+                if (!m->graph_stream) NS_HIP(hipStreamCreateWithFlags(&m->graph_stream, hipStreamNonBlocking));
+                if (!m->graph_event) NS_HIP(hipEventCreateWithFlags(&m->graph_event, hipEventDisableTiming));
+                NS_HIP(hipEventRecord(m->graph_event, s));
+                NS_HIP(hipStreamWaitEvent(m->graph_stream, m->graph_event, 0));
+                run = m->graph_stream;
+                hipGraph_t graph;
+                NS_HIP(hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
+                rounds_chunk(run);
+                NS_HIP(hipStreamEndCapture(run, &graph));
+                const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                NS_HIP(ie);
+            }
+            NS_HIP(hipGraphLaunch(exec, run));
+        }
         rounds += chunk;
-        NS_HIP(hipMemcpyAsync(flag, S.active, sizeof(int), hipMemcpyDeviceToHost, s));
-        NS_HIP(hipStreamSynchronize(s));
+        NS_HIP(hipMemcpyAsync(flag, S.active, sizeof(int), hipMemcpyDeviceToHost, run));
+        NS_HIP(hipStreamSynchronize(run));
         if (*flag == 0) break;
-        NS_CHECK(rounds < max_rounds, NS_E_INVALID, "slice sampler did not terminate");
+        if (rounds >= max_rounds) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            throw Error{NS_E_INVALID, "slice sampler did not terminate"};
+        }
     }
+    if (exec) NS_HIP(hipGraphExecDestroy(exec));
 }
 
 void slice_step_host_lstar(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,

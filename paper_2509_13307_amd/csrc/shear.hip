@@ -20,7 +20,8 @@
 //                      analytic Jacobian, times (1 + m_i)(1 + m_j).
 //                  (a)-(b) are FP64; (c)-(d) run in the form's type T.
 // dense_chi2_kernel  y = L^{-1} d - L^{-1} C with the host-factorised dense
-//                  covariance, logL = -1/2 |y|^2 - sum log L_ii - n/2 log 2 pi (FP64).
+//                  covariance, logL = -1/2 |y|^2 - sum log L_ii - n/2 log 2 pi
+//                  (FP64; L^{-1} C on the FP64 MFMA).
 #include "devutil.h"
 #include "nsmi.h"
 #include "shear_common.h"
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void limber_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
     const int* __restrict__ pidx, const double* __restrict__ pfix, const double* __restrict__ nz_mean,
     const double* __restrict__ agrid, const int* __restrict__ zidx, const double* __restrict__ zcoef,
-    const double* __restrict__ ell, const T* __restrict__ Ytab, const T* __restrict__ Mtab,
+    const double* __restrict__ lell, const T* __restrict__ Ytab, const T* __restrict__ Mtab,
     double* __restrict__ Cout, const int* __restrict__ count) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (count) B = min<int64_t>(B, *count);
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(256) void limber_kernel(
     double* chis = red + MAXB * 4;                                    // [256]
     T* Wt = reinterpret_cast<T*>(chis + 256);                         // [nb][256]
     T* wq = Wt + nb * 256;                                            // [256]
-    T* Pl = wq + 256;                                                 // [n_ell][256]
+    T* Pl = wq + 256;                                                 // [256][n_ell rounded up to 4]
 
     // physical parameters
     auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
@@ -141,19 +142,25 @@ __global__ __launch_bounds__(256) void limber_kernel(
     const double z = 1.0 / a - 1.0;
     const double q = (t == 0 || t == na - 1) ? 0.5 * G.da : G.da;
     double nraw[MAXB];
-    for (int i = 0; i < nb; ++i) {
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        if (i >= nb) continue;
         const double mu = nz_mean[i] + phys(9 + nb + i);
         const double dz = z - mu;
         nraw[i] = (node && t > 0) ? exp(-dz * dz / (2.0 * G.nz_sigma * G.nz_sigma)) : 0.0;
     }
     {
         const int lane = t & 63, wid = t >> 6;
-        for (int i = 0; i < nb; ++i) {
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            if (i >= nb) continue;
             double v = wave_sum(node ? q * nraw[i] / (a * a) : 0.0);
             if (lane == 0) red[i * 4 + wid] = v;
         }
         __syncthreads();
-        for (int i = 0; i < nb; ++i) nraw[i] /= (red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3]);
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i)
+            if (i < nb) nraw[i] /= (red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3]);
         __syncthreads();
     }
     // reverse cumulative trapezoids G0, G1: segment [t, t+1] stored at node t
@@ -161,27 +168,37 @@ __global__ __launch_bounds__(256) void limber_kernel(
     {
         // integrands at this node and the next one
         double g0[MAXB], g1[MAXB];
-        for (int i = 0; i < nb; ++i) {
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            if (i >= nb) continue;
             g0[i] = node ? nraw[i] / (a * a) : 0.0;
             g1[i] = (node && t > 0) ? nraw[i] / (a * a * chi) : 0.0;
         }
         // exchange with the neighbour through LDS
-        for (int i = 0; i < nb; ++i) {
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            if (i >= nb) continue;
             scan[i * 256 + t] = g0[i];
             scan[(MAXB + i) * 256 + t] = g1[i];
         }
         __syncthreads();
-        for (int i = 0; i < nb; ++i) {
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            if (i >= nb) continue;
             const bool has = node && t < na - 1;
             seg[i] = has ? 0.5 * G.da * (g0[i] + scan[i * 256 + t + 1]) : 0.0;
             seg[MAXB + i] = has ? 0.5 * G.da * (g1[i] + scan[(MAXB + i) * 256 + t + 1]) : 0.0;
         }
-        for (int i = nb; i < MAXB; ++i) seg[i] = seg[MAXB + i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i)
+            if (i >= nb) seg[i] = seg[MAXB + i] = 0.0;
         __syncthreads();
     }
     block_scan<2 * MAXB>(seg, scan, true);   // seg[i] = sum_{m >= t} segment_m
     const double pref = 1.5 * Om * H0c * H0c * chi / a;
-    for (int i = 0; i < nb; ++i) {
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        if (i >= nb) continue;
         const double Wg = pref * (seg[i] - chi * seg[MAXB + i]);
         const double AIA = phys(9 + i);
         const double WI = -AIA * C1_RHOCR * Om * nraw[i] * H0c * Ea / D;
@@ -190,92 +207,174 @@ __global__ __launch_bounds__(256) void limber_kernel(
     wq[t] = (node && t > 0) ? (T)(q * fa / (chi * chi)) : T(0);
     __syncthreads();
 
-    // (c) P at the Limber wavenumbers: ell-major [n_ell][256]
-    const T* Yw = Ytab + w * (int64_t)G.n_z * G.n_k;
-    const T* Mw = Mtab + w * (int64_t)G.n_z * G.n_k;
-    for (int e = t; e < G.n_ell * 256; e += 256) {
-        const int b = e >> 8, j = e & 255;
-        T P = T(0);
-        if (j > 0 && j < na) {
-            const double cj = chis[j];
-            const double k = (ell[b] + 0.5) / cj;
-            if (k >= G.k_min && k <= G.k_max) {
-                const double s = (log10(k) - G.u0) / G.du;
-                int i0 = (int)floor(s);
+    // (c) P at the Limber wavenumbers, one thread per node j, node-major
+    // [256][nl4] (ell contiguous); log10 k = log10(l + 1/2) - log10 chi_j
+    const int nl4 = (G.n_ell + 3) & ~3;
+    {
+        const bool live = t > 0 && t < na;
+        const double lchi = live ? log10(chi) : 0.0;
+        const T wqj = wq[t];
+        const int n = live ? zidx[t] : 0;
+        const int zc = live ? 4 * t : 0;                   // z-spline coefficients exist for nodes < n_a
+        const T c0 = (T)zcoef[zc], c1 = (T)zcoef[zc + 1], c2 = (T)zcoef[zc + 2], c3 = (T)zcoef[zc + 3];
+        const T* y0 = Ytab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
+        const T* m0p = Mtab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
+        auto Yz = [&](int col) {
+            return c0 * y0[col] + c1 * y0[col + G.n_k] + c2 * m0p[col] + c3 * m0p[col + G.n_k];
+        };
+#pragma unroll 4
+        for (int b = 0; b < nl4; ++b) {
+            T P = T(0);
+            const double lk = b < G.n_ell ? lell[b] - lchi : 0.0;
+            if (live && b < G.n_ell && lk >= G.u0 && lk <= G.u1) {
+                const double sv = (lk - G.u0) / G.du;
+                int i0 = (int)floor(sv);
                 i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
-                const T tt = (T)(s - i0);
-                const int n = zidx[j];
-                const T c0 = (T)zcoef[4 * j], c1 = (T)zcoef[4 * j + 1], c2 = (T)zcoef[4 * j + 2], c3 = (T)zcoef[4 * j + 3];
-                auto Yz = [&](int col) {
-                    const int64_t o0 = (int64_t)n * G.n_k + col, o1 = o0 + G.n_k;
-                    return c0 * Yw[o0] + c1 * Yw[o1] + c2 * Mw[o0] + c3 * Mw[o1];
-                };
+                const T tt = (T)(sv - i0);
                 const T p0 = Yz(i0), p1 = Yz(i0 + 1);
                 const T pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
                 const T p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
-                const T m0 = T(0.5) * (p1 - pm), m1 = T(0.5) * (p2 - p0);
+                const T mk0 = T(0.5) * (p1 - pm), mk1 = T(0.5) * (p2 - p0);
                 const T t2 = tt * tt, t3 = t2 * tt;
-                const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * m0 +
-                             (T(-2) * t3 + T(3) * t2) * p1 + (t3 - t2) * m1;
-                P = exp(lp * T(LN10)) * wq[j];
+                const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * mk0 +
+                             (T(-2) * t3 + T(3) * t2) * p1 + (t3 - t2) * mk1;
+                P = exp10_of<T>(lp) * wqj;
             }
+            Pl[t * nl4 + b] = P;
         }
-        Pl[e] = P;
     }
     __syncthreads();
 
-    // (d) Limber sums, one thread per (pair, ell); pairs (i <= j) lexicographic
+    // (d) Limber sums.  Item = (pair p, group of 4 ell bins); the node range is
+    // split into nseg segments whose partial sums are added in a fixed order.
+    const int ng = nl4 / 4, nitem = G.n_pairs * ng;
+    const int nseg = nitem >= 256 ? 1 : 256 / nitem;
+    const int len = (na + nseg - 1) / nseg;
     const int nout = G.n_pairs * G.n_ell;
-    for (int o = t; o < nout; o += 256) {
-        const int p = o / G.n_ell, b = o % G.n_ell;
-        int bi = 0, rem = p;
+    T* part = reinterpret_cast<T*>(scan);               // [nseg][nitem][4]; the scan buffer is free here
+    auto pair_of = [&](int p, int& bi, int& bj) {
+        int rem = p;
+        bi = 0;
         while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
-        const int bj = bi + rem;
+        bj = bi + rem;
+    };
+    auto store = [&](int item, const T (&v)[4]) {
+        const int p = item / ng, gq = item % ng;
+        int bi, bj;
+        pair_of(p, bi, bj);
+        const double mi = phys(9 + 2 * nb + bi), mj = phys(9 + 2 * nb + bj);
+        for (int e = 0; e < 4; ++e) {
+            const int b = 4 * gq + e;
+            if (b < G.n_ell) Cout[w * nout + p * G.n_ell + b] = (1.0 + mi) * (1.0 + mj) * (double)v[e];
+        }
+    };
+    for (int it = t; it < nitem * nseg; it += 256) {
+        const int item = it % nitem, sg = it / nitem;
+        const int p = item / ng, gq = item % ng;
+        int bi, bj;
+        pair_of(p, bi, bj);
         const T* Wi = Wt + bi * 256;
         const T* Wj = Wt + bj * 256;
-        const T* Pb = Pl + b * 256;
-        T s = T(0);
-        for (int j = 1; j < na; ++j) s += Wi[j] * Wj[j] * Pb[j];
-        const double mi = phys(9 + 2 * nb + bi), mj = phys(9 + 2 * nb + bj);
-        Cout[w * nout + o] = (1.0 + mi) * (1.0 + mj) * (double)s;
+        T acc[4] = {T(0), T(0), T(0), T(0)};
+        const int j0 = max(1, sg * len), j1 = min(na, (sg + 1) * len);
+        for (int j = j0; j < j1; ++j) {
+            const T A = Wi[j] * Wj[j];
+            const T* Pj = Pl + j * nl4 + 4 * gq;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] += A * Pj[e];
+        }
+        if (nseg == 1) {
+            store(item, acc);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) part[(sg * nitem + item) * 4 + e] = acc[e];
+        }
+    }
+    if (nseg > 1) {
+        __syncthreads();
+        for (int item = t; item < nitem; item += 256) {
+            T v[4] = {T(0), T(0), T(0), T(0)};
+            for (int sg = 0; sg < nseg; ++sg)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] += part[(sg * nitem + item) * 4 + e];
+            store(item, v);
+        }
     }
 }
 
 // ---------------------------------------------------------------- dense chi^2
-// 16 walkers per block; y_i = wv_i - sum_{k <= i} Linv[i][k] C[k] in FP64.
-constexpr int DC_W = 16;
+// Y = C L^{-T} for a block of 16 walkers on v_mfma_f64_16x16x4f64, then
+// chi^2_b = sum_n (w_n - Y_bn)^2 with w = L^{-1} d.  The block's spectra sit
+// in LDS (A operand); L^{-1} is read in fragment order (one coalesced 512-byte
+// load per wave and MFMA), and the K steps above the diagonal, where L^{-1}
+// vanishes, are skipped.  Wave w owns column tiles w, w + 4, ... (DM_CT per
+// pass); row sums are reduced in a fixed order (deterministic).
+constexpr int DM_W = 16;      // walkers per workgroup
+constexpr int DM_CT = 5;      // column tiles per wave per pass
 __global__ __launch_bounds__(256) void dense_chi2_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
     const double* __restrict__ pa, const double* __restrict__ pb, const double* __restrict__ C, int n,
-    const double* __restrict__ Linv, const double* __restrict__ wv, double cst, double* __restrict__ logl,
+    const double* __restrict__ Lf, const double* __restrict__ wv, double cst, double* __restrict__ logl,
     const int* __restrict__ count) {
-    extern __shared__ double Cs[];                 // [DC_W][n]
-    __shared__ double red[DC_W][16];
+    extern __shared__ double Cs[];                 // [DM_W][n16 + 2]
+    __shared__ double red[4][DM_W];
     if (count) B = min<int64_t>(B, *count);
-    const int64_t w0 = (int64_t)blockIdx.x * DC_W;
+    const int64_t w0 = (int64_t)blockIdx.x * DM_W;
     if (w0 >= B) return;
-    for (int e = threadIdx.x; e < DC_W * n; e += 256) {
-        const int64_t w = w0 + e / n;
-        Cs[e] = w < B ? C[w * n + e % n] : 0.0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n16 = (n + 15) & ~15, cs = n16 + 2;
+    const int nt_all = n16 / 16, kc_all = n16 / 4;
+    for (int e = tid; e < DM_W * n16; e += 256) {
+        const int r = e / n16, k = e % n16;
+        const int64_t w = w0 + r;
+        Cs[r * cs + k] = (w < B && k < n) ? C[w * n + k] : 0.0;
     }
     __syncthreads();
-    const int wk = threadIdx.x % DC_W, part = threadIdx.x / DC_W;
-    double s = 0.0;
-    const double* cw = Cs + wk * n;
-    for (int i = part; i < n; i += 256 / DC_W) {
-        const double* Li = Linv + (int64_t)i * n;
-        double acc = 0.0;
-        for (int k = 0; k <= i; ++k) acc = fma(Li[k], cw[k], acc);
-        const double y = wv[i] - acc;
-        s = fma(y, y, s);
+    double srow[4] = {0.0, 0.0, 0.0, 0.0};          // rows (lane >> 4) + 4 r
+    for (int t0 = wave; t0 < nt_all; t0 += 4 * DM_CT) {
+        f64x4_t acc[DM_CT];
+#pragma unroll
+        for (int j = 0; j < DM_CT; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
+        const int jmax = min(DM_CT - 1, (nt_all - 1 - t0) / 4);
+        const int kmax = min(4 * (t0 + 4 * jmax) + 4, kc_all);
+#pragma unroll 2
+        for (int kc = 0; kc < kmax; ++kc) {
+            const double a = Cs[(lane & 15) * cs + 4 * kc + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < DM_CT; ++j) {
+                const int nt = t0 + 4 * j;
+                if (j <= jmax && kc < 4 * nt + 4) {
+                    const double b = Lf[((size_t)nt * kc_all + kc) * 64 + lane];
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < DM_CT; ++j) {
+            const int col = 16 * (t0 + 4 * j) + (lane & 15);
+            if (j > jmax || col >= n) continue;
+            const double wn = wv[col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double e = wn - acc[j][r];
+                srow[r] = fma(e, e, srow[r]);
+            }
+        }
     }
-    red[wk][part] = s;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) srow[r] += __shfl_xor(srow[r], o, 64);
+    if ((lane & 15) == 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave][(lane >> 4) + 4 * r] = srow[r];
     __syncthreads();
-    if (threadIdx.x < DC_W) {
-        const int64_t w = w0 + threadIdx.x;
+    if (tid < DM_W) {
+        const int64_t w = w0 + tid;
         if (w < B) {
-            double chi2 = 0.0;
-            for (int p = 0; p < 256 / DC_W; ++p) chi2 += red[threadIdx.x][p];
+            const double chi2 = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
             bool ok = true;
             const double* th = theta + w * ld;
             for (int i = 0; i < d; ++i)
@@ -292,11 +391,13 @@ ShearGeom shear_geom(const ns_model* m) {
     G.a_min = m->a_min; G.da = (1.0 - m->a_min) / (m->n_a - 1); G.zmax = 1.0 / m->a_min - 1.0;
     G.k_min = m->k_min; G.k_max = m->k_max; G.u0 = log10(m->k_min);
     G.du = (log10(m->k_max) - log10(m->k_min)) / (m->n_k - 1); G.nz_sigma = m->nz_sigma;
+    G.u1 = log10(m->k_max);
     return G;
 }
 
 static size_t limber_smem(const ns_model* m, size_t elem) {
-    return (2 * MAXB * 256 + MAXB * 4 + 256) * sizeof(double) + (size_t)(m->n_bins + 1 + m->n_ell) * 256 * elem;
+    return (2 * MAXB * 256 + MAXB * 4 + 256) * sizeof(double) +
+           (size_t)(m->n_bins + 1 + ((m->n_ell + 3) & ~3)) * 256 * elem;
 }
 
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
@@ -326,31 +427,37 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     const ShearGeom G = shear_geom(m);
     const size_t sm = limber_smem(m, elem);
     NS_CHECK(sm <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
-    if (prec == NS_FP64)
-        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<double>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
-    else
-        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<float>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
+    if (!m->shear_attr_set) {   // once per model, outside any stream capture
+        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+        m->shear_attr_set = true;
+    }
     {
     TraceScope ts(m, s, "limber");
     if (prec == NS_FP64)
         hipLaunchKernelGGL(limber_kernel<double>, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
                            m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
                            m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                           m->ell_d.as<double>(), m->ws_out.as<double>(), (const double*)Mtab, Cv, count);
+                           m->lell_d.as<double>(), m->ws_out.as<double>(), (const double*)Mtab, Cv, count);
     else
         hipLaunchKernelGGL(limber_kernel<float>, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
                            m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
                            m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                           m->ell_d.as<double>(), m->ws_out.as<float>(), (const float*)Mtab, Cv, count);
+                           m->lell_d.as<double>(), m->ws_out.as<float>(), (const float*)Mtab, Cv, count);
     NS_HIP(hipGetLastError());
     }
-    const size_t sm2 = (size_t)DC_W * n * sizeof(double);
+    const size_t sm2 = (size_t)DM_W * (((n + 15) & ~15) + 2) * sizeof(double);
+    if (sm2 > 64 * 1024 && !m->chi2_attr_set) {
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)sm2));
+        m->chi2_attr_set = true;
+    }
     TraceScope ts(m, s, "dense_chi2");
-    hipLaunchKernelGGL(dense_chi2_kernel, dim3((unsigned)((B + DC_W - 1) / DC_W)), dim3(256), sm2, s, theta, ld, B,
+    hipLaunchKernelGGL(dense_chi2_kernel, dim3((unsigned)((B + DM_W - 1) / DM_W)), dim3(256), sm2, s, theta, ld, B,
                        m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), Cv, n,
-                       m->cov_linv.as<double>(), m->cov_w.as<double>(), m->logl_const, logl, count);
+                       m->cov_linv_frag.as<double>(), m->cov_w.as<double>(), m->logl_const, logl, count);
     NS_HIP(hipGetLastError());
 }
 

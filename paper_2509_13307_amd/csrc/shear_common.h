@@ -16,30 +16,38 @@ constexpr int MAXB = 10;                              // tomographic bins suppor
 struct ShearGeom {
     int n_a, n_z, n_k, n_ell, n_bins, n_pairs;
     double a_min, da, zmax, k_min, k_max, u0, du, nz_sigma;
+    double u1;        // log10 k_max
 };
 
 ShearGeom shear_geom(const ns_model* m);
 
 // Inclusive prefix sum over the block (blockDim = 256) of NV per-thread values;
-// reverse = true sums from the last thread down.  buf holds NV x 256 doubles.
+// reverse = true sums from the last thread down.  Each wave scans with
+// shuffles, then adds the totals of the waves before it (buf: NV x 4 doubles).
 template <int NV>
 __device__ void block_scan(double (&v)[NV], double* buf, bool reverse) {
-    const int t = threadIdx.x;
-    const int src = reverse ? 255 - t : t;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) buf[q * 256 + src] = v[q];
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        double add[NV];
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) add[q] = src >= off ? buf[q * 256 + src - off] : 0.0;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NV; ++q) buf[q * 256 + src] += add[q];
-        __syncthreads();
+        for (int off = 1; off < 64; off <<= 1) {
+            const double y = reverse ? __shfl_down(x, off, 64) : __shfl_up(x, off, 64);
+            if (reverse ? lane + off < 64 : lane >= off) x += y;
+        }
+        v[q] = x;
     }
+    if (lane == (reverse ? 0 : 63))
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = buf[q * 256 + src];
+        for (int q = 0; q < NV; ++q) buf[q * 4 + wid] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double pre = 0.0;
+        for (int k = 0; k < 4; ++k)
+            if (reverse ? k > wid : k < wid) pre += buf[q * 4 + k];
+        v[q] += pre;
+    }
     __syncthreads();
 }
 

@@ -190,6 +190,13 @@ class Model:
         C.check(C.lib().ns_trace_report(self._h, buf, len(buf)))
         return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
+    def tuning_report(self):
+        """{layer shape: tile configuration} chosen by the BF16 autotuner."""
+        import json
+        buf = ctypes.create_string_buffer(1 << 14)
+        C.check(C.lib().ns_tuning_report(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
     def close(self):
         if getattr(self, "_h", None):
             C.check(C.lib().ns_model_free(self._h))

@@ -151,3 +151,33 @@ def test_reduced_precision_forms(built, name, prec):
     d = np.abs(got[fin] - ref[fin])
     say(f"{name} {prec}: |dlogL| max {d.max():.3e} median {np.median(d):.3e} over {fin.sum()} walkers")
     assert d.max() <= LOWP_LIMIT[(name, prec)]
+
+
+@pytest.mark.parametrize("name,B", [("cmb6", 300), ("cmb4x2500", 333), ("shear10", 70), ("shear64", 9)])
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
+    """The one-kernel emulator gives bitwise the layer-by-layer result, with
+    the autotuned launch shape and with each candidate shape pinned."""
+    say(f"case fused {prec} {name}")
+    from paper_2509_13307_amd import Model
+    m = W.load_model(name)
+    th = torch.tensor(W.prior_draws(m, B, tag=5), device=DEV)
+
+    def run(env):
+        for k in ("NSMI_NO_FUSED_MLP", "NSMI_FUSED_CFG"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g = Model(m)
+        out = g.loglike(th, prec).cpu().numpy()
+        report = g.tuning_report()
+        g.close()
+        return out, report
+
+    ref, _ = run({"NSMI_NO_FUSED_MLP": "1"})
+    got, report = run({})
+    say(f"{name} {prec}: tuned {report}")
+    np.testing.assert_array_equal(got, ref)
+    for c in range(4):
+        got, _ = run({"NSMI_FUSED_CFG": str(c)})
+        np.testing.assert_array_equal(got, ref)

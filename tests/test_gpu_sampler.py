@@ -95,3 +95,55 @@ def test_ns_run_replays_oracle_cmb6():
     assert res["n_iter"] == ref["n_iter"]
     assert res["n_evals"] == ref["n_evals"]
     assert abs(res["logz"] - ref["logZ"]) < 1e-6
+
+
+def test_graph_replay_and_autotune_do_not_change_results(monkeypatch):
+    """Captured-graph slice rounds and tuned BF16 tiles give bitwise the eager results."""
+    say("case graph/autotune invariance")
+    m = W.load_model("cmb6")
+    u_all, _, lstar, u0, l0 = walkers_above(m, 100, seed=5)
+    L = torch.tensor(nested.direction_cholesky(u_all))
+    outs = []
+    # layer-by-layer emulator, so that the tuned GEMM tiles are the ones exercised
+    monkeypatch.setenv("NSMI_NO_FUSED_MLP", "1")
+    for env in ({}, {"NSMI_NO_GRAPH": "1", "NSMI_NO_AUTOTUNE": "1"}):
+        for k in ("NSMI_NO_GRAPH", "NSMI_NO_AUTOTUNE"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g = mk(m)
+        ut = torch.tensor(u0, device=DEV).contiguous()
+        lt = torch.tensor(l0, device=DEV)
+        ne, ns = g.slice_step(ut, lt, lstar, L, 8, seed=5, it=2, precision="bf16")
+        th = torch.tensor(W.prior_draws(m, 300, tag=3), device=DEV)
+        ll = g.loglike(th, "bf16")
+        outs.append((ut.cpu().numpy(), lt.cpu().numpy(), ne.cpu().numpy(), ll.cpu().numpy()))
+        g.close()
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,n", [("cmb6", 100), ("shear10", 40)])
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_fused_emulator_slice_step_matches_layer_by_layer(monkeypatch, name, n, prec):
+    """Ragged slice rounds (device row count, compacted walkers) through the
+    one-kernel emulator give bitwise the layer-by-layer results."""
+    say(f"case fused slice step {name} {prec}")
+    m = W.load_model(name)
+    u_all, _, lstar, u0, l0 = walkers_above(m, n, seed=6)
+    L = torch.tensor(nested.direction_cholesky(u_all))
+    outs = []
+    for fused in (True, False):
+        if fused:
+            monkeypatch.delenv("NSMI_NO_FUSED_MLP", raising=False)
+        else:
+            monkeypatch.setenv("NSMI_NO_FUSED_MLP", "1")
+        g = mk(m)
+        ut = torch.tensor(u0, device=DEV).contiguous()
+        lt = torch.tensor(l0, device=DEV)
+        ne, ns = g.slice_step(ut, lt, lstar, L, 3, seed=6, it=4, precision=prec)
+        outs.append((ut.cpu().numpy(), lt.cpu().numpy(), ne.cpu().numpy(), ns.cpu().numpy()))
+        g.close()
+    say(f"{name} {prec}: evals {outs[0][2].sum()} (min {outs[0][2].min()}, max {outs[0][2].max()})")
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)

@@ -267,15 +267,22 @@ def structure(name: str):
         return shear_structure(n_z=10)
     if name == "shear10_lcdm":
         return shear_structure(n_z=10, lcdm=True)
+    if name == "shear_cmp_w0wa":
+        return shear_structure(n_z=10)
+    if name == "shear_cmp_lcdm":
+        return shear_structure(n_z=10, lcdm=True)
     raise KeyError(name)
 
 
 def load_model(name: str):
     """Structure plus the stored synthetic data vector and covariance."""
     m = structure(name)
-    path = os.path.join(GOLDEN, f"workload_{name}.npz")
+    data_name = "shear_cmp" if name.startswith("shear_cmp") else name
+    path = os.path.join(GOLDEN, f"workload_{data_name}.npz")
     with np.load(path, allow_pickle=False) as z:
         for key in z.files:
+            if name == "shear_cmp_lcdm" and key in ("theta_fid", "fisher_sigma"):
+                continue       # stored for the 39-parameter model; LCDM keeps its own
             m[key] = z[key]
     return m
 
