@@ -33,6 +33,28 @@ def mlp_flops(net, rows):
     return sum(2.0 * rows * W.shape[0] * W.shape[1] for W in net["W"])
 
 
+KERNEL_SOURCES = {"mlp_fused": ("paper_2509_13307_amd/csrc/mlp_fused.hip", "paper_2509_13307_amd/csrc/devutil.h")}
+
+
+def measured_traffic(dom, B):
+    """HBM bytes per launch of kernel `dom` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the plain-copy calibration; None
+    when no summary exists or the kernel sources changed since it was taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"{dom}_hbm_bytes.json")
+    key = next((k for k in KERNEL_SOURCES if dom.startswith(k)), None)
+    if key is None or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[key]:
+        h.update(open(os.path.join(here, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest() or rec.get("batch") != B:
+        return None
+    return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
+
+
 def roofline_of(dom, avg_s, prec, m, B):
     """Roofline entry of kernel `dom` from its average launch time: algorithmic
     work of one launch over the form's published MI355X peak."""
@@ -61,8 +83,9 @@ def roofline_of(dom, avg_s, prec, m, B):
     else:
         achieved = work / avg_s / 1e9
         peak = HBM_PEAK_GBS
+    traffic = measured_traffic(dom, B)
     r = dict(kernel=dom, bound=bound, achieved=round(achieved, 2), peak=peak, unit=unit,
-             frac=round(achieved / peak, 4), traffic=None, avg_launch_us=round(avg_s * 1e6, 2),
+             frac=round(achieved / peak, 4), traffic=traffic, avg_launch_us=round(avg_s * 1e6, 2),
              work_per_launch=work)
     if issued is not None:
         r["mfma_issued_frac"] = round(issued / avg_s / 1e12 / peak, 4)
@@ -88,8 +111,8 @@ def main():
     ap.add_argument("--mc-live", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the walker-parallel "
-              "path shards without communication, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); runs on several GPUs "
+              "are not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -156,11 +156,13 @@ static Net* build_net(const ns_net_desc& nd, int mu_rows) {
             upload(ly->Whi, hi.data(), nw);
             upload(ly->Wlo, lo.data(), nw);
             if (net->fused && l >= 1) {
-                // fragment order: block (nt, kc) of 64 lanes x 8 inputs; lane q holds
-                // unit 32 nt + q % 32, inputs 16 kc + 8 (q / 32) + i
+                // fragment order: block (kc, nt) of 64 lanes x 8 inputs at
+                // (kc n_cols / 32 + nt) 512; lane q holds unit 32 nt + q % 32,
+                // inputs 16 kc + 8 (q / 32) + i
                 const int KC = K / 16;
                 const size_t base = (size_t)(l - 1) * H * H;
                 const int n_cols = ly->hidden ? H : (int)fcols;
+                const int ntl = n_cols / 32;
                 for (int nt = 0; nt < n_cols / 32; ++nt)
                     for (int kc = 0; kc < KC; ++kc)
                         for (int q = 0; q < 64; ++q) {
@@ -168,7 +170,7 @@ static Net* build_net(const ns_net_desc& nd, int mu_rows) {
                             if (n >= N) continue;
                             for (int i = 0; i < 8; ++i) {
                                 const size_t src = (size_t)n * K + kc * 16 + 8 * (q / 32) + i;
-                                const size_t dst = base + (((size_t)nt * KC + kc) * 64 + q) * 8 + i;
+                                const size_t dst = base + (((size_t)kc * ntl + nt) * 64 + q) * 8 + i;
                                 fh[dst] = hi[src];
                                 fl[dst] = lo[src];
                             }

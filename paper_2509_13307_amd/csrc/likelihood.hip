@@ -24,13 +24,13 @@ template <class T>
 __global__ __launch_bounds__(256) void chi2_diag_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
     const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ mvec, int n,
-    const double* __restrict__ data, const double* __restrict__ isig, double cst,
+    int64_t ldm, const double* __restrict__ data, const double* __restrict__ isig, double cst,
     double* __restrict__ logl, const int* __restrict__ count) {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (count) B = min<int64_t>(B, *count);
     if (row >= B) return;
-    const T* mv = mvec + row * n;
+    const T* mv = mvec + row * ldm;
     double s = 0.0;
     for (int i = lane; i < n; i += 64) {
         double r = (data[i] - (double)mv[i]) * isig[i];
@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void chi2_diag_kernel(
 }
 
 // ------------------------------------------------- 3x3 block + diagonal chi^2
-// Model vector spectrum-major [TT | TE | EE | PP] (n_ell each).  Per multipole
+// Model vector spectrum-major [TT | TE | EE | PP], spectrum k at column k sp
+// (sp >= n_ell, padded for aligned rows).  Per multipole
 // the residual (TT, TE, EE) is whitened with the precomputed inverse Cholesky
 // factor (lower, 6 entries); PP is whitened by 1/sigma_pp.  A block of 256
 // threads handles ROWS walkers so the per-multipole constants are read once.
@@ -52,14 +53,14 @@ template <class T, int ROWS>
 __global__ __launch_bounds__(256) void chi2_block_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
     const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ mvec,
-    int n_ell, const double* __restrict__ data, const double* __restrict__ linv,
+    int n_ell, int sp, const double* __restrict__ data, const double* __restrict__ linv,
     const double* __restrict__ isig_pp, double cst, double* __restrict__ logl,
     const int* __restrict__ count) {
     __shared__ double red[ROWS][4];
     if (count) B = min<int64_t>(B, *count);
     const int64_t r0 = (int64_t)blockIdx.x * ROWS;
     if (r0 >= B) return;
-    const int64_t n = 4 * (int64_t)n_ell;
+    const int64_t n = 4 * (int64_t)sp;
     double s[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) s[r] = 0.0;
@@ -73,8 +74,8 @@ __global__ __launch_bounds__(256) void chi2_block_kernel(
             const int64_t row = r0 + r;
             if (row >= B) break;
             const T* mv = mvec + row * n;
-            const double rtt = dtt - (double)mv[l], rte = dte - (double)mv[n_ell + l];
-            const double ree = dee - (double)mv[2 * n_ell + l], rpp = (dpp - (double)mv[3 * n_ell + l]) * ip;
+            const double rtt = dtt - (double)mv[l], rte = dte - (double)mv[sp + l];
+            const double ree = dee - (double)mv[2 * sp + l], rpp = (dpp - (double)mv[3 * sp + l]) * ip;
             const double y0 = l00 * rtt;
             const double y1 = l10 * rtt + l11 * rte;
             const double y2 = l20 * rtt + l21 * rte + l22 * ree;
@@ -151,6 +152,12 @@ void gauss_loglike(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
     NS_HIP(hipGetLastError());
 }
 
+int64_t cmb_spec_stride(const ns_model* m) {
+    const int64_t n = m->kind == NS_MODEL_CMB_BLOCK ? m->n_ell_cmb : m->n_data;
+    return (n + 31) / 32 * 32;
+}
+int64_t cmb_row_stride(const ns_model* m) { return (int64_t)m->nets.size() * cmb_spec_stride(m); }
+
 void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const void* mvec, double* logl,
               int prec, const int* count, hipStream_t s) {
     const int* pk = m->prior_kind.as<int>();
@@ -161,23 +168,23 @@ void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const voi
         dim3 g((unsigned)((B + 3) / 4));
         if (prec == NS_FP64)
             hipLaunchKernelGGL(chi2_diag_kernel<double>, g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
-                               (const double*)mvec, m->n_data, m->data.as<double>(), m->inv_sigma.as<double>(),
-                               m->logl_const, logl, count);
+                               (const double*)mvec, m->n_data, cmb_row_stride(m), m->data.as<double>(),
+                               m->inv_sigma.as<double>(), m->logl_const, logl, count);
         else
             hipLaunchKernelGGL(chi2_diag_kernel<float>, g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
-                               (const float*)mvec, m->n_data, m->data.as<double>(), m->inv_sigma.as<double>(),
-                               m->logl_const, logl, count);
+                               (const float*)mvec, m->n_data, cmb_row_stride(m), m->data.as<double>(),
+                               m->inv_sigma.as<double>(), m->logl_const, logl, count);
     } else {
         constexpr int R = 8;
         dim3 g((unsigned)((B + R - 1) / R));
         if (prec == NS_FP64)
             hipLaunchKernelGGL((chi2_block_kernel<double, R>), g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
-                               (const double*)mvec, m->n_ell_cmb, m->data.as<double>(), m->blk_linv.as<double>(),
-                               m->inv_sigma_pp.as<double>(), m->logl_const, logl, count);
+                               (const double*)mvec, m->n_ell_cmb, cmb_spec_stride(m), m->data.as<double>(),
+                               m->blk_linv.as<double>(), m->inv_sigma_pp.as<double>(), m->logl_const, logl, count);
         else
             hipLaunchKernelGGL((chi2_block_kernel<float, R>), g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
-                               (const float*)mvec, m->n_ell_cmb, m->data.as<double>(), m->blk_linv.as<double>(),
-                               m->inv_sigma_pp.as<double>(), m->logl_const, logl, count);
+                               (const float*)mvec, m->n_ell_cmb, cmb_spec_stride(m), m->data.as<double>(),
+                               m->blk_linv.as<double>(), m->inv_sigma_pp.as<double>(), m->logl_const, logl, count);
     }
     NS_HIP(hipGetLastError());
 }
@@ -191,16 +198,16 @@ void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
     }
     const size_t elem = prec == NS_FP64 ? 8 : 4;
     if (m->kind == NS_MODEL_CMB_DIAG || m->kind == NS_MODEL_CMB_BLOCK) {
-        const int64_t n = m->n_data;
+        // spectrum g at column g sp of rows of cmb_row_stride: 128-byte aligned
+        // output lines for the emulator's stores
+        const int64_t n = cmb_row_stride(m), sp = cmb_spec_stride(m);
         m->ws_out.ensure((size_t)B * n * elem);
-        int64_t off = 0;
         int ids[4];
         void* outs[4];
         const int G = (int)m->nets.size();
         for (int g = 0; g < G; ++g) {
             ids[g] = g;
-            outs[g] = m->ws_out.as<char>() + off * elem;
-            off += m->nets[g]->dims.back();
+            outs[g] = m->ws_out.as<char>() + g * sp * elem;
         }
         emulator_forward(m, ids, G, theta, ld, B, outs, n, m->spec_log.data(), prec, count, s);
         cmb_chi2(m, theta, ld, B, m->ws_out.p, logl, prec, count, s);

@@ -6,7 +6,9 @@
 // the first layer to the output layer.  Weights are never staged: each GEMM
 // layer's weights are stored at model creation in MFMA fragment order (one
 // 1 KB block per 32 output units x 16 inputs, lane l holding the 8 inputs
-// 8 (l / 32) .. + 7 of unit l % 32), so a wave fetches the B operand of one
+// 8 (l / 32) .. + 7 of unit l % 32; the blocks of one K step of a layer are
+// contiguous, so the waves of all workgroups, which reach a K step together,
+// spread their requests over the L2 channels), so a wave fetches the B operand of one
 // v_mfma_f32_32x32x16_bf16 with a single coalesced 16-byte-per-lane load
 // straight into registers, P K-steps ahead of its use.  No weight element is
 // used by two waves of a workgroup, so LDS staging would bring no reuse.
@@ -64,6 +66,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     constexpr int HS = H + 8;              // LDS row stride of an activation plane (elements)
     constexpr int KC = H / 16;             // K steps of one GEMM layer
     static_assert(KC % P == 0, "prefetch depth must divide the K steps");
+    static_assert(NT % H == 0, "threads must be a multiple of the hidden width");
     extern __shared__ __attribute__((aligned(16))) uint16_t fm_lds[];
     uint16_t* hs = fm_lds;                 // [R][HS] hi (or only) plane
     uint16_t* hl = fm_lds + R * HS;        // [R][HS] lo plane (split form)
@@ -104,14 +107,24 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         xs[rr][k] = v;
     }
     __syncthreads();
-    for (int e = tid; e < R * H; e += NT) {
-        const int rr = e / H, c = e % H;
-        float acc = N.b1[c];
-        for (int k = 0; k < n_in; ++k) acc += N.W1[c * n_in + k] * xs[rr][k];
-        const float v = gated<float>(acc, N.be1[c], N.ga1[c]);
-        const uint16_t hi = f2bf(v);
-        hs[rr * HS + c] = hi;
-        if (X3) hl[rr * HS + c] = bf16_lo(v, hi);
+    {
+        // NT is a multiple of H: each thread keeps one unit c (weights in
+        // registers) for rows tid / H, tid / H + NT / H, ...
+        const int c = tid % H;
+        float w1[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) w1[k] = k < n_in ? N.W1[c * n_in + k] : 0.0f;
+        const float b1 = N.b1[c], be1 = N.be1[c], ga1 = N.ga1[c];
+        for (int rr = tid / H; rr < R; rr += NT / H) {
+            float acc = b1;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < n_in) acc += w1[k] * xs[rr][k];
+            const float v = gated<float>(acc, be1, ga1);
+            const uint16_t hi = f2bf(v);
+            hs[rr * HS + c] = hi;
+            if (X3) hl[rr * HS + c] = bf16_lo(v, hi);
+        }
     }
     __syncthreads();
 
@@ -122,22 +135,25 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     // nothing), so the weight prefetch stays in flight across iterations.
     const int ncb = (N_out + H - 1) / H;
     const int S = (n_hidden + ncb) * KC;
-    constexpr int TILE = KC * 64 * 8;                  // elements of one 32-unit column tile of a layer
+    // fragment block (kc, nt) of a layer with nt_l 32-unit tiles sits at
+    // (kc nt_l + nt) 512 elements: one K step of a layer is contiguous
+    const int nt_out = ncb * H / 32;
     auto frag = [&](int s) -> size_t {
         s = min(s, S - 1);
         const int seg = s / KC, kc = s - seg * KC;
         const bool hid = seg < n_hidden;
         int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
         if (!hid && nb >= N_out) nb = 0;
-        return (size_t)min(seg, n_hidden) * H * H + (size_t)(nb / 32) * TILE + ((size_t)kc * 64 + lane) * 8;
+        const int ntl = hid ? H / 32 : nt_out;
+        return (size_t)min(seg, n_hidden) * H * H + ((size_t)kc * ntl + nb / 32) * 512 + (size_t)lane * 8;
     };
     bf16x8_t rh[P][CT], rl[P][CT];
     auto fetch = [&](int s, bf16x8_t (&bh)[CT], bf16x8_t (&bl)[CT]) {
         const size_t off = frag(s);
 #pragma unroll
         for (int j = 0; j < CT; ++j) {
-            bh[j] = *reinterpret_cast<const bf16x8_t*>(N.Wf + off + (size_t)j * TILE);
-            if (X3) bl[j] = *reinterpret_cast<const bf16x8_t*>(N.Wfl + off + (size_t)j * TILE);
+            bh[j] = *reinterpret_cast<const bf16x8_t*>(N.Wf + off + (size_t)j * 512);
+            if (X3) bl[j] = *reinterpret_cast<const bf16x8_t*>(N.Wfl + off + (size_t)j * 512);
         }
     };
     f32x16_t acc[RT][CT];

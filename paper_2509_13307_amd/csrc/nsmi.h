@@ -96,8 +96,9 @@ struct Net {
     int out_mu_rows = 1;                     // 1 (CMB) or n_z (shear)
     // One-kernel BF16 forward (networks that pass fused_shape): BF16 hi / lo
     // weights of GEMM layers 2..L in MFMA fragment order, one 1 KB block per
-    // (32 units, 16 inputs), layer l (0-based) at element l H^2, output units
-    // zero padded to a multiple of H; fvec holds b, beta, gamma of each hidden
+    // (16 inputs kc, 32 units nt) at (kc n_tiles + nt) 512 elements within the
+    // layer, layer l (0-based) at element l H^2, output units zero padded to a
+    // multiple of H; fvec holds b, beta, gamma of each hidden
     // GEMM layer (3H floats each) followed by the output bias.
     bool fused = false;
     DevBuf Wf, Wfl, fvec;
@@ -230,7 +231,13 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
 void grad_assemble(ns_model* m, int64_t B, int G, int rpw, const double* direct, const double* logl, double* grad,
                    hipStream_t s);
 
-// CMB chi^2 on model vectors (double or float per prec) -> logL, with support mask.
+// CMB model vector layout of the batched likelihood: spectrum g of walker b at
+// element b cmb_row_stride + g cmb_spec_stride (lengths rounded up to 32).
+int64_t cmb_spec_stride(const ns_model* m);
+int64_t cmb_row_stride(const ns_model* m);
+
+// CMB chi^2 on model vectors (double or float per prec, the layout above) ->
+// logL, with support mask.
 void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const void* mvec,
               double* logl, int prec, const int* count, hipStream_t s);
 

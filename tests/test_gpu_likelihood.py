@@ -4,9 +4,12 @@ Tolerances (stated per precision form):
 * FP64: |dlogL| <= 1e-6 for walkers in the posterior region (theta_fid plus
   Fisher-scaled Gaussian draws); for prior draws, where chi^2 reaches 1e6+,
   |dlogL| <= 1e-12 |logL| + 1e-6.
-* FP32 / BF16X3 / BF16: the measured |dlogL| on posterior-region walkers is
-  printed and bounded by the per-form, per-workload limits of LOWP_LIMIT
-  (see the design doc for their derivation from the rounding of each form).
+* FP32 / BF16X3: |dlogL| <= 1e-2 on posterior-region walkers (the bar for the
+  reduced-precision forms).
+* BF16 (operands rounded to 8 bits of mantissa, FP32 accumulation): misses
+  that bar by construction (|dlogL| ~ 0.1-1 on these workloads); the measured
+  value is printed and held under a regression limit about twice the value
+  measured when the kernels were written.
 """
 import sys
 
@@ -129,10 +132,10 @@ def test_batch_and_permutation_invariance(built):
 
 # |dlogL| limits of the reduced-precision forms on posterior-region walkers
 LOWP_LIMIT = {
-    ("cmb6", "fp32"): 1e-2, ("cmb6", "bf16x3"): 1e-2, ("cmb6", "bf16"): 5.0,
-    ("cmb4x2500", "fp32"): 1e-2, ("cmb4x2500", "bf16x3"): 1e-1, ("cmb4x2500", "bf16"): 200.0,
-    ("shear10", "fp32"): 1e-2, ("shear10", "bf16x3"): 1e-2, ("shear10", "bf16"): 5.0,
-    ("shear64", "fp32"): 1e-2, ("shear64", "bf16x3"): 1e-2, ("shear64", "bf16"): 5.0,
+    ("cmb6", "fp32"): 1e-2, ("cmb6", "bf16x3"): 1e-2, ("cmb6", "bf16"): 2.0,
+    ("cmb4x2500", "fp32"): 1e-2, ("cmb4x2500", "bf16x3"): 1e-2, ("cmb4x2500", "bf16"): 1.0,
+    ("shear10", "fp32"): 1e-2, ("shear10", "bf16x3"): 1e-2, ("shear10", "bf16"): 0.1,
+    ("shear64", "fp32"): 1e-2, ("shear64", "bf16x3"): 1e-2, ("shear64", "bf16"): 0.1,
 }
 
 
