@@ -216,6 +216,43 @@ ns_status ns_run(ns_model* model, const ns_run_opts* opts, ns_run_result* result
                  double* dead_logl, int32_t* dead_n, double* dead_u, int64_t capacity,
                  void* stream);
 
+typedef struct ns_hmc_opts {
+    int32_t n_chains;        /* C >= 1 chains advanced together                */
+    int32_t n_iter;          /* trajectories per chain (>= 0)                  */
+    int32_t n_leapfrog;      /* L >= 1 leapfrog steps per trajectory           */
+    int32_t precision;       /* ns_precision of the likelihood and its gradient */
+    double step;             /* leapfrog step eps > 0                          */
+    uint64_t seed;
+} ns_hmc_opts;
+
+typedef struct ns_hmc_result {
+    int64_t n_accept;        /* accepted trajectories over all chains          */
+    int64_t n_left;          /* trajectories rejected for leaving the support  */
+    int64_t n_grad;          /* gradient evaluations per chain                 */
+    double wall_s;
+} ns_hmc_result;
+
+/* Hamiltonian Monte Carlo on the same posterior, with the gradient of
+ * ns_loglike_grad_batch (gradients of the emulated likelihood, Sec. 2.2;
+ * Duane et al. 1987, Neal 2011): target log pi = logL + log prior (normal
+ * priors -(theta - mu)^2 / (2 sigma^2), uniform priors 0 inside their box,
+ * -inf outside the support), momenta p ~ N(0, diag(1 / inv_mass)),
+ * H = -log pi + sum_i inv_mass_i p_i^2 / 2, L leapfrog steps of size step,
+ * Metropolis accept with probability min(1, exp(H0 - H1)); a trajectory that
+ * reaches a point outside the support is rejected.
+ *   inv_mass: device [d], > 0
+ *   theta:    device [C x d] in: start points, out: last state
+ *   samples:  device [n_iter x C x d] or NULL: state after each trajectory
+ *   logp:     device [n_iter x C] or NULL: log pi of those states
+ * Random numbers: Philox4x64-10 as for ns_slice_step, key (seed, 2) for the
+ * momenta (draws 2i, 2i+1 of (chain, 0, iteration) -> Box-Muller normal z_i,
+ * p_i = z_i / sqrt(inv_mass_i)) and key (seed, 3) for the accept uniform u
+ * (draw 0 of (chain, 0, iteration); accept iff log u < H0 - H1).  Every update
+ * is a separately rounded FP64 operation, sums run in parameter order.
+ * NS_E_INVALID / NS_E_SHAPE for bad options; synchronises `stream`. */
+ns_status ns_hmc(ns_model* model, const ns_hmc_opts* opts, const double* inv_mass, double* theta,
+                 double* samples, double* logp, ns_hmc_result* result, void* stream);
+
 /* Kernel tracing (instrumentation, no paper passage): while enabled, every
  * kernel the library launches for `model` is bracketed by a pair of HIP
  * events recorded on its launch stream.  Enabling or disabling synchronises

@@ -96,6 +96,26 @@ class RunResult(ctypes.Structure):
     ]
 
 
+class HmcOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_chains", ctypes.c_int32),
+        ("n_iter", ctypes.c_int32),
+        ("n_leapfrog", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("step", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class HmcResult(ctypes.Structure):
+    _fields_ = [
+        ("n_accept", ctypes.c_int64),
+        ("n_left", ctypes.c_int64),
+        ("n_grad", ctypes.c_int64),
+        ("wall_s", ctypes.c_double),
+    ]
+
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = [
     ("ns_model_create", ctypes.c_int, [ctypes.POINTER(ModelDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -113,6 +133,8 @@ SIGNATURES = [
                                      ctypes.c_void_p]),
     ("ns_run", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RunOpts), ctypes.POINTER(RunResult), ctypes.c_void_p,
                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    ("ns_hmc", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(HmcOpts), ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(HmcResult), ctypes.c_void_p]),
     ("ns_trace_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ns_trace_report", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
     ("ns_tuning_report", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),

@@ -609,6 +609,24 @@ ns_status ns_run(ns_model* model, const ns_run_opts* opts, ns_run_result* result
     });
 }
 
+ns_status ns_hmc(ns_model* model, const ns_hmc_opts* opts, const double* inv_mass, double* theta,
+                 double* samples, double* logp, ns_hmc_result* result, void* stream) {
+    return (ns_status)guard([&] {
+        check_ptr(model, "model");
+        check_ptr(opts, "opts");
+        check_ptr(result, "result");
+        check_prec(opts->precision);
+        NS_CHECK(opts->n_chains >= 1 && opts->n_chains <= (1 << 20), NS_E_SHAPE, "n_chains must be in [1, 2^20]");
+        NS_CHECK(opts->n_iter >= 0, NS_E_SHAPE, "n_iter must be >= 0");
+        NS_CHECK(opts->n_leapfrog >= 1, NS_E_SHAPE, "n_leapfrog must be >= 1");
+        NS_CHECK(opts->step > 0.0 && std::isfinite(opts->step), NS_E_INVALID, "step must be positive and finite");
+        check_ptr(inv_mass, "inv_mass");
+        check_ptr(theta, "theta");
+        bind_device(model);
+        hmc_run(model, opts, inv_mass, theta, samples, logp, result, (hipStream_t)stream);
+    });
+}
+
 ns_status ns_trace_enable(ns_model* model, int32_t enable) {
     return (ns_status)guard([&] {
         check_ptr(model, "model");

@@ -164,6 +164,7 @@ struct ns_model {
     nsmi::DevBuf ws_tsave;           // saved pre-activations [G x (L-1) x rows x width]
     nsmi::DevBuf ws_gact[2];         // adjoint activations ping-pong [G x rows x n_pad]
     nsmi::DevBuf ws_gx;              // input gradients [G x rows x n_in]
+    nsmi::DevBuf ws_hmc;             // HMC chain state
     void* host_pinned = nullptr;     // pinned host flag for completion polling
     hipStream_t graph_stream = nullptr;  // stream the captured slice-step graphs replay on
     hipEvent_t graph_event = nullptr;
@@ -269,6 +270,10 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
 void slice_step_host_lstar(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
                            double lstar, const double* L, int n_inner, uint64_t seed, uint64_t iter, int prec,
                            hipStream_t s);
+
+// Hamiltonian Monte Carlo chains (synchronises s).
+void hmc_run(ns_model* m, const ns_hmc_opts* o, const double* minv, double* theta, double* samples, double* logp,
+             ns_hmc_result* res, hipStream_t s);
 
 // Nested slice sampling to convergence.
 void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, int* dn_h, double* du_h,

@@ -29,9 +29,16 @@
 namespace nsmi {
 
 // -------------------------------------------------------------- z-spline
+// One thread per (walker, k) column, one wave per block.  The column is first
+// staged in LDS ([n_z][64] per wave; the loads are independent, so they are
+// all in flight together), then the Thomas sweep of the (1, 4, 1) system runs
+// from LDS, its forward values overwriting the staged y in place, and each
+// second derivative is written to HBM once.
 template <class T>
-__global__ __launch_bounds__(256) void zspline_kernel(const T* __restrict__ Y, T* __restrict__ M, int64_t B,
-                                                      int nz, int nk, double h, const int* __restrict__ count) {
+__global__ __launch_bounds__(64) void zspline_kernel(const T* __restrict__ Y, T* __restrict__ M, int64_t B,
+                                                     int nz, int nk, double h, const int* __restrict__ count) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char zs_smem[];
+    T* ys = reinterpret_cast<T*>(zs_smem);             // [nz][64]: y, then d' of the sweep
     // c'_n of the (1, 4, 1) Thomas sweep: data independent, tabulated once per block
     __shared__ T cps[256];
     if (threadIdx.x == 0) {
@@ -42,37 +49,46 @@ __global__ __launch_bounds__(256) void zspline_kernel(const T* __restrict__ Y, T
         }
     }
     __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (count) B = min<int64_t>(B, *count);
     if (g >= B * nk) return;
+    const int t = threadIdx.x;
     const int64_t w = g / nk;
     const int c = (int)(g % nk);
     const T* y = Y + w * nz * nk + c;
     T* mm = M + w * nz * nk + c;
+#pragma unroll 8
+    for (int n = 0; n < nz; ++n) ys[n * 64 + t] = y[(int64_t)n * nk];
     const T ih2 = T(1.0 / (h * h));
-    auto yv = [&](int n) { return y[(int64_t)n * nk]; };
+    auto yv = [&](int n) { return ys[n * 64 + t]; };
     const T M1 = (yv(2) - T(2) * yv(1) + yv(0)) * ih2;
     const T Mb = (yv(nz - 1) - T(2) * yv(nz - 2) + yv(nz - 3)) * ih2;   // M_{N-2}
-    mm[(int64_t)1 * nk] = M1;
-    mm[(int64_t)(nz - 2) * nk] = Mb;
+    T M2 = Mb, Mc = M1;                                 // n_z = 4: nodes 2 and n_z - 3 are N-2 and 1
     // interior unknowns n = 2 .. nz-3: M_{n-1} + 4 M_n + M_{n+1} = 6 d2Y_n / h^2
     if (nz > 4) {
-        T dp = T(0);
+        T dpv = T(0);
+        T ym = yv(1), y0 = yv(2);
         for (int n = 2; n <= nz - 3; ++n) {
-            T rhs = T(6) * (yv(n + 1) - T(2) * yv(n) + yv(n - 1)) * ih2;
+            const T yp = yv(n + 1);
+            T rhs = T(6) * (yp - T(2) * y0 + ym) * ih2;
             if (n == 2) rhs -= M1;
             if (n == nz - 3) rhs -= Mb;
-            dp = (rhs - (n == 2 ? T(0) : dp)) * cps[n];
-            mm[(int64_t)n * nk] = dp;                   // d'_n, overwritten below
+            dpv = (rhs - (n == 2 ? T(0) : dpv)) * cps[n];
+            ys[n * 64 + t] = dpv;                       // y_n is held in y0 from here on
+            ym = y0;
+            y0 = yp;
         }
-        T next = dp;                                    // M_{nz-3} = d'_{nz-3}
+        T next = dpv;                                   // M_{nz-3} = d'_{nz-3}
+        mm[(int64_t)(nz - 3) * nk] = next;
+        Mc = next;
         for (int n = nz - 4; n >= 2; --n) {
-            next = mm[(int64_t)n * nk] - cps[n] * next;
+            next = ys[n * 64 + t] - cps[n] * next;
             mm[(int64_t)n * nk] = next;
         }
+        M2 = next;
     }
-    const T M2 = mm[(int64_t)2 * nk];
-    const T Mc = mm[(int64_t)(nz - 3) * nk];
+    mm[(int64_t)1 * nk] = M1;
+    mm[(int64_t)(nz - 2) * nk] = Mb;
     mm[0] = T(2) * M1 - M2;
     mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
 }
@@ -412,28 +428,33 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     double* Cv = reinterpret_cast<double*>(m->ws_aux.as<char>() + mbytes);
     const double zmax = 1.0 / m->a_min - 1.0;
     const double hz = zmax / (nz - 1);
+    if (!m->shear_attr_set) {   // once per model, outside any stream capture
+        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+        NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   150 * 1024));
+        NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   150 * 1024));
+        m->shear_attr_set = true;
+    }
     const int64_t nthr = B * nk;
-    dim3 gz((unsigned)((nthr + 255) / 256));
+    dim3 gz((unsigned)((nthr + 63) / 64));
     {
     TraceScope ts(m, s, "zspline");
+    const size_t zsm = (size_t)nz * 64 * elem;
     if (prec == NS_FP64)
-        hipLaunchKernelGGL(zspline_kernel<double>, gz, dim3(256), 0, s, m->ws_out.as<double>(), (double*)Mtab, B,
+        hipLaunchKernelGGL(zspline_kernel<double>, gz, dim3(64), zsm, s, m->ws_out.as<double>(), (double*)Mtab, B,
                            nz, nk, hz, count);
     else
-        hipLaunchKernelGGL(zspline_kernel<float>, gz, dim3(256), 0, s, m->ws_out.as<float>(), (float*)Mtab, B, nz,
+        hipLaunchKernelGGL(zspline_kernel<float>, gz, dim3(64), zsm, s, m->ws_out.as<float>(), (float*)Mtab, B, nz,
                            nk, hz, count);
     NS_HIP(hipGetLastError());
     }
     const ShearGeom G = shear_geom(m);
     const size_t sm = limber_smem(m, elem);
     NS_CHECK(sm <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
-    if (!m->shear_attr_set) {   // once per model, outside any stream capture
-        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
-        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
-        m->shear_attr_set = true;
-    }
     {
     TraceScope ts(m, s, "limber");
     if (prec == NS_FP64)

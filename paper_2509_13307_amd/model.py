@@ -179,6 +179,25 @@ class Model:
             out.update(dead_logl=dl[:n], dead_n=dn[:n], dead_u=du[:n])
         return out
 
+    def hmc(self, theta0, inv_mass, n_iter, n_leapfrog, step, seed=1, precision="fp64", keep_samples=True):
+        """Hamiltonian Monte Carlo chains from theta0 [chains, d] (device tensor);
+        returns (samples [n_iter, chains, d], logp [n_iter, chains], result dict,
+        last state)."""
+        theta = theta0.to(torch.float64).contiguous().clone()
+        n_ch, d = theta.shape
+        minv = inv_mass.to(device=theta.device, dtype=torch.float64).contiguous()
+        samples = logp = None
+        if keep_samples:
+            samples = torch.empty((n_iter, n_ch, d), dtype=torch.float64, device=theta.device)
+            logp = torch.empty((n_iter, n_ch), dtype=torch.float64, device=theta.device)
+        o = C.HmcOpts(n_ch, n_iter, n_leapfrog, C.PRECISIONS[precision], step, seed)
+        r = C.HmcResult()
+        nullp = ctypes.c_void_p()
+        C.check(C.lib().ns_hmc(self._h, ctypes.byref(o), _ptr(minv), _ptr(theta),
+                               _ptr(samples) if keep_samples else nullp, _ptr(logp) if keep_samples else nullp,
+                               ctypes.byref(r), _stream()))
+        return samples, logp, {f: getattr(r, f) for f, _ in C.HmcResult._fields_}, theta
+
     def trace(self, enable=True):
         """Bracket every kernel launch with HIP events (see ns_trace_enable)."""
         C.check(C.lib().ns_trace_enable(self._h, 1 if enable else 0))

@@ -26,7 +26,7 @@ def capi():
 
 def test_header_declares_the_boundary():
     fns = declared_functions()
-    for name in ("ns_loglike_batch", "ns_loglike_grad_batch", "ns_slice_step", "ns_run",
+    for name in ("ns_loglike_batch", "ns_loglike_grad_batch", "ns_slice_step", "ns_run", "ns_hmc",
                  "ns_model_create", "ns_model_free", "ns_last_error", "ns_prior_transform"):
         assert name in fns
 
@@ -48,6 +48,10 @@ def test_argument_validation_without_device(capi):
     assert lib.ns_last_error() == b""
     assert lib.ns_run(None, None, None, None, None, None, 0, None) == capi.NS_E_INVALID
     assert lib.ns_slice_step(None, None, None, None, None, 4, 0.0, None, 1, 0, 0, 0, None) == capi.NS_E_INVALID
+    res = capi.HmcResult()
+    opts = capi.HmcOpts(4, 10, 5, 0, 0.1, 1)
+    assert lib.ns_hmc(None, ctypes.byref(opts), None, None, None, None, ctypes.byref(res), None) == capi.NS_E_INVALID
+    assert b"model" in lib.ns_last_error()
 
 
 def test_module_refuses_to_run_without_library(tmp_path, monkeypatch):

@@ -184,3 +184,21 @@ def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
     for c in range(4):
         got, _ = run({"NSMI_FUSED_CFG": str(c)})
         np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("n_z", [4, 5, 7])
+def test_fp64_shear_few_redshift_nodes(built, n_z):
+    """Shear likelihood with the smallest redshift-node tables the spline
+    supports (no or one interior unknown in the z system), against the oracle."""
+    say(f"case fp64 shear n_z={n_z}")
+    from paper_2509_13307_amd import Model
+    base = W.load_model("shear10")
+    m = W.shear_structure(n_z=n_z)
+    for key in ("data", "cov", "theta_fid", "fisher_sigma"):
+        m[key] = base[key]
+    g = Model(m)
+    th = W.posterior_draws(m["theta_fid"], post_scale(m), 9, tag=6)
+    ref = oracle_loglike(th, m, chunk=16)
+    got = run_gpu(g, th)
+    g.close()
+    check_fp64(ref, got, f"shear n_z={n_z}")
