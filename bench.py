@@ -109,6 +109,7 @@ def main():
                     help="only run plain device copies of 256 MiB (reference for HBM byte counters)")
     ap.add_argument("--mc-precision", default="bf16x3")
     ap.add_argument("--mc-live", type=int, default=1000)
+    ap.add_argument("--mc-hmc-iter", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); runs on several GPUs "
@@ -130,7 +131,7 @@ def main():
         return
 
     if args.model_comparison:
-        print(json.dumps(model_comparison(Model, W, args.mc_precision, args.mc_live)), flush=True)
+        print(json.dumps(model_comparison(Model, W, args.mc_precision, args.mc_live, args.mc_hmc_iter)), flush=True)
         return
 
     dev = "cuda:0"
@@ -233,24 +234,67 @@ def ns_leg(Model, W):
     return out
 
 
-def model_comparison(Model, W, prec, n_live):
+def ns_posterior(g, r, torch, dev):
+    """Weighted posterior samples from the dead points of an ns_run: weight
+    L_i (X_{i-1} - X_i) with log X_i = -sum_{j <= i} 1 / n_j (Eq. 1)."""
+    n = r["dead_n"].astype(np.float64)
+    logx = -np.cumsum(1.0 / n)
+    x = np.exp(logx)
+    xprev = np.concatenate([[1.0], x[:-1]])
+    logw = r["dead_logl"] + np.log(xprev - x)
+    w = np.exp(logw - logw.max())
+    w /= w.sum()
+    th = g.prior_transform(torch.tensor(r["dead_u"], device=dev)).cpu().numpy()
+    mean = w @ th
+    std = np.sqrt(w @ (th - mean) ** 2)
+    return th, w, mean, std
+
+
+def model_comparison(Model, W, prec, n_live, hmc_iter=400, hmc_warmup=100):
     """Bayes factor of LCDM (37 parameters) against w0wa (39) on the same
     synthetic shear data (made at a seeded w0wa point): nested slice sampling
-    with n_live live points, n_live/2 deleted per iteration, 5 d slice steps."""
+    with n_live live points, n_live/2 deleted per iteration, 5 d slice steps.
+    Alongside, 4 HMC chains on the w0wa posterior with the FP64 adjoint
+    gradient; their posterior means are compared with the nested-sampling
+    posterior (difference in units of its standard deviation)."""
+    import torch
+    dev = "cuda:0"
     out = {"precision": prec, "n_live": n_live, "n_delete": n_live // 2}
+    post = {}
     for name in ("shear_cmp_lcdm", "shear_cmp_w0wa"):
         m = W.load_model(name)
         g = Model(m)
-        r = g.run(n_live, n_live // 2, 5 * m["d"], precision=prec, seed=7, n_replicates=1000)
+        r = g.run(n_live, n_live // 2, 5 * m["d"], precision=prec, seed=7, n_replicates=1000, capacity=2000000)
         out[name] = {k: r[k] for k in ("logz", "sigma", "sigma_skilling", "h", "n_iter", "n_evals", "n_stalls",
-                                       "wall_s")}
+                                       "n_dead", "wall_s")}
         out[name]["d"] = m["d"]
         print(f"# {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
-        g.close()
+        if name == "shear_cmp_w0wa":
+            th, w, mean, std = ns_posterior(g, r, torch, dev)
+            post = dict(th=th, w=w, mean=mean, std=std, model=m, g=g)
+        else:
+            g.close()
     a, b = out["shear_cmp_lcdm"], out["shear_cmp_w0wa"]
     out["log_B01"] = a["logz"] - b["logz"]
     out["log_B01_sigma"] = float(np.hypot(a["sigma"], b["sigma"]))
     out["wall_s_total"] = a["wall_s"] + b["wall_s"]
+    # HMC chains from four posterior draws, inverse mass = NS posterior variance
+    m, g = post["model"], post["g"]
+    rng = np.random.default_rng(3)
+    start = post["th"][rng.choice(len(post["w"]), size=4, p=post["w"])]
+    minv = torch.tensor(post["std"] ** 2)
+    step, L = 0.3, 8
+    g.hmc(torch.tensor(start, device=dev), minv, hmc_warmup, L, step, seed=11, keep_samples=False)
+    s, lp, res, _ = g.hmc(torch.tensor(start, device=dev), minv, hmc_warmup + hmc_iter, L, step, seed=11)
+    x = s[hmc_warmup:].reshape(-1, m["d"]).cpu().numpy()
+    z = (x.mean(axis=0) - post["mean"]) / post["std"]
+    out["hmc"] = dict(chains=4, iterations=hmc_iter, warmup=hmc_warmup, n_leapfrog=L, step=step, precision="fp64",
+                      accept_rate=res["n_accept"] / (4 * (hmc_warmup + hmc_iter)), wall_s=res["wall_s"],
+                      max_abs_mean_diff_in_ns_sigma=float(np.max(np.abs(z))),
+                      rms_mean_diff_in_ns_sigma=float(np.sqrt(np.mean(z ** 2))),
+                      mean_diff_in_ns_sigma=[round(float(v), 3) for v in z])
+    print(f"# hmc: {json.dumps(out['hmc'])}", file=sys.stderr, flush=True)
+    g.close()
     return out
 
 

@@ -16,11 +16,17 @@ Hamiltonian H = -log pi(theta) + sum_i m_i p_i^2 / 2, and L leapfrog
 (Stormer-Verlet) steps of size eps per trajectory:
 
     p <- p + eps/2 grad log pi(theta)
-    repeat L times:  theta <- theta + eps m p;  p <- p + h grad log pi(theta)
+    repeat L times:  theta <- theta + eps m p;  reflect;
+                     p <- p + h grad log pi(theta)
                      with h = eps, except h = eps/2 after the last drift,
 
-then a Metropolis accept with probability min(1, exp(H0 - H1)).  A trajectory
-that reaches a point outside the prior support is rejected.
+then a Metropolis accept with probability min(1, exp(H0 - H1)).  Uniform-prior
+coordinates are kept in their box by reflection (Neal 2011, Sec. 5.5.1): a
+drift that ends beyond a wall b is mirrored to b - (theta - b) and that
+momentum component changes sign, repeated until inside; reflection conserves
+volume, kinetic energy and time reversibility, so the chain stays exact.  A
+trajectory that still reaches log pi = -inf (or needs more than 64 bounces in
+one drift) is rejected.
 
 Random numbers (philox.py): stream 2 draws the momenta, z_i = Box-Muller of
 draws 2i, 2i+1 of the sequence (chain, 0, iteration), p_i = z_i / sqrt(m_i);
@@ -32,8 +38,9 @@ written, and every sum over parameters runs in parameter order, so that the
 HIP sampler (same draws, same order, no contraction) replays a run.
 
 Pinned by: the exact leapfrog map of a Gaussian target (a linear map known in
-closed form), time reversibility of the integrator, its O(eps^2) energy error,
-and the moments of samples of a Gaussian target.
+closed form), time reversibility of the integrator (also through
+reflections), its O(eps^2) energy error, the moments of samples of a Gaussian
+target, and uniform samples of a flat target in a box.
 """
 import numpy as np
 
@@ -85,19 +92,50 @@ def kinetic(p, minv):
     return 0.5 * k
 
 
-def leapfrog(theta, p, grad, minv, step, n_leapfrog, target):
-    """L leapfrog steps from (theta, p) with grad = grad log pi(theta).
-    Returns (theta, p, log pi, grad, left_support [B])."""
+MAX_BOUNCES = 64
+
+
+def reflect(theta, p, lo, hi):
+    """Mirror coordinates beyond lo / hi back inside, flipping their momenta,
+    one wall per pass; returns (theta, p, stuck [B])."""
+    for _ in range(MAX_BOUNCES):
+        up = theta > hi[None, :]
+        dn = ~up & (theta < lo[None, :])
+        if not (up.any() or dn.any()):
+            break
+        theta = np.where(up, hi[None, :] - (theta - hi[None, :]), theta)
+        theta = np.where(dn, lo[None, :] - (theta - lo[None, :]), theta)
+        p = np.where(up | dn, -p, p)
+    stuck = np.any((theta > hi[None, :]) | (theta < lo[None, :]), axis=1)
+    return theta, p, stuck
+
+
+def box(model, d):
+    """(lo, hi) walls of the uniform-prior coordinates; +-inf elsewhere."""
+    if model is None:
+        return np.full(d, -np.inf), np.full(d, np.inf)
+    uni = np.asarray(model["prior_kind"]) == 0
+    return (np.where(uni, model["prior_a"], -np.inf).astype(np.float64),
+            np.where(uni, model["prior_b"], np.inf).astype(np.float64))
+
+
+def leapfrog(theta, p, grad, minv, step, n_leapfrog, target, lo=None, hi=None):
+    """L leapfrog steps from (theta, p) with grad = grad log pi(theta),
+    reflecting at the walls lo / hi.  Returns (theta, p, log pi, grad, rejected [B])."""
     theta = np.array(theta, dtype=np.float64, copy=True)
     p = np.array(p, dtype=np.float64, copy=True)
+    d = theta.shape[1]
+    lo = np.full(d, -np.inf) if lo is None else lo
+    hi = np.full(d, np.inf) if hi is None else hi
     half = 0.5 * step
     p = p + half * grad
     left = np.zeros(theta.shape[0], dtype=bool)
     logpi = None
     for l in range(n_leapfrog):
         theta = theta + step * (minv[None, :] * p)
+        theta, p, stuck = reflect(theta, p, lo, hi)
         logpi, grad = target(theta)
-        left |= ~np.isfinite(logpi)
+        left |= stuck | ~np.isfinite(logpi)
         p = p + (half if l == n_leapfrog - 1 else step) * grad
     return theta, p, logpi, grad, left
 
@@ -119,6 +157,7 @@ def run(model, theta0, minv, n_iter, n_leapfrog, step, seed, target=None):
     theta = np.array(theta0, dtype=np.float64, copy=True)
     minv = np.asarray(minv, dtype=np.float64)
     C, d = theta.shape
+    lo, hi = box(model, d)
     chains = np.arange(C)
     logpi, grad = target(theta)
     samples = np.zeros((n_iter, C, d))
@@ -128,7 +167,7 @@ def run(model, theta0, minv, n_iter, n_leapfrog, step, seed, target=None):
     for t in range(n_iter):
         p = momenta(seed, chains, t, minv)
         H0 = kinetic(p, minv) - logpi
-        th1, p1, lp1, g1, left = leapfrog(theta, p, grad, minv, step, n_leapfrog, target)
+        th1, p1, lp1, g1, left = leapfrog(theta, p, grad, minv, step, n_leapfrog, target, lo, hi)
         H1 = kinetic(p1, minv) - lp1
         u = uniforms(seed, STREAM_ACCEPT, chains, 0, t, [0])[:, 0]
         with np.errstate(invalid="ignore", divide="ignore"):

@@ -113,16 +113,54 @@ def test_log_prior_is_the_normal_density_up_to_a_constant():
     assert np.all(gp[:, ~nrm] == 0.0)
 
 
-def test_trajectory_leaving_the_support_is_rejected():
+def test_reflection_keeps_chains_in_the_box():
+    """cmb6 chains started 0.02 from the theta_0 = 0 wall with posterior-scale
+    steps: the pull toward the mode carries unwalled trajectories beyond
+    theta_0 = 1; with the walls they are reflected, none is rejected for it."""
     m = W.load_model("cmb6")
     target = hmc.make_target(m)
-    th0 = np.array([[0.02, 0.5, 0.5, 0.5, 0.5, 0.5]])
-    lp0, g0 = target(th0)
-    p0 = np.zeros((1, 6))
-    p0[0, 0] = -10.0                                   # one drift of 0.05 * 10 leaves [0, 1]
-    _, _, lp, _, left = hmc.leapfrog(th0, p0, g0, np.ones(6), 0.05, 3, target)
-    assert left[0]
-    # drifts of 10 |p| leave the unit box unless every |p_i| < 0.1: every trajectory is rejected
-    out = hmc.run(m, np.tile(th0, (3, 1)), np.ones(6), n_iter=2, n_leapfrog=1, step=10.0, seed=1, target=target)
-    assert out["left"].all() and not out["accept"].any()
-    np.testing.assert_array_equal(out["theta"], np.tile(th0, (3, 1)))
+    th0 = np.tile(m["theta_fid"], (8, 1))
+    th0[:, 0] = 0.02
+    minv = np.full(6, 0.02 ** 2)
+    lo, hi = hmc.box(m, 6)
+    p0 = hmc.momenta(4, np.arange(8), 0, minv)
+    _, g0 = target(th0)
+    th, _, lp, _, left = hmc.leapfrog(th0, p0, g0, minv, 0.5, 6, target, lo, hi)
+    free, _, _, _, _ = hmc.leapfrog(th0, p0, g0, minv, 0.5, 6, target)        # no walls
+    assert np.any((free < 0) | (free > 1))                                  # unwalled trajectories leave the box ...
+    assert not left.any() and np.all(np.isfinite(lp))                      # ... and is reflected, not rejected
+    assert np.all((th >= 0.0) & (th <= 1.0))
+
+
+def test_reflection_is_reversible_and_conserves_kinetic_energy():
+    rng = np.random.default_rng(5)
+    th0 = 0.2 * rng.normal(size=(4, 2))
+    p0 = 3.0 * rng.normal(size=(4, 2))
+    minv = np.array([0.8, 1.2])
+    lo, hi = np.array([-0.4, -np.inf]), np.array([0.3, np.inf])
+    th0[:, 0] = np.clip(th0[:, 0], -0.39, 0.29)
+    flat = lambda th: (np.zeros(th.shape[0]), np.zeros_like(th))
+    th1, p1, _, _, left = hmc.leapfrog(th0, p0, np.zeros_like(th0), minv, 0.2, 25, flat, lo, hi)
+    assert not left.any()
+    assert np.all((th1[:, 0] >= lo[0]) & (th1[:, 0] <= hi[0]))
+    np.testing.assert_allclose(np.abs(p1), np.abs(p0), rtol=0, atol=0)     # flat target: only sign flips
+    np.testing.assert_allclose(hmc.kinetic(p1, minv), hmc.kinetic(p0, minv), rtol=1e-15)
+    _, g1 = quartic_target(th1)
+    t1, q1, _, g1, _ = hmc.leapfrog(th0, p0, quartic_target(th0)[1], minv, 0.02, 60, quartic_target, lo, hi)
+    t2, q2, _, _, _ = hmc.leapfrog(t1, -q1, g1, minv, 0.02, 60, quartic_target, lo, hi)
+    np.testing.assert_allclose(t2, th0, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(-q2, p0, rtol=0, atol=1e-9)
+
+
+def test_flat_target_in_a_box_gives_uniform_samples():
+    """A flat log pi in [0, 1]^2: H is conserved exactly (reflections only flip
+    momenta), every trajectory is accepted and the chains sample U(0, 1)^2."""
+    flat = lambda th: (np.zeros(th.shape[0]), np.zeros_like(th))
+    model = {"prior_kind": np.zeros(2, dtype=np.int32), "prior_a": np.zeros(2), "prior_b": np.ones(2)}
+    out = hmc.run(model, np.full((16, 2), 0.5), np.ones(2), n_iter=400, n_leapfrog=5, step=0.37, seed=2,
+                  target=flat)
+    assert out["accept"].all()
+    x = out["samples"][50:].reshape(-1, 2)
+    assert np.all((x >= 0) & (x <= 1))
+    assert np.all(np.abs(x.mean(axis=0) - 0.5) < 0.02)
+    np.testing.assert_allclose(x.var(axis=0), 1 / 12, rtol=0.06)
