@@ -238,8 +238,11 @@ typedef struct ns_hmc_result {
  * priors -(theta - mu)^2 / (2 sigma^2), uniform priors 0 inside their box,
  * -inf outside the support), momenta p ~ N(0, diag(1 / inv_mass)),
  * H = -log pi + sum_i inv_mass_i p_i^2 / 2, L leapfrog steps of size step,
- * Metropolis accept with probability min(1, exp(H0 - H1)); a trajectory that
- * reaches a point outside the support is rejected.
+ * Metropolis accept with probability min(1, exp(H0 - H1)).  A drift that
+ * crosses a wall of a uniform prior is mirrored back (x -> b - (x - b), that
+ * momentum component negated; Neal 2011, Sec. 5.5.1), at most 64 walls per
+ * drift; a trajectory that still meets log pi = -inf is rejected
+ * (result->n_left).
  *   inv_mass: device [d], > 0
  *   theta:    device [C x d] in: start points, out: last state
  *   samples:  device [n_iter x C x d] or NULL: state after each trajectory

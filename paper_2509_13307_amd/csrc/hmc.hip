@@ -3,7 +3,9 @@
 //   log pi = logL + log prior (normal priors -(theta - mu)^2 / 2 sigma^2,
 //   uniform priors 0 inside their box, -inf outside the support),
 // diagonal inverse mass m, L leapfrog steps of size eps per trajectory,
-// Metropolis accept; a trajectory that leaves the support is rejected.
+// Metropolis accept.  Uniform-prior coordinates are reflected at their walls
+// (momentum sign flipped); a trajectory that still meets log pi = -inf is
+// rejected.
 //
 // Per trajectory: hmc_start_kernel (momenta, H0, first half kick and drift),
 // then per leapfrog step one batched gradient of logL and hmc_step_kernel
@@ -30,6 +32,24 @@ struct HmcState {
     int* left;                              // trajectory left the support [C]
     int* n_acc; int* n_left;                // per-chain counters
 };
+
+// Mirrors x back into [lo, hi] (one wall per pass, at most 64 passes),
+// flipping p at every wall (Neal 2011, Sec. 5.5.1); false if still outside.
+__device__ __forceinline__ bool reflect(double& x, double& p, double lo, double hi) {
+#pragma clang fp contract(off)
+    for (int b = 0; b < 64; ++b) {
+        if (x > hi) {
+            x = hi - (x - hi);
+            p = -p;
+        } else if (x < lo) {
+            x = lo - (x - lo);
+            p = -p;
+        } else {
+            return true;
+        }
+    }
+    return !(x > hi || x < lo);
+}
 
 // Adds the prior terms to (lp, g), which hold logL and its gradient at th.
 __device__ __forceinline__ void add_prior(const double* th, double& lp, double* g, int d, const int* pk,
@@ -59,12 +79,14 @@ __global__ void hmc_prior_kernel(HmcState S, int C, int d, const int* __restrict
 
 // Momenta, H0, first half kick and first drift.
 __global__ void hmc_start_kernel(HmcState S, const double* __restrict__ minv, int C, int d, double step,
-                                 uint64_t seed, uint64_t it) {
+                                 uint64_t seed, uint64_t it, const int* __restrict__ pk,
+                                 const double* __restrict__ pa, const double* __restrict__ pb) {
 #pragma clang fp contract(off)
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
     const double half = 0.5 * step;
     double k = 0.0;
+    bool inside = true;
     for (int i = 0; i < d; ++i) {
         const double u1 = philox_uniform(seed, HMC_STREAM_MOMENTUM, (uint64_t)c, 0, it, 2 * i);
         const double u2 = philox_uniform(seed, HMC_STREAM_MOMENTUM, (uint64_t)c, 0, it, 2 * i + 1);
@@ -72,12 +94,14 @@ __global__ void hmc_start_kernel(HmcState S, const double* __restrict__ minv, in
         const double p = z / sqrt(minv[i]);
         k = k + (minv[i] * p) * p;
         const int64_t e = (int64_t)c * d + i;
-        const double pk1 = p + half * S.g[e];
+        double pk1 = p + half * S.g[e];
+        double x = S.th[e] + step * (minv[i] * pk1);
+        if (pk[i] == NS_PRIOR_UNIFORM) inside = reflect(x, pk1, pa[i], pb[i]) && inside;
         S.p[e] = pk1;
-        S.th1[e] = S.th[e] + step * (minv[i] * pk1);
+        S.th1[e] = x;
     }
     S.h0[c] = 0.5 * k - S.lp[c];
-    S.left[c] = 0;
+    S.left[c] = inside ? 0 : 1;
 }
 
 // After the gradient of logL at th1: prior terms, support flag, kick by h,
@@ -90,12 +114,17 @@ __global__ void hmc_step_kernel(HmcState S, const double* __restrict__ minv, int
     if (c >= C) return;
     const int64_t o = (int64_t)c * d;
     add_prior(S.th1 + o, S.lp1[c], S.g1 + o, d, pk, pa, pb);
-    if (!isfinite(S.lp1[c])) S.left[c] = 1;
+    bool inside = isfinite(S.lp1[c]);
     for (int i = 0; i < d; ++i) {
-        const double pn = S.p[o + i] + h * S.g1[o + i];
+        double pn = S.p[o + i] + h * S.g1[o + i];
+        if (!last) {
+            double x = S.th1[o + i] + step * (minv[i] * pn);
+            if (pk[i] == NS_PRIOR_UNIFORM) inside = reflect(x, pn, pa[i], pb[i]) && inside;
+            S.th1[o + i] = x;
+        }
         S.p[o + i] = pn;
-        if (!last) S.th1[o + i] = S.th1[o + i] + step * (minv[i] * pn);
     }
+    if (!inside) S.left[c] = 1;
 }
 
 __global__ void hmc_accept_kernel(HmcState S, const double* __restrict__ minv, int C, int d, uint64_t seed,
@@ -145,7 +174,8 @@ void hmc_run(ns_model* m, const ns_hmc_opts* o, const double* minv, double* thet
     hipLaunchKernelGGL(hmc_prior_kernel, grid, blk, 0, s, S, C, d, pk, pa, pb);
     NS_HIP(hipGetLastError());
     for (int64_t t = 0; t < o->n_iter; ++t) {
-        hipLaunchKernelGGL(hmc_start_kernel, grid, blk, 0, s, S, minv, C, d, o->step, o->seed, (uint64_t)t);
+        hipLaunchKernelGGL(hmc_start_kernel, grid, blk, 0, s, S, minv, C, d, o->step, o->seed, (uint64_t)t, pk, pa,
+                           pb);
         for (int l = 0; l < L; ++l) {
             loglike_grad_batch(m, S.th1, d, C, S.lp1, S.g1, o->precision, s);
             const bool last = l == L - 1;
