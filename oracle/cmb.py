@@ -14,10 +14,20 @@ vector against a synthetic data vector:
              - sum log diag(L_l) - sum log sigma_pp,l - n/2 log 2 pi,
   with L_l the lower Cholesky factor of Sigma_l.
 
+Cosmic-variance-limited temperature likelihood (the paper's CMB analysis,
+Sec. 2.3): with no noise, (2l+1) Ch_l / C_l follows a chi^2 distribution with
+k = 2l+1 degrees of freedom, so the density of the observed Ch_l given the
+emulated C_l = 10^y_l is p(Ch_l | C_l) = (k / C_l) f_k(k Ch_l / C_l), with
+      log f_k(x) = (k/2 - 1) log x - x/2 - (k/2) log 2 - log Gamma(k/2),
+and logL = sum_l log p(Ch_l | C_l) over l = l_min, l_min + 1, ...
+
 Pinned by: scipy.stats.multivariate_normal.logpdf on the full covariance
-(a library the oracle does not call) for small multipole ranges.
+(a library the oracle does not call) for small multipole ranges; for the
+cosmic-variance form, scipy.stats.chi2.logpdf, the closed-form maximum at
+C_l = Ch_l and the unit normalisation of p(Ch_l | C_l).
 """
 import numpy as np
+from scipy.special import gammaln
 
 from .emulator import emulate
 
@@ -56,3 +66,13 @@ def loglike_block(theta, model):
     logdet_half = np.sum(np.log(np.diagonal(L, axis1=1, axis2=2))) + np.sum(np.log(model["sigma_pp"]))
     n = 4 * n_ell
     return -0.5 * chi2 - logdet_half - 0.5 * n * LOG2PI
+
+
+def loglike_cv(theta, model):
+    """Cosmic-variance-limited TT log-likelihood for a batch theta [B, d]."""
+    C = 10.0 ** emulate(theta, model["nets"][0])          # [B, n_ell]
+    ell = model["ell_min"] + np.arange(C.shape[1], dtype=np.float64)
+    k = 2.0 * ell + 1.0
+    x = k[None, :] * model["data"][None, :] / C
+    log_f = (0.5 * k - 1.0) * np.log(x) - 0.5 * x - 0.5 * k * np.log(2.0) - gammaln(0.5 * k)
+    return np.sum(np.log(k[None, :] / C) + log_f, axis=1)

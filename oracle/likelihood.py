@@ -52,6 +52,8 @@ def loglike_raw(theta, model):
         return cmb.loglike_diag(theta, model)
     if kind == "cmb_block":
         return cmb.loglike_block(theta, model)
+    if kind == "cmb_cv":
+        return cmb.loglike_cv(theta, model)
     if kind == "shear":
         return shear.loglike(theta, model)
     if kind == "gauss":

@@ -11,6 +11,8 @@ cmb6        data = m(theta_fid) + sigma eps; one scalar sigma chosen so that the
 cmb4x2500   per-multipole 3x3 covariance Sigma_l = D_l R_l D_l over (TT, TE, EE),
             D = sqrt(2/(2l+1)) |C_fid| (TE: sqrt(C_TT C_EE)), R_l a seeded
             correlation; PP diagonal sqrt(2/(2l+1)) C_pp; data = C_fid + noise.
+cmbtt_cv    cosmic-variance-limited TT: data Ch_l = C_l(theta_fid) X_l / (2l+1),
+            X_l ~ chi^2 with 2l+1 degrees of freedom (seeded).
 shear*      Gaussian (Knox) covariance per multipole,
             Cov[(ij),(kl)] = (Ch_ik Ch_jl + Ch_il Ch_jk) / ((2l+1) dl f_sky),
             Ch = C + delta sigma_e^2 / n_bar  (sigma_e = 0.3, n_bar = 6 arcmin^-2
@@ -30,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 import workloads as W                                   # noqa: E402
 from oracle import cmb, shear                           # noqa: E402
+from oracle.emulator import emulate                     # noqa: E402
 from oracle.likelihood import loglike                   # noqa: E402
 
 OUT = os.path.dirname(os.path.abspath(__file__))
@@ -73,6 +76,23 @@ def make_cmb6():
                         sigma=np.full(mf.size, sigma), theta_fid=th, fisher_sigma=fs)
     m.update(data=data, sigma=np.full(mf.size, sigma))
     print("cmb6: sigma", sigma, "logL(fid)", loglike(th[None, :], m))
+
+
+def make_cmb_cv():
+    m = W.structure("cmbtt_cv")
+    th = W.fiducial_cmb()
+    net = m["nets"][0]
+    y = emulate(th[None, :], net)[0]
+    ell = m["ell_min"] + np.arange(y.size, dtype=np.float64)
+    k = 2.0 * ell + 1.0
+    data = 10.0 ** y * np.random.default_rng([W.NOISE_SEED, 400]).chisquare(k) / k
+    # Fisher matrix of the cosmic-variance likelihood: sum_l (k/2) dlnC/dtheta_i dlnC/dtheta_j
+    J = np.log(10.0) * jacobian_cs(lambda t: emulate(t, net), th)
+    F = (J * (0.5 * k)[:, None]).T @ J
+    fs = np.sqrt(np.diag(np.linalg.inv(F)))
+    np.savez_compressed(os.path.join(OUT, "workload_cmbtt_cv.npz"), data=data, theta_fid=th, fisher_sigma=fs)
+    m.update(data=data)
+    print("cmbtt_cv: fisher sigma", fs, "logL(fid)", loglike(th[None, :], m))
 
 
 def make_cmb_block():
@@ -150,6 +170,7 @@ def make_shear(name, structure_name, w0wa=None, tag=3):
 if __name__ == "__main__":
     make_cmb6()
     make_cmb_block()
+    make_cmb_cv()
     make_shear("shear64", "shear64", tag=3)
     make_shear("shear10", "shear10", tag=4)
     make_shear("shear_cmp", "shear10", w0wa=W.w0wa_point(), tag=5)

@@ -54,3 +54,60 @@ def test_te_linear_other_spectra_exponentiated():
     for s, is_log in enumerate(m["spec_log"]):
         y = emulate(th, m["nets"][s])[0]
         np.testing.assert_allclose(mv[4 * s:4 * s + 4], 10 ** y if is_log else y, rtol=1e-14)
+
+
+# ------------------------------------------------------- cosmic-variance limit
+def constant_cv_model(logc, data, ell_min):
+    """CV model whose emulator returns log10 C = logc for every theta (zero last
+    layer), so the likelihood is an explicit function of C_l."""
+    import copy
+    m = copy.deepcopy(W.structure("cmbtt_cv"))
+    n = len(logc)
+    net = m["nets"][0]
+    net["W"][-1] = np.zeros((n, net["W"][-1].shape[1]))
+    net["b"][-1] = np.zeros(n)
+    net["out_mu"] = np.asarray(logc, dtype=np.float64)
+    net["out_sigma"] = np.ones(n)
+    m["data"] = np.asarray(data, dtype=np.float64)
+    m["ell_min"] = ell_min
+    return m
+
+
+def test_cv_likelihood_is_the_chi2_density():
+    from scipy import stats
+    rng = np.random.default_rng(0)
+    ell_min, n = 7, 40
+    ell = ell_min + np.arange(n)
+    k = 2.0 * ell + 1
+    C = 10.0 ** rng.uniform(-10, -8, n)
+    data = C * rng.chisquare(k) / k
+    m = constant_cv_model(np.log10(C), data, ell_min)
+    got = cmb.loglike_cv(np.full((2, 6), 0.5), m)
+    want = np.sum(stats.chi2.logpdf(k * data / C, k) + np.log(k / C))
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+def test_cv_likelihood_peaks_at_the_observed_spectrum():
+    rng = np.random.default_rng(1)
+    n = 30
+    data = 10.0 ** rng.uniform(-10, -8, n)
+    base = cmb.loglike_cv(np.full((1, 6), 0.5), constant_cv_model(np.log10(data), data, 2))[0]
+    for j in (0, 11, 29):
+        for dlog in (1e-3, -1e-3):
+            logc = np.log10(data).copy()
+            logc[j] += dlog
+            assert cmb.loglike_cv(np.full((1, 6), 0.5), constant_cv_model(logc, data, 2))[0] < base
+
+
+def test_cv_density_is_normalised():
+    """Integral over the observed Ch_l of p(Ch_l | C_l) is 1 (single multipole)."""
+    from scipy import integrate
+    for ell in (2, 30, 400):
+        C = 3e-9
+        m = constant_cv_model([np.log10(C)], [C], ell)
+
+        def p(ch):
+            m["data"] = np.array([ch])
+            return np.exp(cmb.loglike_cv(np.full((1, 6), 0.5), m)[0])
+        total, _ = integrate.quad(p, 0.0, 20 * C, points=[C], limit=200)
+        assert abs(total - 1.0) < 1e-8, (ell, total)

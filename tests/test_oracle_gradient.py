@@ -27,6 +27,12 @@ def test_cmb_block_gradient():
     check(m, th, 1e-5)
 
 
+def test_cmb_cv_gradient():
+    m = W.load_model("cmbtt_cv")
+    th = W.posterior_draws(m["theta_fid"], m["fisher_sigma"], 2)
+    check(m, th, 1e-5)
+
+
 def test_shear_gradient_and_extra_nuisance_zero():
     m = W.load_model("shear10")
     scale = np.minimum(m["fisher_sigma"], 0.1 * np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0))

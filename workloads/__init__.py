@@ -108,6 +108,28 @@ def net_dict(layers, in_shift, in_scale, out_mu, out_sigma):
 
 
 # -------------------------------------------------------------------- configs
+def cmb_cv_structure(n_ell=2500, hidden=(512, 512, 512, 512), seed=MODEL_SEED):
+    """Temperature spectrum emulator 6 -> 4x512 -> n_ell (log10 C_l at l = 2, 3, ...)
+    for the cosmic-variance-limited likelihood; output baseline as the TT
+    network of the four-spectrum workload, sigma_out = 0.1."""
+    d = 6
+    ell = np.arange(2, 2 + n_ell, dtype=np.float64)
+    tt = 1e-9 * (ell / 100.0) ** -1.0 * np.exp(-((ell / 1500.0) ** 2))
+    layers = draw_mlp((d, *hidden, n_ell), seed, 20, "wide")
+    net = net_dict(layers, np.full(d, 0.5), np.full(d, 0.5), np.log10(tt), np.full(n_ell, 0.1))
+    return {
+        "kind": "cmb_cv",
+        "d": d,
+        "prior_kind": np.zeros(d, dtype=np.int32),
+        "prior_a": np.zeros(d),
+        "prior_b": np.ones(d),
+        "nets": [net],
+        "spec_log": [True],
+        "ell_min": 2,
+    }
+
+
+
 def cmb_diag_structure(hidden=(128, 128, 128), n_out=200, seed=MODEL_SEED):
     """Small CMB-style emulator: 6 -> 3x128 -> 200, weights N(0, 0.1^2)."""
     d = 6
@@ -261,6 +283,8 @@ def structure(name: str):
         return cmb_diag_structure()
     if name == "cmb4x2500":
         return cmb_block_structure()
+    if name == "cmbtt_cv":
+        return cmb_cv_structure()
     if name == "shear64":
         return shear_structure(n_z=64)
     if name == "shear10":
