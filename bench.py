@@ -230,6 +230,16 @@ def ns_leg(Model, W):
         r = g.run(2400, 1200, 30, precision=prec, seed=2, n_replicates=1000)
         out[f"to_sigma_0.1_{prec}"] = dict(n_live=2400, n_delete=1200, logz=r["logz"], sigma=r["sigma"],
                                            wall_s=r["wall_s"], n_iter=r["n_iter"], n_evals=r["n_evals"])
+    g.close()
+    # the paper's CMB analysis shape: cosmic-variance-limited TT likelihood of
+    # one 6-512x4-2500 emulator, 1000 live points, 500 replaced per iteration
+    m = W.load_model("cmbtt_cv")
+    g = Model(m)
+    for prec in ("fp64", "bf16x3"):
+        r = g.run(1000, 500, 30, precision=prec, seed=3, n_replicates=1000)
+        out[f"cmbtt_cv_{prec}"] = dict(n_live=1000, n_delete=500, logz=r["logz"], sigma=r["sigma"],
+                                       wall_s=r["wall_s"], n_iter=r["n_iter"], n_evals=r["n_evals"])
+    g.close()
     print(f"# ns: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
 

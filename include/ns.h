@@ -69,7 +69,9 @@ typedef enum {
     NS_MODEL_CMB_DIAG = 0,   /* one emulator, Gaussian with diagonal covariance */
     NS_MODEL_CMB_BLOCK = 1,  /* TT, TE, EE, PP emulators; 3x3 block + diagonal  */
     NS_MODEL_SHEAR = 2,      /* cosmic shear, App. A                            */
-    NS_MODEL_GAUSS = 3       /* diagonal Gaussian in theta (closed-form evidence) */
+    NS_MODEL_GAUSS = 3,      /* diagonal Gaussian in theta (closed-form evidence) */
+    NS_MODEL_CMB_CV = 4      /* TT emulator, cosmic-variance-limited likelihood:
+                                (2l+1) Ch_l / C_l ~ chi^2 with 2l+1 d.o.f. (Sec. 2.3) */
 } ns_model_kind;
 
 enum { NS_PRIOR_UNIFORM = 0, NS_PRIOR_NORMAL = 1 };
@@ -100,12 +102,14 @@ typedef struct ns_model_desc {
     const double* prior_a;        /* [d] uniform lower bound / normal mean      */
     const double* prior_b;        /* [d] uniform upper bound / normal sigma     */
 
-    int32_t n_nets;               /* CMB_DIAG 1, CMB_BLOCK 4, SHEAR 1, GAUSS 0   */
+    int32_t n_nets;               /* CMB_DIAG 1, CMB_BLOCK 4, SHEAR 1, GAUSS 0,
+                                     CMB_CV 1 (outputs log10 C_l, spec_log 1)   */
     const ns_net_desc* nets;
     const int32_t* spec_log;      /* CMB: [n_nets], 1 -> C = 10^y, 0 -> C = y    */
 
     int32_t n_data;               /* data vector length                         */
-    const double* data;           /* [n_data]                                   */
+    const double* data;           /* [n_data]; CMB_CV: observed Ch_l > 0 at
+                                     l = ell_min, ell_min + 1, ...               */
     const double* sigma;          /* CMB_DIAG: [n_data] standard deviations     */
     const double* cov_blocks;     /* CMB_BLOCK: [n_ell x 3 x 3] (TT, TE, EE)    */
     const double* sigma_pp;       /* CMB_BLOCK: [n_ell]                         */
@@ -120,7 +124,8 @@ typedef struct ns_model_desc {
     int32_t n_z;                  /* emulator redshift nodes on [0, 1/a_min-1]  */
     double k_min, k_max;          /* emulated k range [1/Mpc], log-spaced       */
     int32_t n_k;
-    double ell_min, ell_max;      /* log-spaced multipoles                      */
+    double ell_min, ell_max;      /* SHEAR: log-spaced multipoles; CMB_CV:
+                                     ell_min = first multipole (integer >= 0)    */
     int32_t n_ell;
     const int32_t* pidx;          /* [9 + 3 n_bins] theta index per physical slot
                                      (omega_b, omega_cdm, h, n_s, lnAs, w0, wa,

@@ -13,7 +13,7 @@ NS_OK, NS_E_INVALID, NS_E_SHAPE, NS_E_HIP, NS_E_NOMEM, NS_E_NOT_SPD, NS_E_UNSUPP
 STATUS_NAMES = {0: "NS_OK", -1: "NS_E_INVALID", -2: "NS_E_SHAPE", -3: "NS_E_HIP", -4: "NS_E_NOMEM",
                 -5: "NS_E_NOT_SPD", -6: "NS_E_UNSUPPORTED"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
-KINDS = {"cmb_diag": 0, "cmb_block": 1, "shear": 2, "gauss": 3}
+KINDS = {"cmb_diag": 0, "cmb_block": 1, "shear": 2, "gauss": 3, "cmb_cv": 4}
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)

@@ -89,6 +89,39 @@ __global__ __launch_bounds__(256) void cmb_seed_kernel(
     }
 }
 
+// Cosmic-variance seeds: y = log10 C_l, logL = c - sum (k/2)(ln 10 y + Ch 10^-y),
+// d logL / d y_l = -(k/2) ln 10 (1 - Ch_l / C_l); delta = that times sigma_out.
+template <class T>
+__global__ __launch_bounds__(256) void cv_seed_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
+    const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ y, int n,
+    const double* __restrict__ data, const double* __restrict__ halfk, const double* __restrict__ sigma_out,
+    double cst, int n_pad, T* __restrict__ delta, double* __restrict__ logl) {
+    __shared__ double red[4];
+    const int64_t row = blockIdx.x;
+    if (row >= B) return;
+    const bool ok = in_support_row(theta + row * ld, d, pk, pa, pb);
+    const T* yr = y + row * (int64_t)n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
+        double dv = 0.0;
+        if (i < n) {
+            const double lc = 2.302585092994045684 * (double)yr[i];
+            const double r = data[i] * exp(-lc);
+            s += halfk[i] * (lc + r);
+            dv = -halfk[i] * 2.302585092994045684 * (1.0 - r) * sigma_out[i];
+        }
+        delta[row * n_pad + i] = ok ? (T)dv : T(0);
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = red[0] + red[1] + red[2] + red[3];
+        logl[row] = ok ? cst - t : -INFINITY;
+    }
+}
+
 // grad[w][c] = direct[w][c] + sum_g sum_z sum_k [src_k == c] gx[g][w rpw + z][k]; zero outside the support.
 __global__ void grad_assemble_kernel(int64_t B, int d, int G, int rpw, int n_in, const int* __restrict__ src,
                                      const double* __restrict__ gx, const double* __restrict__ direct,
@@ -153,6 +186,31 @@ void loglike_grad_batch(ns_model* m, const double* theta, int64_t ld, int64_t B,
     m->ws_gact[1].ensure(G * gstride * elem);
     // reduced forms: forward in the requested form, adjoint in FP32
     const int bprec = f64 ? NS_FP64 : NS_FP32;
+    if (m->kind == NS_MODEL_CMB_CV) {
+        const int64_t n = m->n_data;
+        m->ws_out.ensure((size_t)B * n * elem);
+        void* outs[1] = {m->ws_out.p};
+        const int raw[1] = {0};
+        emulator_forward(m, ids, 1, theta, ld, B, outs, n, raw, prec, nullptr, s, true);
+        {
+            TraceScope ts(m, s, "adj_seed_cv");
+            if (f64)
+                hipLaunchKernelGGL(cv_seed_kernel<double>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, m->d, pk,
+                                   pa, pb, m->ws_out.as<double>(), (int)n, m->data.as<double>(),
+                                   m->cv_halfk.as<double>(), m->nets[0]->out_sigma64.as<double>(), m->logl_const,
+                                   n_pad, m->ws_gact[0].as<double>(), logl);
+            else
+                hipLaunchKernelGGL(cv_seed_kernel<float>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, m->d, pk,
+                                   pa, pb, m->ws_out.as<float>(), (int)n, m->data.as<double>(),
+                                   m->cv_halfk.as<double>(), m->nets[0]->out_sigma64.as<double>(), m->logl_const,
+                                   n_pad, m->ws_gact[0].as<float>(), logl);
+            NS_HIP(hipGetLastError());
+        }
+        emulator_backward(m, ids, 1, B, bprec, s);
+        TraceScope ts(m, s, "adj_assemble");
+        grad_assemble(m, B, 1, rpw, nullptr, logl, grad, s);
+        return;
+    }
     if (m->kind == NS_MODEL_CMB_DIAG || m->kind == NS_MODEL_CMB_BLOCK) {
         const int64_t n = m->n_data;
         m->ws_out.ensure((size_t)B * n * elem);

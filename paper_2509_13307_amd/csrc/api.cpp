@@ -239,7 +239,7 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
     const double LOG2PI = std::log(2.0 * M_PI);
     m->kind = D->kind;
     m->d = D->d;
-    NS_CHECK(D->kind >= 0 && D->kind <= 3, NS_E_INVALID, "unknown model kind");
+    NS_CHECK(D->kind >= 0 && D->kind <= 4, NS_E_INVALID, "unknown model kind");
     NS_CHECK(D->d >= 1 && D->d <= 64, NS_E_SHAPE, "d must be in [1, 64]");
     check_ptr(D->prior_kind, "prior_kind");
     check_ptr(D->prior_a, "prior_a");
@@ -283,7 +283,7 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
     for (auto* n : m->nets) NS_CHECK(n->dims[0] == n_in, NS_E_SHAPE, "networks must share their inputs");
     m->n_data = D->n_data;
 
-    if (D->kind == NS_MODEL_CMB_DIAG || D->kind == NS_MODEL_CMB_BLOCK) {
+    if (D->kind == NS_MODEL_CMB_DIAG || D->kind == NS_MODEL_CMB_BLOCK || D->kind == NS_MODEL_CMB_CV) {
         NS_CHECK(n_in <= D->d, NS_E_SHAPE, "CMB emulator inputs exceed d");
         m->emu_src.resize(n_in);
         for (int i = 0; i < n_in; ++i) m->emu_src[i] = i;
@@ -291,7 +291,26 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         check_ptr(D->spec_log, "spec_log");
         m->spec_log.assign(D->spec_log, D->spec_log + D->n_nets);
     }
-    if (D->kind == NS_MODEL_CMB_DIAG) {
+    if (D->kind == NS_MODEL_CMB_CV) {
+        const int n = D->n_data;
+        NS_CHECK(n == m->nets[0]->dims.back(), NS_E_SHAPE, "n_data must equal the emulator outputs");
+        NS_CHECK(m->spec_log[0] == 1, NS_E_INVALID, "the CMB_CV emulator must output log10 C_l (spec_log 1)");
+        NS_CHECK(D->ell_min >= 0.0 && D->ell_min == std::floor(D->ell_min), NS_E_INVALID,
+                 "ell_min must be a non-negative integer");
+        // log p(Ch | C) = c_l - (k/2)(ln C + Ch/C), k = 2l+1, with
+        // c_l = ln k + (k/2 - 1)(ln k + ln Ch) - (k/2) ln 2 - ln Gamma(k/2)
+        std::vector<double> hk(n);
+        double c = 0.0;
+        for (int b = 0; b < n; ++b) {
+            NS_CHECK(D->data[b] > 0.0, NS_E_INVALID, "observed spectrum must be > 0");
+            const double k = 2.0 * (D->ell_min + b) + 1.0;
+            hk[b] = 0.5 * k;
+            c += std::log(k) + (0.5 * k - 1.0) * (std::log(k) + std::log(D->data[b])) - 0.5 * k * std::log(2.0) -
+                 std::lgamma(0.5 * k);
+        }
+        upload(m->cv_halfk, hk.data(), hk.size());
+        m->logl_const = c;
+    } else if (D->kind == NS_MODEL_CMB_DIAG) {
         NS_CHECK(D->n_data == m->nets[0]->dims.back(), NS_E_SHAPE, "n_data must equal the emulator outputs");
         check_ptr(D->sigma, "sigma");
         std::vector<double> is(D->n_data);

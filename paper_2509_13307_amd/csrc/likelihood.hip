@@ -99,6 +99,32 @@ __global__ __launch_bounds__(256) void chi2_block_kernel(
     }
 }
 
+// ----------------------------------------------- cosmic-variance-limited TT
+// One wave per walker; y = log10 C_l (emulator output), FP64 accumulation:
+// logL = c - sum_l (k_l/2) (ln 10 y_l + Ch_l 10^-y_l).
+template <class T>
+__global__ __launch_bounds__(256) void cv_loglike_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
+    const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ y, int n, int64_t ldm,
+    const double* __restrict__ data, const double* __restrict__ halfk, double cst, double* __restrict__ logl,
+    const int* __restrict__ count) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (count) B = min<int64_t>(B, *count);
+    if (row >= B) return;
+    const T* yr = y + row * ldm;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double lc = 2.302585092994045684 * (double)yr[i];     // ln C_l
+        s += halfk[i] * (lc + data[i] * exp(-lc));
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+        const bool ok = in_support(theta + row * ld, d, pk, pa, pb);
+        logl[row] = ok ? cst - s : -INFINITY;
+    }
+}
+
 // ------------------------------------------------------------ Gaussian test
 __global__ void gauss_kernel(const double* __restrict__ theta, int64_t ld, int64_t B, int d,
                              const int* __restrict__ pk, const double* __restrict__ pa,
@@ -163,8 +189,19 @@ void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const voi
     const int* pk = m->prior_kind.as<int>();
     const double* pa = m->prior_a.as<double>();
     const double* pb = m->prior_b.as<double>();
-    TraceScope ts(m, s, m->kind == NS_MODEL_CMB_DIAG ? "chi2_diag" : "chi2_block");
-    if (m->kind == NS_MODEL_CMB_DIAG) {
+    TraceScope ts(m, s, m->kind == NS_MODEL_CMB_DIAG ? "chi2_diag" : (m->kind == NS_MODEL_CMB_CV ? "cv_loglike"
+                                                                                                 : "chi2_block"));
+    if (m->kind == NS_MODEL_CMB_CV) {
+        dim3 g((unsigned)((B + 3) / 4));
+        if (prec == NS_FP64)
+            hipLaunchKernelGGL(cv_loglike_kernel<double>, g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
+                               (const double*)mvec, m->n_data, cmb_row_stride(m), m->data.as<double>(),
+                               m->cv_halfk.as<double>(), m->logl_const, logl, count);
+        else
+            hipLaunchKernelGGL(cv_loglike_kernel<float>, g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
+                               (const float*)mvec, m->n_data, cmb_row_stride(m), m->data.as<double>(),
+                               m->cv_halfk.as<double>(), m->logl_const, logl, count);
+    } else if (m->kind == NS_MODEL_CMB_DIAG) {
         dim3 g((unsigned)((B + 3) / 4));
         if (prec == NS_FP64)
             hipLaunchKernelGGL(chi2_diag_kernel<double>, g, dim3(256), 0, s, theta, ld, B, m->d, pk, pa, pb,
@@ -197,7 +234,7 @@ void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
         return;
     }
     const size_t elem = prec == NS_FP64 ? 8 : 4;
-    if (m->kind == NS_MODEL_CMB_DIAG || m->kind == NS_MODEL_CMB_BLOCK) {
+    if (m->kind == NS_MODEL_CMB_DIAG || m->kind == NS_MODEL_CMB_BLOCK || m->kind == NS_MODEL_CMB_CV) {
         // spectrum g at column g sp of rows of cmb_row_stride: 128-byte aligned
         // output lines for the emulator's stores
         const int64_t n = cmb_row_stride(m), sp = cmb_spec_stride(m);
@@ -209,7 +246,10 @@ void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
             ids[g] = g;
             outs[g] = m->ws_out.as<char>() + g * sp * elem;
         }
-        emulator_forward(m, ids, G, theta, ld, B, outs, n, m->spec_log.data(), prec, count, s);
+        // the cosmic-variance stage reads log10 C_l itself
+        static const int raw[4] = {0, 0, 0, 0};
+        emulator_forward(m, ids, G, theta, ld, B, outs, n, m->kind == NS_MODEL_CMB_CV ? raw : m->spec_log.data(),
+                         prec, count, s);
         cmb_chi2(m, theta, ld, B, m->ws_out.p, logl, prec, count, s);
         return;
     }

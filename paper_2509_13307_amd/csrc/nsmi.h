@@ -131,6 +131,7 @@ struct ns_model {
     nsmi::DevBuf inv_sigma_pp;       // block: [n_ell]
     int n_ell_cmb = 0;
     double logl_const = 0.0;         // -sum log diag(L) - n/2 log 2pi
+    nsmi::DevBuf cv_halfk;           // CMB_CV: (2l+1)/2 per multipole [n]
 
     // shear
     int n_bins = 0, n_a = 0, n_z = 0, n_k = 0, n_ell = 0, n_pairs = 0;

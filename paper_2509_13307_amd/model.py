@@ -29,7 +29,7 @@ class Model:
     """A likelihood model resident on one HIP device.
 
     ``desc`` is a dict with the fields of ``ns_model_desc`` (see include/ns.h):
-    kind ("cmb_diag", "cmb_block", "shear", "gauss"), d, prior_kind/a/b, nets
+    kind ("cmb_diag", "cmb_block", "cmb_cv", "shear", "gauss"), d, prior_kind/a/b, nets
     (each with W, b, beta, gamma, in_shift, in_scale, out_mu, out_sigma),
     spec_log, data, sigma / cov_blocks + sigma_pp / cov, the shear geometry,
     pidx/pfix, and mu/sigma for "gauss".
@@ -60,8 +60,10 @@ class Model:
             data = _f64(desc["data"])
             D.n_data = data.size
             D.data = self._p(data, C.c_double_p)
-            if self.kind in ("cmb_diag", "cmb_block"):
+            if self.kind in ("cmb_diag", "cmb_block", "cmb_cv"):
                 D.spec_log = self._p(_i32([int(x) for x in desc["spec_log"]]), C.c_int32_p)
+            if self.kind == "cmb_cv":
+                D.ell_min = float(desc["ell_min"])
             if self.kind == "cmb_diag":
                 D.sigma = self._p(_f64(desc["sigma"]), C.c_double_p)
             elif self.kind == "cmb_block":

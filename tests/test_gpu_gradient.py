@@ -45,7 +45,7 @@ def center_of(m):
     return m["theta_fid"] if "theta_fid" in m else np.asarray(m["mu"])
 
 
-@pytest.mark.parametrize("name,B", [("gauss", 33), ("cmb6", 77), ("cmb4x2500", 20)])
+@pytest.mark.parametrize("name,B", [("gauss", 33), ("cmb6", 77), ("cmb4x2500", 20), ("cmbtt_cv", 20)])
 def test_fp64_gradient_matches_complex_step(name, B):
     say(f"case grad fp64 {name}")
     m, g = gm(name)
@@ -64,17 +64,18 @@ def test_fp64_gradient_matches_complex_step(name, B):
     assert err.max() < 1e-8
 
 
+@pytest.mark.parametrize("name", ["cmb4x2500", "cmbtt_cv"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
-def test_reduced_gradient(prec):
-    say(f"case grad {prec} cmb4x2500")
-    m, g = gm("cmb4x2500")
+def test_reduced_gradient(name, prec):
+    say(f"case grad {prec} {name}")
+    m, g = gm(name)
     th = W.posterior_draws(center_of(m), scale_of(m), 16, tag=6)
     ref_l, ref_g = loglike_grad(th, m)
     logl, grad = g.loglike_grad(torch.tensor(th, device=DEV), prec)
     grad = grad.cpu().numpy()
     scale = np.max(np.abs(ref_g), axis=1, keepdims=True)
     err = np.abs(grad - ref_g) / scale
-    say(f"cmb4x2500 {prec}: max rel gradient error {err.max():.3e}")
+    say(f"{name} {prec}: max rel gradient error {err.max():.3e}")
     lim = {"fp32": 1e-3, "bf16x3": 1e-3, "bf16": 0.5}[prec]
     assert err.max() < lim
 

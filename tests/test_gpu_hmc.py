@@ -72,6 +72,14 @@ def test_hmc_replays_oracle_cmb6():
     assert res["n_accept"] > 0
 
 
+def test_hmc_replays_oracle_cmbtt_cv():
+    say("case hmc cmbtt_cv")
+    m = W.load_model("cmbtt_cv")
+    minv = np.minimum(m["fisher_sigma"], 0.1) ** 2
+    res, ref = replay(m, C=3, n_iter=3, L=5, step=0.25, minv=minv, seed=6, tag=6)
+    assert res["n_accept"] > 0
+
+
 def test_hmc_replays_oracle_shear10():
     say("case hmc shear10")
     m = W.load_model("shear10")

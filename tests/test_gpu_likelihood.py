@@ -68,7 +68,8 @@ def check_fp64(ref, got, label):
     assert np.all(d <= tol), (label, d.max())
 
 
-@pytest.mark.parametrize("name,B", [("cmb6", 1000), ("cmb4x2500", 300), ("shear10", 24), ("shear64", 12)])
+@pytest.mark.parametrize("name,B", [("cmb6", 1000), ("cmb4x2500", 300), ("cmbtt_cv", 300), ("shear10", 24),
+                                    ("shear64", 12)])
 def test_fp64_posterior_and_prior(built, name, B):
     say(f"case fp64 {name} B={B}")
     m, g = gpu_model(name)
@@ -80,7 +81,8 @@ def test_fp64_posterior_and_prior(built, name, B):
         check_fp64(ref, got, f"{name} {label}")
 
 
-@pytest.mark.parametrize("name,B,sample", [("cmb4x2500", 4096, 40), ("shear64", 4096, 6), ("shear10", 16384, 6)])
+@pytest.mark.parametrize("name,B,sample", [("cmb4x2500", 4096, 40), ("cmbtt_cv", 4096, 40), ("shear64", 4096, 6),
+                                           ("shear10", 16384, 6)])
 def test_fp64_full_size_sampled(built, name, B, sample):
     say(f"case fp64 full {name} B={B}")
     m, g = gpu_model(name)
@@ -134,12 +136,13 @@ def test_batch_and_permutation_invariance(built):
 LOWP_LIMIT = {
     ("cmb6", "fp32"): 1e-2, ("cmb6", "bf16x3"): 1e-2, ("cmb6", "bf16"): 2.0,
     ("cmb4x2500", "fp32"): 1e-2, ("cmb4x2500", "bf16x3"): 1e-2, ("cmb4x2500", "bf16"): 1.0,
+    ("cmbtt_cv", "fp32"): 1e-2, ("cmbtt_cv", "bf16x3"): 1e-2, ("cmbtt_cv", "bf16"): 5.0,
     ("shear10", "fp32"): 1e-2, ("shear10", "bf16x3"): 1e-2, ("shear10", "bf16"): 0.1,
     ("shear64", "fp32"): 1e-2, ("shear64", "bf16x3"): 1e-2, ("shear64", "bf16"): 0.1,
 }
 
 
-@pytest.mark.parametrize("name", ["cmb6", "cmb4x2500", "shear10", "shear64"])
+@pytest.mark.parametrize("name", ["cmb6", "cmb4x2500", "cmbtt_cv", "shear10", "shear64"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
 def test_reduced_precision_forms(built, name, prec):
     say(f"case {prec} {name}")
@@ -156,7 +159,8 @@ def test_reduced_precision_forms(built, name, prec):
     assert d.max() <= LOWP_LIMIT[(name, prec)]
 
 
-@pytest.mark.parametrize("name,B", [("cmb6", 300), ("cmb4x2500", 333), ("shear10", 70), ("shear64", 9)])
+@pytest.mark.parametrize("name,B", [("cmb6", 300), ("cmb4x2500", 333), ("cmbtt_cv", 333), ("shear10", 70),
+                                    ("shear64", 9)])
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
 def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
     """The one-kernel emulator gives bitwise the layer-by-layer result, with
@@ -202,3 +206,43 @@ def test_fp64_shear_few_redshift_nodes(built, n_z):
     got = run_gpu(g, th)
     g.close()
     check_fp64(ref, got, f"shear n_z={n_z}")
+
+
+def test_cv_model_validation(built):
+    """The cosmic-variance model rejects a non-positive observed spectrum, a
+    non-integer first multipole and an emulator that does not output log10 C_l."""
+    say("case cv validation")
+    from paper_2509_13307_amd import Model
+    from paper_2509_13307_amd._capi import NSError
+    base = W.load_model("cmbtt_cv")
+    for key, val in (("data", np.where(np.arange(base["data"].size) == 7, 0.0, base["data"])),
+                     ("ell_min", 2.5), ("spec_log", [False])):
+        bad = dict(base)
+        bad[key] = val
+        with pytest.raises(NSError):
+            Model(bad)
+
+
+def test_cv_loglike_shifts_with_a_constant_offset(built):
+    """Scaling every emulated C_l by 10^c (an output shift c in log10 C_l) changes
+    logL by -sum_l (k_l/2)(ln 10 c + Ch_l/C_l (10^-c - 1)): checked on the GPU
+    against that closed form evaluated with the oracle's spectra."""
+    say("case cv offset")
+    from paper_2509_13307_amd import Model
+    from oracle.emulator import emulate
+    m = W.load_model("cmbtt_cv")
+    th = W.posterior_draws(m["theta_fid"], post_scale(m), 9, tag=12)
+    c = 0.013
+    shifted = dict(m)
+    net = dict(m["nets"][0])
+    net["out_mu"] = np.asarray(net["out_mu"]) + c
+    shifted["nets"] = [net]
+    g0, g1 = Model(m), Model(shifted)
+    l0, l1 = run_gpu(g0, th), run_gpu(g1, th)
+    g0.close()
+    g1.close()
+    C = 10.0 ** emulate(th, m["nets"][0])
+    k = 2.0 * (m["ell_min"] + np.arange(C.shape[1])) + 1.0
+    want = -np.sum(0.5 * k * (np.log(10.0) * c + m["data"] / C * (10.0 ** -c - 1.0)), axis=1)
+    say(f"cv offset: max |d| {np.abs((l1 - l0) - want).max():.3e}")
+    np.testing.assert_allclose(l1 - l0, want, rtol=1e-9, atol=1e-6)

@@ -45,7 +45,7 @@ def walkers_above(model, n, seed):
     return u, ll, lstar, u[keep], ll[keep]
 
 
-@pytest.mark.parametrize("name,k_live,n_inner", [("cmb6", 100, 6), ("shear10", 40, 2)])
+@pytest.mark.parametrize("name,k_live,n_inner", [("cmb6", 100, 6), ("cmbtt_cv", 64, 3), ("shear10", 40, 2)])
 def test_slice_step_replays_oracle(name, k_live, n_inner):
     say(f"case slice step {name}")
     m = W.load_model(name)
