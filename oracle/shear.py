@@ -23,10 +23,15 @@ a_min = 1/(1 + 5.02) (App. A, last paragraph):
 4. Eq. (A1) sums four Limber integrals that all use P_dd, so the sum equals one
    Limber integral of the effective window W_i = W^g_i + W^I_i.
 5. Matter power spectrum: the emulator gives log10 P at n_k log-spaced k and
-   N_z redshift nodes uniform on [0, z_max]; a not-a-knot cubic spline in z
-   carries it to the z of every grid node; a Catmull-Rom cubic in log10 k
-   (linear ghost nodes at both ends) evaluates it at k = (l + 1/2)/chi
-   (Eq. A2).  P = 0 outside [k_min, k_max] and at chi = 0.
+   N_z redshift nodes; the table is carried to the z of every grid node in z,
+   either ("cubic") by a not-a-knot cubic spline over nodes uniform on
+   [0, z_max], or ("linear", App. B) by linear interpolation over nodes at
+   scale factors evenly spaced from 1 to a_min.  With N_z = n_a the linear
+   nodes are the integration nodes themselves, so the emulator is evaluated at
+   every node (the paper's "full" likelihood); N_z about n_a / 10 is its
+   interpolated likelihood.  A Catmull-Rom cubic in log10 k (linear ghost nodes
+   at both ends) then evaluates it at k = (l + 1/2)/chi (Eq. A2).  P = 0
+   outside [k_min, k_max] and at chi = 0.
 6. Limber, Eq. (A2), trapezoid in a with the analytic Jacobian J, and the
    multiplicative bias (App. A, second item):
        C_ij(l) = (1 + m_i)(1 + m_j) sum_j q_j J_j W_i W_j / chi_j^2 P(k_lj, z_j).
@@ -36,8 +41,11 @@ a_min = 1/(1 + 5.02) (App. A, last paragraph):
 Pinned by: the Einstein-de Sitter closed forms chi = 2 (c/H0)(1 - sqrt a),
 D = a; scipy.integrate.quad distances for flat LCDM; Eqs. (A2)-(A4) integrated
 directly in chi by adaptive quadrature for an EdS background and a power-law
-P; exactness of the z-spline on cubics and of the k-interpolation on
-quadratics; and scipy.stats.multivariate_normal for the Gaussian.
+P; exactness of the z-spline on cubics, of the linear z-interpolation on
+lines, its one-sided error bound on concave tables, and the identity of the
+N_z = n_a table with the emulator evaluated at every node; exactness of the
+k-interpolation on quadratics; identical spectra for identical bins; and
+scipy.stats.multivariate_normal for the Gaussian.
 """
 import numpy as np
 from scipy.interpolate import CubicSpline
@@ -54,7 +62,15 @@ def a_grid(model):
     return np.linspace(1.0, model["a_min"], model["n_a"])
 
 
+def linear_z(model):
+    return model.get("z_interp", "cubic") == "linear"
+
+
 def z_nodes(model):
+    """Emulator redshift nodes: uniform in z ("cubic"), or at scale factors
+    evenly spaced from 1 to a_min ("linear")."""
+    if linear_z(model):
+        return 1.0 / np.linspace(1.0, model["a_min"], model["n_z"]) - 1.0
     return np.linspace(0.0, 1.0 / model["a_min"] - 1.0, model["n_z"])
 
 
@@ -183,10 +199,18 @@ def emulator_table(cos, model):
 
 
 def interp_z(Y, model):
-    """Not-a-knot cubic spline along z from the nodes to z_j = 1/a_j - 1."""
+    """Y [B, N_z, n_k] at the nodes -> [B, n_a, n_k] at z_j = 1/a_j - 1: a
+    not-a-knot cubic spline, or piecewise-linear interpolation, along z."""
     a = a_grid(model)
-    zj = np.minimum(1.0 / a - 1.0, z_nodes(model)[-1])
-    return CubicSpline(z_nodes(model), Y, axis=1, bc_type="not-a-knot")(zj)  # [B, n_a, n_k]
+    zn = z_nodes(model)
+    zj = np.minimum(1.0 / a - 1.0, zn[-1])
+    if linear_z(model):
+        out = np.empty((Y.shape[0], zj.size, Y.shape[2]), dtype=Y.dtype)
+        for b in range(Y.shape[0]):
+            for c in range(Y.shape[2]):
+                out[b, :, c] = np.interp(zj, zn, Y[b, :, c])
+        return out
+    return CubicSpline(zn, Y, axis=1, bc_type="not-a-knot")(zj)
 
 
 def interp_k(Yz, log10k, model):

@@ -19,6 +19,10 @@ shear*      Gaussian (Knox) covariance per multipole,
             per bin, f_sky = 0.35), plus (0.01)^2 C_fid C_fid^T; data = C_fid + L eps.
 shear_cmp   as shear10 with the data made at a seeded (w0, wa) point; shared by
             the LCDM (37 parameters) and w0wa (39 parameters) models.
+shear_paper the paper's shape: 10 bins, 1025 nodes, n_bar = 3 arcmin^-2 per bin
+            (30 in total); data made with the full likelihood (emulator at
+            every node) at theta_fid (LCDM values); shared by shear_full,
+            shear_interp and their LCDM variants.
 Every file also stores theta_fid and fisher_sigma (Fisher 1-sigma per
 parameter; prior width for parameters the data do not constrain).
 """
@@ -130,7 +134,7 @@ def knox_cov(C, model):
     ell = shear.ell_grid(model)
     rho = (model["ell_max"] / model["ell_min"]) ** (1.0 / (ne - 1))
     dl = ell * (np.sqrt(rho) - 1.0 / np.sqrt(rho))
-    n_sr = 6.0 * (60.0 * 180.0 / np.pi) ** 2
+    n_sr = 30.0 / nb * (60.0 * 180.0 / np.pi) ** 2        # 30 arcmin^-2 over the bins
     noise = 0.3 ** 2 / n_sr
     prs = shear.pairs(nb)
     Cm = np.zeros((ne, nb, nb))
@@ -174,3 +178,4 @@ if __name__ == "__main__":
     make_shear("shear64", "shear64", tag=3)
     make_shear("shear10", "shear10", tag=4)
     make_shear("shear_cmp", "shear10", w0wa=W.w0wa_point(), tag=5)
+    make_shear("shear_paper", "shear_full", tag=6)

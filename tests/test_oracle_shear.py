@@ -207,3 +207,89 @@ def test_extra_nuisances_do_not_enter():
     from oracle.likelihood import loglike
     ll = loglike(th, m)
     assert ll[0] == ll[1]
+
+
+def small_linear(n_z, n_a=41, n_bins=2):
+    return W.shear_structure(n_z=n_z, n_bins=n_bins, n_extra=0, hidden=(8,), n_k=30, n_a=n_a,
+                             z_interp="linear")
+
+
+def test_linear_z_full_grid_is_the_emulator_at_every_node():
+    """N_z = n_a: the table carried to the integration nodes equals the emulator
+    evaluated directly at z_j = (1 - a_j)/a_j of every node (App. B's full
+    likelihood), built here from the a-grid without the node tables."""
+    from oracle.emulator import emulate
+    m = small_linear(n_z=41)
+    th = W.posterior_draws(m["theta_fid"], np.full(m["d"], 0.01), 2, tag=40)
+    cos = shear.unpack(shear.physical(th, m), m["n_bins"])
+    Yz = shear.interp_z(shear.emulator_table(cos, m), m)
+    a = 1.0 - np.arange(41) * ((1.0 - m["a_min"]) / 40.0)
+    z = (1.0 - a) / a
+    base = np.concatenate([cos[k] for k in ("omega_b", "omega_cdm", "h", "n_s", "lnAs", "c_min", "eta0")], axis=1)
+    for b in range(2):
+        inp = np.concatenate([np.repeat(base[b:b + 1], 41, axis=0), z[:, None]], axis=1)
+        want = emulate(inp, m["nets"][0], out_mu=m["nets"][0]["out_mu"])
+        np.testing.assert_allclose(Yz[b], want, rtol=1e-12, atol=1e-12)
+
+
+def test_linear_z_exact_on_lines():
+    m = small_linear(n_z=5)
+    zn = shear.z_nodes(m)
+    assert zn[0] == 0.0 and np.isclose(zn[-1], 5.02) and np.all(np.diff(1.0 / (1.0 + zn)) < 0)
+    rng = np.random.default_rng(41)
+    c = rng.normal(size=(2, 30))
+    Y = (c[0] + c[1] * zn[:, None])[None]
+    z = 1.0 / shear.a_grid(m) - 1.0
+    np.testing.assert_allclose(shear.interp_z(Y, m)[0], c[0] + c[1] * z[:, None], rtol=1e-12, atol=1e-12)
+
+
+def test_linear_z_error_on_concave_tables_is_one_sided_and_bounded():
+    """For a concave f the chord lies below f: 0 <= f - interp <= h^2/8 max|f''|
+    on every interval (h its width), equality at the nodes."""
+    m = small_linear(n_z=9, n_a=101)
+    zn = shear.z_nodes(m)
+    f = lambda z: -2.0 * (0.22 * z + 0.02 * z ** 2) + np.log10(1.0 - z / 9.0)
+    Y = np.broadcast_to(f(zn)[:, None], (1, 9, 30)).copy()
+    z = np.minimum(1.0 / shear.a_grid(m) - 1.0, zn[-1])
+    err = f(z) - shear.interp_z(Y, m)[0, :, 0]
+    n = np.clip(np.searchsorted(zn, z, side="right") - 1, 0, 7)
+    h = zn[n + 1] - zn[n]
+    f2 = 0.08 + 1.0 / (np.log(10.0) * (9.0 - zn[n + 1]) ** 2)      # max |f''| on the interval
+    assert np.all(err >= -1e-15)
+    assert np.all(err <= h * h / 8.0 * f2 + 1e-15)
+    assert err.max() > 1e-3                                      # the bias is really there
+    assert abs(err[0]) < 1e-15 and abs(err[-1]) < 1e-14
+
+
+def test_identical_bins_give_identical_spectra():
+    """Ten bins with one n(z) and equal nuisances: all 55 spectra coincide
+    (a wrong pair index, bin offset or window term would split them)."""
+    m = W.shear_structure(n_z=6, n_bins=10, n_extra=0, hidden=(4,), n_a=64, n_k=40)
+    m["nz_mean"] = np.full(10, 0.9)
+    th = m["theta_fid"][None].copy()
+    for i in range(1, 11):
+        th[0, m["names"].index(f"A_IA_{i}")] = 0.5
+        th[0, m["names"].index(f"Dz_{i}")] = 0.0
+        th[0, m["names"].index(f"m_{i}")] = 0.01
+    rng = np.random.default_rng(42)
+    Y = rng.normal(size=(1, 6, 40)) * 0.05 + 2.0
+    C = shear.spectra(th, m, Y=Y)[0][0].reshape(55, -1)
+    assert C.shape == (55, m["n_ell"]) and np.all(C[0] != 0)
+    np.testing.assert_allclose(C, np.broadcast_to(C[0], C.shape), rtol=1e-13)
+    # one bin shifted: exactly the ten spectra involving it change
+    th2 = th.copy()
+    th2[0, m["names"].index("Dz_4")] = 0.05
+    C2 = shear.spectra(th2, m, Y=Y)[0][0].reshape(55, -1)
+    changed = np.any(C2 != C, axis=1)
+    involve = np.array([3 in p for p in shear.pairs(10)])
+    np.testing.assert_array_equal(changed, involve)
+
+
+def test_paper_shaped_structures():
+    for lcdm, d in ((False, 39), (True, 37)):
+        for v in ("full", "interp"):
+            m = W.shear_paper_structure(v, lcdm=lcdm)
+            assert m["d"] == d and m["n_bins"] == 10 and m["n_a"] == 1025
+            assert m["n_z"] == (1025 if v == "full" else 103) and m["z_interp"] == "linear"
+            assert len(shear.pairs(10)) * m["n_ell"] == 1100
+            assert m["nets"][0]["out_mu"].shape == (m["n_z"], 420)

@@ -181,13 +181,18 @@ def cmb_block_structure(n_ell=2500, hidden=(512, 512, 512, 512), seed=MODEL_SEED
 
 
 def shear_structure(n_z=64, n_bins=5, n_extra=15, lcdm=False, hidden=(512, 512, 512, 512),
-                    n_a=256, n_k=420, n_ell=20, seed=MODEL_SEED):
+                    n_a=256, n_k=420, n_ell=20, seed=MODEL_SEED, z_interp="cubic", growth="power"):
     """Cosmic-shear likelihood structure (App. A of the paper, synthetic emulator).
 
     Emulator: 8 inputs (5 cosmological, c_min, eta0, z) -> hidden -> n_k values
-    of log10 P(k, z_n) at z nodes uniform on [0, z_max].  Output normalisation
-    mu(k, z) = log10 P_base(k) - 2 log10(1 + z),
-    P_base(k) = 2e4 (k/0.02) / (1 + (k/0.02)^2)^1.75 Mpc^3, sigma_out = 0.1.
+    of log10 P(k, z_n) at the z nodes (uniform on [0, z_max] for z_interp
+    "cubic"; at scale factors evenly spaced from 1 to a_min for "linear").
+    Output normalisation mu(k, z) = log10 P_base(k) + g(z),
+    P_base(k) = 2e4 (k/0.02) / (1 + (k/0.02)^2)^1.75 Mpc^3, sigma_out = 0.1,
+    g(z) = -2 log10(1 + z) ("power"), or the concave stand-in
+    g(z) = -2 (0.15 z + 0.06 z^2) ("concave": P falls as D^2 with
+    log10 D = -(0.15 z + 0.06 z^2), so linear interpolation in z underestimates
+    it, as App. B describes for the emulated spectrum).
     """
     a_min = 1.0 / (1.0 + 5.02)
     z_max = 1.0 / a_min - 1.0
@@ -222,9 +227,16 @@ def shear_structure(n_z=64, n_bins=5, n_extra=15, lcdm=False, hidden=(512, 512, 
     in_shift = [0.5 * (TABLE1[c][1] + TABLE1[c][2]) for c in SHEAR_EMU_INPUTS] + [0.5 * z_max]
     in_scale = [0.5 * (TABLE1[c][2] - TABLE1[c][1]) for c in SHEAR_EMU_INPUTS] + [0.5 * z_max]
     k = np.logspace(np.log10(k_min), np.log10(k_max), n_k)
-    z_nodes = np.linspace(0.0, z_max, n_z)
+    if z_interp == "linear":
+        z_nodes = 1.0 / np.linspace(1.0, a_min, n_z) - 1.0
+    else:
+        z_nodes = np.linspace(0.0, z_max, n_z)
     p_base = 2e4 * (k / 0.02) / (1.0 + (k / 0.02) ** 2) ** 1.75
-    out_mu = np.log10(p_base)[None, :] - 2.0 * np.log10(1.0 + z_nodes)[:, None]
+    if growth == "concave":
+        gz = -2.0 * (0.15 * z_nodes + 0.06 * z_nodes ** 2)
+    else:
+        gz = -2.0 * np.log10(1.0 + z_nodes)
+    out_mu = np.log10(p_base)[None, :] + gz[:, None]
     layers = draw_mlp((8, *hidden, n_k), seed, 30, "wide")
     net = net_dict(layers, in_shift, in_scale, out_mu, np.full(n_k, 0.1))
     return {
@@ -250,7 +262,18 @@ def shear_structure(n_z=64, n_bins=5, n_extra=15, lcdm=False, hidden=(512, 512, 
         "ell_min": 20.0,
         "ell_max": 3000.0,
         "n_ell": n_ell,
+        "z_interp": z_interp,
     }
+
+
+def shear_paper_structure(variant="full", lcdm=False):
+    """The paper's shear analysis shape (App. A): 10 tomographic bins (55
+    spectra x 20 multipoles), 3 nuisances per bin (37 / 39 parameters), 1025
+    scale-factor nodes; "full" evaluates the emulator at every node, "interp"
+    at 103 nodes (10x coarser) with linear interpolation in z (App. B)."""
+    n_z = {"full": 1025, "interp": 103}[variant]
+    return shear_structure(n_z=n_z, n_bins=10, n_extra=0, lcdm=lcdm, n_a=1025, z_interp="linear",
+                           growth="concave")
 
 
 def gauss_structure(d=6, mu=None, sigma=None):
@@ -295,17 +318,23 @@ def structure(name: str):
         return shear_structure(n_z=10)
     if name == "shear_cmp_lcdm":
         return shear_structure(n_z=10, lcdm=True)
+    if name in ("shear_full", "shear_interp", "shear_full_lcdm", "shear_interp_lcdm"):
+        return shear_paper_structure(name.split("_")[1], lcdm=name.endswith("_lcdm"))
     raise KeyError(name)
 
 
 def load_model(name: str):
     """Structure plus the stored synthetic data vector and covariance."""
     m = structure(name)
-    data_name = "shear_cmp" if name.startswith("shear_cmp") else name
+    data_name = name
+    if name.startswith("shear_cmp"):
+        data_name = "shear_cmp"
+    elif name.startswith("shear_full") or name.startswith("shear_interp"):
+        data_name = "shear_paper"
     path = os.path.join(GOLDEN, f"workload_{data_name}.npz")
     with np.load(path, allow_pickle=False) as z:
         for key in z.files:
-            if name == "shear_cmp_lcdm" and key in ("theta_fid", "fisher_sigma"):
+            if name.endswith("_lcdm") and key in ("theta_fid", "fisher_sigma"):
                 continue       # stored for the 39-parameter model; LCDM keeps its own
             m[key] = z[key]
     return m
