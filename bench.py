@@ -107,6 +107,10 @@ def main():
                     help="only run the LCDM vs w0wa nested-sampling comparison and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain device copies of 256 MiB (reference for HBM byte counters)")
+    ap.add_argument("--shear-paper", action="store_true",
+                    help="only run the paper-shaped shear pair (full vs linear-z interpolated) and print its JSON")
+    ap.add_argument("--sp-ns", default="",
+                    help="with --shear-paper: comma list of precisions for the nested-sampling comparison")
     ap.add_argument("--mc-precision", default="bf16x3")
     ap.add_argument("--mc-live", type=int, default=1000)
     ap.add_argument("--mc-hmc-iter", type=int, default=400)
@@ -128,6 +132,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return
+
+    if args.shear_paper:
+        ns_precs = [p for p in args.sp_ns.split(",") if p]
+        print(json.dumps(shear_paper(Model, W, torch, ns_precs, args.mc_live)), flush=True)
         return
 
     if args.model_comparison:
@@ -314,6 +323,83 @@ def model_comparison(Model, W, prec, n_live, hmc_iter=400, hmc_warmup=100):
                       mean_diff_in_ns_sigma=[round(float(v), 3) for v in z])
     print(f"# hmc: {json.dumps(out['hmc'])}", file=sys.stderr, flush=True)
     g.close()
+    return out
+
+
+def shear_paper(Model, W, torch, ns_precs, n_live):
+    """The paper's shear pair (App. A, B): 10 bins, 1025 scale-factor nodes,
+    the emulator at every node ("full") or at 103 nodes with linear
+    interpolation in z ("interp").  Likelihood throughput at batch 512 and
+    4096, the interpolation's logL offset over posterior draws, and
+    optionally LCDM vs w0wa nested sampling on both (n_live live points,
+    n_live / 2 replaced per iteration, 5 d slice steps)."""
+    dev = "cuda:0"
+    out = {}
+    models = {}
+    for name in ("shear_full", "shear_interp"):
+        m = W.load_model(name)
+        g = Model(m)
+        models[name] = (m, g)
+        res = {}
+        for B in (512, 4096):
+            th = torch.tensor(W.prior_draws(m, B, tag=14), dtype=torch.float64, device=dev)
+            for prec in ("bf16x3", "fp64"):
+                if name == "shear_full" and B == 4096 and prec == "fp64":
+                    continue
+                g.loglike(th, prec)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = 3
+                e0.record()
+                for _ in range(reps):
+                    g.loglike(th, prec)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                g.trace(True)
+                g.loglike(th, prec)
+                tr = g.trace_report()
+                g.trace(False)
+                res[f"b{B}_{prec}"] = dict(ms_per_step=round(ms, 3), evals_per_s=round(B / (ms * 1e-3), 1),
+                                           kernels_us={k: round(t / n * 1e3, 2) for k, (n, t) in tr.items()})
+            del th
+        out[name] = res
+        print(f"# {name}: {json.dumps(res)}", file=sys.stderr, flush=True)
+    out["speedup_interp_over_full"] = {
+        k: round(out["shear_full"][k]["ms_per_step"] / out["shear_interp"][k]["ms_per_step"], 2)
+        for k in out["shear_full"] if k in out["shear_interp"]}
+    # systematic offset of the interpolated likelihood over the posterior
+    mf, gf = models["shear_full"]
+    mi, gi = models["shear_interp"]
+    width = np.where(mf["prior_kind"] == 0, mf["prior_b"] - mf["prior_a"], 1.0)
+    th = W.posterior_draws(mf["theta_fid"], np.minimum(mf["fisher_sigma"], 0.1 * width), 512, tag=15)
+    th = np.clip(th, mf["prior_a"] + 1e-9 * width, np.where(mf["prior_kind"] == 0, mf["prior_b"] - 1e-9 * width, np.inf))
+    tt = torch.tensor(th, device=dev)
+    lf, li = gf.loglike(tt).cpu().numpy(), gi.loglike(tt).cpu().numpy()
+    dl = li - lf
+    out["dlogL_interp_minus_full"] = dict(walkers=int(dl.size), mean=float(dl.mean()), std=float(dl.std()),
+                                          min=float(dl.min()), max=float(dl.max()),
+                                          logL_full_std=float(lf.std()))
+    print(f"# dlogL: {json.dumps(out['dlogL_interp_minus_full'])}", file=sys.stderr, flush=True)
+    for name in list(models):
+        models[name][1].close()
+    for prec in ns_precs:
+        runs = {}
+        for name in ("shear_full_lcdm", "shear_full", "shear_interp_lcdm", "shear_interp"):
+            m = W.load_model(name)
+            g = Model(m)
+            r = g.run(n_live, n_live // 2, 5 * m["d"], precision=prec, seed=7, n_replicates=1000)
+            runs[name] = {k: r[k] for k in ("logz", "sigma", "n_iter", "n_evals", "wall_s")}
+            runs[name]["d"] = m["d"]
+            print(f"# ns {prec} {name}: {json.dumps(runs[name])}", file=sys.stderr, flush=True)
+            g.close()
+        for v in ("full", "interp"):
+            a, b = runs[f"shear_{v}_lcdm"], runs[f"shear_{v}"]
+            runs[f"log_B01_{v}"] = a["logz"] - b["logz"]
+            runs[f"log_B01_{v}_sigma"] = float(np.hypot(a["sigma"], b["sigma"]))
+            runs[f"wall_s_{v}"] = a["wall_s"] + b["wall_s"]
+        runs["ns_speedup_interp_over_full"] = runs["wall_s_full"] / runs["wall_s_interp"]
+        out[f"ns_{prec}"] = runs
     return out
 
 

@@ -119,9 +119,9 @@ typedef struct ns_model_desc {
     int32_t n_bins;               /* tomographic bins (<= 10)                   */
     const double* nz_mean;        /* [n_bins] Gaussian n(z) means               */
     double nz_sigma;              /* Gaussian n(z) width                        */
-    int32_t n_a;                  /* scale-factor nodes, a = 1 .. a_min         */
+    int32_t n_a;                  /* scale-factor nodes, a = 1 .. a_min (<= 2048) */
     double a_min;
-    int32_t n_z;                  /* emulator redshift nodes on [0, 1/a_min-1]  */
+    int32_t n_z;                  /* emulator redshift nodes (see z_interp)     */
     double k_min, k_max;          /* emulated k range [1/Mpc], log-spaced       */
     int32_t n_k;
     double ell_min, ell_max;      /* SHEAR: log-spaced multipoles; CMB_CV:
@@ -135,6 +135,14 @@ typedef struct ns_model_desc {
     /* GAUSS */
     const double* mu;             /* [d]                                        */
     const double* gsigma;         /* [d]                                        */
+
+    /* SHEAR: how the emulated log10 P reaches the z of every a-node (App. B).
+     * 0: not-a-knot cubic spline over n_z nodes uniform on [0, 1/a_min - 1]
+     *    (4 <= n_z <= 256);
+     * 1: linear in z over n_z nodes at scale factors evenly spaced from 1 to
+     *    a_min (2 <= n_z <= n_a); n_z = n_a puts a node on every a-node (the
+     *    paper's full likelihood), n_z ~ n_a / 10 is its interpolated one. */
+    int32_t z_interp;
 } ns_model_desc;
 
 typedef struct ns_model ns_model; /* opaque, library-owned */

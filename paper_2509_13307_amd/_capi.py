@@ -66,6 +66,7 @@ class ModelDesc(ctypes.Structure):
         ("pfix", c_double_p),
         ("mu", c_double_p),
         ("gsigma", c_double_p),
+        ("z_interp", ctypes.c_int32),
     ]
 
 

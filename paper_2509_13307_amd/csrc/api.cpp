@@ -352,8 +352,12 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
     } else {
         // cosmic shear
         NS_CHECK(D->n_bins >= 1 && D->n_bins <= 10, NS_E_UNSUPPORTED, "n_bins must be in [1, 10]");
-        NS_CHECK(D->n_a >= 3 && D->n_a <= 256, NS_E_UNSUPPORTED, "n_a must be in [3, 256]");
-        NS_CHECK(D->n_z >= 4 && D->n_z <= 256, NS_E_UNSUPPORTED, "n_z must be in [4, 256] (not-a-knot spline)");
+        NS_CHECK(D->z_interp == 0 || D->z_interp == 1, NS_E_INVALID, "z_interp must be 0 (cubic) or 1 (linear)");
+        NS_CHECK(D->n_a >= 3 && D->n_a <= 2048, NS_E_UNSUPPORTED, "n_a must be in [3, 2048]");
+        if (D->z_interp == 0)
+            NS_CHECK(D->n_z >= 4 && D->n_z <= 256, NS_E_UNSUPPORTED, "n_z must be in [4, 256] (not-a-knot spline)");
+        else
+            NS_CHECK(D->n_z >= 2 && D->n_z <= D->n_a, NS_E_UNSUPPORTED, "n_z must be in [2, n_a] (linear z)");
         NS_CHECK(D->n_k >= 4, NS_E_SHAPE, "n_k must be >= 4");
         NS_CHECK(D->n_ell >= 1 && D->n_ell <= 64, NS_E_UNSUPPORTED, "n_ell must be in [1, 64]");
         NS_CHECK(D->a_min > 0.0 && D->a_min < 1.0, NS_E_INVALID, "a_min must be in (0, 1)");
@@ -369,7 +373,9 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         m->n_pairs = nb * (nb + 1) / 2;
         m->nz_sigma = D->nz_sigma; m->a_min = D->a_min; m->k_min = D->k_min; m->k_max = D->k_max;
         NS_CHECK(D->n_data == m->n_pairs * D->n_ell, NS_E_SHAPE, "n_data must be n_pairs * n_ell");
-        NS_CHECK(D->n_data <= 1024, NS_E_UNSUPPORTED, "shear data vector longer than 1024");
+        NS_CHECK(D->n_data <= 1248, NS_E_UNSUPPORTED, "shear data vector longer than 1248");
+        NS_CHECK(m->n_pairs * ((D->n_ell + 3) / 4) <= 512, NS_E_UNSUPPORTED, "too many (pair, 4-ell) items");
+        m->z_linear = D->z_interp == 1;
         NS_CHECK(n_in == 8, NS_E_SHAPE, "shear emulator takes 8 inputs");
         NS_CHECK(m->nets[0]->dims.back() == D->n_k, NS_E_SHAPE, "shear emulator must output n_k values");
         const int nphys = 9 + 3 * nb;
@@ -398,22 +404,42 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         const double zmax = 1.0 / D->a_min - 1.0;
         const double hz = zmax / (nz - 1);
         std::vector<double> zn(nz);
-        for (int n = 0; n < nz; ++n) zn[n] = n * hz;
-        zn[nz - 1] = zmax;
-        upload(m->znodes_d, zn.data(), zn.size());
         std::vector<int> zi(na);
-        std::vector<double> zc((size_t)na * 4);
-        for (int j = 0; j < na; ++j) {
-            const double z = std::min(1.0 / a[j] - 1.0, zmax);
-            int n = (int)std::floor(z / hz);
-            n = std::max(0, std::min(n, nz - 2));
-            const double t = (z - zn[n]) / hz, u = 1.0 - t;
-            zi[j] = n;
-            zc[4 * j + 0] = u;
-            zc[4 * j + 1] = t;
-            zc[4 * j + 2] = hz * hz / 6.0 * (u * u * u - u);
-            zc[4 * j + 3] = hz * hz / 6.0 * (t * t * t - t);
+        std::vector<double> zc((size_t)na * 4, 0.0);
+        if (m->z_linear) {
+            // nodes at scale factors evenly spaced from 1 to a_min, computed like
+            // the a-grid (with n_z = n_a they are its nodes); linear weights in z
+            std::vector<double> an(nz);
+            const double stz = (D->a_min - 1.0) / (nz - 1);
+            for (int n = 0; n < nz; ++n) an[n] = 1.0 + n * stz;
+            an[nz - 1] = D->a_min;
+            for (int n = 0; n < nz; ++n) zn[n] = 1.0 / an[n] - 1.0;
+            int n = 0;
+            for (int j = 0; j < na; ++j) {
+                const double z = std::min(1.0 / a[j] - 1.0, zn[nz - 1]);
+                while (n < nz - 2 && zn[n + 1] <= z) ++n;
+                double t = (z - zn[n]) / (zn[n + 1] - zn[n]);
+                t = std::min(1.0, std::max(0.0, t));
+                zi[j] = n;
+                zc[4 * j + 0] = 1.0 - t;
+                zc[4 * j + 1] = t;
+            }
+        } else {
+            for (int n = 0; n < nz; ++n) zn[n] = n * hz;
+            zn[nz - 1] = zmax;
+            for (int j = 0; j < na; ++j) {
+                const double z = std::min(1.0 / a[j] - 1.0, zmax);
+                int n = (int)std::floor(z / hz);
+                n = std::max(0, std::min(n, nz - 2));
+                const double t = (z - zn[n]) / hz, u = 1.0 - t;
+                zi[j] = n;
+                zc[4 * j + 0] = u;
+                zc[4 * j + 1] = t;
+                zc[4 * j + 2] = hz * hz / 6.0 * (u * u * u - u);
+                zc[4 * j + 3] = hz * hz / 6.0 * (t * t * t - t);
+            }
         }
+        upload(m->znodes_d, zn.data(), zn.size());
         upload(m->zsp_idx_d, zi.data(), zi.size());
         upload(m->zsp_coef_d, zc.data(), zc.size());
         std::vector<double> ell(D->n_ell);

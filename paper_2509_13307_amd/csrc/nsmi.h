@@ -141,7 +141,9 @@ struct ns_model {
     nsmi::DevBuf pidx_d, pfix_d, nz_mean_d;
     nsmi::DevBuf agrid_d;            // a_j [n_a]
     nsmi::DevBuf zsp_idx_d;          // int [n_a]: spline interval of z_j
-    nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t))
+    nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t));
+                                     // linear z: (1-t, t, 0, 0)
+    bool z_linear = false;           // linear z-interpolation on nodes evenly spaced in a
     nsmi::DevBuf ell_d;              // double [n_ell]
     nsmi::DevBuf lell_d;             // double [n_ell]: log10(l + 1/2)
     nsmi::DevBuf cov_linv;           // double [n x n] lower-triangular inverse Cholesky factor

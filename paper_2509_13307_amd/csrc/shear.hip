@@ -6,7 +6,7 @@
 //                  conditions on a uniform grid, the interior (1, 4, 1)
 //                  system is solved by a Thomas sweep, M_0 and M_{N-1} are
 //                  linear extrapolations.
-// limber_kernel    one workgroup per walker:
+// limber_kernel    one workgroup per walker, nodes in chunks of 256:
 //                  (a) background on the a-grid: E(a), chi by per-interval
 //                      Simpson, J = dchi/d(-a), growth D (growth index 0.55);
 //                  (b) n_i(z) with photo-z shifts, normalised by the trapezoid
@@ -14,8 +14,9 @@
 //                      with reverse cumulative trapezoids; NLA window Eq. (A4);
 //                      effective window W = W^g + W^I (the four terms of Eq. (A1)
 //                      share P_dd);
-//                  (c) P(k = (l+1/2)/chi_j, z_j): spline in z, Catmull-Rom in
-//                      log10 k (linear ghost nodes), zero outside [k_min, k_max];
+//                  (c) P(k = (l+1/2)/chi_j, z_j): spline or linear in z,
+//                      Catmull-Rom in log10 k (linear ghost nodes), zero
+//                      outside [k_min, k_max];
 //                  (d) Limber sum Eq. (A2) by the trapezoid rule in a with the
 //                      analytic Jacobian, times (1 + m_i)(1 + m_j).
 //                  (a)-(b) are FP64; (c)-(d) run in the form's type T.
@@ -93,8 +94,15 @@ __global__ __launch_bounds__(64) void zspline_kernel(const T* __restrict__ Y, T*
     mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
 }
 
-// One workgroup (256 threads) per walker; n_a <= 256 nodes (one per thread).
-template <class T>
+// One workgroup (256 threads) per walker.  The n_a nodes are taken in chunks
+// of 256, one node per thread: a forward pass builds chi and -ln D (kept in
+// LDS for every node) and the n(z) normalisations; a reverse pass, from the
+// last chunk to the first, builds the windows (reverse cumulative sums carried
+// from chunk to chunk), looks up P and adds each chunk's share of the Limber
+// sums to per-thread accumulators.  LINZ: linear z-interpolation (no spline
+// second derivatives).
+constexpr int LB_SLOTS = 2;     // (pair, 4-ell group) items per thread
+template <class T, bool LINZ>
 __global__ __launch_bounds__(256) void limber_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
     const int* __restrict__ pidx, const double* __restrict__ pfix, const double* __restrict__ nz_mean,
@@ -105,14 +113,22 @@ __global__ __launch_bounds__(256) void limber_kernel(
     if (count) B = min<int64_t>(B, *count);
     const int64_t w = blockIdx.x;
     if (w >= B) return;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int na = G.n_a, nb = G.n_bins;
-    double* scan = reinterpret_cast<double*>(smem);                   // [2*MAXB][256]
-    double* red = scan + 2 * MAXB * 256;                              // [MAXB][4]
-    double* chis = red + MAXB * 4;                                    // [256]
-    T* Wt = reinterpret_cast<T*>(chis + 256);                         // [nb][256]
-    T* wq = Wt + nb * 256;                                            // [256]
-    T* Pl = wq + 256;                                                 // [256][n_ell rounded up to 4]
+    const int nch = (na + 255) / 256;
+    const int nl4 = (G.n_ell + 3) & ~3;
+    double* buf = reinterpret_cast<double*>(smem);                    // [2 MAXB][4] block_scan totals
+    double* red = buf + 2 * MAXB * 4;                                 // [MAXB][4]
+    double* bc = red + MAXB * 4;                                      // [2 MAXB] next carry (thread 0)
+    double* gcs = bc + 2 * MAXB;                                      // [2 MAXB] sums over the chunks above
+    double* mus = gcs + 2 * MAXB;                                     // [MAXB] n(z) means
+    double* nrm = mus + MAXB;                                         // [MAXB] n(z) normalisations
+    double* gnx = nrm + MAXB;                                         // [2 MAXB] g0, g1 of the node above the chunk
+    double* xw = gnx + 2 * MAXB;                                      // [4][2 MAXB] wave-boundary exchange
+    double* chis = xw + 4 * 2 * MAXB;                                 // [nch 256 + 1]
+    double* lnDs = chis + nch * 256 + 1;                              // [nch 256 + 1]
+    T* Wt = reinterpret_cast<T*>(lnDs + nch * 256 + 1);               // [nb][256]
+    T* Pl = Wt + nb * 256;                                            // [256][nl4]
 
     // physical parameters
     auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
@@ -127,153 +143,206 @@ __global__ __launch_bounds__(256) void limber_kernel(
         const double E = Efn(a);
         return pow(Om / (a * a * a) / (E * E), GROWTH_INDEX) / a;
     };
+    if (t < MAXB) mus[t] = t < nb ? nz_mean[t] + phys(9 + nb + t) : 0.0;
+    __syncthreads();
+    const double s2 = 2.0 * G.nz_sigma * G.nz_sigma;
 
-    // (a) background: Simpson increments of chi and -ln D on interval [a_t, a_{t+1}]
-    const bool node = t < na;
-    const double a = node ? agrid[t] : 1.0;
-    double inc[2] = {0.0, 0.0};
-    double fa = 0.0, Ea = 1.0;
-    if (node) {
-        Ea = Efn(a);
-        fa = cH0 / (a * a * Ea);
-        if (t < na - 1) {
-            const double a1 = agrid[t + 1], am = 0.5 * (a + a1);
-            inc[0] = G.da / 6.0 * (fa + 4.0 * ffn(am) + ffn(a1));
+    // (a) forward pass: Simpson increments of chi and -ln D on [a_j, a_{j+1}];
+    // chis[j] / lnDs[j] = sums over intervals 0..j-1; n(z) normalisations
+    double nsum[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) nsum[i] = 0.0;
+    if (t == 0) chis[0] = lnDs[0] = 0.0;
+    double carry0 = 0.0, carry1 = 0.0;
+    for (int c = 0; c < nch; ++c) {
+        const int j = c * 256 + t;
+        const bool node = j < na;
+        const double a = node ? agrid[j] : 1.0;
+        double inc[2] = {0.0, 0.0};
+        if (node && j < na - 1) {
+            const double a1 = agrid[j + 1], am = 0.5 * (a + a1);
+            inc[0] = G.da / 6.0 * (ffn(a) + 4.0 * ffn(am) + ffn(a1));
             inc[1] = G.da / 6.0 * (gfn(a) + 4.0 * gfn(am) + gfn(a1));
         }
-    }
-    block_scan<2>(inc, scan, false);        // inclusive sums over intervals 0..t
-    // values at node t are the sums over intervals 0..t-1
-    chis[t] = inc[0];
-    __syncthreads();
-    const double chi = (node && t > 0) ? chis[t - 1] : 0.0;
-    __syncthreads();
-    chis[t] = inc[1];
-    __syncthreads();
-    const double D = exp(-((node && t > 0) ? chis[t - 1] : 0.0));
-    __syncthreads();
-    chis[t] = chi;
-
-    // (b) redshift distributions, normalisation
-    const double z = 1.0 / a - 1.0;
-    const double q = (t == 0 || t == na - 1) ? 0.5 * G.da : G.da;
-    double nraw[MAXB];
+        block_scan<2>(inc, buf, false);
+        chis[j + 1] = carry0 + inc[0];
+        lnDs[j + 1] = carry1 + inc[1];
+        if (node && j > 0) {
+            const double z = 1.0 / a - 1.0;
+            const double q = j == na - 1 ? 0.5 * G.da : G.da;
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-        if (i >= nb) continue;
-        const double mu = nz_mean[i] + phys(9 + nb + i);
-        const double dz = z - mu;
-        nraw[i] = (node && t > 0) ? exp(-dz * dz / (2.0 * G.nz_sigma * G.nz_sigma)) : 0.0;
-    }
-    {
-        const int lane = t & 63, wid = t >> 6;
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            if (i >= nb) continue;
-            double v = wave_sum(node ? q * nraw[i] / (a * a) : 0.0);
-            if (lane == 0) red[i * 4 + wid] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i)
-            if (i < nb) nraw[i] /= (red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3]);
-        __syncthreads();
-    }
-    // reverse cumulative trapezoids G0, G1: segment [t, t+1] stored at node t
-    double seg[2 * MAXB];
-    {
-        // integrands at this node and the next one
-        double g0[MAXB], g1[MAXB];
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            if (i >= nb) continue;
-            g0[i] = node ? nraw[i] / (a * a) : 0.0;
-            g1[i] = (node && t > 0) ? nraw[i] / (a * a * chi) : 0.0;
-        }
-        // exchange with the neighbour through LDS
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            if (i >= nb) continue;
-            scan[i * 256 + t] = g0[i];
-            scan[(MAXB + i) * 256 + t] = g1[i];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            if (i >= nb) continue;
-            const bool has = node && t < na - 1;
-            seg[i] = has ? 0.5 * G.da * (g0[i] + scan[i * 256 + t + 1]) : 0.0;
-            seg[MAXB + i] = has ? 0.5 * G.da * (g1[i] + scan[(MAXB + i) * 256 + t + 1]) : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i)
-            if (i >= nb) seg[i] = seg[MAXB + i] = 0.0;
-        __syncthreads();
-    }
-    block_scan<2 * MAXB>(seg, scan, true);   // seg[i] = sum_{m >= t} segment_m
-    const double pref = 1.5 * Om * H0c * H0c * chi / a;
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-        if (i >= nb) continue;
-        const double Wg = pref * (seg[i] - chi * seg[MAXB + i]);
-        const double AIA = phys(9 + i);
-        const double WI = -AIA * C1_RHOCR * Om * nraw[i] * H0c * Ea / D;
-        Wt[i * 256 + t] = node ? (T)(Wg + WI) : T(0);
-    }
-    wq[t] = (node && t > 0) ? (T)(q * fa / (chi * chi)) : T(0);
-    __syncthreads();
-
-    // (c) P at the Limber wavenumbers, one thread per node j, node-major
-    // [256][nl4] (ell contiguous); log10 k = log10(l + 1/2) - log10 chi_j
-    const int nl4 = (G.n_ell + 3) & ~3;
-    {
-        const bool live = t > 0 && t < na;
-        const double lchi = live ? log10(chi) : 0.0;
-        const T wqj = wq[t];
-        const int n = live ? zidx[t] : 0;
-        const int zc = live ? 4 * t : 0;                   // z-spline coefficients exist for nodes < n_a
-        const T c0 = (T)zcoef[zc], c1 = (T)zcoef[zc + 1], c2 = (T)zcoef[zc + 2], c3 = (T)zcoef[zc + 3];
-        const T* y0 = Ytab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
-        const T* m0p = Mtab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
-        auto Yz = [&](int col) {
-            return c0 * y0[col] + c1 * y0[col + G.n_k] + c2 * m0p[col] + c3 * m0p[col + G.n_k];
-        };
-#pragma unroll 4
-        for (int b = 0; b < nl4; ++b) {
-            T P = T(0);
-            const double lk = b < G.n_ell ? lell[b] - lchi : 0.0;
-            if (live && b < G.n_ell && lk >= G.u0 && lk <= G.u1) {
-                const double sv = (lk - G.u0) / G.du;
-                int i0 = (int)floor(sv);
-                i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
-                const T tt = (T)(sv - i0);
-                const T p0 = Yz(i0), p1 = Yz(i0 + 1);
-                const T pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
-                const T p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
-                const T mk0 = T(0.5) * (p1 - pm), mk1 = T(0.5) * (p2 - p0);
-                const T t2 = tt * tt, t3 = t2 * tt;
-                const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * mk0 +
-                             (T(-2) * t3 + T(3) * t2) * p1 + (t3 - t2) * mk1;
-                P = exp10_of<T>(lp) * wqj;
+            for (int i = 0; i < MAXB; ++i) {
+                if (i >= nb) continue;
+                const double dz = z - mus[i];
+                nsum[i] += q * exp(-dz * dz / s2) / (a * a);
             }
-            Pl[t * nl4 + b] = P;
         }
+        __syncthreads();
+        carry0 = chis[c * 256 + 256];
+        carry1 = lnDs[c * 256 + 256];
     }
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        if (i >= nb) continue;
+        const double v = wave_sum(nsum[i]);
+        if (lane == 0) red[i * 4 + wid] = v;
+    }
+    if (t < 2 * MAXB) gnx[t] = gcs[t] = 0.0;
+    __syncthreads();
+    if (t < MAXB) nrm[t] = t < nb ? red[t * 4] + red[t * 4 + 1] + red[t * 4 + 2] + red[t * 4 + 3] : 1.0;
     __syncthreads();
 
-    // (d) Limber sums.  Item = (pair p, group of 4 ell bins); the node range is
-    // split into nseg segments whose partial sums are added in a fixed order.
+    // (d) bookkeeping: item = (pair p, group of 4 ell bins); each chunk's node
+    // range is split into nseg segments whose partial sums are added in a
+    // fixed order at the end
     const int ng = nl4 / 4, nitem = G.n_pairs * ng;
     const int nseg = nitem >= 256 ? 1 : 256 / nitem;
-    const int len = (na + nseg - 1) / nseg;
+    const int len = (min(na, 256) + nseg - 1) / nseg;
     const int nout = G.n_pairs * G.n_ell;
-    T* part = reinterpret_cast<T*>(scan);               // [nseg][nitem][4]; the scan buffer is free here
     auto pair_of = [&](int p, int& bi, int& bj) {
         int rem = p;
         bi = 0;
         while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
         bj = bi + rem;
     };
+    T acc[LB_SLOTS][4];
+#pragma unroll
+    for (int s = 0; s < LB_SLOTS; ++s)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[s][e] = T(0);
+
+    // reverse pass over the chunks
+    for (int c = nch - 1; c >= 0; --c) {
+        const int j = c * 256 + t;
+        const bool node = j < na;
+        const double a = node ? agrid[j] : 1.0;
+        const double Ea = node ? Efn(a) : 1.0;
+        const double fa = cH0 / (a * a * Ea);
+        const double chi = node ? chis[j] : 0.0;
+        const double D = exp(-(node ? lnDs[j] : 0.0));
+        const double z = 1.0 / a - 1.0;
+        const double q = (j == 0 || j == na - 1) ? 0.5 * G.da : G.da;
+        // (b) normalised n_i(z_j); integrands of G0, G1 at this node
+        double nr[MAXB], g0[MAXB], g1[MAXB];
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            if (i >= nb) { nr[i] = g0[i] = g1[i] = 0.0; continue; }
+            const double dz = z - mus[i];
+            nr[i] = (node && j > 0) ? exp(-dz * dz / s2) : 0.0;
+            nr[i] /= nrm[i];
+            g0[i] = node ? nr[i] / (a * a) : 0.0;
+            g1[i] = (node && j > 0) ? nr[i] / (a * a * chi) : 0.0;
+        }
+        // trapezoid segment [j, j+1]: node j+1 from the next lane, the next
+        // wave (through LDS) or the chunk above (gnx)
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i) {
+                xw[wid * 2 * MAXB + i] = g0[i];
+                xw[wid * 2 * MAXB + MAXB + i] = g1[i];
+            }
+        __syncthreads();
+        double seg[2 * MAXB];
+        const bool has = node && j < na - 1;
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            double n0 = __shfl_down(g0[i], 1, 64), n1 = __shfl_down(g1[i], 1, 64);
+            if (lane == 63) {
+                const double* src = wid < 3 ? xw + (wid + 1) * 2 * MAXB : gnx;
+                n0 = src[i];
+                n1 = src[MAXB + i];
+            }
+            seg[i] = (has && i < nb) ? 0.5 * G.da * (g0[i] + n0) : 0.0;
+            seg[MAXB + i] = (has && i < nb) ? 0.5 * G.da * (g1[i] + n1) : 0.0;
+        }
+        __syncthreads();
+        if (t == 0)
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i) {
+                gnx[i] = g0[i];
+                gnx[MAXB + i] = g1[i];
+            }
+        block_scan<2 * MAXB>(seg, buf, true);      // sum over the chunk's segments m >= j
+#pragma unroll
+        for (int k = 0; k < 2 * MAXB; ++k) seg[k] += gcs[k];
+        if (t == 0)
+#pragma unroll
+            for (int k = 0; k < 2 * MAXB; ++k) bc[k] = seg[k];
+        const double pref = 1.5 * Om * H0c * H0c * chi / a;
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            if (i >= nb) continue;
+            const double Wg = pref * (seg[i] - chi * seg[MAXB + i]);
+            const double AIA = phys(9 + i);
+            const double WI = -AIA * C1_RHOCR * Om * nr[i] * H0c * Ea / D;
+            Wt[i * 256 + t] = node ? (T)(Wg + WI) : T(0);
+        }
+
+        // (c) P at the Limber wavenumbers for this node, node-major [256][nl4]
+        // (ell contiguous); log10 k = log10(l + 1/2) - log10 chi_j
+        {
+            const bool live = node && j > 0;
+            const double lchi = live ? log10(chi) : 0.0;
+            const T wqj = (node && j > 0) ? (T)(q * fa / (chi * chi)) : T(0);
+            const int n = live ? zidx[j] : 0;
+            const int zc = live ? 4 * j : 0;
+            const T c0 = (T)zcoef[zc], c1 = (T)zcoef[zc + 1];
+            const T c2 = LINZ ? T(0) : (T)zcoef[zc + 2], c3 = LINZ ? T(0) : (T)zcoef[zc + 3];
+            const T* y0 = Ytab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
+            const T* m0p = LINZ ? y0 : Mtab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
+            auto Yz = [&](int col) {
+                if (LINZ) return c0 * y0[col] + c1 * y0[col + G.n_k];
+                return c0 * y0[col] + c1 * y0[col + G.n_k] + c2 * m0p[col] + c3 * m0p[col + G.n_k];
+            };
+#pragma unroll 4
+            for (int b = 0; b < nl4; ++b) {
+                T P = T(0);
+                const double lk = b < G.n_ell ? lell[b] - lchi : 0.0;
+                if (live && b < G.n_ell && lk >= G.u0 && lk <= G.u1) {
+                    const double sv = (lk - G.u0) / G.du;
+                    int i0 = (int)floor(sv);
+                    i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
+                    const T tt = (T)(sv - i0);
+                    const T p0 = Yz(i0), p1 = Yz(i0 + 1);
+                    const T pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
+                    const T p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
+                    const T mk0 = T(0.5) * (p1 - pm), mk1 = T(0.5) * (p2 - p0);
+                    const T t2 = tt * tt, t3 = t2 * tt;
+                    const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * mk0 +
+                                 (T(-2) * t3 + T(3) * t2) * p1 + (t3 - t2) * mk1;
+                    P = exp10_of<T>(lp) * wqj;
+                }
+                Pl[t * nl4 + b] = P;
+            }
+        }
+        __syncthreads();
+        if (t == 0)
+#pragma unroll
+            for (int k = 0; k < 2 * MAXB; ++k) gcs[k] = bc[k];
+
+        // (d) this chunk's share of the Limber sums
+        const int jl1 = min(256, na - c * 256);
+#pragma unroll
+        for (int s = 0; s < LB_SLOTS; ++s) {
+            const int it = t + 256 * s;
+            if (it >= nitem * nseg) continue;
+            const int item = it % nitem, sg = it / nitem;
+            const int p = item / ng, gq = item % ng;
+            int bi, bj;
+            pair_of(p, bi, bj);
+            const T* Wi = Wt + bi * 256;
+            const T* Wj = Wt + bj * 256;
+            const int j0 = max(c == 0 ? 1 : 0, sg * len), j1 = min(jl1, (sg + 1) * len);
+            for (int jl = j0; jl < j1; ++jl) {
+                const T A = Wi[jl] * Wj[jl];
+                const T* Pj = Pl + jl * nl4 + 4 * gq;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[s][e] += A * Pj[e];
+            }
+        }
+        __syncthreads();
+    }
+
     auto store = [&](int item, const T (&v)[4]) {
         const int p = item / ng, gq = item % ng;
         int bi, bj;
@@ -284,29 +353,15 @@ __global__ __launch_bounds__(256) void limber_kernel(
             if (b < G.n_ell) Cout[w * nout + p * G.n_ell + b] = (1.0 + mi) * (1.0 + mj) * (double)v[e];
         }
     };
-    for (int it = t; it < nitem * nseg; it += 256) {
-        const int item = it % nitem, sg = it / nitem;
-        const int p = item / ng, gq = item % ng;
-        int bi, bj;
-        pair_of(p, bi, bj);
-        const T* Wi = Wt + bi * 256;
-        const T* Wj = Wt + bj * 256;
-        T acc[4] = {T(0), T(0), T(0), T(0)};
-        const int j0 = max(1, sg * len), j1 = min(na, (sg + 1) * len);
-        for (int j = j0; j < j1; ++j) {
-            const T A = Wi[j] * Wj[j];
-            const T* Pj = Pl + j * nl4 + 4 * gq;
+    if (nseg == 1) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[e] += A * Pj[e];
-        }
-        if (nseg == 1) {
-            store(item, acc);
-        } else {
+        for (int s = 0; s < LB_SLOTS; ++s)
+            if (t + 256 * s < nitem) store(t + 256 * s, acc[s]);
+    } else {
+        T* part = Pl;                                   // [nseg][nitem][4] (nseg nitem <= 256)
+        if (t < nitem * nseg)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) part[(sg * nitem + item) * 4 + e] = acc[e];
-        }
-    }
-    if (nseg > 1) {
+            for (int e = 0; e < 4; ++e) part[t * 4 + e] = acc[0][e];
         __syncthreads();
         for (int item = t; item < nitem; item += 256) {
             T v[4] = {T(0), T(0), T(0), T(0)};
@@ -412,8 +467,26 @@ ShearGeom shear_geom(const ns_model* m) {
 }
 
 static size_t limber_smem(const ns_model* m, size_t elem) {
-    return (2 * MAXB * 256 + MAXB * 4 + 256) * sizeof(double) +
-           (size_t)(m->n_bins + 1 + ((m->n_ell + 3) & ~3)) * 256 * elem;
+    const size_t nch = (m->n_a + 255) / 256;
+    return (2 * MAXB * 4 + MAXB * 4 + 3 * 2 * MAXB + 2 * MAXB + 4 * 2 * MAXB + 2 * (nch * 256 + 1)) * sizeof(double) +
+           (size_t)(m->n_bins + ((m->n_ell + 3) & ~3)) * 256 * elem;
+}
+
+template <bool LINZ>
+static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t B, int prec, const void* Mtab,
+                          double* Cv, const int* count, size_t sm, hipStream_t s) {
+    const ShearGeom G = shear_geom(m);
+    if (prec == NS_FP64)
+        hipLaunchKernelGGL((limber_kernel<double, LINZ>), dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
+                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
+                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
+                           m->lell_d.as<double>(), m->ws_out.as<double>(), (const double*)Mtab, Cv, count);
+    else
+        hipLaunchKernelGGL((limber_kernel<float, LINZ>), dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
+                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
+                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
+                           m->lell_d.as<double>(), m->ws_out.as<float>(), (const float*)Mtab, Cv, count);
+    NS_HIP(hipGetLastError());
 }
 
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
@@ -421,53 +494,45 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     const int nk = m->n_k, nz = m->n_z;
     const size_t elem = prec == NS_FP64 ? 8 : 4;
     const int n = m->n_data;
-    // aux: spline second derivatives [B x nz x nk] then spectra [B x n] (double)
-    const size_t mbytes = (size_t)B * nz * nk * elem;
+    // aux: spline second derivatives [B x nz x nk] (cubic z only) then spectra [B x n] (double)
+    const size_t mbytes = m->z_linear ? 0 : (size_t)B * nz * nk * elem;
     m->ws_aux.ensure(mbytes + (size_t)B * n * sizeof(double));
     void* Mtab = m->ws_aux.p;
     double* Cv = reinterpret_cast<double*>(m->ws_aux.as<char>() + mbytes);
     const double zmax = 1.0 / m->a_min - 1.0;
     const double hz = zmax / (nz - 1);
     if (!m->shear_attr_set) {   // once per model, outside any stream capture
-        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
-        NS_HIP(hipFuncSetAttribute((const void*)limber_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
+        const void* fns[4] = {(const void*)limber_kernel<double, false>, (const void*)limber_kernel<float, false>,
+                              (const void*)limber_kernel<double, true>, (const void*)limber_kernel<float, true>};
+        for (const void* f : fns)
+            NS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    150 * 1024));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    150 * 1024));
         m->shear_attr_set = true;
     }
-    const int64_t nthr = B * nk;
-    dim3 gz((unsigned)((nthr + 63) / 64));
-    {
-    TraceScope ts(m, s, "zspline");
-    const size_t zsm = (size_t)nz * 64 * elem;
-    if (prec == NS_FP64)
-        hipLaunchKernelGGL(zspline_kernel<double>, gz, dim3(64), zsm, s, m->ws_out.as<double>(), (double*)Mtab, B,
-                           nz, nk, hz, count);
-    else
-        hipLaunchKernelGGL(zspline_kernel<float>, gz, dim3(64), zsm, s, m->ws_out.as<float>(), (float*)Mtab, B, nz,
-                           nk, hz, count);
-    NS_HIP(hipGetLastError());
+    if (!m->z_linear) {
+        const int64_t nthr = B * nk;
+        dim3 gz((unsigned)((nthr + 63) / 64));
+        TraceScope ts(m, s, "zspline");
+        const size_t zsm = (size_t)nz * 64 * elem;
+        if (prec == NS_FP64)
+            hipLaunchKernelGGL(zspline_kernel<double>, gz, dim3(64), zsm, s, m->ws_out.as<double>(), (double*)Mtab,
+                               B, nz, nk, hz, count);
+        else
+            hipLaunchKernelGGL(zspline_kernel<float>, gz, dim3(64), zsm, s, m->ws_out.as<float>(), (float*)Mtab, B,
+                               nz, nk, hz, count);
+        NS_HIP(hipGetLastError());
     }
-    const ShearGeom G = shear_geom(m);
     const size_t sm = limber_smem(m, elem);
     NS_CHECK(sm <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
     {
-    TraceScope ts(m, s, "limber");
-    if (prec == NS_FP64)
-        hipLaunchKernelGGL(limber_kernel<double>, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
-                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
-                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                           m->lell_d.as<double>(), m->ws_out.as<double>(), (const double*)Mtab, Cv, count);
-    else
-        hipLaunchKernelGGL(limber_kernel<float>, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
-                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
-                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                           m->lell_d.as<double>(), m->ws_out.as<float>(), (const float*)Mtab, Cv, count);
-    NS_HIP(hipGetLastError());
+        TraceScope ts(m, s, "limber");
+        if (m->z_linear)
+            launch_limber<true>(m, theta, ld, B, prec, Mtab, Cv, count, sm, s);
+        else
+            launch_limber<false>(m, theta, ld, B, prec, Mtab, Cv, count, sm, s);
     }
     const size_t sm2 = (size_t)DM_W * (((n + 15) & ~15) + 2) * sizeof(double);
     if (sm2 > 64 * 1024 && !m->chi2_attr_set) {

@@ -462,6 +462,8 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
 // ------------------------------------------------------------------ driver
 void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, double* grad, int prec,
                 hipStream_t s) {
+    NS_CHECK(!m->z_linear && m->n_a <= 256, NS_E_UNSUPPORTED,
+             "the shear gradient covers the cubic z-spline on at most 256 nodes");
     const bool f64 = prec == NS_FP64;
     const size_t elem = f64 ? 8 : 4;
     const int nk = m->n_k, nz = m->n_z, n = m->n_data, d = m->d;

@@ -83,6 +83,7 @@ class Model:
                 D.ell_min = float(desc["ell_min"])
                 D.ell_max = float(desc["ell_max"])
                 D.n_ell = int(desc["n_ell"])
+                D.z_interp = 1 if desc.get("z_interp", "cubic") == "linear" else 0
                 D.pidx = self._p(_i32(desc["pidx"]), C.c_int32_p)
                 D.pfix = self._p(_f64(desc["pfix"]), C.c_double_p)
         h = ctypes.c_void_p()

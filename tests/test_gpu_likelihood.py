@@ -69,7 +69,7 @@ def check_fp64(ref, got, label):
 
 
 @pytest.mark.parametrize("name,B", [("cmb6", 1000), ("cmb4x2500", 300), ("cmbtt_cv", 300), ("shear10", 24),
-                                    ("shear64", 12)])
+                                    ("shear64", 12), ("shear_full", 5), ("shear_interp", 9)])
 def test_fp64_posterior_and_prior(built, name, B):
     say(f"case fp64 {name} B={B}")
     m, g = gpu_model(name)
@@ -82,7 +82,7 @@ def test_fp64_posterior_and_prior(built, name, B):
 
 
 @pytest.mark.parametrize("name,B,sample", [("cmb4x2500", 4096, 40), ("cmbtt_cv", 4096, 40), ("shear64", 4096, 6),
-                                           ("shear10", 16384, 6)])
+                                           ("shear10", 16384, 6), ("shear_interp", 4096, 4), ("shear_full", 512, 3)])
 def test_fp64_full_size_sampled(built, name, B, sample):
     say(f"case fp64 full {name} B={B}")
     m, g = gpu_model(name)
@@ -139,15 +139,18 @@ LOWP_LIMIT = {
     ("cmbtt_cv", "fp32"): 1e-2, ("cmbtt_cv", "bf16x3"): 1e-2, ("cmbtt_cv", "bf16"): 5.0,
     ("shear10", "fp32"): 1e-2, ("shear10", "bf16x3"): 1e-2, ("shear10", "bf16"): 0.1,
     ("shear64", "fp32"): 1e-2, ("shear64", "bf16x3"): 1e-2, ("shear64", "bf16"): 0.1,
+    ("shear_full", "fp32"): 1e-2, ("shear_full", "bf16x3"): 1e-2, ("shear_full", "bf16"): 0.5,
+    ("shear_interp", "fp32"): 1e-2, ("shear_interp", "bf16x3"): 1e-2, ("shear_interp", "bf16"): 0.5,
 }
 
 
-@pytest.mark.parametrize("name", ["cmb6", "cmb4x2500", "cmbtt_cv", "shear10", "shear64"])
+@pytest.mark.parametrize("name", ["cmb6", "cmb4x2500", "cmbtt_cv", "shear10", "shear64", "shear_full",
+                                  "shear_interp"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
 def test_reduced_precision_forms(built, name, prec):
     say(f"case {prec} {name}")
     m, g = gpu_model(name)
-    B = 64 if name.startswith("shear") else 256
+    B = {"shear_full": 12, "shear_interp": 32}.get(name, 64 if name.startswith("shear") else 256)
     th = W.posterior_draws(m["theta_fid"], post_scale(m), B, tag=4)
     ref = oracle_loglike(th, m, chunk=64)
     got = run_gpu(g, th, prec)
@@ -160,7 +163,7 @@ def test_reduced_precision_forms(built, name, prec):
 
 
 @pytest.mark.parametrize("name,B", [("cmb6", 300), ("cmb4x2500", 333), ("cmbtt_cv", 333), ("shear10", 70),
-                                    ("shear64", 9)])
+                                    ("shear64", 9), ("shear_interp", 5)])
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
 def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
     """The one-kernel emulator gives bitwise the layer-by-layer result, with
@@ -246,3 +249,30 @@ def test_cv_loglike_shifts_with_a_constant_offset(built):
     want = -np.sum(0.5 * k * (np.log(10.0) * c + m["data"] / C * (10.0 ** -c - 1.0)), axis=1)
     say(f"cv offset: max |d| {np.abs((l1 - l0) - want).max():.3e}")
     np.testing.assert_allclose(l1 - l0, want, rtol=1e-9, atol=1e-6)
+
+
+def test_full_and_interpolated_shear_share_their_data(built):
+    """App. B's pair on the same data: the GPU's logL difference interpolated -
+    full matches the oracle's walker by walker, and the interpolated spectra
+    (oracle) sit below the full ones almost everywhere (concave log10 P in z)."""
+    say("case shear full vs interp")
+    from oracle import shear as oshear
+    mf, gf = gpu_model("shear_full")
+    mi, gi = gpu_model("shear_interp")
+    th = W.posterior_draws(mf["theta_fid"], post_scale(mf), 6, tag=13)
+    th[:, 2] = np.maximum(th[:, 2], 0.65)
+    d_gpu = run_gpu(gi, th) - run_gpu(gf, th)
+    d_ref = oracle_loglike(th, mi) - oracle_loglike(th, mf)
+    say(f"logL interp - full: gpu {np.round(d_gpu, 6)} oracle {np.round(d_ref, 6)}")
+    np.testing.assert_allclose(d_gpu, d_ref, rtol=0, atol=2e-6)
+    Cf = oshear.spectra(th[:1], mf)[0][0]
+    Ci = oshear.spectra(th[:1], mi)[0][0]
+    assert np.mean(Ci < Cf) > 0.95
+
+
+def test_shear_gradient_refuses_linear_z(built):
+    say("case shear_interp gradient refused")
+    from paper_2509_13307_amd._capi import NSError
+    m, g = gpu_model("shear_interp")
+    with pytest.raises(NSError):
+        g.loglike_grad(torch.tensor(m["theta_fid"][None], device=DEV), "fp64")
