@@ -126,7 +126,7 @@ typedef struct ns_model_desc {
     int32_t n_k;
     double ell_min, ell_max;      /* SHEAR: log-spaced multipoles; CMB_CV:
                                      ell_min = first multipole (integer >= 0)    */
-    int32_t n_ell;
+    int32_t n_ell;                /* SHEAR: <= 32                               */
     const int32_t* pidx;          /* [9 + 3 n_bins] theta index per physical slot
                                      (omega_b, omega_cdm, h, n_s, lnAs, w0, wa,
                                       c_min, eta0, A_IA.., Dz.., m..), -1 = fixed */

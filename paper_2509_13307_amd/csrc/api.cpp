@@ -359,7 +359,7 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         else
             NS_CHECK(D->n_z >= 2 && D->n_z <= D->n_a, NS_E_UNSUPPORTED, "n_z must be in [2, n_a] (linear z)");
         NS_CHECK(D->n_k >= 4, NS_E_SHAPE, "n_k must be >= 4");
-        NS_CHECK(D->n_ell >= 1 && D->n_ell <= 64, NS_E_UNSUPPORTED, "n_ell must be in [1, 64]");
+        NS_CHECK(D->n_ell >= 1 && D->n_ell <= 32, NS_E_UNSUPPORTED, "n_ell must be in [1, 32]");
         NS_CHECK(D->a_min > 0.0 && D->a_min < 1.0, NS_E_INVALID, "a_min must be in (0, 1)");
         NS_CHECK(D->k_min > 0.0 && D->k_max > D->k_min, NS_E_INVALID, "need 0 < k_min < k_max");
         NS_CHECK(D->ell_min > 0.0 && D->ell_max >= D->ell_min, NS_E_INVALID, "need 0 < ell_min <= ell_max");
@@ -374,7 +374,6 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         m->nz_sigma = D->nz_sigma; m->a_min = D->a_min; m->k_min = D->k_min; m->k_max = D->k_max;
         NS_CHECK(D->n_data == m->n_pairs * D->n_ell, NS_E_SHAPE, "n_data must be n_pairs * n_ell");
         NS_CHECK(D->n_data <= 1248, NS_E_UNSUPPORTED, "shear data vector longer than 1248");
-        NS_CHECK(m->n_pairs * ((D->n_ell + 3) / 4) <= 512, NS_E_UNSUPPORTED, "too many (pair, 4-ell) items");
         m->z_linear = D->z_interp == 1;
         NS_CHECK(n_in == 8, NS_E_SHAPE, "shear emulator takes 8 inputs");
         NS_CHECK(m->nets[0]->dims.back() == D->n_k, NS_E_SHAPE, "shear emulator must output n_k values");
@@ -468,16 +467,11 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < n; ++k) XT[(size_t)k * n + i] = X[(size_t)i * n + k];
         upload(m->cov_linvT, XT.data(), XT.size());
-        const int n16 = (n + 15) / 16 * 16, kc_all = n16 / 4;
-        std::vector<double> XF((size_t)n16 * n16, 0.0);
-        for (int nt = 0; nt < n16 / 16; ++nt)
-            for (int kc = 0; kc < kc_all; ++kc)
-                for (int q = 0; q < 64; ++q) {
-                    const int row = 16 * nt + q % 16, col = 4 * kc + q / 16;
-                    if (row < n && col < n)
-                        XF[((size_t)nt * kc_all + kc) * 64 + q] = X[(size_t)row * n + col];
-                }
-        upload(m->cov_linv_frag, XF.data(), XF.size());
+        const int np = (n + 63) / 64 * 64;
+        std::vector<double> LP((size_t)np * np, 0.0);
+        for (int k = 0; k < n; ++k)
+            for (int i = 0; i < n; ++i) LP[(size_t)k * np + i] = X[(size_t)i * n + k];
+        upload(m->cov_lt_pad, LP.data(), LP.size());
         upload(m->cov_w, w.data(), w.size());
         m->logl_const = c;
     }

@@ -143,13 +143,13 @@ struct ns_model {
     nsmi::DevBuf zsp_idx_d;          // int [n_a]: spline interval of z_j
     nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t));
                                      // linear z: (1-t, t, 0, 0)
+    nsmi::DevBuf ws_win;             // shear windows [B][nb][n_a] (form type), log10 chi, n(z) normalisations
     bool z_linear = false;           // linear z-interpolation on nodes evenly spaced in a
     nsmi::DevBuf ell_d;              // double [n_ell]
     nsmi::DevBuf lell_d;             // double [n_ell]: log10(l + 1/2)
     nsmi::DevBuf cov_linv;           // double [n x n] lower-triangular inverse Cholesky factor
     nsmi::DevBuf cov_linvT;          // its transpose (row k holds column k), for the adjoint
-    nsmi::DevBuf cov_linv_frag;      // L^{-1} in FP64-MFMA B-fragment order: [n16/16][n16/4][64],
-                                     // lane q of block (nt, kc) = L^{-1}[16 nt + q % 16][4 kc + q / 16]
+    nsmi::DevBuf cov_lt_pad;         // L^{-T} row-major [np x np], np = n rounded up to 64, zero padded
     nsmi::DevBuf cov_w;              // double [n]: L^{-1} d
 
     // GAUSS
@@ -172,7 +172,6 @@ struct ns_model {
     hipStream_t graph_stream = nullptr;  // stream the captured slice-step graphs replay on
     hipEvent_t graph_event = nullptr;
     bool shear_attr_set = false;     // hipFuncSetAttribute done for the Limber kernels
-    bool chi2_attr_set = false;      // ... and for the dense chi^2 kernel (n > 496)
     unsigned fused_attr_set = 0;     // ... and per instance of the one-kernel emulator
     // BF16 tile / fused launch-shape choice per (kind, M, N, K, networks), measured at first use
     std::map<std::tuple<int, int64_t, int, int, int>, int> tune;

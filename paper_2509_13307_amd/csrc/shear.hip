@@ -6,23 +6,25 @@
 //                  conditions on a uniform grid, the interior (1, 4, 1)
 //                  system is solved by a Thomas sweep, M_0 and M_{N-1} are
 //                  linear extrapolations.
-// limber_kernel    one workgroup per walker, nodes in chunks of 256:
+// shear_windows_kernel  one workgroup per walker, nodes in chunks of 256:
 //                  (a) background on the a-grid: E(a), chi by per-interval
 //                      Simpson, J = dchi/d(-a), growth D (growth index 0.55);
-//                  (b) n_i(z) with photo-z shifts, normalised by the trapezoid
-//                      rule; lensing window Eq. (A3) as (chi/a)(G0 - chi G1)
+//                  (b) n_i(z) with photo-z shifts (normalised by the trapezoid
+//                      rule); lensing window Eq. (A3) as (chi/a)(G0 - chi G1)
 //                      with reverse cumulative trapezoids; NLA window Eq. (A4);
 //                      effective window W = W^g + W^I (the four terms of Eq. (A1)
-//                      share P_dd);
+//                      share P_dd); all FP64.
+// limber_sum_kernel  one workgroup per walker:
 //                  (c) P(k = (l+1/2)/chi_j, z_j): spline or linear in z,
 //                      Catmull-Rom in log10 k (linear ghost nodes), zero
 //                      outside [k_min, k_max];
 //                  (d) Limber sum Eq. (A2) by the trapezoid rule in a with the
-//                      analytic Jacobian, times (1 + m_i)(1 + m_j).
-//                  (a)-(b) are FP64; (c)-(d) run in the form's type T.
-// dense_chi2_kernel  y = L^{-1} d - L^{-1} C with the host-factorised dense
+//                      analytic Jacobian, times (1 + m_i)(1 + m_j);
+//                  (c)-(d) run in the form's type T.
+// dense_chi2_gemm_kernel, dense_chi2_finish_kernel
+//                  y = L^{-1} d - L^{-1} C with the host-factorised dense
 //                  covariance, logL = -1/2 |y|^2 - sum log L_ii - n/2 log 2 pi
-//                  (FP64; L^{-1} C on the FP64 MFMA).
+//                  (FP64; L^{-1} C as a tiled GEMM on the FP64 MFMA).
 #include "devutil.h"
 #include "nsmi.h"
 #include "shear_common.h"
@@ -94,43 +96,41 @@ __global__ __launch_bounds__(64) void zspline_kernel(const T* __restrict__ Y, T*
     mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
 }
 
-// One workgroup (256 threads) per walker.  The n_a nodes are taken in chunks
-// of 256, one node per thread: a forward pass builds chi and -ln D (kept in
-// LDS for every node) and the n(z) normalisations; a reverse pass, from the
-// last chunk to the first, builds the windows (reverse cumulative sums carried
-// from chunk to chunk), looks up P and adds each chunk's share of the Limber
-// sums to per-thread accumulators.  LINZ: linear z-interpolation (no spline
-// second derivatives).
-constexpr int LB_SLOTS = 2;     // (pair, 4-ell group) items per thread
-template <class T, bool LINZ>
-__global__ __launch_bounds__(256) void limber_kernel(
+// shear_windows_kernel: one workgroup (256 threads) per walker, the n_a nodes
+// in chunks of 256 (one node per thread).  E(a_j) and the growth integrand at
+// every node go to LDS first, so that each Simpson interval evaluates only its
+// midpoint; a forward pass then builds chi and -ln D by prefix sums.  The
+// reverse pass (last chunk first) builds the windows from unnormalised n_i(z)
+// (reverse cumulative trapezoids carried from chunk to chunk) and sums the
+// n(z) normalisations on the way; the windows are linear in n_i, so the
+// normalisations are applied to the spectra.  Output per walker: W_i(a_j)
+// sqrt(q_j J_j / chi_j^2) [nb][n_a] (the Limber integrand is the product of
+// two of them and P), log10 chi_j [n_a], normalisations [nb].
+template <class T>
+__global__ __launch_bounds__(256) void shear_windows_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
     const int* __restrict__ pidx, const double* __restrict__ pfix, const double* __restrict__ nz_mean,
-    const double* __restrict__ agrid, const int* __restrict__ zidx, const double* __restrict__ zcoef,
-    const double* __restrict__ lell, const T* __restrict__ Ytab, const T* __restrict__ Mtab,
-    double* __restrict__ Cout, const int* __restrict__ count) {
+    const double* __restrict__ agrid, T* __restrict__ Wout, double* __restrict__ lchi_out,
+    double* __restrict__ norm_out, const int* __restrict__ count) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (count) B = min<int64_t>(B, *count);
     const int64_t w = blockIdx.x;
     if (w >= B) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int na = G.n_a, nb = G.n_bins;
-    const int nch = (na + 255) / 256;
-    const int nl4 = (G.n_ell + 3) & ~3;
+    const int nch = (na + 255) / 256, nap = nch * 256 + 1;
     double* buf = reinterpret_cast<double*>(smem);                    // [2 MAXB][4] block_scan totals
     double* red = buf + 2 * MAXB * 4;                                 // [MAXB][4]
     double* bc = red + MAXB * 4;                                      // [2 MAXB] next carry (thread 0)
     double* gcs = bc + 2 * MAXB;                                      // [2 MAXB] sums over the chunks above
     double* mus = gcs + 2 * MAXB;                                     // [MAXB] n(z) means
-    double* nrm = mus + MAXB;                                         // [MAXB] n(z) normalisations
-    double* gnx = nrm + MAXB;                                         // [2 MAXB] g0, g1 of the node above the chunk
+    double* gnx = mus + MAXB;                                         // [2 MAXB] g0, g1 of the node above the chunk
     double* xw = gnx + 2 * MAXB;                                      // [4][2 MAXB] wave-boundary exchange
-    double* chis = xw + 4 * 2 * MAXB;                                 // [nch 256 + 1]
-    double* lnDs = chis + nch * 256 + 1;                              // [nch 256 + 1]
-    T* Wt = reinterpret_cast<T*>(lnDs + nch * 256 + 1);               // [nb][256]
-    T* Pl = Wt + nb * 256;                                            // [256][nl4]
+    double* chis = xw + 4 * 2 * MAXB;                                 // [nap]
+    double* lnDs = chis + nap;                                        // [nap]
+    double* EA = lnDs + nap;                                          // [nap] E(a_j)
+    double* GA = EA + nap;                                            // [nap] growth integrand at a_j
 
-    // physical parameters
     auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
     const double ob = phys(0), oc = phys(1), h = phys(2), w0 = phys(5), wa = phys(6);
     const double Om = (ob + oc) / (h * h);
@@ -138,98 +138,61 @@ __global__ __launch_bounds__(256) void limber_kernel(
     auto Efn = [&](double a) {
         return sqrt(Om / (a * a * a) + (1.0 - Om) * pow(a, -3.0 * (1.0 + w0 + wa)) * exp(-3.0 * wa * (1.0 - a)));
     };
-    auto ffn = [&](double a) { return cH0 / (a * a * Efn(a)); };
-    auto gfn = [&](double a) {
-        const double E = Efn(a);
-        return pow(Om / (a * a * a) / (E * E), GROWTH_INDEX) / a;
-    };
     if (t < MAXB) mus[t] = t < nb ? nz_mean[t] + phys(9 + nb + t) : 0.0;
+    if (t < 2 * MAXB) gnx[t] = gcs[t] = 0.0;
+    if (t == 0) chis[0] = lnDs[0] = 0.0;
+    for (int j = t; j < na; j += 256) {
+        const double a = agrid[j], E = Efn(a);
+        EA[j] = E;
+        GA[j] = pow(Om / (a * a * a) / (E * E), GROWTH_INDEX) / a;
+    }
     __syncthreads();
     const double s2 = 2.0 * G.nz_sigma * G.nz_sigma;
 
-    // (a) forward pass: Simpson increments of chi and -ln D on [a_j, a_{j+1}];
-    // chis[j] / lnDs[j] = sums over intervals 0..j-1; n(z) normalisations
-    double nsum[MAXB];
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) nsum[i] = 0.0;
-    if (t == 0) chis[0] = lnDs[0] = 0.0;
+    // forward pass: Simpson increments of chi and -ln D on [a_j, a_{j+1}];
+    // chis[j] / lnDs[j] = sums over intervals 0..j-1
     double carry0 = 0.0, carry1 = 0.0;
     for (int c = 0; c < nch; ++c) {
         const int j = c * 256 + t;
-        const bool node = j < na;
-        const double a = node ? agrid[j] : 1.0;
         double inc[2] = {0.0, 0.0};
-        if (node && j < na - 1) {
-            const double a1 = agrid[j + 1], am = 0.5 * (a + a1);
-            inc[0] = G.da / 6.0 * (ffn(a) + 4.0 * ffn(am) + ffn(a1));
-            inc[1] = G.da / 6.0 * (gfn(a) + 4.0 * gfn(am) + gfn(a1));
+        if (j < na - 1) {
+            const double a = agrid[j], a1 = agrid[j + 1], am = 0.5 * (a + a1);
+            const double Em = Efn(am);
+            const double fm = cH0 / (am * am * Em);
+            const double gm = pow(Om / (am * am * am) / (Em * Em), GROWTH_INDEX) / am;
+            inc[0] = G.da / 6.0 * (cH0 / (a * a * EA[j]) + 4.0 * fm + cH0 / (a1 * a1 * EA[j + 1]));
+            inc[1] = G.da / 6.0 * (GA[j] + 4.0 * gm + GA[j + 1]);
         }
         block_scan<2>(inc, buf, false);
         chis[j + 1] = carry0 + inc[0];
         lnDs[j + 1] = carry1 + inc[1];
-        if (node && j > 0) {
-            const double z = 1.0 / a - 1.0;
-            const double q = j == na - 1 ? 0.5 * G.da : G.da;
-#pragma unroll
-            for (int i = 0; i < MAXB; ++i) {
-                if (i >= nb) continue;
-                const double dz = z - mus[i];
-                nsum[i] += q * exp(-dz * dz / s2) / (a * a);
-            }
-        }
         __syncthreads();
         carry0 = chis[c * 256 + 256];
         carry1 = lnDs[c * 256 + 256];
     }
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-        if (i >= nb) continue;
-        const double v = wave_sum(nsum[i]);
-        if (lane == 0) red[i * 4 + wid] = v;
-    }
-    if (t < 2 * MAXB) gnx[t] = gcs[t] = 0.0;
-    __syncthreads();
-    if (t < MAXB) nrm[t] = t < nb ? red[t * 4] + red[t * 4 + 1] + red[t * 4 + 2] + red[t * 4 + 3] : 1.0;
-    __syncthreads();
-
-    // (d) bookkeeping: item = (pair p, group of 4 ell bins); each chunk's node
-    // range is split into nseg segments whose partial sums are added in a
-    // fixed order at the end
-    const int ng = nl4 / 4, nitem = G.n_pairs * ng;
-    const int nseg = nitem >= 256 ? 1 : 256 / nitem;
-    const int len = (min(na, 256) + nseg - 1) / nseg;
-    const int nout = G.n_pairs * G.n_ell;
-    auto pair_of = [&](int p, int& bi, int& bj) {
-        int rem = p;
-        bi = 0;
-        while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
-        bj = bi + rem;
-    };
-    T acc[LB_SLOTS][4];
-#pragma unroll
-    for (int s = 0; s < LB_SLOTS; ++s)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[s][e] = T(0);
 
     // reverse pass over the chunks
+    double nsum[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) nsum[i] = 0.0;
     for (int c = nch - 1; c >= 0; --c) {
         const int j = c * 256 + t;
         const bool node = j < na;
         const double a = node ? agrid[j] : 1.0;
-        const double Ea = node ? Efn(a) : 1.0;
+        const double Ea = node ? EA[j] : 1.0;
         const double fa = cH0 / (a * a * Ea);
         const double chi = node ? chis[j] : 0.0;
         const double D = exp(-(node ? lnDs[j] : 0.0));
         const double z = 1.0 / a - 1.0;
         const double q = (j == 0 || j == na - 1) ? 0.5 * G.da : G.da;
-        // (b) normalised n_i(z_j); integrands of G0, G1 at this node
+        // unnormalised n_i(z_j); integrands of G0, G1 at this node
         double nr[MAXB], g0[MAXB], g1[MAXB];
 #pragma unroll
         for (int i = 0; i < MAXB; ++i) {
             if (i >= nb) { nr[i] = g0[i] = g1[i] = 0.0; continue; }
             const double dz = z - mus[i];
             nr[i] = (node && j > 0) ? exp(-dz * dz / s2) : 0.0;
-            nr[i] /= nrm[i];
+            nsum[i] += q * nr[i] / (a * a);
             g0[i] = node ? nr[i] / (a * a) : 0.0;
             g1[i] = (node && j > 0) ? nr[i] / (a * a * chi) : 0.0;
         }
@@ -269,190 +232,265 @@ __global__ __launch_bounds__(256) void limber_kernel(
 #pragma unroll
             for (int k = 0; k < 2 * MAXB; ++k) bc[k] = seg[k];
         const double pref = 1.5 * Om * H0c * H0c * chi / a;
+        const double sw = (node && j > 0) ? sqrt(q * fa / (chi * chi)) : 0.0;
+        if (node) {
 #pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            if (i >= nb) continue;
-            const double Wg = pref * (seg[i] - chi * seg[MAXB + i]);
-            const double AIA = phys(9 + i);
-            const double WI = -AIA * C1_RHOCR * Om * nr[i] * H0c * Ea / D;
-            Wt[i * 256 + t] = node ? (T)(Wg + WI) : T(0);
-        }
-
-        // (c) P at the Limber wavenumbers for this node, node-major [256][nl4]
-        // (ell contiguous); log10 k = log10(l + 1/2) - log10 chi_j
-        {
-            const bool live = node && j > 0;
-            const double lchi = live ? log10(chi) : 0.0;
-            const T wqj = (node && j > 0) ? (T)(q * fa / (chi * chi)) : T(0);
-            const int n = live ? zidx[j] : 0;
-            const int zc = live ? 4 * j : 0;
-            const T c0 = (T)zcoef[zc], c1 = (T)zcoef[zc + 1];
-            const T c2 = LINZ ? T(0) : (T)zcoef[zc + 2], c3 = LINZ ? T(0) : (T)zcoef[zc + 3];
-            const T* y0 = Ytab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
-            const T* m0p = LINZ ? y0 : Mtab + w * (int64_t)G.n_z * G.n_k + (int64_t)n * G.n_k;
-            auto Yz = [&](int col) {
-                if (LINZ) return c0 * y0[col] + c1 * y0[col + G.n_k];
-                return c0 * y0[col] + c1 * y0[col + G.n_k] + c2 * m0p[col] + c3 * m0p[col + G.n_k];
-            };
-#pragma unroll 4
-            for (int b = 0; b < nl4; ++b) {
-                T P = T(0);
-                const double lk = b < G.n_ell ? lell[b] - lchi : 0.0;
-                if (live && b < G.n_ell && lk >= G.u0 && lk <= G.u1) {
-                    const double sv = (lk - G.u0) / G.du;
-                    int i0 = (int)floor(sv);
-                    i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
-                    const T tt = (T)(sv - i0);
-                    const T p0 = Yz(i0), p1 = Yz(i0 + 1);
-                    const T pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
-                    const T p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
-                    const T mk0 = T(0.5) * (p1 - pm), mk1 = T(0.5) * (p2 - p0);
-                    const T t2 = tt * tt, t3 = t2 * tt;
-                    const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * mk0 +
-                                 (T(-2) * t3 + T(3) * t2) * p1 + (t3 - t2) * mk1;
-                    P = exp10_of<T>(lp) * wqj;
-                }
-                Pl[t * nl4 + b] = P;
+            for (int i = 0; i < MAXB; ++i) {
+                if (i >= nb) continue;
+                const double Wg = pref * (seg[i] - chi * seg[MAXB + i]);
+                const double AIA = phys(9 + i);
+                const double WI = -AIA * C1_RHOCR * Om * nr[i] * H0c * Ea / D;
+                Wout[(w * nb + i) * na + j] = (T)((Wg + WI) * sw);
             }
+            lchi_out[w * na + j] = j > 0 ? log10(chi) : 0.0;
         }
         __syncthreads();
         if (t == 0)
 #pragma unroll
             for (int k = 0; k < 2 * MAXB; ++k) gcs[k] = bc[k];
-
-        // (d) this chunk's share of the Limber sums
-        const int jl1 = min(256, na - c * 256);
+        __syncthreads();
+    }
 #pragma unroll
-        for (int s = 0; s < LB_SLOTS; ++s) {
-            const int it = t + 256 * s;
-            if (it >= nitem * nseg) continue;
-            const int item = it % nitem, sg = it / nitem;
-            const int p = item / ng, gq = item % ng;
-            int bi, bj;
-            pair_of(p, bi, bj);
-            const T* Wi = Wt + bi * 256;
-            const T* Wj = Wt + bj * 256;
-            const int j0 = max(c == 0 ? 1 : 0, sg * len), j1 = min(jl1, (sg + 1) * len);
+    for (int i = 0; i < MAXB; ++i) {
+        if (i >= nb) continue;
+        const double v = wave_sum(nsum[i]);
+        if (lane == 0) red[i * 4 + wid] = v;
+    }
+    __syncthreads();
+    if (t < nb) norm_out[w * nb + t] = red[t * 4] + red[t * 4 + 1] + red[t * 4 + 2] + red[t * 4 + 3];
+}
+
+// limber_sum_kernel: one workgroup (256 threads) per walker, nodes in chunks
+// of 256.  (c) thread = node: log10 P carried to z_j (cubic spline or linear
+// in z), Catmull-Rom in log10 k at k = (l + 1/2)/chi_j, P = 10^(.), zero
+// outside [k_min, k_max]; [256][LB] in LDS with the chunk's scaled windows.
+// (d) thread = (pair, node segment): all LB multipoles of one pair in
+// registers, C_ij(l) += W~_i W~_j P(l); the segments are added in a fixed
+// order, times (1 + m_i)(1 + m_j) / (N_i N_j) with the n(z) normalisations N.
+template <class T, bool LINZ, int LB>
+__global__ __launch_bounds__(256) void limber_sum_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
+    const int* __restrict__ pidx, const double* __restrict__ pfix, const int* __restrict__ zidx,
+    const double* __restrict__ zcoef, const double* __restrict__ lell, const T* __restrict__ Ytab,
+    const T* __restrict__ Mtab, const T* __restrict__ Win, const double* __restrict__ lchi_in,
+    const double* __restrict__ norm_in, double* __restrict__ Cout, const int* __restrict__ count) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    if (count) B = min<int64_t>(B, *count);
+    const int64_t w = blockIdx.x;
+    if (w >= B) return;
+    const int t = threadIdx.x;
+    const int na = G.n_a, nb = G.n_bins, npr = G.n_pairs, nl = G.n_ell;
+    const int nch = (na + 255) / 256;
+    constexpr int WS = 257;                                           // padded row of the window table
+    T* Ws = reinterpret_cast<T*>(smem);                               // [nb][WS]
+    T* Pl = Ws + nb * WS;                                             // [256][LB]
+    auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
+    auto pair_of = [&](int p, int& bi, int& bj) {
+        int rem = p;
+        bi = 0;
+        while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+        bj = bi + rem;
+    };
+    const int nseg = max(1, 256 / npr);
+    const int len = (256 + nseg - 1) / nseg;
+    const bool worker = t < npr * nseg;
+    const int pw = t % npr, sg = t / npr;
+    int bi = 0, bj = 0;
+    if (worker) pair_of(pw, bi, bj);
+    T acc[LB];
+#pragma unroll
+    for (int e = 0; e < LB; ++e) acc[e] = T(0);
+    const int64_t tab = w * (int64_t)G.n_z * G.n_k;
+    for (int c = 0; c < nch; ++c) {
+        const int j = c * 256 + t;
+        const bool node = j < na;
+        for (int i = 0; i < nb; ++i) Ws[i * WS + t] = node ? Win[(w * nb + i) * na + j] : T(0);
+        const bool live = node && j > 0;
+        const double lchi = live ? lchi_in[w * na + j] : 0.0;
+        const int n = live ? zidx[j] : 0;
+        const int zc = live ? 4 * j : 0;
+        const T c0 = (T)zcoef[zc], c1 = (T)zcoef[zc + 1];
+        const T c2 = LINZ ? T(0) : (T)zcoef[zc + 2], c3 = LINZ ? T(0) : (T)zcoef[zc + 3];
+        const T* y0 = Ytab + tab + (int64_t)n * G.n_k;
+        const T* m0p = LINZ ? y0 : Mtab + tab + (int64_t)n * G.n_k;
+        auto Yz = [&](int col) {
+            if (LINZ) return c0 * y0[col] + c1 * y0[col + G.n_k];
+            return c0 * y0[col] + c1 * y0[col + G.n_k] + c2 * m0p[col] + c3 * m0p[col + G.n_k];
+        };
+#pragma unroll 4
+        for (int b = 0; b < LB; ++b) {
+            T P = T(0);
+            const double lk = b < nl ? lell[b] - lchi : 0.0;
+            if (live && b < nl && lk >= G.u0 && lk <= G.u1) {
+                const double sv = (lk - G.u0) / G.du;
+                int i0 = (int)floor(sv);
+                i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
+                const T tt = (T)(sv - i0);
+                const T p0 = Yz(i0), p1 = Yz(i0 + 1);
+                const T pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
+                const T p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
+                const T mk0 = T(0.5) * (p1 - pm), mk1 = T(0.5) * (p2 - p0);
+                const T t2 = tt * tt, t3 = t2 * tt;
+                const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * mk0 +
+                             (T(-2) * t3 + T(3) * t2) * p1 + (t3 - t2) * mk1;
+                P = exp10_of<T>(lp);
+            }
+            Pl[t * LB + b] = P;
+        }
+        __syncthreads();
+        if (worker) {
+            const int j0 = sg * len, j1 = min(min(256, na - c * 256), (sg + 1) * len);
+            const T* Wi = Ws + bi * WS;
+            const T* Wj = Ws + bj * WS;
             for (int jl = j0; jl < j1; ++jl) {
                 const T A = Wi[jl] * Wj[jl];
-                const T* Pj = Pl + jl * nl4 + 4 * gq;
+                const T* Pj = Pl + jl * LB;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc[s][e] += A * Pj[e];
+                for (int e = 0; e < LB; ++e) acc[e] += A * Pj[e];
             }
         }
         __syncthreads();
     }
-
-    auto store = [&](int item, const T (&v)[4]) {
-        const int p = item / ng, gq = item % ng;
-        int bi, bj;
-        pair_of(p, bi, bj);
-        const double mi = phys(9 + 2 * nb + bi), mj = phys(9 + 2 * nb + bj);
-        for (int e = 0; e < 4; ++e) {
-            const int b = 4 * gq + e;
-            if (b < G.n_ell) Cout[w * nout + p * G.n_ell + b] = (1.0 + mi) * (1.0 + mj) * (double)v[e];
-        }
-    };
-    if (nseg == 1) {
+    // segments -> LDS (nseg npr <= 256 rows of LB), added in order
+    if (worker)
 #pragma unroll
-        for (int s = 0; s < LB_SLOTS; ++s)
-            if (t + 256 * s < nitem) store(t + 256 * s, acc[s]);
-    } else {
-        T* part = Pl;                                   // [nseg][nitem][4] (nseg nitem <= 256)
-        if (t < nitem * nseg)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) part[t * 4 + e] = acc[0][e];
-        __syncthreads();
-        for (int item = t; item < nitem; item += 256) {
-            T v[4] = {T(0), T(0), T(0), T(0)};
-            for (int sg = 0; sg < nseg; ++sg)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] += part[(sg * nitem + item) * 4 + e];
-            store(item, v);
-        }
+        for (int e = 0; e < LB; ++e) Pl[(sg * npr + pw) * LB + e] = acc[e];
+    __syncthreads();
+    const int nout = npr * nl;
+    for (int o = t; o < nout; o += 256) {
+        const int p = o / nl, b = o % nl;
+        T v = T(0);
+        for (int s = 0; s < nseg; ++s) v += Pl[(s * npr + p) * LB + b];
+        int ci, cj;
+        pair_of(p, ci, cj);
+        const double mi = phys(9 + 2 * nb + ci), mj = phys(9 + 2 * nb + cj);
+        Cout[w * nout + o] = (1.0 + mi) * (1.0 + mj) * (double)v / (norm_in[w * nb + ci] * norm_in[w * nb + cj]);
     }
 }
 
 // ---------------------------------------------------------------- dense chi^2
-// Y = C L^{-T} for a block of 16 walkers on v_mfma_f64_16x16x4f64, then
-// chi^2_b = sum_n (w_n - Y_bn)^2 with w = L^{-1} d.  The block's spectra sit
-// in LDS (A operand); L^{-1} is read in fragment order (one coalesced 512-byte
-// load per wave and MFMA), and the K steps above the diagonal, where L^{-1}
-// vanishes, are skipped.  Wave w owns column tiles w, w + 4, ... (DM_CT per
-// pass); row sums are reduced in a fixed order (deterministic).
-constexpr int DM_W = 16;      // walkers per workgroup
-constexpr int DM_CT = 5;      // column tiles per wave per pass
-__global__ __launch_bounds__(256) void dense_chi2_kernel(
-    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
-    const double* __restrict__ pa, const double* __restrict__ pb, const double* __restrict__ C, int n,
-    const double* __restrict__ Lf, const double* __restrict__ wv, double cst, double* __restrict__ logl,
-    const int* __restrict__ count) {
-    extern __shared__ double Cs[];                 // [DM_W][n16 + 2]
-    __shared__ double red[4][DM_W];
+// Y = C L^{-T} as a GEMM over (64-walker x 64-column) output tiles on
+// v_mfma_f64_16x16x4f64: each wave owns a 32 x 32 quarter (2 x 2 MFMA
+// tiles); K blocks of 16 are staged through LDS (double-buffered, the next
+// block's global loads in flight during the current block's MFMAs).  L^{-T}
+// is lower-triangular in (column, k), so a column tile stops at its own K
+// range.  Each tile writes its walkers' partial sums of (w_n - Y_bn)^2 over its
+// 64 columns, w = L^{-1} d; dense_chi2_finish_kernel adds the column tiles in
+// a fixed order (deterministic).
+constexpr int DG_M = 64, DG_N = 64, DG_KB = 16;
+__global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __restrict__ C, int64_t B, int n, int np,
+                                                              const double* __restrict__ Lt,
+                                                              const double* __restrict__ wv,
+                                                              double* __restrict__ part, int64_t pstride,
+                                                              const int* __restrict__ count) {
+    __shared__ double As[2][DG_KB][DG_M];     // [k][walker]
+    __shared__ double Bs[2][DG_KB][DG_N];     // [k][column]
+    __shared__ double red[2][DG_M];
     if (count) B = min<int64_t>(B, *count);
-    const int64_t w0 = (int64_t)blockIdx.x * DM_W;
-    if (w0 >= B) return;
+    const int64_t b0 = (int64_t)blockIdx.x * DG_M;
+    if (b0 >= B) return;
+    const int ct = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n16 = (n + 15) & ~15, cs = n16 + 2;
-    const int nt_all = n16 / 16, kc_all = n16 / 4;
-    for (int e = tid; e < DM_W * n16; e += 256) {
-        const int r = e / n16, k = e % n16;
-        const int64_t w = w0 + r;
-        Cs[r * cs + k] = (w < B && k < n) ? C[w * n + k] : 0.0;
-    }
+    const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
+    const int kend = min(np, DG_N * (ct + 1));
+    double ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;                  // 0 .. 1023
+            const int row = e >> 4, k = e & 15;           // A: 16 consecutive k of one walker
+            const int64_t b = b0 + row;
+            const int kk = k0 + k;
+            ra[q] = (b < B && kk < n) ? C[b * n + kk] : 0.0;
+            const int kb = e >> 6, col = e & 63;          // B: one row of the column tile
+            rb[q] = Lt[(size_t)(k0 + kb) * np + DG_N * ct + col];
+        }
+    };
+    auto sstore = [&](int bf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            As[bf][e & 15][e >> 4] = ra[q];
+            Bs[bf][e >> 6][e & 63] = rb[q];
+        }
+    };
+    f64x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+    gload(0);
+    sstore(0);
     __syncthreads();
-    double srow[4] = {0.0, 0.0, 0.0, 0.0};          // rows (lane >> 4) + 4 r
-    for (int t0 = wave; t0 < nt_all; t0 += 4 * DM_CT) {
-        f64x4_t acc[DM_CT];
+    int bf = 0;
+    for (int k0 = 0; k0 < kend; k0 += DG_KB) {
+        const bool more = k0 + DG_KB < kend;
+        if (more) gload(k0 + DG_KB);
 #pragma unroll
-        for (int j = 0; j < DM_CT; ++j)
+        for (int kk = 0; kk < DG_KB; kk += 4) {
+            double a[2], bv[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
-        const int jmax = min(DM_CT - 1, (nt_all - 1 - t0) / 4);
-        const int kmax = min(4 * (t0 + 4 * jmax) + 4, kc_all);
-#pragma unroll 2
-        for (int kc = 0; kc < kmax; ++kc) {
-            const double a = Cs[(lane & 15) * cs + 4 * kc + (lane >> 4)];
+            for (int i = 0; i < 2; ++i) a[i] = As[bf][kk + (lane >> 4)][wr + 16 * i + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < DM_CT; ++j) {
-                const int nt = t0 + 4 * j;
-                if (j <= jmax && kc < 4 * nt + 4) {
-                    const double b = Lf[((size_t)nt * kc_all + kc) * 64 + lane];
-                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[bf][kk + (lane >> 4)][wc + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) sstore(bf ^ 1);
+        __syncthreads();
+        bf ^= 1;
+    }
+    // (w_n - Y_bn)^2 summed over this wave's columns: D row (lane >> 4) + 4 r, column lane & 15
+    double srow[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = DG_N * ct + wc + 16 * j + (lane & 15);
+                if (col < n) {
+                    const double e = wv[col] - acc[i][j][r];
+                    sacc = fma(e, e, sacc);
                 }
             }
+            srow[i][r] = sacc;
         }
 #pragma unroll
-        for (int j = 0; j < DM_CT; ++j) {
-            const int col = 16 * (t0 + 4 * j) + (lane & 15);
-            if (j > jmax || col >= n) continue;
-            const double wn = wv[col];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double e = wn - acc[j][r];
-                srow[r] = fma(e, e, srow[r]);
-            }
-        }
-    }
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) srow[r] += __shfl_xor(srow[r], o, 64);
+            for (int o = 1; o < 16; o <<= 1) srow[i][r] += __shfl_xor(srow[i][r], o, 64);
     if ((lane & 15) == 0)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[wave][(lane >> 4) + 4 * r] = srow[r];
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave & 1][wr + 16 * i + (lane >> 4) + 4 * r] = srow[i][r];
     __syncthreads();
-    if (tid < DM_W) {
-        const int64_t w = w0 + tid;
-        if (w < B) {
-            const double chi2 = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-            bool ok = true;
-            const double* th = theta + w * ld;
-            for (int i = 0; i < d; ++i)
-                if (pk[i] == NS_PRIOR_UNIFORM && (th[i] < pa[i] || th[i] > pb[i])) ok = false;
-            logl[w] = ok ? -0.5 * chi2 + cst : -INFINITY;
-        }
-    }
+    if (tid < DG_M && b0 + tid < B) part[(int64_t)ct * pstride + b0 + tid] = red[0][tid] + red[1][tid];
+}
+
+__global__ void dense_chi2_finish_kernel(const double* __restrict__ theta, int64_t ld, int64_t B, int d,
+                                         const int* __restrict__ pk, const double* __restrict__ pa,
+                                         const double* __restrict__ pb, const double* __restrict__ part,
+                                         int64_t pstride, int n_ct, double cst, double* __restrict__ logl,
+                                         const int* __restrict__ count) {
+    if (count) B = min<int64_t>(B, *count);
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    double chi2 = 0.0;
+    for (int c = 0; c < n_ct; ++c) chi2 += part[(int64_t)c * pstride + w];
+    bool ok = true;
+    const double* th = theta + w * ld;
+    for (int i = 0; i < d; ++i)
+        if (pk[i] == NS_PRIOR_UNIFORM && (th[i] < pa[i] || th[i] > pb[i])) ok = false;
+    logl[w] = ok ? -0.5 * chi2 + cst : -INFINITY;
 }
 
 ShearGeom shear_geom(const ns_model* m) {
@@ -466,27 +504,53 @@ ShearGeom shear_geom(const ns_model* m) {
     return G;
 }
 
-static size_t limber_smem(const ns_model* m, size_t elem) {
-    const size_t nch = (m->n_a + 255) / 256;
-    return (2 * MAXB * 4 + MAXB * 4 + 3 * 2 * MAXB + 2 * MAXB + 4 * 2 * MAXB + 2 * (nch * 256 + 1)) * sizeof(double) +
-           (size_t)(m->n_bins + ((m->n_ell + 3) & ~3)) * 256 * elem;
+static size_t windows_smem(const ns_model* m) {
+    const size_t nap = (m->n_a + 255) / 256 * 256 + 1;
+    return (2 * MAXB * 4 + MAXB * 4 + 2 * MAXB + 2 * MAXB + MAXB + 2 * MAXB + 4 * 2 * MAXB + 4 * nap) * sizeof(double);
 }
 
-template <bool LINZ>
-static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t B, int prec, const void* Mtab,
-                          double* Cv, const int* count, size_t sm, hipStream_t s) {
-    const ShearGeom G = shear_geom(m);
-    if (prec == NS_FP64)
-        hipLaunchKernelGGL((limber_kernel<double, LINZ>), dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
-                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
-                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                           m->lell_d.as<double>(), m->ws_out.as<double>(), (const double*)Mtab, Cv, count);
-    else
-        hipLaunchKernelGGL((limber_kernel<float, LINZ>), dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G,
-                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
-                           m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                           m->lell_d.as<double>(), m->ws_out.as<float>(), (const float*)Mtab, Cv, count);
+static int limber_lb(const ns_model* m) { return m->n_ell <= 20 ? 20 : 32; }
+
+static size_t limber_sum_smem(const ns_model* m, size_t elem) {
+    return ((size_t)m->n_bins * 257 + 256 * (size_t)limber_lb(m)) * elem;
+}
+
+template <class T, bool LINZ>
+static void launch_limber_sum(ns_model* m, const ShearGeom& G, const double* theta, int64_t ld, int64_t B,
+                              const void* Mtab, const T* Win, const double* lchi, const double* norm, double* Cv,
+                              const int* count, size_t sm, hipStream_t s) {
+    auto kern = limber_lb(m) == 20 ? limber_sum_kernel<T, LINZ, 20> : limber_sum_kernel<T, LINZ, 32>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G, m->pidx_d.as<int>(),
+                       m->pfix_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
+                       m->lell_d.as<double>(), m->ws_out.as<T>(), (const T*)Mtab, Win, lchi, norm, Cv, count);
     NS_HIP(hipGetLastError());
+}
+
+template <class T>
+static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t B, const void* Mtab, double* Cv,
+                          const int* count, hipStream_t s) {
+    const ShearGeom G = shear_geom(m);
+    const int na = m->n_a, nb = m->n_bins;
+    // windows [B][nb][na] (T), log10 chi [B][na], normalisations [B][nb]
+    const size_t wbytes = ((size_t)B * nb * na * sizeof(T) + 7) / 8 * 8;
+    m->ws_win.ensure(wbytes + (size_t)B * (na + nb) * sizeof(double));
+    T* Win = m->ws_win.as<T>();
+    double* lchi = reinterpret_cast<double*>(m->ws_win.as<char>() + wbytes);
+    double* norm = lchi + (size_t)B * na;
+    const size_t sm1 = windows_smem(m), sm2 = limber_sum_smem(m, sizeof(T));
+    NS_CHECK(sm1 <= 160 * 1024 && sm2 <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
+    {
+        TraceScope ts(m, s, "shear_windows");
+        hipLaunchKernelGGL(shear_windows_kernel<T>, dim3((unsigned)B), dim3(256), sm1, s, theta, ld, B, G,
+                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
+                           m->agrid_d.as<double>(), Win, lchi, norm, count);
+        NS_HIP(hipGetLastError());
+    }
+    TraceScope ts(m, s, "limber");
+    if (m->z_linear)
+        launch_limber_sum<T, true>(m, G, theta, ld, B, Mtab, Win, lchi, norm, Cv, count, sm2, s);
+    else
+        launch_limber_sum<T, false>(m, G, theta, ld, B, Mtab, Win, lchi, norm, Cv, count, sm2, s);
 }
 
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
@@ -496,14 +560,22 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     const int n = m->n_data;
     // aux: spline second derivatives [B x nz x nk] (cubic z only) then spectra [B x n] (double)
     const size_t mbytes = m->z_linear ? 0 : (size_t)B * nz * nk * elem;
-    m->ws_aux.ensure(mbytes + (size_t)B * n * sizeof(double));
+    const size_t n_ct_max = (n + 63) / 64;
+    m->ws_aux.ensure(mbytes + (size_t)B * (n + n_ct_max) * sizeof(double));
     void* Mtab = m->ws_aux.p;
     double* Cv = reinterpret_cast<double*>(m->ws_aux.as<char>() + mbytes);
     const double zmax = 1.0 / m->a_min - 1.0;
     const double hz = zmax / (nz - 1);
     if (!m->shear_attr_set) {   // once per model, outside any stream capture
-        const void* fns[4] = {(const void*)limber_kernel<double, false>, (const void*)limber_kernel<float, false>,
-                              (const void*)limber_kernel<double, true>, (const void*)limber_kernel<float, true>};
+        const void* fns[] = {(const void*)shear_windows_kernel<double>, (const void*)shear_windows_kernel<float>,
+                             (const void*)limber_sum_kernel<double, false, 20>,
+                             (const void*)limber_sum_kernel<double, false, 32>,
+                             (const void*)limber_sum_kernel<double, true, 20>,
+                             (const void*)limber_sum_kernel<double, true, 32>,
+                             (const void*)limber_sum_kernel<float, false, 20>,
+                             (const void*)limber_sum_kernel<float, false, 32>,
+                             (const void*)limber_sum_kernel<float, true, 20>,
+                             (const void*)limber_sum_kernel<float, true, 32>};
         for (const void* f : fns)
             NS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -525,26 +597,23 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
                                nz, nk, hz, count);
         NS_HIP(hipGetLastError());
     }
-    const size_t sm = limber_smem(m, elem);
-    NS_CHECK(sm <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
+    if (prec == NS_FP64)
+        launch_limber<double>(m, theta, ld, B, Mtab, Cv, count, s);
+    else
+        launch_limber<float>(m, theta, ld, B, Mtab, Cv, count, s);
+    // chi^2 partial sums per 64-column tile: [n_ct x B] after the spectra
+    const int np = (n + DG_N - 1) / DG_N * DG_N, n_ct = np / DG_N;
+    double* part = Cv + (size_t)B * n;
     {
-        TraceScope ts(m, s, "limber");
-        if (m->z_linear)
-            launch_limber<true>(m, theta, ld, B, prec, Mtab, Cv, count, sm, s);
-        else
-            launch_limber<false>(m, theta, ld, B, prec, Mtab, Cv, count, sm, s);
+        TraceScope ts(m, s, "dense_chi2");
+        hipLaunchKernelGGL(dense_chi2_gemm_kernel, dim3((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct), dim3(256),
+                           0, s, Cv, B, n, np, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part, B, count);
+        NS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(dense_chi2_finish_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld,
+                           B, m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), part, B,
+                           n_ct, m->logl_const, logl, count);
+        NS_HIP(hipGetLastError());
     }
-    const size_t sm2 = (size_t)DM_W * (((n + 15) & ~15) + 2) * sizeof(double);
-    if (sm2 > 64 * 1024 && !m->chi2_attr_set) {
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)sm2));
-        m->chi2_attr_set = true;
-    }
-    TraceScope ts(m, s, "dense_chi2");
-    hipLaunchKernelGGL(dense_chi2_kernel, dim3((unsigned)((B + DM_W - 1) / DM_W)), dim3(256), sm2, s, theta, ld, B,
-                       m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), Cv, n,
-                       m->cov_linv_frag.as<double>(), m->cov_w.as<double>(), m->logl_const, logl, count);
-    NS_HIP(hipGetLastError());
 }
 
 }  // namespace nsmi
