@@ -414,9 +414,10 @@ def to_unit_cube(theta, model):
 
 def shear_leg(Model, W, torch, dev):
     """Cosmic-shear likelihood throughput at batch 4096 (64 and 10 redshift
-    nodes), and ragged slice-step batches of 1024-16384 walkers on the
-    10-node likelihood, where walkers need different numbers of likelihood
-    evaluations per step (compacted each round)."""
+    nodes), the paper-shaped full / interpolated pair at batch 512, and ragged
+    slice-step batches of 1024-16384 walkers on the 10-node likelihood, where
+    walkers need different numbers of likelihood evaluations per step
+    (compacted each round)."""
     out = {}
     for name in ("shear64", "shear10"):
         m = W.load_model(name)
@@ -442,6 +443,30 @@ def shear_leg(Model, W, torch, dev):
                              kernels_us={k: round(t / n * 1e3, 2) for k, (n, t) in tr.items()})
         out[f"{name}_b4096"] = res
         print(f"# {name}: {json.dumps(res)}", file=sys.stderr, flush=True)
+    # the paper's shear pair (10 bins, 1025 nodes): full vs linear-z interpolated
+    # likelihood at the nested-sampling batch (512 walkers)
+    pair = {}
+    for name in ("shear_full", "shear_interp"):
+        m = W.load_model(name)
+        g = Model(m)
+        th = torch.tensor(W.prior_draws(m, 512, tag=14), dtype=torch.float64, device=dev)
+        for prec in ("bf16x3", "bf16"):
+            g.loglike(th, prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                g.loglike(th, prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            pair[f"{name}_b512_{prec}"] = dict(ms_per_step=round(ms, 3), evals_per_s=round(512 / (ms * 1e-3), 1))
+        g.close()
+    for prec in ("bf16x3", "bf16"):
+        pair[f"speedup_interp_over_full_{prec}"] = round(pair[f"shear_full_b512_{prec}"]["ms_per_step"] /
+                                                         pair[f"shear_interp_b512_{prec}"]["ms_per_step"], 2)
+    out["paper_shear_pair"] = pair
+    print(f"# paper shear pair: {json.dumps(pair)}", file=sys.stderr, flush=True)
     m = W.load_model("shear10")
     g = Model(m)
     width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
