@@ -36,10 +36,11 @@ def mlp_flops(net, rows):
 KERNEL_SOURCES = {"mlp_fused": ("paper_2509_13307_amd/csrc/mlp_fused.hip", "paper_2509_13307_amd/csrc/devutil.h")}
 
 
-def measured_traffic(dom, B):
+def measured_traffic(dom, B, workload):
     """HBM bytes per launch of kernel `dom` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, scaled by the plain-copy calibration; None
-    when no summary exists or the kernel sources changed since it was taken."""
+    when no summary exists for this workload and batch or the kernel sources
+    changed since it was taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"{dom}_hbm_bytes.json")
@@ -50,12 +51,12 @@ def measured_traffic(dom, B):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[key]:
         h.update(open(os.path.join(here, f), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest() or rec.get("batch") != B:
+    if rec.get("source_sha256") != h.hexdigest() or rec.get("batch") != B or rec.get("workload") != workload:
         return None
     return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
 
 
-def roofline_of(dom, avg_s, prec, m, B):
+def roofline_of(dom, avg_s, prec, m, B, workload):
     """Roofline entry of kernel `dom` from its average launch time: algorithmic
     work of one launch over the form's published MI355X peak."""
     net = m["nets"][0]
@@ -83,13 +84,29 @@ def roofline_of(dom, avg_s, prec, m, B):
     else:
         achieved = work / avg_s / 1e9
         peak = HBM_PEAK_GBS
-    traffic = measured_traffic(dom, B)
+    traffic = measured_traffic(dom, B, workload)
     r = dict(kernel=dom, bound=bound, achieved=round(achieved, 2), peak=peak, unit=unit,
              frac=round(achieved / peak, 4), traffic=traffic, avg_launch_us=round(avg_s * 1e6, 2),
              work_per_launch=work)
     if issued is not None:
         r["mfma_issued_frac"] = round(issued / avg_s / 1e12 / peak, 4)
     return r
+
+
+WORKLOAD_TEXT = {
+    "cmb4x2500": "6 params -> 4 x (6-512-512-512-512-2500) emulators, 3x3 block + diagonal Gaussian over 10000 "
+                 "data, prior-draw theta",
+    "cmb6": "6 params -> 6-128-128-128-200 emulator, diagonal Gaussian over 200 data, prior-draw theta",
+    "cmbtt_cv": "6 params -> 6-512-512-512-512-2500 TT emulator, cosmic-variance-limited likelihood, prior-draw theta",
+    "shear10": "39 params, emulator 8-512-512-512-512-420 at 10 z nodes (cubic in z), 256 a-nodes, 5 bins, "
+               "dense 300 x 300 chi^2, prior-draw theta",
+    "shear64": "39 params, emulator 8-512-512-512-512-420 at 64 z nodes (cubic in z), 256 a-nodes, 5 bins, "
+               "dense 300 x 300 chi^2, prior-draw theta",
+    "shear_full": "39 params, emulator 8-512-512-512-512-420 at all 1025 a-nodes, 10 bins, dense 1100 x 1100 "
+                  "chi^2, prior-draw theta",
+    "shear_interp": "39 params, emulator 8-512-512-512-512-420 at 103 nodes (linear in z), 1025 a-nodes, 10 bins, "
+                    "dense 1100 x 1100 chi^2, prior-draw theta",
+}
 
 
 def main():
@@ -188,7 +205,7 @@ def main():
     dom = max(tr, key=lambda k: tr[k][1])
     n_launch, tot_ms = tr[dom]
     avg_s = tot_ms / n_launch * 1e-3
-    roofline = roofline_of(dom, avg_s, head, m, B)
+    roofline = roofline_of(dom, avg_s, head, m, B, args.workload)
     out = {
         "metric": "likelihood evals/sec @batch 4096 (BF16 vs FP64); NS wall time to logZ +/-0.1",
         "value": round(res[head]["evals_per_s"], 1),
@@ -202,8 +219,7 @@ def main():
         "vs_baseline": None,
         "dtype": head,
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: 6 params -> 4 x (6-512-512-512-512-2500) emulators, "
-                               "3x3 block + diagonal Gaussian over 10000 data, prior-draw theta",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, '')}",
                    "batch": B, "parallelism": "single GPU"},
         "forms": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for p, r in res.items()},
         "fp64_evals_per_s": round(res["fp64"]["evals_per_s"], 1) if "fp64" in res else None,

@@ -271,42 +271,52 @@ static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, i
     constexpr int NT = 64 * (H / (32 * CT));
     const size_t smem = (size_t)(X3 ? 2 : 1) * R * (H + 8) * sizeof(uint16_t);
     const auto kern = mlp_fused_kernel<H, RT, X3, P, CT>;
-    const int bit = (H == 512 ? 16 : 0) + (X3 ? 8 : 0) + (CT == 1 ? 4 : 0) + (P == 2 ? 0 : (P == 4 ? 1 : 2));
-    if (smem > 64 * 1024 && !(m->fused_attr_set & (1u << bit))) {
+    const int bit = (RT == 1 ? 32 : 0) + (H == 512 ? 16 : 0) + (X3 ? 8 : 0) + (CT == 1 ? 4 : 0) +
+                    (P == 2 ? 0 : (P == 4 ? 1 : 2));
+    if (smem > 64 * 1024 && !(m->fused_attr_set & (1ull << bit))) {
         NS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-        m->fused_attr_set |= 1u << bit;
+        m->fused_attr_set |= 1ull << bit;
     }
     const dim3 grid((unsigned)((rows + R - 1) / R), (unsigned)G);
     hipLaunchKernelGGL(kern, grid, dim3(NT), smem, s, theta, ld, rows, rpw, m->emu_src_d.as<int>(),
                        m->emu_fix_d.as<double>(), m->znodes_d.as<double>(), A, count);
 }
 
-// Candidate launch shapes (64-row blocks): waves of 32 or 64 output units,
-// 2-8 K steps of weight prefetch.  All candidates give identical results.
+// Candidate launch shapes: 64-row blocks with waves of 32 or 64 output units
+// and 2-8 K steps of weight prefetch, and 32-row blocks (twice the workgroups
+// for small batches of one network).  All candidates give identical results.
 using FusedLaunch = void (*)(ns_model*, const FusedArgs&, const double*, int64_t, int64_t, int, int, const int*,
                              hipStream_t);
 struct FusedCfg { FusedLaunch fn; const char* name; };
-constexpr int FUSED_NCFG = 4;
+constexpr int FUSED_NCFG = 6;
 static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
     {   // H = 128
         {{launch_fused<128, 2, false, 4, 2>, "fused 2 waves x 64 units, prefetch 4"},
          {launch_fused<128, 2, false, 8, 2>, "fused 2 waves x 64 units, prefetch 8"},
          {launch_fused<128, 2, false, 4, 1>, "fused 4 waves x 32 units, prefetch 4"},
-         {launch_fused<128, 2, false, 8, 1>, "fused 4 waves x 32 units, prefetch 8"}},
+         {launch_fused<128, 2, false, 8, 1>, "fused 4 waves x 32 units, prefetch 8"},
+         {launch_fused<128, 1, false, 4, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 4"},
+         {launch_fused<128, 1, false, 8, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 8"}},
         {{launch_fused<128, 2, true, 2, 2>, "fused split 2 waves x 64 units, prefetch 2"},
          {launch_fused<128, 2, true, 4, 2>, "fused split 2 waves x 64 units, prefetch 4"},
          {launch_fused<128, 2, true, 2, 1>, "fused split 4 waves x 32 units, prefetch 2"},
-         {launch_fused<128, 2, true, 4, 1>, "fused split 4 waves x 32 units, prefetch 4"}},
+         {launch_fused<128, 2, true, 4, 1>, "fused split 4 waves x 32 units, prefetch 4"},
+         {launch_fused<128, 1, true, 2, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 2"},
+         {launch_fused<128, 1, true, 4, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 4"}},
     },
     {   // H = 512
         {{launch_fused<512, 2, false, 4, 2>, "fused 8 waves x 64 units, prefetch 4"},
          {launch_fused<512, 2, false, 8, 2>, "fused 8 waves x 64 units, prefetch 8"},
          {launch_fused<512, 2, false, 4, 1>, "fused 16 waves x 32 units, prefetch 4"},
-         {launch_fused<512, 2, false, 8, 1>, "fused 16 waves x 32 units, prefetch 8"}},
+         {launch_fused<512, 2, false, 8, 1>, "fused 16 waves x 32 units, prefetch 8"},
+         {launch_fused<512, 1, false, 4, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 4"},
+         {launch_fused<512, 1, false, 8, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 8"}},
         {{launch_fused<512, 2, true, 2, 2>, "fused split 8 waves x 64 units, prefetch 2"},
          {launch_fused<512, 2, true, 4, 2>, "fused split 8 waves x 64 units, prefetch 4"},
          {launch_fused<512, 2, true, 2, 1>, "fused split 16 waves x 32 units, prefetch 2"},
-         {launch_fused<512, 2, true, 4, 1>, "fused split 16 waves x 32 units, prefetch 4"}},
+         {launch_fused<512, 2, true, 4, 1>, "fused split 16 waves x 32 units, prefetch 4"},
+         {launch_fused<512, 1, true, 2, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 2"},
+         {launch_fused<512, 1, true, 4, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 4"}},
     },
 };
 

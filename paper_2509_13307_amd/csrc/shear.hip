@@ -106,7 +106,7 @@ __global__ __launch_bounds__(64) void zspline_kernel(const T* __restrict__ Y, T*
 // normalisations are applied to the spectra.  Output per walker: W_i(a_j)
 // sqrt(q_j J_j / chi_j^2) [nb][n_a] (the Limber integrand is the product of
 // two of them and P), log10 chi_j [n_a], normalisations [nb].
-template <class T>
+template <class T, int NB>
 __global__ __launch_bounds__(256) void shear_windows_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
     const int* __restrict__ pidx, const double* __restrict__ pfix, const double* __restrict__ nz_mean,
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void shear_windows_kernel(
         return sqrt(Om / (a * a * a) + (1.0 - Om) * pow(a, -3.0 * (1.0 + w0 + wa)) * exp(-3.0 * wa * (1.0 - a)));
     };
     if (t < MAXB) mus[t] = t < nb ? nz_mean[t] + phys(9 + nb + t) : 0.0;
-    if (t < 2 * MAXB) gnx[t] = gcs[t] = 0.0;
+    if (t < 2 * MAXB) gnx[t] = gcs[t] = bc[t] = 0.0;
     if (t == 0) chis[0] = lnDs[0] = 0.0;
     for (int j = t; j < na; j += 256) {
         const double a = agrid[j], E = Efn(a);
@@ -172,9 +172,9 @@ __global__ __launch_bounds__(256) void shear_windows_kernel(
     }
 
     // reverse pass over the chunks
-    double nsum[MAXB];
+    double nsum[NB];
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) nsum[i] = 0.0;
+    for (int i = 0; i < NB; ++i) nsum[i] = 0.0;
     for (int c = nch - 1; c >= 0; --c) {
         const int j = c * 256 + t;
         const bool node = j < na;
@@ -186,9 +186,9 @@ __global__ __launch_bounds__(256) void shear_windows_kernel(
         const double z = 1.0 / a - 1.0;
         const double q = (j == 0 || j == na - 1) ? 0.5 * G.da : G.da;
         // unnormalised n_i(z_j); integrands of G0, G1 at this node
-        double nr[MAXB], g0[MAXB], g1[MAXB];
+        double nr[NB], g0[NB], g1[NB];
 #pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
+        for (int i = 0; i < NB; ++i) {
             if (i >= nb) { nr[i] = g0[i] = g1[i] = 0.0; continue; }
             const double dz = z - mus[i];
             nr[i] = (node && j > 0) ? exp(-dz * dz / s2) : 0.0;
@@ -200,15 +200,15 @@ __global__ __launch_bounds__(256) void shear_windows_kernel(
         // wave (through LDS) or the chunk above (gnx)
         if (lane == 0)
 #pragma unroll
-            for (int i = 0; i < MAXB; ++i) {
+            for (int i = 0; i < NB; ++i) {
                 xw[wid * 2 * MAXB + i] = g0[i];
                 xw[wid * 2 * MAXB + MAXB + i] = g1[i];
             }
         __syncthreads();
-        double seg[2 * MAXB];
+        double seg[2 * NB];
         const bool has = node && j < na - 1;
 #pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
+        for (int i = 0; i < NB; ++i) {
             double n0 = __shfl_down(g0[i], 1, 64), n1 = __shfl_down(g1[i], 1, 64);
             if (lane == 63) {
                 const double* src = wid < 3 ? xw + (wid + 1) * 2 * MAXB : gnx;
@@ -216,28 +216,34 @@ __global__ __launch_bounds__(256) void shear_windows_kernel(
                 n1 = src[MAXB + i];
             }
             seg[i] = (has && i < nb) ? 0.5 * G.da * (g0[i] + n0) : 0.0;
-            seg[MAXB + i] = (has && i < nb) ? 0.5 * G.da * (g1[i] + n1) : 0.0;
+            seg[NB + i] = (has && i < nb) ? 0.5 * G.da * (g1[i] + n1) : 0.0;
         }
         __syncthreads();
         if (t == 0)
 #pragma unroll
-            for (int i = 0; i < MAXB; ++i) {
+            for (int i = 0; i < NB; ++i) {
                 gnx[i] = g0[i];
                 gnx[MAXB + i] = g1[i];
             }
-        block_scan<2 * MAXB>(seg, buf, true);      // sum over the chunk's segments m >= j
+        block_scan<2 * NB>(seg, buf, true);        // sum over the chunk's segments m >= j
 #pragma unroll
-        for (int k = 0; k < 2 * MAXB; ++k) seg[k] += gcs[k];
+        for (int k = 0; k < NB; ++k) {
+            seg[k] += gcs[k];
+            seg[NB + k] += gcs[MAXB + k];
+        }
         if (t == 0)
 #pragma unroll
-            for (int k = 0; k < 2 * MAXB; ++k) bc[k] = seg[k];
+            for (int k = 0; k < NB; ++k) {
+                bc[k] = seg[k];
+                bc[MAXB + k] = seg[NB + k];
+            }
         const double pref = 1.5 * Om * H0c * H0c * chi / a;
         const double sw = (node && j > 0) ? sqrt(q * fa / (chi * chi)) : 0.0;
         if (node) {
 #pragma unroll
-            for (int i = 0; i < MAXB; ++i) {
+            for (int i = 0; i < NB; ++i) {
                 if (i >= nb) continue;
-                const double Wg = pref * (seg[i] - chi * seg[MAXB + i]);
+                const double Wg = pref * (seg[i] - chi * seg[NB + i]);
                 const double AIA = phys(9 + i);
                 const double WI = -AIA * C1_RHOCR * Om * nr[i] * H0c * Ea / D;
                 Wout[(w * nb + i) * na + j] = (T)((Wg + WI) * sw);
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(256) void shear_windows_kernel(
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
+    for (int i = 0; i < NB; ++i) {
         if (i >= nb) continue;
         const double v = wave_sum(nsum[i]);
         if (lane == 0) red[i * 4 + wid] = v;
@@ -541,9 +547,10 @@ static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t 
     NS_CHECK(sm1 <= 160 * 1024 && sm2 <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
     {
         TraceScope ts(m, s, "shear_windows");
-        hipLaunchKernelGGL(shear_windows_kernel<T>, dim3((unsigned)B), dim3(256), sm1, s, theta, ld, B, G,
-                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
-                           m->agrid_d.as<double>(), Win, lchi, norm, count);
+        auto kern = nb <= 5 ? shear_windows_kernel<T, 5> : shear_windows_kernel<T, MAXB>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), sm1, s, theta, ld, B, G, m->pidx_d.as<int>(),
+                           m->pfix_d.as<double>(), m->nz_mean_d.as<double>(), m->agrid_d.as<double>(), Win, lchi,
+                           norm, count);
         NS_HIP(hipGetLastError());
     }
     TraceScope ts(m, s, "limber");
@@ -567,7 +574,9 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     const double zmax = 1.0 / m->a_min - 1.0;
     const double hz = zmax / (nz - 1);
     if (!m->shear_attr_set) {   // once per model, outside any stream capture
-        const void* fns[] = {(const void*)shear_windows_kernel<double>, (const void*)shear_windows_kernel<float>,
+        const void* fns[] = {(const void*)shear_windows_kernel<double, 5>, (const void*)shear_windows_kernel<float, 5>,
+                             (const void*)shear_windows_kernel<double, MAXB>,
+                             (const void*)shear_windows_kernel<float, MAXB>,
                              (const void*)limber_sum_kernel<double, false, 20>,
                              (const void*)limber_sum_kernel<double, false, 32>,
                              (const void*)limber_sum_kernel<double, true, 20>,
