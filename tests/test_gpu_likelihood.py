@@ -7,9 +7,10 @@ Tolerances (stated per precision form):
 * FP32 / BF16X3: |dlogL| <= 1e-2 on posterior-region walkers (the bar for the
   reduced-precision forms).
 * BF16 (operands rounded to 8 bits of mantissa, FP32 accumulation): misses
-  that bar by construction (|dlogL| ~ 0.1-1 on these workloads); the measured
-  value is printed and held under a regression limit about twice the value
-  measured when the kernels were written.
+  that bar on the CMB workloads (|dlogL| ~ 0.1-1) and on shear10; the
+  measured value is printed and held under a regression limit about twice the
+  value measured when the kernels were written.  The paper-shaped shear pair
+  meets the 1e-2 bar in BF16 and is held to it.
 """
 import sys
 
@@ -139,8 +140,8 @@ LOWP_LIMIT = {
     ("cmbtt_cv", "fp32"): 1e-2, ("cmbtt_cv", "bf16x3"): 1e-2, ("cmbtt_cv", "bf16"): 5.0,
     ("shear10", "fp32"): 1e-2, ("shear10", "bf16x3"): 1e-2, ("shear10", "bf16"): 0.1,
     ("shear64", "fp32"): 1e-2, ("shear64", "bf16x3"): 1e-2, ("shear64", "bf16"): 0.1,
-    ("shear_full", "fp32"): 1e-2, ("shear_full", "bf16x3"): 1e-2, ("shear_full", "bf16"): 0.5,
-    ("shear_interp", "fp32"): 1e-2, ("shear_interp", "bf16x3"): 1e-2, ("shear_interp", "bf16"): 0.5,
+    ("shear_full", "fp32"): 1e-2, ("shear_full", "bf16x3"): 1e-2, ("shear_full", "bf16"): 1e-2,
+    ("shear_interp", "fp32"): 1e-2, ("shear_interp", "bf16x3"): 1e-2, ("shear_interp", "bf16"): 1e-2,
 }
 
 
@@ -209,6 +210,46 @@ def test_fp64_shear_few_redshift_nodes(built, n_z):
     got = run_gpu(g, th)
     g.close()
     check_fp64(ref, got, f"shear n_z={n_z}")
+
+
+SHEAR_GRIDS = [
+    # n_a, n_bins, n_ell, z_interp, n_z: ragged node chunks, 1-10 bins, 1-32 multipoles
+    (300, 3, 25, "linear", 31),
+    (3, 1, 1, "linear", 2),
+    (700, 7, 32, "cubic", 12),
+    (257, 10, 4, "linear", 257),
+]
+
+
+@pytest.mark.parametrize("n_a,n_bins,n_ell,z_interp,n_z", SHEAR_GRIDS)
+def test_shear_grid_shapes(built, n_a, n_bins, n_ell, z_interp, n_z):
+    """Shear likelihoods on grids away from the workloads' (node counts that
+    leave a partial chunk, the smallest grid, 7 and 10 bins, up to 32
+    multipoles, both z modes) with a small emulator, against the oracle; the
+    data are the oracle's spectra at theta_fid with 5% noise and a diagonal
+    covariance."""
+    say(f"case shear grid n_a={n_a} bins={n_bins} n_ell={n_ell} {z_interp} n_z={n_z}")
+    from paper_2509_13307_amd import Model
+    from oracle import shear as oshear
+    m = W.shear_structure(n_z=n_z, n_bins=n_bins, n_extra=0, hidden=(64, 64), n_a=n_a, n_k=60, n_ell=n_ell,
+                          z_interp=z_interp)
+    C = oshear.spectra(m["theta_fid"][None], m)[0][0]
+    sig = 0.05 * np.abs(C) + 1e-3 * np.abs(C).max()
+    m["data"] = C + sig * np.random.default_rng(n_a).normal(size=C.size)
+    m["cov"] = np.diag(sig ** 2)
+    width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
+    th = W.posterior_draws(m["theta_fid"], 0.02 * width, 7, tag=9)
+    th[:, 2] = np.clip(th[:, 2], 0.65, None)
+    ref = oracle_loglike(th, m, chunk=8)
+    g = Model(m)
+    got = run_gpu(g, th)
+    check_fp64(ref, got, f"shear grid n_a={n_a}")
+    fin = np.isfinite(ref)
+    for prec in ("fp32", "bf16x3"):
+        d = np.abs(run_gpu(g, th, prec)[fin] - ref[fin])
+        say(f"  {prec}: max |dlogL| {d.max():.3e}")
+        assert d.max() <= 1e-2
+    g.close()
 
 
 def test_cv_model_validation(built):
