@@ -472,6 +472,10 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         for (int k = 0; k < n; ++k)
             for (int i = 0; i < n; ++i) LP[(size_t)k * np + i] = X[(size_t)i * n + k];
         upload(m->cov_lt_pad, LP.data(), LP.size());
+        std::fill(LP.begin(), LP.end(), 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) LP[(size_t)i * np + k] = X[(size_t)i * n + k];
+        upload(m->cov_l_pad, LP.data(), LP.size());
         upload(m->cov_w, w.data(), w.size());
         m->logl_const = c;
     }

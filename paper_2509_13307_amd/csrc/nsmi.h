@@ -150,6 +150,7 @@ struct ns_model {
     nsmi::DevBuf cov_linv;           // double [n x n] lower-triangular inverse Cholesky factor
     nsmi::DevBuf cov_linvT;          // its transpose (row k holds column k), for the adjoint
     nsmi::DevBuf cov_lt_pad;         // L^{-T} row-major [np x np], np = n rounded up to 64, zero padded
+    nsmi::DevBuf cov_l_pad;          // L^{-1} row-major [np x np], zero padded (chi^2 adjoint)
     nsmi::DevBuf cov_w;              // double [n]: L^{-1} d
 
     // GAUSS
@@ -245,6 +246,8 @@ void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const voi
               double* logl, int prec, const int* count, hipStream_t s);
 
 // Shear likelihood stages after the emulator table is in m->ws_out.
+void dense_chi2_adjoint(ns_model* m, const double* theta, int64_t ld, int64_t B, const double* Cv, double* R,
+                        double* part, double* logl, double* gC, hipStream_t s);
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B,
                               double* logl, int prec, const int* count, hipStream_t s);
 

@@ -384,11 +384,16 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
 // 64 columns, w = L^{-1} d; dense_chi2_finish_kernel adds the column tiles in
 // a fixed order (deterministic).
 constexpr int DG_M = 64, DG_N = 64, DG_KB = 16;
+// MODE 0: Y = C L^{-T} (Bm = L^{-T}, K range [0, 64 (ct + 1))), partial sums of
+//         (w - Y)^2; with R != nullptr also the residuals R = w - Y.
+// MODE 1: out = R L^{-1} (Bm = L^{-1} row-major, K range [64 ct, np)), the
+//         chi^2 adjoint g_C = L^{-T} L^{-1} (d - C), written to `out`.
+template <int MODE>
 __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __restrict__ C, int64_t B, int n, int np,
                                                               const double* __restrict__ Lt,
                                                               const double* __restrict__ wv,
                                                               double* __restrict__ part, int64_t pstride,
-                                                              const int* __restrict__ count) {
+                                                              double* __restrict__ R, const int* __restrict__ count) {
     __shared__ double As[2][DG_KB][DG_M];     // [k][walker]
     __shared__ double Bs[2][DG_KB][DG_N];     // [k][column]
     __shared__ double red[2][DG_M];
@@ -398,7 +403,8 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
     const int ct = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
-    const int kend = min(np, DG_N * (ct + 1));
+    const int kbeg = MODE == 0 ? 0 : DG_N * ct;
+    const int kend = MODE == 0 ? min(np, DG_N * (ct + 1)) : np;
     double ra[4], rb[4];
     auto gload = [&](int k0) {
 #pragma unroll
@@ -427,11 +433,11 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
-    gload(0);
+    gload(kbeg);
     sstore(0);
     __syncthreads();
     int bf = 0;
-    for (int k0 = 0; k0 < kend; k0 += DG_KB) {
+    for (int k0 = kbeg; k0 < kend; k0 += DG_KB) {
         const bool more = k0 + DG_KB < kend;
         if (more) gload(k0 + DG_KB);
 #pragma unroll
@@ -450,19 +456,35 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
         __syncthreads();
         bf ^= 1;
     }
-    // (w_n - Y_bn)^2 summed over this wave's columns: D row (lane >> 4) + 4 r, column lane & 15
+    // D row (lane >> 4) + 4 r, column lane & 15 of MFMA tile (i, j)
+    if (MODE == 1) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t b = b0 + wr + 16 * i + (lane >> 4) + 4 * r;
+                    const int col = DG_N * ct + wc + 16 * j + (lane & 15);
+                    if (b < B && col < n) R[b * n + col] = acc[i][j][r];
+                }
+        return;
+    }
+    // (w_n - Y_bn)^2 summed over this wave's columns
     double srow[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             double sacc = 0.0;
+            const int64_t b = b0 + wr + 16 * i + (lane >> 4) + 4 * r;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int col = DG_N * ct + wc + 16 * j + (lane & 15);
                 if (col < n) {
                     const double e = wv[col] - acc[i][j][r];
                     sacc = fma(e, e, sacc);
+                    if (R != nullptr && b < B) R[b * n + col] = e;
                 }
             }
             srow[i][r] = sacc;
@@ -615,14 +637,35 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     double* part = Cv + (size_t)B * n;
     {
         TraceScope ts(m, s, "dense_chi2");
-        hipLaunchKernelGGL(dense_chi2_gemm_kernel, dim3((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct), dim3(256),
-                           0, s, Cv, B, n, np, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part, B, count);
+        hipLaunchKernelGGL(dense_chi2_gemm_kernel<0>, dim3((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct),
+                           dim3(256), 0, s, Cv, B, n, np, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part, B,
+                           (double*)nullptr, count);
         NS_HIP(hipGetLastError());
         hipLaunchKernelGGL(dense_chi2_finish_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld,
                            B, m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), part, B,
                            n_ct, m->logl_const, logl, count);
         NS_HIP(hipGetLastError());
     }
+}
+
+// logL and its gradient with respect to the spectra C [B x n] of the dense
+// Gaussian: R = w - L^{-1} C (scratch [B x n]), logL from the partial sums
+// (part: [n_ct x B] scratch), g_C = L^{-T} R.
+void dense_chi2_adjoint(ns_model* m, const double* theta, int64_t ld, int64_t B, const double* Cv, double* R,
+                        double* part, double* logl, double* gC, hipStream_t s) {
+    const int n = m->n_data;
+    const int np = (n + DG_N - 1) / DG_N * DG_N, n_ct = np / DG_N;
+    const dim3 grid((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct);
+    hipLaunchKernelGGL(dense_chi2_gemm_kernel<0>, grid, dim3(256), 0, s, Cv, B, n, np, m->cov_lt_pad.as<double>(),
+                       m->cov_w.as<double>(), part, B, R, (const int*)nullptr);
+    NS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(dense_chi2_finish_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld, B,
+                       m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), part, B, n_ct,
+                       m->logl_const, logl, (const int*)nullptr);
+    NS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(dense_chi2_gemm_kernel<1>, grid, dim3(256), 0, s, R, B, n, np, m->cov_l_pad.as<double>(),
+                       (const double*)nullptr, (double*)nullptr, B, gC, (const int*)nullptr);
+    NS_HIP(hipGetLastError());
 }
 
 }  // namespace nsmi

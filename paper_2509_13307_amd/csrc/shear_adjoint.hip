@@ -2,112 +2,65 @@
 // gradients only.
 //
 // Reverse mode runs from logL back to the emulator table:
-//   dense chi^2:   g_C = L^{-T} L^{-1} (d - C)                                  (FP64)
+//   dense chi^2:   g_C = L^{-T} L^{-1} (d - C)  (two FP64-MFMA GEMMs, shear.hip)
 //   Limber (A2):   C_pb = f_p sum_j W_a(j) W_b(j) P_bj wq_j,  f_p = (1+m_a)(1+m_b)
 //                  -> g(P wq)_bj, g W_i(j), g wq_j, and g chi_j through k = (l+1/2)/chi_j
-//   P lookup:      P = 10^{CR(t; Yhat_j(c))}, Yhat = spline along z of the table
-//                  -> scatter into g Y, g M (second derivatives), then M = S(Y)
-//                  is transposed (zspline_adjoint_kernel) -> g Y -> emulator backward.
+//   P lookup:      P = 10^{CR(t; Yhat_j(c))}, Yhat = the table carried to z_j
+//                  (cubic spline or linear in z) -> scatter into g Y (and g M, the
+//                  spline second derivatives, whose map M = S(Y) is then
+//                  transposed by zspline_adjoint_kernel) -> emulator backward.
 // Forward mode covers the per-walker background and windows, which depend on
-// few parameters: tangents of chi, J, E, D, n_i, W_i and wq in the directions
-// (Om, h, w0, wa) and, per bin, (Dz_i, A_IA_i); the direct gradient is
+// few parameters: shear_tangent_kernel stores, per a-node, chi, wq, W_i and
+// their tangents in the directions (Om, h, w0, wa) and, per bin, (Dz_i,
+// A_IA,i); limber_adjoint_kernel contracts them into the direct gradient
 //   sum_j [ sum_i gW_i(j) dW_i(j) + g wq_j dwq_j + g chi_j dchi_j ].
-// Every Limber-adjoint term belongs to one a-node, so thread j owns node j.
+// Every Limber-adjoint term belongs to one a-node, so a thread owns a node
+// (the a-grid is taken in chunks of 256 nodes).
 #include "devutil.h"
 #include "nsmi.h"
 #include "shear_common.h"
 
 namespace nsmi {
 
-// ------------------------------------------------------- dense chi^2 adjoint
-// 16 walkers per block: y = L^{-1}d - L^{-1}C, g_C = L^{-T} y, logL.
-constexpr int DA_W = 16;
-__global__ __launch_bounds__(256) void dense_chi2_adjoint_kernel(
-    const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
-    const double* __restrict__ pa, const double* __restrict__ pb, const double* __restrict__ C, int n,
-    const double* __restrict__ Linv, const double* __restrict__ LinvT, const double* __restrict__ wv, double cst,
-    double* __restrict__ logl, double* __restrict__ gC) {
-    extern __shared__ double sm[];
-    double* Cs = sm;                   // [DA_W][n]
-    double* Ys = sm + DA_W * n;        // [DA_W][n]
-    __shared__ double red[DA_W][16];
-    const int64_t w0 = (int64_t)blockIdx.x * DA_W;
-    if (w0 >= B) return;
-    for (int e = threadIdx.x; e < DA_W * n; e += 256) {
-        const int64_t w = w0 + e / n;
-        Cs[e] = w < B ? C[w * n + e % n] : 0.0;
-    }
-    __syncthreads();
-    const int wk = threadIdx.x % DA_W, part = threadIdx.x / DA_W;
-    double s = 0.0;
-    for (int i = part; i < n; i += 256 / DA_W) {
-        const double* Li = Linv + (int64_t)i * n;
-        double acc = 0.0;
-        for (int k = 0; k <= i; ++k) acc = fma(Li[k], Cs[wk * n + k], acc);
-        const double y = wv[i] - acc;
-        Ys[wk * n + i] = y;
-        s = fma(y, y, s);
-    }
-    red[wk][part] = s;
-    __syncthreads();
-    const int64_t w = w0 + wk;
-    bool ok = false;
-    if (w < B) {
-        ok = true;
-        const double* th = theta + w * ld;
-        for (int i = 0; i < d; ++i)
-            if (pk[i] == NS_PRIOR_UNIFORM && (th[i] < pa[i] || th[i] > pb[i])) ok = false;
-    }
-    for (int k = part; k < n; k += 256 / DA_W) {
-        const double* Lk = LinvT + (int64_t)k * n;     // row k of L^{-T}: entries i >= k
-        double acc = 0.0;
-        for (int i = k; i < n; ++i) acc = fma(Lk[i], Ys[wk * n + i], acc);
-        if (w < B) gC[w * n + k] = ok ? acc : 0.0;
-    }
-    if (part == 0 && w < B) {
-        double chi2 = 0.0;
-        for (int p = 0; p < 256 / DA_W; ++p) chi2 += red[wk][p];
-        logl[w] = ok ? -0.5 * chi2 + cst : -INFINITY;
-    }
-}
+// ------------------------------------------------ background / window tangents
+// Forward-mode tangents per node, one workgroup (256 threads) per walker,
+// nodes in chunks of 256.  Directions 0..3 = (Om, h, w0, wa); per bin, Dz_i
+// and A_IA,i.  Output record per node, structure of arrays
+// tg[(w S + field) n_a + j], S = TG_FIXED + 7 n_bins:
+constexpr int TG_CHI = 0, TG_DCHI = 1, TG_WQ = 5, TG_DWQ = 6, TG_LND = 10, TG_DLND = 11, TG_FIXED = 15;
+// W_i at TG_FIXED + i, dW_i / d(Om, h, w0, wa)_q at TG_FIXED + nb + 4 i + q,
+// dW_i / dDz_i at TG_FIXED + 5 nb + i, dW_i / dA_IA,i at TG_FIXED + 6 nb + i.
+//   (a) forward pass: Simpson increments of chi, -ln D and their tangents,
+//       prefix sums carried from chunk to chunk;
+//   (b) n(z) normalisations N_i and dN_i / dDz_i;
+//   (c) reverse pass (last chunk first), bins in groups of 5: reverse
+//       cumulative trapezoids G0, G1 and their Dz tangents, then the
+//       (Om, h, w0, wa) tangents of G1; windows and their tangents.
+struct EB { double E, dE[4]; };
 
-// ---------------------------------------------------- Limber + window adjoint
-// One workgroup (256 threads, thread j = a-node j) per walker.
-// Outputs: gY, gM [B x n_z x n_k] (accumulated, must start at zero) and the
-// direct gradient gdir [B x d] (fully written).
-template <class T>
-__global__ __launch_bounds__(256) void limber_adjoint_kernel(
-    const double* __restrict__ theta, int64_t ld, int64_t B, int d, ShearGeom G,
-    const int* __restrict__ pidx, const double* __restrict__ pfix, const double* __restrict__ nz_mean,
-    const double* __restrict__ agrid, const int* __restrict__ zidx, const double* __restrict__ zcoef,
-    const double* __restrict__ ell, const T* __restrict__ Ytab, const T* __restrict__ Mtab,
-    const double* __restrict__ Cv, const double* __restrict__ gC, double* __restrict__ gY,
-    double* __restrict__ gM, double* __restrict__ gdir) {
-    __shared__ double scan[20 * 256];
-    __shared__ double Hs[64 * 55];          // G_pb f_p, pair-major
-    __shared__ double red[32][4];
-    __shared__ double node_chi[256];
+__global__ __launch_bounds__(256) void shear_tangent_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G, const int* __restrict__ pidx,
+    const double* __restrict__ pfix, const double* __restrict__ nz_mean, const double* __restrict__ agrid,
+    double* __restrict__ tg) {
+    __shared__ double buf[20 * 4];              // block_scan totals
+    __shared__ double red[2 * MAXB][4];
+    __shared__ double carry[10];                // forward prefix sums of the chunks before
+    __shared__ double nrm[2 * MAXB];            // N_i, dN_i
+    __shared__ double gcs[4][20];               // reverse sums of the chunks above, per (group, scan)
+    __shared__ double bcs[4][20];               // ... and after this chunk (thread 0)
+    __shared__ double gnx[4][20];               // integrands of the node above the chunk
+    __shared__ double xw[4][20];                // wave-boundary exchange
     const int64_t w = blockIdx.x;
     if (w >= B) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const int na = G.n_a, nb = G.n_bins, ne = G.n_ell, npair = G.n_pairs;
+    const int na = G.n_a, nb = G.n_bins, nch = (na + 255) / 256;
+    const int S = TG_FIXED + 7 * nb;
+    auto rec = [&](int f, int j) -> double& { return tg[((int64_t)w * S + f) * na + j]; };
     auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
     const double ob = phys(0), oc = phys(1), h = phys(2), w0 = phys(5), wa = phys(6);
     const double Om = (ob + oc) / (h * h);
     const double cH0 = C_KM_S / (100.0 * h), H0c = 1.0 / cH0;
-    const int nout = npair * ne;
-
-    // H_pb = g_C[pb] (1 + m_a)(1 + m_b)
-    for (int o = t; o < nout; o += 256) {
-        const int p = o / ne;
-        int a = 0, rem = p;
-        while (rem >= nb - a) { rem -= nb - a; ++a; }
-        const int bb = a + rem;
-        Hs[o] = gC[w * nout + o] * (1.0 + phys(9 + 2 * nb + a)) * (1.0 + phys(9 + 2 * nb + bb));
-    }
-
-    // ---- background with tangents in (Om, h, w0, wa)
-    struct EB { double E, dE[4]; };
+    const double s2 = G.nz_sigma * G.nz_sigma;
     auto Eval = [&](double a) {
         EB r;
         const double X = pow(a, -3.0 * (1.0 + w0 + wa)) * exp(-3.0 * wa * (1.0 - a));
@@ -120,161 +73,239 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
         return r;
     };
     // f = cH0/(a^2 E), g = (Om a^-3/E^2)^0.55 / a, with tangents
-    auto FG = [&](double a, double* f, double* df, double* g, double* dg) {
+    auto FG = [&](double a, double& f, double* df, double& g, double* dg) {
         const EB e = Eval(a);
-        *f = cH0 / (a * a * e.E);
-        *g = pow(Om / (a * a * a) / (e.E * e.E), GROWTH_INDEX) / a;
+        f = cH0 / (a * a * e.E);
+        g = pow(Om / (a * a * a) / (e.E * e.E), GROWTH_INDEX) / a;
         for (int q = 0; q < 4; ++q) {
-            df[q] = -*f * e.dE[q] / e.E;
-            dg[q] = -2.0 * GROWTH_INDEX * *g * e.dE[q] / e.E;
+            df[q] = -f * e.dE[q] / e.E;
+            dg[q] = -2.0 * GROWTH_INDEX * g * e.dE[q] / e.E;
         }
-        df[1] += -*f / h;
-        dg[0] += GROWTH_INDEX * *g / Om;
+        df[1] += -f / h;
+        dg[0] += GROWTH_INDEX * g / Om;
     };
-    const bool node = t < na;
-    const double a = node ? agrid[t] : 1.0;
-    double fa = 0.0, dfa[4] = {0, 0, 0, 0}, ga, dga[4];
-    FG(a, &fa, dfa, &ga, dga);
-    const EB ea = Eval(a);
-    double inc[10];
-    for (int q = 0; q < 10; ++q) inc[q] = 0.0;
-    if (node && t < na - 1) {
-        const double a1 = agrid[t + 1], am = 0.5 * (a + a1);
-        double fm, dfm[4], gm, dgm[4], f1, df1[4], g1, dg1[4];
-        FG(am, &fm, dfm, &gm, dgm);
-        FG(a1, &f1, df1, &g1, dg1);
-        inc[0] = G.da / 6.0 * (fa + 4.0 * fm + f1);
-        inc[1] = G.da / 6.0 * (ga + 4.0 * gm + g1);
-        for (int q = 0; q < 4; ++q) {
-            inc[2 + q] = G.da / 6.0 * (dfa[q] + 4.0 * dfm[q] + df1[q]);
-            inc[6 + q] = G.da / 6.0 * (dga[q] + 4.0 * dgm[q] + dg1[q]);
-        }
-    }
-    block_scan<10>(inc, scan, false);
-    // exclusive values at node t
-    for (int q = 0; q < 10; ++q) scan[q * 256 + t] = inc[q];
-    __syncthreads();
-    double bg[10];
-    for (int q = 0; q < 10; ++q) bg[q] = (node && t > 0) ? scan[q * 256 + t - 1] : 0.0;
-    __syncthreads();
-    const double chi = bg[0], D = exp(-bg[1]);
-    double dchi[4], dlnD[4];
-    for (int q = 0; q < 4; ++q) { dchi[q] = bg[2 + q]; dlnD[q] = -bg[6 + q]; }
-    node_chi[t] = chi;
-    const double E = ea.E;
-    const double qw = (t == 0 || t == na - 1) ? 0.5 * G.da : G.da;
 
-    // ---- n_i(z) with Dz tangents, normalisation
-    const double z = 1.0 / a - 1.0;
-    double n[MAXB], dn[MAXB];
-    for (int i = 0; i < nb; ++i) {
-        const double mu = nz_mean[i] + phys(9 + nb + i);
-        const double dz = z - mu;
-        const double raw = (node && t > 0) ? exp(-dz * dz / (2.0 * G.nz_sigma * G.nz_sigma)) : 0.0;
-        n[i] = raw;
-        dn[i] = raw * dz / (G.nz_sigma * G.nz_sigma);
-    }
-    for (int i = 0; i < nb; ++i) {
-        double v0 = wave_sum(node ? qw * n[i] / (a * a) : 0.0);
-        double v1 = wave_sum(node ? qw * dn[i] / (a * a) : 0.0);
-        if (lane == 0) { red[2 * i][wid] = v0; red[2 * i + 1][wid] = v1; }
+    // (a) chi, ln D and tangents at every node
+    if (t < 10) carry[t] = 0.0;
+    if (t == 0) {
+        rec(TG_CHI, 0) = rec(TG_LND, 0) = 0.0;
+        for (int q = 0; q < 4; ++q) rec(TG_DCHI + q, 0) = rec(TG_DLND + q, 0) = 0.0;
     }
     __syncthreads();
-    for (int i = 0; i < nb; ++i) {
-        const double N = red[2 * i][0] + red[2 * i][1] + red[2 * i][2] + red[2 * i][3];
-        const double dN = red[2 * i + 1][0] + red[2 * i + 1][1] + red[2 * i + 1][2] + red[2 * i + 1][3];
-        n[i] /= N;
-        dn[i] = dn[i] / N - n[i] * dN / N;
-    }
-    __syncthreads();
-
-    // ---- reverse cumulative trapezoids G0, G1 and their tangents, 5 bins per pass
-    // per bin: G0, G1, dG0/dDz, dG1/dDz, dG1/d(Om, h, w0, wa)
-    double G0[MAXB], G1[MAXB], G0z[MAXB], G1z[MAXB], G1c[MAXB][4];
-    const double a2 = a * a;
-    for (int b0 = 0; b0 < nb; b0 += 5) {
-        const int cnt = nb - b0 < 5 ? nb - b0 : 5;
-        // integrands at this node: g0 = n/a^2, g1 = n/(a^2 chi), tangents
-        double v[20];
-        for (int q = 0; q < 20; ++q) v[q] = 0.0;
-        for (int c = 0; c < cnt; ++c) {
-            const int i = b0 + c;
-            v[c] = node ? n[i] / a2 : 0.0;
-            v[5 + c] = (node && t > 0) ? n[i] / (a2 * chi) : 0.0;
-            v[10 + c] = node ? dn[i] / a2 : 0.0;
-            v[15 + c] = (node && t > 0) ? dn[i] / (a2 * chi) : 0.0;
+    for (int c = 0; c < nch; ++c) {
+        const int j = c * 256 + t;
+        double inc[10];
+        for (int q = 0; q < 10; ++q) inc[q] = 0.0;
+        if (j < na - 1) {
+            const double a = agrid[j], a1 = agrid[j + 1], am = 0.5 * (a + a1);
+            double fa, dfa[4], ga, dga[4], fm, dfm[4], gm, dgm[4], f1, df1[4], g1, dg1[4];
+            FG(a, fa, dfa, ga, dga);
+            FG(am, fm, dfm, gm, dgm);
+            FG(a1, f1, df1, g1, dg1);
+            inc[0] = G.da / 6.0 * (fa + 4.0 * fm + f1);
+            inc[1] = G.da / 6.0 * (ga + 4.0 * gm + g1);
+            for (int q = 0; q < 4; ++q) {
+                inc[2 + q] = G.da / 6.0 * (dfa[q] + 4.0 * dfm[q] + df1[q]);
+                inc[6 + q] = G.da / 6.0 * (dga[q] + 4.0 * dgm[q] + dg1[q]);
+            }
         }
-        // segment [t, t+1] from the neighbour's integrand
-        for (int q = 0; q < 20; ++q) scan[q * 256 + t] = v[q];
-        __syncthreads();
-        double sg[20];
-        const bool has = node && t < na - 1;
-        for (int q = 0; q < 20; ++q) sg[q] = has ? 0.5 * G.da * (v[q] + scan[q * 256 + t + 1]) : 0.0;
-        __syncthreads();
-        block_scan<20>(sg, scan, true);
-        for (int c = 0; c < cnt; ++c) {
-            G0[b0 + c] = sg[c];
-            G1[b0 + c] = sg[5 + c];
-            G0z[b0 + c] = sg[10 + c];
-            G1z[b0 + c] = sg[15 + c];
+        block_scan<10>(inc, buf, false);
+        if (j < na - 1) {                        // sums over intervals 0..j: values at node j + 1
+            rec(TG_CHI, j + 1) = carry[0] + inc[0];
+            rec(TG_LND, j + 1) = -(carry[1] + inc[1]);
+            for (int q = 0; q < 4; ++q) {
+                rec(TG_DCHI + q, j + 1) = carry[2 + q] + inc[2 + q];
+                rec(TG_DLND + q, j + 1) = -(carry[6 + q] + inc[6 + q]);
+            }
         }
-        // cosmological tangents of G1: integrand -n chi_dot / (a^2 chi^2)
-        for (int q = 0; q < 20; ++q) v[q] = 0.0;
-        for (int c = 0; c < cnt; ++c)
-            for (int q = 0; q < 4; ++q)
-                v[4 * c + q] = (node && t > 0) ? -n[b0 + c] * dchi[q] / (a2 * chi * chi) : 0.0;
-        for (int q = 0; q < 20; ++q) scan[q * 256 + t] = v[q];
         __syncthreads();
-        for (int q = 0; q < 20; ++q) sg[q] = has ? 0.5 * G.da * (v[q] + scan[q * 256 + t + 1]) : 0.0;
-        __syncthreads();
-        block_scan<20>(sg, scan, true);
-        for (int c = 0; c < cnt; ++c)
-            for (int q = 0; q < 4; ++q) G1c[b0 + c][q] = sg[4 * c + q];
+        if (t == 255)
+            for (int q = 0; q < 10; ++q) carry[q] += inc[q];
     }
 
-    // ---- windows and tangents: directions 0..3 = (Om, h, w0, wa), 4 = Dz_i, 5 = A_i
-    double W[MAXB], dW[MAXB][6];
+    // (b) normalisations of n_i(z) and their Dz tangents
+    {
+        double sn[MAXB], sd[MAXB];
+        for (int i = 0; i < MAXB; ++i) sn[i] = sd[i] = 0.0;
+        for (int c = 0; c < nch; ++c) {
+            const int j = c * 256 + t;
+            if (j <= 0 || j >= na) continue;
+            const double a = agrid[j], z = 1.0 / a - 1.0;
+            const double qw = j == na - 1 ? 0.5 * G.da : G.da;
+            for (int i = 0; i < nb; ++i) {
+                const double dz = z - (nz_mean[i] + phys(9 + nb + i));
+                const double raw = exp(-dz * dz / (2.0 * s2));
+                sn[i] += qw * raw / (a * a);
+                sd[i] += qw * (raw * dz / s2) / (a * a);
+            }
+        }
+        for (int i = 0; i < nb; ++i) {
+            const double v0 = wave_sum(sn[i]), v1 = wave_sum(sd[i]);
+            if (lane == 0) { red[2 * i][wid] = v0; red[2 * i + 1][wid] = v1; }
+        }
+        if (t < 80) { gcs[t / 20][t % 20] = 0.0; gnx[t / 20][t % 20] = 0.0; }
+        __syncthreads();
+        if (t < 2 * nb) nrm[t] = red[t][0] + red[t][1] + red[t][2] + red[t][3];
+        __syncthreads();
+    }
+
+    // (c) reverse pass: G sums, windows and tangents
     const double pref = 1.5 * Om * H0c * H0c;
     const double dpref[4] = {pref / Om, 2.0 * pref / h, 0.0, 0.0};
-    const double dlnE[4] = {ea.dE[0] / E, 0.0, ea.dE[2] / E, ea.dE[3] / E};
-    for (int i = 0; i < nb; ++i) {
-        const double Q = G0[i] - chi * G1[i];
-        const double Wg = pref * chi / a * Q;
-        const double A = phys(9 + i);
-        const double base = C1_RHOCR * Om * H0c * E / D;     // W^I = -A n base
-        const double WI = -A * n[i] * base;
-        W[i] = node ? Wg + WI : 0.0;
+    for (int c = nch - 1; c >= 0; --c) {
+        const int j = c * 256 + t;
+        const bool node = j < na, live = node && j > 0, has = node && j < na - 1;
+        const double a = node ? agrid[j] : 1.0, a2 = a * a, z = 1.0 / a - 1.0;
+        const double chi = node ? rec(TG_CHI, j) : 0.0;
+        double dchi[4], dlnD[4];
         for (int q = 0; q < 4; ++q) {
-            const double dQ = -dchi[q] * G1[i] - chi * G1c[i][q];
-            const double dWg = dpref[q] * chi / a * Q + pref * dchi[q] / a * Q + pref * chi / a * dQ;
-            double dlnbase = dlnE[q] - dlnD[q];
-            if (q == 0) dlnbase += 1.0 / Om;
-            if (q == 1) dlnbase += 1.0 / h;
-            dW[i][q] = node ? dWg + WI * dlnbase : 0.0;
+            dchi[q] = node ? rec(TG_DCHI + q, j) : 0.0;
+            dlnD[q] = node ? rec(TG_DLND + q, j) : 0.0;
         }
-        const double dQz = G0z[i] - chi * G1z[i];
-        dW[i][4] = node ? pref * chi / a * dQz - A * dn[i] * base : 0.0;
-        dW[i][5] = node ? -n[i] * base : 0.0;
+        const double D = exp(node ? rec(TG_LND, j) : 0.0);
+        const EB ea = Eval(a);
+        const double E = ea.E;
+        const double dlnE[4] = {ea.dE[0] / E, 0.0, ea.dE[2] / E, ea.dE[3] / E};
+        double fa, dfa[4], ga, dga[4];
+        FG(a, fa, dfa, ga, dga);
+        const double qw = (j == 0 || j == na - 1) ? 0.5 * G.da : G.da;
+        if (node) {
+            const double wq = live ? qw * fa / (chi * chi) : 0.0;
+            rec(TG_WQ, j) = wq;
+            for (int q = 0; q < 4; ++q) rec(TG_DWQ + q, j) = live ? wq * (dfa[q] / fa - 2.0 * dchi[q] / chi) : 0.0;
+        }
+        for (int grp = 0; grp * 5 < nb; ++grp) {
+            const int b0 = 5 * grp, cnt = min(5, nb - b0);
+            double n[5], dn[5];
+            for (int cc = 0; cc < 5; ++cc) {
+                n[cc] = dn[cc] = 0.0;
+                if (cc >= cnt || !live) continue;
+                const int i = b0 + cc;
+                const double dz = z - (nz_mean[i] + phys(9 + nb + i));
+                const double raw = exp(-dz * dz / (2.0 * s2));
+                const double N = nrm[2 * i], dN = nrm[2 * i + 1];
+                n[cc] = raw / N;
+                dn[cc] = (raw * dz / s2) / N - n[cc] * dN / N;
+            }
+            double Gs[20], Gc[20];
+            for (int sc = 0; sc < 2; ++sc) {
+                const int slot = 2 * grp + sc;
+                double v[20];
+                for (int k = 0; k < 20; ++k) v[k] = 0.0;
+                for (int cc = 0; cc < cnt; ++cc) {
+                    if (sc == 0) {
+                        v[cc] = node ? n[cc] / a2 : 0.0;
+                        v[5 + cc] = live ? n[cc] / (a2 * chi) : 0.0;
+                        v[10 + cc] = node ? dn[cc] / a2 : 0.0;
+                        v[15 + cc] = live ? dn[cc] / (a2 * chi) : 0.0;
+                    } else {
+                        for (int q = 0; q < 4; ++q) v[4 * cc + q] = live ? -n[cc] * dchi[q] / (a2 * chi * chi) : 0.0;
+                    }
+                }
+                if (lane == 0)
+                    for (int k = 0; k < 20; ++k) xw[wid][k] = v[k];
+                __syncthreads();
+                double sg[20];
+                for (int k = 0; k < 20; ++k) {
+                    double nv = __shfl_down(v[k], 1, 64);
+                    if (lane == 63) nv = wid < 3 ? xw[wid + 1][k] : gnx[slot][k];
+                    sg[k] = has ? 0.5 * G.da * (v[k] + nv) : 0.0;
+                }
+                __syncthreads();
+                if (t == 0)
+                    for (int k = 0; k < 20; ++k) gnx[slot][k] = v[k];
+                block_scan<20>(sg, buf, true);
+                for (int k = 0; k < 20; ++k) sg[k] += gcs[slot][k];
+                if (t == 0)
+                    for (int k = 0; k < 20; ++k) bcs[slot][k] = sg[k];
+                for (int k = 0; k < 20; ++k) {
+                    if (sc == 0) Gs[k] = sg[k];
+                    else Gc[k] = sg[k];
+                }
+            }
+            if (node) {
+                for (int cc = 0; cc < cnt; ++cc) {
+                    const int i = b0 + cc;
+                    const double G0 = Gs[cc], G1 = Gs[5 + cc], G0z = Gs[10 + cc], G1z = Gs[15 + cc];
+                    const double Q = G0 - chi * G1;
+                    const double Wg = pref * chi / a * Q;
+                    const double A = phys(9 + i);
+                    const double base = C1_RHOCR * Om * H0c * E / D;     // W^I = -A n base
+                    const double WI = -A * n[cc] * base;
+                    rec(TG_FIXED + i, j) = Wg + WI;
+                    for (int q = 0; q < 4; ++q) {
+                        const double dQ = -dchi[q] * G1 - chi * Gc[4 * cc + q];
+                        const double dWg = dpref[q] * chi / a * Q + pref * dchi[q] / a * Q + pref * chi / a * dQ;
+                        double dlnbase = dlnE[q] - dlnD[q];
+                        if (q == 0) dlnbase += 1.0 / Om;
+                        if (q == 1) dlnbase += 1.0 / h;
+                        rec(TG_FIXED + nb + 4 * i + q, j) = dWg + WI * dlnbase;
+                    }
+                    rec(TG_FIXED + 5 * nb + i, j) = pref * chi / a * (G0z - chi * G1z) - A * dn[cc] * base;
+                    rec(TG_FIXED + 6 * nb + i, j) = -n[cc] * base;
+                }
+            }
+        }
+        __syncthreads();
+        if (t < 80) gcs[t / 20][t % 20] = bcs[t / 20][t % 20];
+        __syncthreads();
     }
-    // wq = q J / chi^2 and tangents
-    double wq = 0.0, dwq[4] = {0, 0, 0, 0};
-    if (node && t > 0) {
-        wq = qw * fa / (chi * chi);
-        for (int q = 0; q < 4; ++q) dwq[q] = wq * (dfa[q] / fa - 2.0 * dchi[q] / chi);
+}
+
+// --------------------------------------------------------- Limber adjoint
+// One workgroup (256 threads) per walker, thread = a-node j (chunks of 256):
+// g(P wq), g W_i(j), g wq_j and g chi_j (through k = (l+1/2)/chi_j) from the
+// Limber sums, scattered into g Y (and g M for the cubic z-spline; atomics),
+// then contracted with the tangents of shear_tangent_kernel into the direct
+// gradient gdir [B x d] (fully written).  gY, gM accumulate: start at zero.
+template <class T, bool LINZ>
+__global__ __launch_bounds__(256) void limber_adjoint_kernel(
+    const double* __restrict__ theta, int64_t ld, int64_t B, int d, ShearGeom G,
+    const int* __restrict__ pidx, const double* __restrict__ pfix, const int* __restrict__ zidx,
+    const double* __restrict__ zcoef, const double* __restrict__ ell, const T* __restrict__ Ytab,
+    const T* __restrict__ Mtab, const double* __restrict__ Cv, const double* __restrict__ gC,
+    const double* __restrict__ tg, double* __restrict__ gY, double* __restrict__ gM, double* __restrict__ gdir) {
+    __shared__ double Hs[55 * 32];          // G_pb f_p, pair-major
+    __shared__ double red[4 + 2 * MAXB][4];
+    const int64_t w = blockIdx.x;
+    if (w >= B) return;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int na = G.n_a, nb = G.n_bins, ne = G.n_ell, npair = G.n_pairs, nch = (na + 255) / 256;
+    const int S = TG_FIXED + 7 * nb;
+    auto rec = [&](int f, int j) { return tg[((int64_t)w * S + f) * na + j]; };
+    auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
+    const double h = phys(2);
+    const double Om = (phys(0) + phys(1)) / (h * h);
+    const int nout = npair * ne;
+
+    // H_pb = g_C[pb] (1 + m_a)(1 + m_b)
+    for (int o = t; o < nout; o += 256) {
+        const int p = o / ne;
+        int a = 0, rem = p;
+        while (rem >= nb - a) { rem -= nb - a; ++a; }
+        const int bb = a + rem;
+        Hs[o] = gC[w * nout + o] * (1.0 + phys(9 + 2 * nb + a)) * (1.0 + phys(9 + 2 * nb + bb));
     }
     __syncthreads();
-
-    // ---- Limber adjoint at node t, all multipoles
-    double gW[MAXB];
-    for (int i = 0; i < nb; ++i) gW[i] = 0.0;
-    double gwq = 0.0, gchi = 0.0;
-    if (node && t > 0) {
-        const int nn = zidx[t];
-        const double c0 = zcoef[4 * t], c1 = zcoef[4 * t + 1], c2 = zcoef[4 * t + 2], c3 = zcoef[4 * t + 3];
-        const T* Yw = Ytab + w * (int64_t)G.n_z * G.n_k;
-        const T* Mw = Mtab + w * (int64_t)G.n_z * G.n_k;
-        double* gYw = gY + w * (int64_t)G.n_z * G.n_k;
-        double* gMw = gM + w * (int64_t)G.n_z * G.n_k;
+    double acc[4 + 2 * MAXB];
+    for (int q = 0; q < 4 + 2 * MAXB; ++q) acc[q] = 0.0;
+    const T* Yw = Ytab + w * (int64_t)G.n_z * G.n_k;
+    const T* Mw = LINZ ? Yw : Mtab + w * (int64_t)G.n_z * G.n_k;
+    double* gYw = gY + w * (int64_t)G.n_z * G.n_k;
+    double* gMw = LINZ ? gYw : gM + w * (int64_t)G.n_z * G.n_k;
+    for (int c = 0; c < nch; ++c) {
+        const int j = c * 256 + t;
+        if (j <= 0 || j >= na) continue;
+        double W[MAXB], gW[MAXB];
+        for (int i = 0; i < nb; ++i) {
+            W[i] = rec(TG_FIXED + i, j);
+            gW[i] = 0.0;
+        }
+        const double chi = rec(TG_CHI, j), wq = rec(TG_WQ, j);
+        double gwq = 0.0, gchi = 0.0;
+        const int nn = zidx[j];
+        const double c0 = zcoef[4 * j], c1 = zcoef[4 * j + 1];
+        const double c2 = LINZ ? 0.0 : zcoef[4 * j + 2], c3 = LINZ ? 0.0 : zcoef[4 * j + 3];
         for (int b = 0; b < ne; ++b) {
             const double k = (ell[b] + 0.5) / chi;
             if (!(k >= G.k_min && k <= G.k_max)) continue;
@@ -284,6 +315,7 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
             const double tt = s - i0;
             auto Yz = [&](int col) {
                 const int64_t o0 = (int64_t)nn * G.n_k + col, o1 = o0 + G.n_k;
+                if (LINZ) return c0 * (double)Yw[o0] + c1 * (double)Yw[o1];
                 return c0 * (double)Yw[o0] + c1 * (double)Yw[o1] + c2 * (double)Mw[o0] + c3 * (double)Mw[o1];
             };
             const bool lo_ghost = i0 == 0, hi_ghost = i0 + 2 >= G.n_k;
@@ -298,7 +330,6 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
                                   (3 * t2 - 2 * tt) * m1;
             const double P = exp(lp * LN10);
             const double Pw = P * wq;
-            // gPw = sum_p H_pb W_a W_b; gW accumulation
             double gPw = 0.0;
             int p = 0;
             for (int ia = 0; ia < nb; ++ia)
@@ -325,35 +356,35 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
                 const int64_t o0 = (int64_t)nn * G.n_k + col, o1 = o0 + G.n_k;
                 atomicAdd(&gYw[o0], c0 * gy);
                 atomicAdd(&gYw[o1], c1 * gy);
-                atomicAdd(&gMw[o0], c2 * gy);
-                atomicAdd(&gMw[o1], c3 * gy);
+                if (!LINZ) {
+                    atomicAdd(&gMw[o0], c2 * gy);
+                    atomicAdd(&gMw[o1], c3 * gy);
+                }
             };
             if (!lo_ghost) scatter(i0 - 1, wm);
             scatter(i0, w0c);
             scatter(i0 + 1, w1c);
             if (!hi_ghost) scatter(i0 + 2, w2);
         }
+        // contract with the tangents of this node
+        for (int q = 0; q < 4; ++q) {
+            double v = gwq * rec(TG_DWQ + q, j) + gchi * rec(TG_DCHI + q, j);
+            for (int i = 0; i < nb; ++i) v += gW[i] * rec(TG_FIXED + nb + 4 * i + q, j);
+            acc[q] += v;
+        }
+        for (int i = 0; i < nb; ++i) {
+            acc[4 + i] += gW[i] * rec(TG_FIXED + 5 * nb + i, j);
+            acc[4 + nb + i] += gW[i] * rec(TG_FIXED + 6 * nb + i, j);
+        }
     }
 
     // ---- direct gradient: reduce over nodes
-    double acc[4 + 2 * MAXB];
-    for (int q = 0; q < 4; ++q) {
-        double v = gwq * dwq[q] + gchi * dchi[q];
-        for (int i = 0; i < nb; ++i) v += gW[i] * dW[i][q];
-        acc[q] = v;
-    }
-    for (int i = 0; i < nb; ++i) {
-        acc[4 + i] = gW[i] * dW[i][4];
-        acc[4 + nb + i] = gW[i] * dW[i][5];
-    }
     const int nacc = 4 + 2 * nb;
-    __syncthreads();
     for (int q = 0; q < nacc; ++q) {
         const double v = wave_sum(acc[q]);
         if (lane == 0) red[q][wid] = v;
     }
-    __syncthreads();
-    if (t < d) gdir[w * d + t] = 0.0;
+    for (int k = t; k < d; k += 256) gdir[w * d + k] = 0.0;
     __syncthreads();
     if (t == 0) {
         double tot[4 + 2 * MAXB];
@@ -393,7 +424,7 @@ template <class T>
 __global__ __launch_bounds__(256) void zspline_adjoint_kernel(double* __restrict__ gY, double* __restrict__ gM,
                                                               int64_t B, int nz, int nk, double h,
                                                               const double* __restrict__ sigma_out, int n_pad,
-                                                              T* __restrict__ delta) {
+                                                              T* __restrict__ delta, int linear) {
     __shared__ double cps[256];
     if (threadIdx.x == 0) {
         double c = 0.0;
@@ -412,6 +443,11 @@ __global__ __launch_bounds__(256) void zspline_adjoint_kernel(double* __restrict
         return;
     }
     double* gy = gY + w * nz * nk + c;
+    if (linear) {                               // no spline: delta = g Y sigma_out
+        const double sg = sigma_out[c];
+        for (int n = 0; n < nz; ++n) delta[(w * nz + n) * n_pad + c] = (T)(gy[(int64_t)n * nk] * sg);
+        return;
+    }
     double* gm = gM + w * nz * nk + c;
     auto Y = [&](int n) -> double& { return gy[(int64_t)n * nk]; };
     auto Mg = [&](int n) -> double& { return gm[(int64_t)n * nk]; };
@@ -462,11 +498,9 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
 // ------------------------------------------------------------------ driver
 void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, double* grad, int prec,
                 hipStream_t s) {
-    NS_CHECK(!m->z_linear && m->n_a <= 256, NS_E_UNSUPPORTED,
-             "the shear gradient covers the cubic z-spline on at most 256 nodes");
-    const bool f64 = prec == NS_FP64;
+    const bool f64 = prec == NS_FP64, lin = m->z_linear;
     const size_t elem = f64 ? 8 : 4;
-    const int nk = m->n_k, nz = m->n_z, n = m->n_data, d = m->d;
+    const int nk = m->n_k, nz = m->n_z, n = m->n_data, d = m->d, na = m->n_a, nb = m->n_bins;
     const int64_t rows = B * nz;
     // forward: emulator table (with pre-activation saves), spline, spectra
     m->ws_out.ensure((size_t)B * nz * nk * elem);
@@ -474,42 +508,49 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
     void* out0 = m->ws_out.p;
     emulator_forward(m, &id0, 1, theta, ld, B, &out0, nk, &no_log, prec, nullptr, s, true);
     shear_loglike_from_table(m, theta, ld, B, logl, prec, nullptr, s);
-    const size_t mbytes = (size_t)B * nz * nk * elem;
+    const size_t mbytes = lin ? 0 : (size_t)B * nz * nk * elem;
     const void* Mtab = m->ws_aux.p;
     const double* Cv = reinterpret_cast<const double*>(m->ws_aux.as<char>() + mbytes);
-    // adjoint scratch: gC [B n], gY, gM [B nz nk], gdir [B d]
-    const size_t ntab = (size_t)B * nz * nk;
-    m->ws_grad.ensure(((size_t)B * n + 2 * ntab + (size_t)B * d) * sizeof(double));
+    // adjoint scratch: gC, R [B n], chi^2 partial sums [n_ct B], gY (and gM) [B nz nk],
+    // tangents [B S n_a], gdir [B d]
+    const size_t ntab = (size_t)B * nz * nk, n_ct = (n + 63) / 64;
+    const size_t S = TG_FIXED + 7 * (size_t)nb;
+    m->ws_grad.ensure(((size_t)B * (2 * n + n_ct) + (lin ? 1 : 2) * ntab + (size_t)B * S * na + (size_t)B * d) *
+                      sizeof(double));
     double* gC = m->ws_grad.as<double>();
-    double* gY = gC + (size_t)B * n;
-    double* gM = gY + ntab;
-    double* gdir = gM + ntab;
+    double* R = gC + (size_t)B * n;
+    double* part = R + (size_t)B * n;
+    double* gY = part + (size_t)B * n_ct;
+    double* gM = lin ? gY : gY + ntab;          // spline second derivatives: cubic z only
+    double* tg = gY + (lin ? 1 : 2) * ntab;
+    double* gdir = tg + (size_t)B * S * na;
     {
         TraceScope ts(m, s, "adj_dense_chi2");
-        const size_t sm = 2 * (size_t)DA_W * n * sizeof(double);
-        NS_CHECK(sm <= 160 * 1024, NS_E_UNSUPPORTED, "data vector too long for the chi^2 adjoint");
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_adjoint_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)sm));
-        hipLaunchKernelGGL(dense_chi2_adjoint_kernel, dim3((unsigned)((B + DA_W - 1) / DA_W)), dim3(256), sm, s, theta,
-                           ld, B, d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), Cv, n,
-                           m->cov_linv.as<double>(), m->cov_linvT.as<double>(), m->cov_w.as<double>(), m->logl_const,
-                           logl, gC);
+        dense_chi2_adjoint(m, theta, ld, B, Cv, R, part, logl, gC, s);
+    }
+    const ShearGeom G = shear_geom(m);
+    {
+        TraceScope ts(m, s, "adj_tangents");
+        hipLaunchKernelGGL(shear_tangent_kernel, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, G,
+                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
+                           m->agrid_d.as<double>(), tg);
         NS_HIP(hipGetLastError());
     }
     {
         TraceScope ts(m, s, "adj_limber");
-        hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, gY, (int64_t)(2 * ntab));
-        const ShearGeom G = shear_geom(m);
-        if (f64)
-            hipLaunchKernelGGL(limber_adjoint_kernel<double>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, d, G,
-                               m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
-                               m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                               m->ell_d.as<double>(), m->ws_out.as<double>(), (const double*)Mtab, Cv, gC, gY, gM, gdir);
-        else
-            hipLaunchKernelGGL(limber_adjoint_kernel<float>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, d, G,
-                               m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->nz_mean_d.as<double>(),
-                               m->agrid_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                               m->ell_d.as<double>(), m->ws_out.as<float>(), (const float*)Mtab, Cv, gC, gY, gM, gdir);
+        hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, gY, (int64_t)((lin ? 1 : 2) * ntab));
+        auto launch = [&](auto kern, const auto* Y) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, d, G, m->pidx_d.as<int>(),
+                               m->pfix_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
+                               m->ell_d.as<double>(), Y, (decltype(Y))Mtab, Cv, gC, tg, gY, gM, gdir);
+        };
+        if (f64) {
+            if (lin) launch(limber_adjoint_kernel<double, true>, m->ws_out.as<double>());
+            else launch(limber_adjoint_kernel<double, false>, m->ws_out.as<double>());
+        } else {
+            if (lin) launch(limber_adjoint_kernel<float, true>, m->ws_out.as<float>());
+            else launch(limber_adjoint_kernel<float, false>, m->ws_out.as<float>());
+        }
         NS_HIP(hipGetLastError());
     }
     // spline adjoint -> delta for the emulator's raw outputs
@@ -526,10 +567,10 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
         const dim3 gz((unsigned)((B * n_pad + 255) / 256));
         if (f64)
             hipLaunchKernelGGL(zspline_adjoint_kernel<double>, gz, dim3(256), 0, s, gY, gM, B, nz, nk, hz,
-                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<double>());
+                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<double>(), (int)lin);
         else
             hipLaunchKernelGGL(zspline_adjoint_kernel<float>, gz, dim3(256), 0, s, gY, gM, B, nz, nk, hz,
-                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<float>());
+                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<float>(), (int)lin);
         NS_HIP(hipGetLastError());
     }
     emulator_backward(m, &id0, 1, B, f64 ? NS_FP64 : NS_FP32, s);

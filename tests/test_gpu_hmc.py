@@ -88,6 +88,23 @@ def test_hmc_replays_oracle_shear10():
     replay(m, C=2, n_iter=2, L=3, step=0.2, minv=minv, seed=7, tag=3)
 
 
+def test_hmc_replays_oracle_linear_z_shear():
+    """Shear with linear z-interpolation and two node chunks (small emulator,
+    diagonal covariance): the chunked adjoint drives the chains."""
+    say("case hmc shear linear z")
+    from oracle import shear as oshear
+    m = W.shear_structure(n_z=31, n_bins=3, n_extra=0, hidden=(64, 64), n_a=300, n_k=60, n_ell=25,
+                          z_interp="linear")
+    C = oshear.spectra(m["theta_fid"][None], m)[0][0]
+    sig = 0.05 * np.abs(C) + 1e-3 * np.abs(C).max()
+    m["data"] = C + sig * np.random.default_rng(300).normal(size=C.size)
+    m["cov"] = np.diag(sig ** 2)
+    width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
+    m["fisher_sigma"] = 0.005 * width
+    res, _ = replay(m, C=2, n_iter=3, L=3, step=0.05, minv=(0.005 * width) ** 2, seed=8, tag=7)
+    assert res["n_accept"] > 0
+
+
 def test_hmc_reflects_at_the_walls():
     """A Gaussian centred 0.05 from the theta_0 = 0 wall: drifts cross the wall
     and are reflected; the oracle replays positions, accepts and rejections."""

@@ -311,9 +311,3 @@ def test_full_and_interpolated_shear_share_their_data(built):
     assert np.mean(Ci < Cf) > 0.95
 
 
-def test_shear_gradient_refuses_linear_z(built):
-    say("case shear_interp gradient refused")
-    from paper_2509_13307_amd._capi import NSError
-    m, g = gpu_model("shear_interp")
-    with pytest.raises(NSError):
-        g.loglike_grad(torch.tensor(m["theta_fid"][None], device=DEV), "fp64")
