@@ -397,6 +397,31 @@ def shear_paper(Model, W, torch, ns_precs, n_live):
                                           min=float(dl.min()), max=float(dl.max()),
                                           logL_full_std=float(lf.std()))
     print(f"# dlogL: {json.dumps(out['dlogL_interp_minus_full'])}", file=sys.stderr, flush=True)
+    # HMC on the same pair (the paper's gradient-sampler comparison): 60 chains,
+    # FP64 adjoint gradients, 16 leapfrog steps, step adapted over 15 warmup
+    # trajectories, then 20 timed trajectories
+    hmc = {}
+    for name in ("shear_full", "shear_interp"):
+        m, g = models[name]
+        sig = np.minimum(m["fisher_sigma"], 0.1 * width)
+        th0 = W.posterior_draws(m["theta_fid"], 0.5 * sig, 60, tag=16)
+        th0 = np.clip(th0, m["prior_a"] + 1e-6 * width,
+                      np.where(m["prior_kind"] == 0, m["prior_b"] - 1e-6 * width, np.inf))
+        cur = torch.tensor(th0, device=dev)
+        minv = torch.tensor(sig ** 2)
+        step, L, warm = 0.1, 16, 0.0
+        for r in range(3):
+            _, _, res, cur = g.hmc(cur, minv, 5, L, step, seed=200 + r, keep_samples=False)
+            warm += res["wall_s"]
+            step *= float(np.clip(np.exp(2.0 * (res["n_accept"] / 300.0 - 0.7)), 0.5, 2.0))
+        _, _, res, cur = g.hmc(cur, minv, 20, L, step, seed=210, keep_samples=False)
+        hmc[name] = dict(chains=60, n_leapfrog=L, iterations=20, step=round(step, 4),
+                         accept_rate=res["n_accept"] / 1200.0, rejected_at_walls=res["n_left"],
+                         wall_s=round(res["wall_s"], 3), s_per_trajectory=round(res["wall_s"] / 20, 4),
+                         gradient_evals=int(res["n_grad"]) * 60, warmup_wall_s=round(warm, 3))
+        print(f"# hmc {name}: {json.dumps(hmc[name])}", file=sys.stderr, flush=True)
+    hmc["speedup_interp_over_full"] = round(hmc["shear_full"]["wall_s"] / hmc["shear_interp"]["wall_s"], 2)
+    out["hmc_fp64"] = hmc
     for name in list(models):
         models[name][1].close()
     for prec in ns_precs:
