@@ -113,7 +113,8 @@ typedef struct ns_model_desc {
     const double* sigma;          /* CMB_DIAG: [n_data] standard deviations     */
     const double* cov_blocks;     /* CMB_BLOCK: [n_ell x 3 x 3] (TT, TE, EE)    */
     const double* sigma_pp;       /* CMB_BLOCK: [n_ell]                         */
-    const double* cov;            /* SHEAR: [n_data x n_data] row-major         */
+    const double* cov;            /* SHEAR: [n_data x n_data] row-major,
+                                     n_data = n_pairs n_ell <= 1248              */
 
     /* SHEAR geometry (App. A) */
     int32_t n_bins;               /* tomographic bins (<= 10)                   */
