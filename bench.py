@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--no-ns", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-shear", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batch-scaling sweep")
     ap.add_argument("--model-comparison", action="store_true",
                     help="only run the LCDM vs w0wa nested-sampling comparison and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -229,6 +230,22 @@ def main():
         "bf16_tiles": g.tuning_report(),
     }
 
+    # per-call distribution of the headline form: 50 calls, each between its own events
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+    for e0, e1 in evs:
+        e0.record()
+        g.loglike(theta, head, out=logl)
+        e1.record()
+    torch.cuda.synchronize()
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    out["per_call_ms"] = {"form": head, "calls": 50, "median": round(float(np.median(per)), 4),
+                          "p10": round(float(np.percentile(per, 10)), 4),
+                          "p90": round(float(np.percentile(per, 90)), 4)}
+    out["env"] = environment(torch)
+
+    if not args.no_sweep:
+        out["batch_scaling"] = batch_sweep(Model, W, torch, dev)
+
     if not args.no_ns:
         out["ns"] = ns_leg(Model, W)
 
@@ -239,6 +256,65 @@ def main():
         out["cpu_baseline"], out["accuracy"] = cpu_leg(m, g, forms, torch, dev)
 
     print(json.dumps(out), flush=True)
+
+
+def environment(torch):
+    """ROCm / device / host description and, when rocm-smi answers, clocks and power."""
+    import platform
+    import subprocess
+    env = {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__}
+    try:
+        env["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        env["rocm"] = None
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], capture_output=True, text=True,
+                           timeout=30)
+        env["rocm_smi"] = json.loads(r.stdout) if r.returncode == 0 else None
+    except (OSError, subprocess.SubprocessError, ValueError):
+        env["rocm_smi"] = None
+    env["host"] = platform.node()
+    return env
+
+
+def time_calls(g, th, prec, torch, warm=2, reps=5):
+    """Mean ms per call of g.loglike over `reps` calls after `warm` (HIP events)."""
+    for _ in range(warm):
+        g.loglike(th, prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.loglike(th, prec)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_sweep(Model, W, torch, dev):
+    """Likelihood time against batch size (the analogue of the paper's Fig. 1:
+    time of a batched call relative to a call on one parameter set)."""
+    plan = [("cmb4x2500", ("bf16x3", "fp64"), (1, 16, 64, 256, 1024, 4096, 16384, 65536)),
+            ("shear_interp", ("bf16x3", "fp64"), (1, 16, 64, 256, 1024, 4096)),
+            ("shear_full", ("bf16x3",), (1, 16, 64, 256, 1024))]
+    out = {}
+    for name, precs, batches in plan:
+        m = W.load_model(name)
+        g = Model(m)
+        th_all = W.prior_draws(m, max(batches), tag=17)
+        for prec in precs:
+            rows = []
+            t1 = None
+            for B in batches:
+                th = torch.tensor(th_all[:B], dtype=torch.float64, device=dev)
+                ms = time_calls(g, th, prec, torch)
+                t1 = ms if t1 is None else t1
+                rows.append(dict(batch=B, ms_per_call=round(ms, 4), evals_per_s=round(B / (ms * 1e-3), 1),
+                                 time_rel_single=round(ms / t1, 3)))
+            out[f"{name}_{prec}"] = rows
+            print(f"# sweep {name} {prec}: {json.dumps(rows)}", file=sys.stderr, flush=True)
+        g.close()
+    return out
 
 
 def ns_leg(Model, W):
@@ -554,10 +630,31 @@ def cpu_leg(m, g, forms, torch, dev):
         ref = oracle_loglike(th, m, chunk=64)
         n += th.shape[0]
     dt = time.perf_counter() - t0
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    info = threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info] + [1])
     cpu = dict(value=round(n / dt, 2), unit="likelihood evals/s", cores=threads, kind="oracle",
                sample=f"{n} FP64 oracle evaluations ({n // th.shape[0]} passes over 64 posterior-region "
                       f"walkers of the same workload) in {dt:.1f} s")
+    # the same with one BLAS thread (about 5 s)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0, n1 = time.perf_counter(), 0
+        while time.perf_counter() - t0 < 5.0:
+            oracle_loglike(th[:16], m, chunk=16)
+            n1 += 16
+        cpu["value_1_thread"] = round(n1 / (time.perf_counter() - t0), 2)
+    cpu["host_cpu"] = next((l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")),
+                           None)
+    cpu["nproc"] = os.cpu_count()
+    cpu["blas"] = [{k: i.get(k) for k in ("internal_api", "version", "num_threads")} for i in info]
+    # the oracle's nested sampler on the 6-parameter CMB workload, as configured
+    from oracle import nested
+    from oracle.likelihood import loglike_u
+    m6 = W.load_model("cmb6")
+    t0 = time.perf_counter()
+    r6 = nested.run(lambda u: loglike_u(u, m6), 6, 100, 50, 30, seed=1, n_rep=100)
+    cpu["ns_cmb6_oracle"] = dict(n_live=100, n_delete=50, logz=r6["logZ"], n_evals=int(r6["n_evals"]),
+                                 wall_s=round(time.perf_counter() - t0, 2))
     acc = {}
     t = torch.tensor(th, dtype=torch.float64, device=dev)
     for p in forms:

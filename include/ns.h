@@ -287,8 +287,9 @@ ns_status ns_trace_report(ns_model* model, char* buf, int64_t buf_len);
  * {"<kind> M=.. N=.. K=.. networks=..": "<shape>"} (host buf, NUL-terminated;
  * NS_E_SHAPE if it does not fit).  Every candidate accumulates in the same
  * order, so the choice never changes a result.  Environment: NSMI_NO_AUTOTUNE
- * keeps the first candidate; NSMI_FUSED_CFG=c pins candidate c (0-5) of the
- * one-kernel forward; NSMI_NO_FUSED_MLP selects the layer-by-layer forward. */
+ * keeps the first candidate; NSMI_FUSED_CFG=c pins candidate c (0-7 for
+ * BF16, 0-5 for BF16X3) of the one-kernel forward; NSMI_NO_FUSED_MLP selects
+ * the layer-by-layer forward. */
 ns_status ns_tuning_report(ns_model* model, char* buf, int64_t buf_len);
 
 /* Message of the last failed call on this thread ("" if none). */

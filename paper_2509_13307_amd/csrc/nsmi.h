@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <bitset>
 #include <cmath>
 #include <cstddef>
 #include <cstring>
@@ -173,7 +174,7 @@ struct ns_model {
     hipStream_t graph_stream = nullptr;  // stream the captured slice-step graphs replay on
     hipEvent_t graph_event = nullptr;
     bool shear_attr_set = false;     // hipFuncSetAttribute done for the Limber kernels
-    uint64_t fused_attr_set = 0;     // ... and per instance of the one-kernel emulator
+    std::bitset<96> fused_attr_set;  // ... and per instance of the one-kernel emulator
     // BF16 tile / fused launch-shape choice per (kind, M, N, K, networks), measured at first use
     std::map<std::tuple<int, int64_t, int, int, int>, int> tune;
 
