@@ -69,101 +69,116 @@ __global__ void slice_reset_kernel(SliceState S) {
     }
 }
 
-__device__ __forceinline__ void apply_result(const SliceState& S, int64_t w, int d, bool inside, double ll) {
-    const int st = S.st[w];
-    if (st == ST_OUT_L) {
-        if (inside) { S.tl[w] -= 1.0; S.ne[w] += 1; }
-        else { S.st[w] = ST_OUT_R; S.ne[w] = 0; }
-    } else if (st == ST_OUT_R) {
-        if (inside) { S.tr[w] += 1.0; S.ne[w] += 1; }
-        else { S.st[w] = ST_SHRINK; S.ne[w] = 0; }
-    } else if (st == ST_SHRINK) {
-        const double t = S.tp[w];
-        if (inside) {
-            for (int i = 0; i < d; ++i)
-                S.u[w * d + i] = __dadd_rn(S.u[w * d + i], __dmul_rn(t, S.v[w * d + i]));
-            S.logl[w] = ll;
-            S.st[w] = ST_NEWSTEP;
-        } else {
-            if (t < 0.0) S.tl[w] = t; else S.tr[w] = t;
-            S.ne[w] += 1;
-            if (S.tr[w] - S.tl[w] < STALL_WIDTH || S.ne[w] >= MAX_SHRINK) {
-                S.n_stalls[w] += 1;
-                S.st[w] = ST_NEWSTEP;
-            }
-        }
-    }
-}
-
+// One wave per walker, lane i = coordinate i (d <= 64).  The walker's phase
+// state is uniform across the wave and kept in registers; the direction draw
+// (lane i: Box-Muller of draws 2i, 2i+1), the product with L (lane i sums row
+// i in column order, as a serial loop would) and the proposal are spread over
+// the lanes, so every value is bitwise that of one thread per walker.
 __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_t k, int d,
                                                             const double* __restrict__ lstar_p,
                                                             const double* __restrict__ L, int n_inner,
                                                             uint64_t seed, uint64_t iter) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= k) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= k) return;                                   // whole waves
+    const bool act = lane < d;
     const double lstar = *lstar_p;
-    if (S.pend[w] >= 0) {
-        const double ll = S.llc[S.pend[w]];
-        S.pend[w] = -1;
-        S.n_evals[w] += 1;
-        apply_result(S, w, d, ll > lstar, ll);
+    int st = S.st[w], step = S.step[w], q = S.q[w], ne = S.ne[w], pend = S.pend[w];
+    int nev = S.n_evals[w], nst = S.n_stalls[w];
+    double tl = S.tl[w], tr = S.tr[w], tp = S.tp[w], logl = S.logl[w];
+    double ui = act ? S.u[w * d + lane] : 0.0, vi = act ? S.v[w * d + lane] : 0.0;
+    bool moved = false;
+    auto apply = [&](bool inside, double ll) {
+        if (st == ST_OUT_L) {
+            if (inside) { tl -= 1.0; ne += 1; }
+            else { st = ST_OUT_R; ne = 0; }
+        } else if (st == ST_OUT_R) {
+            if (inside) { tr += 1.0; ne += 1; }
+            else { st = ST_SHRINK; ne = 0; }
+        } else if (st == ST_SHRINK) {
+            if (inside) {
+                ui = __dadd_rn(ui, __dmul_rn(tp, vi));
+                logl = ll;
+                moved = true;
+                st = ST_NEWSTEP;
+            } else {
+                if (tp < 0.0) tl = tp; else tr = tp;
+                ne += 1;
+                if (tr - tl < STALL_WIDTH || ne >= MAX_SHRINK) {
+                    nst += 1;
+                    st = ST_NEWSTEP;
+                }
+            }
+        }
+    };
+    if (pend >= 0) {
+        const double ll = S.llc[pend];
+        pend = -1;
+        nev += 1;
+        apply(ll > lstar, ll);
     }
-    double x[MAX_DIM];
     while (true) {
-        int st = S.st[w];
         if (st == ST_DONE) break;
         if (st == ST_NEWSTEP) {
-            if (S.step[w] >= n_inner) { S.st[w] = ST_DONE; break; }
-            const int s = ++S.step[w];
-            double zeta[MAX_DIM];
-            for (int i = 0; i < d; ++i) {
-                const double u1 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * i);
-                const double u2 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * i + 1);
-                zeta[i] = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
+            if (step >= n_inner) { st = ST_DONE; break; }
+            const int s = ++step;
+            double z = 0.0;
+            if (act) {
+                const double u1 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * lane);
+                const double u2 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * lane + 1);
+                z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
             }
-            for (int i = 0; i < d; ++i) {
-                double acc = 0.0;
-                for (int j = 0; j <= i; ++j) acc = __dadd_rn(acc, __dmul_rn(L[i * d + j], zeta[j]));
-                S.v[w * d + i] = acc;
+            double acc = 0.0;
+            for (int j = 0; j < d; ++j) {
+                const double zj = __shfl(z, j, 64);
+                if (act && j <= lane) acc = __dadd_rn(acc, __dmul_rn(L[lane * d + j], zj));
             }
+            vi = act ? acc : 0.0;
             const double r = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * d);
-            S.tl[w] = -r;
-            S.tr[w] = 1.0 - r;
-            S.q[w] = 2 * d + 1;
-            S.ne[w] = 0;
-            S.st[w] = ST_OUT_L;
+            tl = -r;
+            tr = 1.0 - r;
+            q = 2 * d + 1;
+            ne = 0;
+            st = ST_OUT_L;
             continue;
         }
         double t;
         if (st == ST_OUT_L) {
-            if (S.ne[w] >= MAX_EXPAND) { S.st[w] = ST_OUT_R; S.ne[w] = 0; continue; }
-            t = S.tl[w];
+            if (ne >= MAX_EXPAND) { st = ST_OUT_R; ne = 0; continue; }
+            t = tl;
         } else if (st == ST_OUT_R) {
-            if (S.ne[w] >= MAX_EXPAND) { S.st[w] = ST_SHRINK; S.ne[w] = 0; continue; }
-            t = S.tr[w];
+            if (ne >= MAX_EXPAND) { st = ST_SHRINK; ne = 0; continue; }
+            t = tr;
         } else {
-            const int qq = S.q[w]++;
-            const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)S.step[w], iter, (uint64_t)qq);
-            const double tl = S.tl[w], tr = S.tr[w];
+            const int qq = q++;
+            const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)qq);
             t = __dadd_rn(tl, __dmul_rn(U, __dsub_rn(tr, tl)));
         }
-        bool inbox = true;
-        for (int i = 0; i < d; ++i) {
-            x[i] = __dadd_rn(S.u[w * d + i], __dmul_rn(t, S.v[w * d + i]));
-            inbox = inbox && (x[i] >= 0.0) && (x[i] <= 1.0);
-        }
-        S.tp[w] = t;
+        const double xi = __dadd_rn(ui, __dmul_rn(t, vi));
+        const bool inbox = __ballot(act && !((xi >= 0.0) && (xi <= 1.0))) == 0;
+        tp = t;
         if (!inbox) {
-            apply_result(S, w, d, false, -INFINITY);
+            apply(false, -INFINITY);
             continue;
         }
-        const int slot = atomicAdd(S.ccount, 1);
-        for (int i = 0; i < d; ++i) S.xc[(int64_t)slot * d + i] = x[i];
-        S.cidx[slot] = (int)w;
-        S.pend[w] = slot;
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(S.ccount, 1);
+        slot = __shfl(slot, 0, 64);
+        if (act) S.xc[(int64_t)slot * d + lane] = xi;
+        if (lane == 0) S.cidx[slot] = (int)w;
+        pend = slot;
         break;
     }
-    if (S.st[w] != ST_DONE) atomicAdd(S.active, 1);
+    if (act) {
+        if (moved) S.u[w * d + lane] = ui;
+        S.v[w * d + lane] = vi;
+    }
+    if (lane == 0) {
+        S.st[w] = st; S.step[w] = step; S.q[w] = q; S.ne[w] = ne; S.pend[w] = pend;
+        S.n_evals[w] = nev; S.n_stalls[w] = nst;
+        S.tl[w] = tl; S.tr[w] = tr; S.tp[w] = tp; S.logl[w] = logl;
+        if (st != ST_DONE) atomicAdd(S.active, 1);
+    }
 }
 
 // ------------------------------------------------------------- NS kernels
@@ -481,8 +496,8 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
             {
                 TraceScope ts(m, st, "slice_advance");
                 hipLaunchKernelGGL(slice_reset_kernel, dim3(1), dim3(64), 0, st, S);
-                hipLaunchKernelGGL(slice_advance_kernel, gw, dim3(256), 0, st, S, k, d, lstar_dev, L, n_inner, seed,
-                                   iter);
+                hipLaunchKernelGGL(slice_advance_kernel, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, st, S, k, d,
+                                   lstar_dev, L, n_inner, seed, iter);
             }
             prior_transform(m, S.xc, thc, d, k, S.ccount, st);
             loglike_batch(m, thc, d, k, S.llc, prec, S.ccount, st);
