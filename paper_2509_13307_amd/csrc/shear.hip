@@ -377,13 +377,14 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
 // ---------------------------------------------------------------- dense chi^2
 // Y = C L^{-T} as a GEMM over (64-walker x 64-column) output tiles on
 // v_mfma_f64_16x16x4f64: each wave owns a 32 x 32 quarter (2 x 2 MFMA
-// tiles); K blocks of 16 are staged through LDS (double-buffered, the next
+// tiles); K blocks of 32 are staged through LDS (double-buffered, the next
 // block's global loads in flight during the current block's MFMAs).  L^{-T}
 // is lower-triangular in (column, k), so a column tile stops at its own K
 // range.  Each tile writes its walkers' partial sums of (w_n - Y_bn)^2 over its
 // 64 columns, w = L^{-1} d; dense_chi2_finish_kernel adds the column tiles in
 // a fixed order (deterministic).
-constexpr int DG_M = 64, DG_N = 64, DG_KB = 16;
+constexpr int DG_M = 64, DG_N = 64, DG_KB = 32;
+constexpr size_t DG_SMEM = (2 * DG_KB * DG_M + 2 * DG_KB * DG_N + 2 * DG_M) * sizeof(double);
 // MODE 0: Y = C L^{-T} (Bm = L^{-T}, K range [0, 64 (ct + 1))), partial sums of
 //         (w - Y)^2; with R != nullptr also the residuals R = w - Y.
 // MODE 1: out = R L^{-1} (Bm = L^{-1} row-major, K range [64 ct, np)), the
@@ -394,9 +395,10 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
                                                               const double* __restrict__ wv,
                                                               double* __restrict__ part, int64_t pstride,
                                                               double* __restrict__ R, const int* __restrict__ count) {
-    __shared__ double As[2][DG_KB][DG_M];     // [k][walker]
-    __shared__ double Bs[2][DG_KB][DG_N];     // [k][column]
-    __shared__ double red[2][DG_M];
+    extern __shared__ double dg_lds[];
+    auto As = reinterpret_cast<double (*)[DG_KB][DG_M]>(dg_lds);                      // [2][k][walker]
+    auto Bs = reinterpret_cast<double (*)[DG_KB][DG_N]>(dg_lds + 2 * DG_KB * DG_M);   // [2][k][column]
+    auto red = reinterpret_cast<double (*)[DG_M]>(dg_lds + 2 * DG_KB * (DG_M + DG_N)); // [2][walker]
     if (count) B = min<int64_t>(B, *count);
     const int64_t b0 = (int64_t)blockIdx.x * DG_M;
     if (b0 >= B) return;
@@ -405,12 +407,12 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
     const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
     const int kbeg = MODE == 0 ? 0 : DG_N * ct;
     const int kend = MODE == 0 ? min(np, DG_N * (ct + 1)) : np;
-    double ra[4], rb[4];
+    double ra[8], rb[8];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + 256 * q;                  // 0 .. 1023
-            const int row = e >> 4, k = e & 15;           // A: 16 consecutive k of one walker
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;                  // 0 .. 2047
+            const int row = e >> 5, k = e & 31;           // A: 32 consecutive k of one walker
             const int64_t b = b0 + row;
             const int kk = k0 + k;
             ra[q] = (b < B && kk < n) ? C[b * n + kk] : 0.0;
@@ -420,9 +422,9 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
     };
     auto sstore = [&](int bf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int e = tid + 256 * q;
-            As[bf][e & 15][e >> 4] = ra[q];
+            As[bf][e & 31][e >> 5] = ra[q];
             Bs[bf][e >> 6][e & 63] = rb[q];
         }
     };
@@ -609,6 +611,10 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
                              (const void*)limber_sum_kernel<float, true, 32>};
         for (const void* f : fns)
             NS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)DG_SMEM));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)DG_SMEM));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    150 * 1024));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -638,8 +644,8 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     {
         TraceScope ts(m, s, "dense_chi2");
         hipLaunchKernelGGL(dense_chi2_gemm_kernel<0>, dim3((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct),
-                           dim3(256), 0, s, Cv, B, n, np, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part, B,
-                           (double*)nullptr, count);
+                           dim3(256), DG_SMEM, s, Cv, B, n, np, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part,
+                           B, (double*)nullptr, count);
         NS_HIP(hipGetLastError());
         hipLaunchKernelGGL(dense_chi2_finish_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld,
                            B, m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), part, B,
@@ -656,15 +662,15 @@ void dense_chi2_adjoint(ns_model* m, const double* theta, int64_t ld, int64_t B,
     const int n = m->n_data;
     const int np = (n + DG_N - 1) / DG_N * DG_N, n_ct = np / DG_N;
     const dim3 grid((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct);
-    hipLaunchKernelGGL(dense_chi2_gemm_kernel<0>, grid, dim3(256), 0, s, Cv, B, n, np, m->cov_lt_pad.as<double>(),
-                       m->cov_w.as<double>(), part, B, R, (const int*)nullptr);
+    hipLaunchKernelGGL(dense_chi2_gemm_kernel<0>, grid, dim3(256), DG_SMEM, s, Cv, B, n, np,
+                       m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part, B, R, (const int*)nullptr);
     NS_HIP(hipGetLastError());
     hipLaunchKernelGGL(dense_chi2_finish_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld, B,
                        m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), part, B, n_ct,
                        m->logl_const, logl, (const int*)nullptr);
     NS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(dense_chi2_gemm_kernel<1>, grid, dim3(256), 0, s, R, B, n, np, m->cov_l_pad.as<double>(),
-                       (const double*)nullptr, (double*)nullptr, B, gC, (const int*)nullptr);
+    hipLaunchKernelGGL(dense_chi2_gemm_kernel<1>, grid, dim3(256), DG_SMEM, s, R, B, n, np,
+                       m->cov_l_pad.as<double>(), (const double*)nullptr, (double*)nullptr, B, gC, (const int*)nullptr);
     NS_HIP(hipGetLastError());
 }
 
