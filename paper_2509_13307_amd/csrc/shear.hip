@@ -266,8 +266,8 @@ __global__ __launch_bounds__(256) void shear_windows_kernel(
     if (t < nb) norm_out[w * nb + t] = red[t * 4] + red[t * 4 + 1] + red[t * 4 + 2] + red[t * 4 + 3];
 }
 
-// limber_sum_kernel: one workgroup (256 threads) per walker, nodes in chunks
-// of 256.  (c) thread = node: log10 P carried to z_j (cubic spline or linear
+// limber_sum_kernel: one workgroup (256 threads) per (walker, chunk of 256
+// nodes).  (c) thread = node: log10 P carried to z_j (cubic spline or linear
 // in z), Catmull-Rom in log10 k at k = (l + 1/2)/chi_j, P = 10^(.), zero
 // outside [k_min, k_max]; [256][LB] in LDS with the chunk's scaled windows.
 // (d) thread = (pair, node segment): all LB multipoles of one pair in
@@ -279,14 +279,15 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
     const int* __restrict__ pidx, const double* __restrict__ pfix, const int* __restrict__ zidx,
     const double* __restrict__ zcoef, const double* __restrict__ lell, const T* __restrict__ Ytab,
     const T* __restrict__ Mtab, const T* __restrict__ Win, const double* __restrict__ lchi_in,
-    const double* __restrict__ norm_in, double* __restrict__ Cout, const int* __restrict__ count) {
+    const double* __restrict__ norm_in, double* __restrict__ Cout, double* __restrict__ part,
+    const int* __restrict__ count) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (count) B = min<int64_t>(B, *count);
     const int64_t w = blockIdx.x;
     if (w >= B) return;
     const int t = threadIdx.x;
     const int na = G.n_a, nb = G.n_bins, npr = G.n_pairs, nl = G.n_ell;
-    const int nch = (na + 255) / 256;
+    const int nch = (na + 255) / 256, c = blockIdx.y;    // this workgroup's chunk of nodes
     constexpr int WS = 257;                                           // padded row of the window table
     T* Ws = reinterpret_cast<T*>(smem);                               // [nb][WS]
     T* Pl = Ws + nb * WS;                                             // [256][LB]
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
 #pragma unroll
     for (int e = 0; e < LB; ++e) acc[e] = T(0);
     const int64_t tab = w * (int64_t)G.n_z * G.n_k;
-    for (int c = 0; c < nch; ++c) {
+    {
         const int j = c * 256 + t;
         const bool node = j < na;
         for (int i = 0; i < nb; ++i) Ws[i * WS + t] = node ? Win[(w * nb + i) * na + j] : T(0);
@@ -357,7 +358,8 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
         }
         __syncthreads();
     }
-    // segments -> LDS (nseg npr <= 256 rows of LB), added in order
+    // segments -> LDS (nseg npr <= 256 rows of LB), added in order; with
+    // several chunks the chunk's sums go to `part` for limber_reduce_kernel
     if (worker)
 #pragma unroll
         for (int e = 0; e < LB; ++e) Pl[(sg * npr + pw) * LB + e] = acc[e];
@@ -367,11 +369,37 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
         const int p = o / nl, b = o % nl;
         T v = T(0);
         for (int s = 0; s < nseg; ++s) v += Pl[(s * npr + p) * LB + b];
+        if (nch > 1) {
+            part[(w * nch + c) * nout + o] = (double)v;
+            continue;
+        }
         int ci, cj;
         pair_of(p, ci, cj);
         const double mi = phys(9 + 2 * nb + ci), mj = phys(9 + 2 * nb + cj);
         Cout[w * nout + o] = (1.0 + mi) * (1.0 + mj) * (double)v / (norm_in[w * nb + ci] * norm_in[w * nb + cj]);
     }
+}
+
+// Sum of the node chunks' Limber partial sums in chunk order, times
+// (1 + m_i)(1 + m_j) / (N_i N_j); one thread per (walker, spectrum, multipole).
+__global__ void limber_reduce_kernel(const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
+                                     const int* __restrict__ pidx, const double* __restrict__ pfix,
+                                     const double* __restrict__ norm_in, const double* __restrict__ part,
+                                     double* __restrict__ Cout, const int* __restrict__ count) {
+    if (count) B = min<int64_t>(B, *count);
+    const int nb = G.n_bins, nl = G.n_ell, nout = G.n_pairs * nl, nch = (G.n_a + 255) / 256;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= B * nout) return;
+    const int64_t w = g / nout;
+    const int o = (int)(g % nout), p = o / nl;
+    double v = 0.0;
+    for (int c = 0; c < nch; ++c) v += part[(w * nch + c) * nout + o];
+    int ci = 0, rem = p;
+    while (rem >= nb - ci) { rem -= nb - ci; ++ci; }
+    const int cj = ci + rem;
+    auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
+    const double mi = phys(9 + 2 * nb + ci), mj = phys(9 + 2 * nb + cj);
+    Cout[w * nout + o] = (1.0 + mi) * (1.0 + mj) * v / (norm_in[w * nb + ci] * norm_in[w * nb + cj]);
 }
 
 // ---------------------------------------------------------------- dense chi^2
@@ -548,12 +576,20 @@ static size_t limber_sum_smem(const ns_model* m, size_t elem) {
 template <class T, bool LINZ>
 static void launch_limber_sum(ns_model* m, const ShearGeom& G, const double* theta, int64_t ld, int64_t B,
                               const void* Mtab, const T* Win, const double* lchi, const double* norm, double* Cv,
-                              const int* count, size_t sm, hipStream_t s) {
+                              double* part, const int* count, size_t sm, hipStream_t s) {
+    const int nch = (m->n_a + 255) / 256;
     auto kern = limber_lb(m) == 20 ? limber_sum_kernel<T, LINZ, 20> : limber_sum_kernel<T, LINZ, 32>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), sm, s, theta, ld, B, G, m->pidx_d.as<int>(),
-                       m->pfix_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                       m->lell_d.as<double>(), m->ws_out.as<T>(), (const T*)Mtab, Win, lchi, norm, Cv, count);
+    hipLaunchKernelGGL(kern, dim3((unsigned)B, (unsigned)nch), dim3(256), sm, s, theta, ld, B, G,
+                       m->pidx_d.as<int>(), m->pfix_d.as<double>(), m->zsp_idx_d.as<int>(),
+                       m->zsp_coef_d.as<double>(), m->lell_d.as<double>(), m->ws_out.as<T>(), (const T*)Mtab, Win,
+                       lchi, norm, Cv, part, count);
     NS_HIP(hipGetLastError());
+    if (nch > 1) {
+        const int64_t n = B * m->n_data;
+        hipLaunchKernelGGL(limber_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, ld, B, G,
+                           m->pidx_d.as<int>(), m->pfix_d.as<double>(), norm, part, Cv, count);
+        NS_HIP(hipGetLastError());
+    }
 }
 
 template <class T>
@@ -561,12 +597,15 @@ static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t 
                           const int* count, hipStream_t s) {
     const ShearGeom G = shear_geom(m);
     const int na = m->n_a, nb = m->n_bins;
-    // windows [B][nb][na] (T), log10 chi [B][na], normalisations [B][nb]
+    // windows [B][nb][na] (T), log10 chi [B][na], normalisations [B][nb], and
+    // the Limber sums of each node chunk [B][nch][n_data]
+    const size_t nch = (na + 255) / 256;
     const size_t wbytes = ((size_t)B * nb * na * sizeof(T) + 7) / 8 * 8;
-    m->ws_win.ensure(wbytes + (size_t)B * (na + nb) * sizeof(double));
+    m->ws_win.ensure(wbytes + (size_t)B * (na + nb + (nch > 1 ? nch * m->n_data : 0)) * sizeof(double));
     T* Win = m->ws_win.as<T>();
     double* lchi = reinterpret_cast<double*>(m->ws_win.as<char>() + wbytes);
     double* norm = lchi + (size_t)B * na;
+    double* part = norm + (size_t)B * nb;
     const size_t sm1 = windows_smem(m), sm2 = limber_sum_smem(m, sizeof(T));
     NS_CHECK(sm1 <= 160 * 1024 && sm2 <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
     {
@@ -579,9 +618,9 @@ static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t 
     }
     TraceScope ts(m, s, "limber");
     if (m->z_linear)
-        launch_limber_sum<T, true>(m, G, theta, ld, B, Mtab, Win, lchi, norm, Cv, count, sm2, s);
+        launch_limber_sum<T, true>(m, G, theta, ld, B, Mtab, Win, lchi, norm, Cv, part, count, sm2, s);
     else
-        launch_limber_sum<T, false>(m, G, theta, ld, B, Mtab, Win, lchi, norm, Cv, count, sm2, s);
+        launch_limber_sum<T, false>(m, G, theta, ld, B, Mtab, Win, lchi, norm, Cv, part, count, sm2, s);
 }
 
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
