@@ -411,8 +411,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Group<Epi> G, int64_t lda
 // v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
 // register r of lane l returns D[l / 16 + 4 r][l % 16].
 // WG tile 64 x 64, four waves in 2 x 2, each wave 32 x 32 = 2 x 2 tiles of
-// 16 x 16; BK = 16, LDS row stride 17 doubles.
-constexpr int GD_M = 64, GD_N = 64, GD_K = 16, GD_LDS = GD_K + 1;
+// 16 x 16; BK = 32, LDS row stride 33 doubles.  The next K block's tiles are
+// fetched into registers while the current one feeds the MFMAs (the K order of
+// every accumulator is unchanged: k = 0, 4, 8, ...).
+constexpr int GD_M = 64, GD_N = 64, GD_K = 32, GD_LDS = GD_K + 1;
 
 template <class Epi>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(Group<Epi> G, int64_t lda, int64_t M, int N, int K,
@@ -436,17 +438,31 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Group<Epi> G, int64_t lda
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
-    for (int k0 = 0; k0 < K; k0 += GD_K) {
+    double ra[8], rb[8];
+    auto gload = [&](int k0) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int c = tid + it * 256;          // 64 rows x 16 k
-            const int row = c >> 4, kk = c & 15;
+        for (int it = 0; it < 8; ++it) {
+            const int c = tid + it * 256;          // 64 rows x 32 k
+            const int row = c >> 5, kk = c & 31;
             const int64_t gr = m0 + row;
-            As[row * GD_LDS + kk] = (gr < M && k0 + kk < K) ? A[gr * lda + k0 + kk] : 0.0;
+            ra[it] = (gr < M && k0 + kk < K) ? A[gr * lda + k0 + kk] : 0.0;
             const int gn = n0 + row;
-            Bs[row * GD_LDS + kk] = (gn < N && k0 + kk < K) ? W[(int64_t)gn * K + k0 + kk] : 0.0;
+            rb[it] = (gn < N && k0 + kk < K) ? W[(int64_t)gn * K + k0 + kk] : 0.0;
         }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int c = tid + it * 256;
+            As[(c >> 5) * GD_LDS + (c & 31)] = ra[it];
+            Bs[(c >> 5) * GD_LDS + (c & 31)] = rb[it];
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < K; k0 += GD_K) {
+        sstore();
         __syncthreads();
+        if (k0 + GD_K < K) gload(k0 + GD_K);
 #pragma unroll
         for (int kq = 0; kq < GD_K; kq += 4) {
             const int koff = kq + (lane >> 4);

@@ -97,6 +97,26 @@ def test_fp64_full_size_sampled(built, name, B, sample):
     check_fp64(ref, got[idx], f"{name} full B={B}")
 
 
+@pytest.mark.parametrize("name,B,sample", [("cmb4x2500", 4096, 40), ("cmbtt_cv", 4096, 40), ("shear10", 4096, 6),
+                                           ("shear_interp", 4096, 4)])
+def test_bf16x3_full_size_sampled(built, name, B, sample):
+    """The headline form at the benchmark's batch and launch shape: posterior-
+    region walkers, sampled rows (ends of the batch, block boundaries and random
+    rows) against the FP64 oracle, |dlogL| <= 1e-2."""
+    say(f"case bf16x3 full {name} B={B}")
+    m, g = gpu_model(name)
+    th = W.posterior_draws(m["theta_fid"], post_scale(m), B, tag=18)
+    got = run_gpu(g, th, "bf16x3")
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([[0, 1, 31, 32, 63, 64, B // 2, B - 2, B - 1], rng.integers(0, B, size=sample)]))
+    ref = oracle_loglike(th[idx], m, chunk=64)
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got[idx]))
+    d = np.abs(got[idx][fin] - ref[fin])
+    say(f"{name} bf16x3 B={B}: |dlogL| max {d.max():.3e} over {fin.sum()} sampled walkers")
+    assert d.max() <= 1e-2
+
+
 def test_edge_cases(built):
     say("case edge cmb6")
     m, g = gpu_model("cmb6")
