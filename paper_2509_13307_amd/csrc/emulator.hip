@@ -46,7 +46,7 @@ template <class T, class OutT> struct FirstArgs {
 // units (its CPT x n_in weights held in registers) for every
 // (256 / (n_out / CPT))-th row of the block.  Each unit's sum runs in input
 // order starting from the bias, whatever the thread mapping.
-constexpr int FL_ROWS = 64;
+constexpr int FL_ROWS = 16;                  // small blocks: short serial chains per thread
 
 template <class T, class OutT, int NI, int CPT>
 __global__ __launch_bounds__(256) void first_layer_kernel(
