@@ -359,23 +359,35 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Group<Epi> G, int64_t lda
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    for (int k0 = 0; k0 < K; k0 += GF_K) {
-        // 128 rows x 32 k = 1024 float4 chunks
+    // 128 rows x 32 k = 1024 float4 chunks per operand; the next K block is
+    // fetched into registers while the current one feeds the MFMAs
+    float4 ra[4], rb[4];
+    auto gload = [&](int k0) {
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int c = tid + it * 256;
             const int row = c >> 3, kc = (c & 7) * 4;
             const int64_t gr = m0 + row;
-            float4 av = make_float4(0.f, 0.f, 0.f, 0.f), wv = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gr < M) av = *reinterpret_cast<const float4*>(A + gr * lda + k0 + kc);
+            ra[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rb[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gr < M) ra[it] = *reinterpret_cast<const float4*>(A + gr * lda + k0 + kc);
             const int gn = n0 + row;
-            if (gn < N) wv = *reinterpret_cast<const float4*>(W + (int64_t)gn * K + k0 + kc);
+            if (gn < N) rb[it] = *reinterpret_cast<const float4*>(W + (int64_t)gn * K + k0 + kc);
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < K; k0 += GF_K) {
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int c = tid + it * 256;
+            const int row = c >> 3, kc = (c & 7) * 4;
             float* ad = &As[row * GF_LDS + kc];
-            ad[0] = av.x; ad[1] = av.y; ad[2] = av.z; ad[3] = av.w;
+            ad[0] = ra[it].x; ad[1] = ra[it].y; ad[2] = ra[it].z; ad[3] = ra[it].w;
             float* bd = &Bs[row * GF_LDS + kc];
-            bd[0] = wv.x; bd[1] = wv.y; bd[2] = wv.z; bd[3] = wv.w;
+            bd[0] = rb[it].x; bd[1] = rb[it].y; bd[2] = rb[it].z; bd[3] = rb[it].w;
         }
         __syncthreads();
+        if (k0 + GF_K < K) gload(k0 + GF_K);
 #pragma unroll
         for (int kk = 0; kk < GF_K; kk += 2) {
             const int koff = kk + (lane >> 5);
