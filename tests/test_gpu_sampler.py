@@ -66,6 +66,54 @@ def test_slice_step_replays_oracle(name, k_live, n_inner):
     assert np.all(lt.cpu().numpy() > lstar)
 
 
+def small_linear_shear():
+    """Linear-z shear on two node chunks with a small emulator (fast oracle)."""
+    from oracle import shear as oshear
+    m = W.shear_structure(n_z=31, n_bins=3, n_extra=0, hidden=(64, 64), n_a=300, n_k=60, n_ell=25,
+                          z_interp="linear")
+    C = oshear.spectra(m["theta_fid"][None], m)[0][0]
+    sig = 0.05 * np.abs(C) + 1e-3 * np.abs(C).max()
+    m["data"] = C + sig * np.random.default_rng(300).normal(size=C.size)
+    m["cov"] = np.diag(sig ** 2)
+    return m
+
+
+def test_slice_step_graph_replays_oracle_linear_z_shear(monkeypatch):
+    """Enough rounds for the captured graphs (16 rounds per launch) on the
+    chunked, linear-z shear likelihood: the oracle's trajectory is replayed,
+    and turning the graphs off changes nothing."""
+    say("case slice step shear linear z, graphs")
+    m = small_linear_shear()
+    u_all, _, lstar, u0, l0 = walkers_above(m, 48, seed=21)
+    L = nested.direction_cholesky(u_all)
+    fn = lambda x: loglike_u(x, m)
+    u_ref, l_ref, ne_ref, ns_ref = nested.slice_step(fn, u0, l0, lstar, L, 10, seed=21, it=3)
+
+    def run(env):
+        monkeypatch.delenv("NSMI_NO_GRAPH", raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g = mk(m)
+        ut = torch.tensor(u0, device=DEV).contiguous()
+        lt = torch.tensor(l0, device=DEV)
+        ne, ns = g.slice_step(ut, lt, lstar, torch.tensor(L), 10, seed=21, it=3)
+        torch.cuda.synchronize()
+        out = ut.cpu().numpy(), lt.cpu().numpy(), ne.cpu().numpy(), ns.cpu().numpy()
+        g.close()
+        return out
+
+    got = run({})
+    say(f"evals {int(got[2].sum())} vs oracle {int(ne_ref.sum())}, rounds >= {int(got[2].max())}")
+    assert got[2].max() > 16
+    np.testing.assert_array_equal(got[2], ne_ref)
+    np.testing.assert_array_equal(got[3], ns_ref)
+    np.testing.assert_allclose(got[0], u_ref, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(got[1], l_ref, rtol=1e-12, atol=1e-7)
+    other = run({"NSMI_NO_GRAPH": "1"})
+    for a, b in zip(got, other):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_ns_run_replays_oracle_gauss():
     say("case ns_run gauss")
     desc = W.gauss_structure(d=3, mu=[0.1, 0.5, 0.8], sigma=[0.05, 0.1, 0.08])
