@@ -268,10 +268,13 @@ def environment(torch):
     except OSError:
         env["rocm"] = None
     try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], capture_output=True, text=True,
-                           timeout=30)
+        import shutil
+        smi = shutil.which("rocm-smi")
+        # run the (Python) tool through this interpreter, not through its #! line
+        r = subprocess.run([sys.executable, smi, "--showclocks", "--showpower", "--json"], capture_output=True,
+                           text=True, timeout=30)
         env["rocm_smi"] = json.loads(r.stdout) if r.returncode == 0 else None
-    except (OSError, subprocess.SubprocessError, ValueError):
+    except (OSError, subprocess.SubprocessError, ValueError, TypeError):
         env["rocm_smi"] = None
     env["host"] = platform.node()
     return env
