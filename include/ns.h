@@ -173,6 +173,21 @@ ns_status ns_prior_transform(ns_model* model, const double* u, double* theta, in
 ns_status ns_loglike_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
                            double* logl, int32_t precision, void* stream);
 
+/* Theory vector of every walker: the prediction the likelihood compares with
+ * the data, in the data's order, after every stage before the chi^2 (or the
+ * cosmic-variance sum), by the same kernels as ns_loglike_batch.
+ *   CMB_DIAG: the emulator outputs y (Sec. 3.1); CMB_BLOCK: C^TT | C^TE |
+ *   C^EE | C^pp, each n_ell long, C = 10^y where spec_log is 1; CMB_CV:
+ *   C^TT_l = 10^y; SHEAR: C_ij(l_b) after the multiplicative bias
+ *   (Eqs. (A1)-(A4)), pairs i <= j in lexicographic order, then l_b.
+ * theta: device [B x ld]; out: device [B x ldo] double, ldo >= n_data; both
+ * caller-owned.  Rows of theta outside the prior support are computed all the
+ * same (the support test belongs to the likelihood).  Asynchronous on stream.
+ * NS_E_UNSUPPORTED for GAUSS; NS_E_SHAPE for ldo < n_data or B > 2^24;
+ * B = 0 is a no-op. */
+ns_status ns_theory_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
+                          double* out, int64_t ldo, int32_t precision, void* stream);
+
 /* As ns_loglike_batch, plus grad: device [B x d], d logL / d theta by the
  * hand-written adjoint of every stage (input gradients only). */
 ns_status ns_loglike_grad_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,

@@ -602,6 +602,24 @@ ns_status ns_loglike_batch(ns_model* model, const double* theta, int64_t ld, int
     });
 }
 
+ns_status ns_theory_batch(ns_model* model, const double* theta, int64_t ld, int64_t B, double* out, int64_t ldo,
+                          int32_t precision, void* stream) {
+    return (ns_status)guard([&] {
+        check_ptr(model, "model");
+        check_prec(precision);
+        NS_CHECK(B >= 0, NS_E_SHAPE, "B must be >= 0");
+        NS_CHECK(ld >= model->d, NS_E_SHAPE, "ld must be >= d");
+        NS_CHECK(B <= (int64_t)1 << 24, NS_E_SHAPE, "B too large");
+        NS_CHECK(model->kind != NS_MODEL_GAUSS, NS_E_UNSUPPORTED, "the Gaussian test model has no theory vector");
+        NS_CHECK(ldo >= model->n_data, NS_E_SHAPE, "ldo must be >= n_data");
+        if (B == 0) return;
+        check_ptr(theta, "theta");
+        check_ptr(out, "out");
+        bind_device(model);
+        theory_batch(model, theta, ld, B, out, ldo, precision, (hipStream_t)stream);
+    });
+}
+
 ns_status ns_loglike_grad_batch(ns_model* model, const double* theta, int64_t ld, int64_t B, double* logl,
                                 double* grad, int32_t precision, void* stream) {
     return (ns_status)guard([&] {

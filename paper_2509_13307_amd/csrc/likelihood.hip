@@ -226,6 +226,62 @@ void cmb_chi2(ns_model* m, const double* theta, int64_t ld, int64_t B, const voi
     NS_HIP(hipGetLastError());
 }
 
+// Theory rows of the CMB kinds: spectrum g of walker b sits at columns
+// b rs + g sp + i of the emulator output (T); out[b ldo + g nper + i] (double),
+// the data order of the likelihood.  Grid-stride over B G nper elements.
+template <class T>
+__global__ __launch_bounds__(256) void theory_gather_kernel(const T* __restrict__ src, int64_t B, int G, int nper,
+                                                            int64_t sp, int64_t rs, double* __restrict__ out,
+                                                            int64_t ldo) {
+    const int64_t n = (int64_t)G * nper, total = B * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = e / n, j = e - b * n;
+        const int g = (int)(j / nper), i = (int)(j - (int64_t)g * nper);
+        out[b * ldo + j] = (double)src[b * rs + g * sp + i];
+    }
+}
+
+void theory_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* out, int64_t ldo, int prec,
+                  hipStream_t s) {
+    if (B == 0) return;
+    NS_CHECK(m->kind != NS_MODEL_GAUSS, NS_E_UNSUPPORTED, "the Gaussian test model has no theory vector");
+    const size_t elem = prec == NS_FP64 ? 8 : 4;
+    if (m->kind == NS_MODEL_SHEAR) {
+        const int n_k = m->nets[0]->dims.back();
+        m->ws_out.ensure((size_t)B * m->n_z * n_k * elem);
+        const int id0 = 0, no_log = 0;
+        void* out0 = m->ws_out.p;
+        emulator_forward(m, &id0, 1, theta, ld, B, &out0, n_k, &no_log, prec, nullptr, s);
+        const double* Cv = shear_spectra_from_table(m, theta, ld, B, prec, nullptr, s);
+        const size_t row = (size_t)m->n_data * sizeof(double);
+        NS_HIP(hipMemcpy2DAsync(out, (size_t)ldo * sizeof(double), Cv, row, row, (size_t)B, hipMemcpyDeviceToDevice,
+                                s));
+        return;
+    }
+    // CMB kinds: the emulator with every output transform (C = 10^y where the
+    // spectrum is emulated in log10), then a gather into data order
+    const int64_t n = cmb_row_stride(m), sp = cmb_spec_stride(m);
+    m->ws_out.ensure((size_t)B * n * elem);
+    int ids[4];
+    void* outs[4];
+    const int G = (int)m->nets.size();
+    for (int g = 0; g < G; ++g) {
+        ids[g] = g;
+        outs[g] = m->ws_out.as<char>() + g * sp * elem;
+    }
+    emulator_forward(m, ids, G, theta, ld, B, outs, n, m->spec_log.data(), prec, nullptr, s);
+    const int nper = m->n_data / G;
+    const int64_t total = B * m->n_data;
+    const dim3 grid((unsigned)std::min<int64_t>((total + 255) / 256, 65536));
+    if (prec == NS_FP64)
+        hipLaunchKernelGGL(theory_gather_kernel<double>, grid, dim3(256), 0, s, m->ws_out.as<double>(), B, G, nper, sp,
+                           n, out, ldo);
+    else
+        hipLaunchKernelGGL(theory_gather_kernel<float>, grid, dim3(256), 0, s, m->ws_out.as<float>(), B, G, nper, sp,
+                           n, out, ldo);
+    NS_HIP(hipGetLastError());
+}
+
 void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, int prec,
                    const int* count, hipStream_t s) {
     if (B == 0) return;

@@ -251,6 +251,9 @@ void dense_chi2_adjoint(ns_model* m, const double* theta, int64_t ld, int64_t B,
                         double* part, double* logl, double* gC, hipStream_t s);
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B,
                               double* logl, int prec, const int* count, hipStream_t s);
+// The spectra C [B x n_data] (double, in m->ws_aux) without the chi^2.
+double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, int prec,
+                                 const int* count, hipStream_t s);
 
 void gauss_loglike(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
                    const int* count, hipStream_t s);
@@ -258,6 +261,10 @@ void gauss_loglike(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
 // Full batched likelihood (dispatch by kind).
 void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
                    int prec, const int* count, hipStream_t s);
+
+// Theory vector of every walker, in data order, as double: out [B x ldo].
+void theory_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, double* out, int64_t ldo,
+                  int prec, hipStream_t s);
 
 void prior_transform(ns_model* m, const double* u, double* theta, int64_t ld, int64_t B,
                      const int* count, hipStream_t s);

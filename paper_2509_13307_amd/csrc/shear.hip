@@ -623,8 +623,8 @@ static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t 
         launch_limber_sum<T, false>(m, G, theta, ld, B, Mtab, Win, lchi, norm, Cv, part, count, sm2, s);
 }
 
-void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
-                              int prec, const int* count, hipStream_t s) {
+double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, int prec,
+                                 const int* count, hipStream_t s) {
     const int nk = m->n_k, nz = m->n_z;
     const size_t elem = prec == NS_FP64 ? 8 : 4;
     const int n = m->n_data;
@@ -677,6 +677,13 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
         launch_limber<double>(m, theta, ld, B, Mtab, Cv, count, s);
     else
         launch_limber<float>(m, theta, ld, B, Mtab, Cv, count, s);
+    return Cv;
+}
+
+void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
+                              int prec, const int* count, hipStream_t s) {
+    const int n = m->n_data;
+    double* Cv = shear_spectra_from_table(m, theta, ld, B, prec, count, s);
     // chi^2 partial sums per 64-column tile: [n_ct x B] after the spectra
     const int np = (n + DG_N - 1) / DG_N * DG_N, n_ct = np / DG_N;
     double* part = Cv + (size_t)B * n;

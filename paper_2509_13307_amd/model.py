@@ -40,6 +40,7 @@ class Model:
         self.kind = desc["kind"]
         self.d = int(desc["d"])
         self.device = device
+        self.n_data = 0
         D = C.ModelDesc()
         D.kind = C.KINDS[self.kind]
         D.d = self.d
@@ -59,6 +60,7 @@ class Model:
             D.nets = ctypes.cast(arr, ctypes.POINTER(C.NetDesc))
             data = _f64(desc["data"])
             D.n_data = data.size
+            self.n_data = int(data.size)
             D.data = self._p(data, C.c_double_p)
             if self.kind in ("cmb_diag", "cmb_block", "cmb_cv"):
                 D.spec_log = self._p(_i32([int(x) for x in desc["spec_log"]]), C.c_int32_p)
@@ -134,6 +136,16 @@ class Model:
             out = torch.empty(B, dtype=torch.float64, device=theta.device)
         C.check(C.lib().ns_loglike_batch(self._h, _ptr(theta), theta.stride(0), B, _ptr(out),
                                          C.PRECISIONS[precision], _stream()))
+        return out
+
+    def theory(self, theta, precision="fp64"):
+        """Theory vector [B, n_data] (float64 device tensor) of theta [B, >= d]:
+        the prediction the likelihood compares with the data, in data order."""
+        self._check_theta(theta)
+        B = theta.shape[0]
+        out = torch.empty(B, self.n_data, dtype=torch.float64, device=theta.device)
+        C.check(C.lib().ns_theory_batch(self._h, _ptr(theta), theta.stride(0), B, _ptr(out), self.n_data,
+                                        C.PRECISIONS[precision], _stream()))
         return out
 
     def loglike_grad(self, theta, precision="fp64"):

@@ -26,7 +26,7 @@ def capi():
 
 def test_header_declares_the_boundary():
     fns = declared_functions()
-    for name in ("ns_loglike_batch", "ns_loglike_grad_batch", "ns_slice_step", "ns_run", "ns_hmc",
+    for name in ("ns_loglike_batch", "ns_loglike_grad_batch", "ns_theory_batch", "ns_slice_step", "ns_run", "ns_hmc",
                  "ns_model_create", "ns_model_free", "ns_last_error", "ns_prior_transform"):
         assert name in fns
 
@@ -44,6 +44,7 @@ def test_argument_validation_without_device(capi):
     assert lib.ns_model_create(None, 0, ctypes.byref(out)) == capi.NS_E_INVALID
     assert b"desc" in lib.ns_last_error()
     assert lib.ns_loglike_batch(None, None, 6, 10, None, 0, None) == capi.NS_E_INVALID
+    assert lib.ns_theory_batch(None, None, 6, 10, None, 100, 0, None) == capi.NS_E_INVALID
     assert lib.ns_model_free(None) == capi.NS_OK
     assert lib.ns_last_error() == b""
     assert lib.ns_run(None, None, None, None, None, None, 0, None) == capi.NS_E_INVALID
