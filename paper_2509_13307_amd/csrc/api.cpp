@@ -400,6 +400,10 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         for (int j = 0; j < na; ++j) a[j] = 1.0 + j * step;
         a[na - 1] = D->a_min;
         upload(m->agrid_d, a.data(), a.size());
+        std::vector<double> la(2 * (size_t)na, 0.0);
+        for (int j = 0; j < na; ++j) la[j] = std::log(a[j]);
+        for (int j = 0; j + 1 < na; ++j) la[na + j] = std::log(0.5 * (a[j] + a[j + 1]));
+        upload(m->lna_d, la.data(), la.size());
         const double zmax = 1.0 / D->a_min - 1.0;
         const double hz = zmax / (nz - 1);
         std::vector<double> zn(nz);

@@ -141,6 +141,7 @@ struct ns_model {
     std::vector<double> pfix;
     nsmi::DevBuf pidx_d, pfix_d, nz_mean_d;
     nsmi::DevBuf agrid_d;            // a_j [n_a]
+    nsmi::DevBuf lna_d;              // ln a_j [n_a], then ln of the interval midpoints [n_a - 1]
     nsmi::DevBuf zsp_idx_d;          // int [n_a]: spline interval of z_j
     nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t));
                                      // linear z: (1-t, t, 0, 0)

@@ -6,7 +6,7 @@
 //                  conditions on a uniform grid, the interior (1, 4, 1)
 //                  system is solved by a Thomas sweep, M_0 and M_{N-1} are
 //                  linear extrapolations.
-// shear_windows_kernel  one workgroup per walker, nodes in chunks of 256:
+// shear_windows_kernel  one workgroup per walker, one wave per bin for (b):
 //                  (a) background on the a-grid: E(a), chi by per-interval
 //                      Simpson, J = dchi/d(-a), growth D (growth index 0.55);
 //                  (b) n_i(z) with photo-z shifts (normalised by the trapezoid
@@ -96,174 +96,213 @@ __global__ __launch_bounds__(64) void zspline_kernel(const T* __restrict__ Y, T*
     mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
 }
 
-// shear_windows_kernel: one workgroup (256 threads) per walker, the n_a nodes
-// in chunks of 256 (one node per thread).  E(a_j) and the growth integrand at
-// every node go to LDS first, so that each Simpson interval evaluates only its
-// midpoint; a forward pass then builds chi and -ln D by prefix sums.  The
-// reverse pass (last chunk first) builds the windows from unnormalised n_i(z)
-// (reverse cumulative trapezoids carried from chunk to chunk) and sums the
-// n(z) normalisations on the way; the windows are linear in n_i, so the
-// normalisations are applied to the spectra.  Output per walker: W_i(a_j)
-// sqrt(q_j J_j / chi_j^2) [nb][n_a] (the Limber integrand is the product of
-// two of them and P), log10 chi_j [n_a], normalisations [nb].
-template <class T, int NB>
-__global__ __launch_bounds__(256) void shear_windows_kernel(
+// shear_windows_kernel: one workgroup (256 threads) per walker, in four
+// phases over the n_a nodes.  Per-node values live in LDS in lane-major order:
+// with k = ceil(n_a / 64), node j sits at (j mod k) 64 + j / k, so lane l of a
+// wave that owns the consecutive nodes l k .. l k + k - 1 reads them without
+// bank conflicts, and every running sum below is a serial pass over k nodes
+// in registers plus one wave-wide scan of the 64 lane totals.
+// (1) every thread: E(a), f = dchi/d(-a) = c / (H0 a^2 E) and the growth
+//     integrand Om(a)^0.55 / a at its nodes, then at the midpoints of its
+//     intervals, giving the Simpson increments of chi and of -ln D; powers of
+//     a come from the model's ln a_j and ln a_mid tables (one exp each);
+// (2) waves 0 and 1: exclusive prefix sums of the two increments, in place
+//     (chi_j and -ln D_j);
+// (3) every thread: the per-node factors of the windows; log10 chi_j out;
+// (4) one wave per tomographic bin (bins i, i + 4, ...): unnormalised n_i(z_j),
+//     the reverse cumulative trapezoids G0, G1 (a first pass for the lane
+//     totals, a suffix scan over the lanes, a second pass that carries the
+//     sums down the lane's nodes), and W_i = W^g_i + W^I_i
+//     (Eqs. (A3), (A4)) times sqrt(q_j J_j / chi_j^2); the n_i normalisation
+//     is summed on the way.
+// The windows are linear in n_i, so the normalisations are applied to the
+// spectra.  Output per walker: the scaled windows [nb][n_a] (the Limber
+// integrand is the product of two of them and P), log10 chi_j [n_a] and the
+// normalisations [nb].
+template <class T, int KMAX>
+__global__ __launch_bounds__(256, 2) void shear_windows_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, ShearGeom G,
     const int* __restrict__ pidx, const double* __restrict__ pfix, const double* __restrict__ nz_mean,
-    const double* __restrict__ agrid, T* __restrict__ Wout, double* __restrict__ lchi_out,
-    double* __restrict__ norm_out, const int* __restrict__ count) {
+    const double* __restrict__ agrid, const double* __restrict__ lna, T* __restrict__ Wout,
+    double* __restrict__ lchi_out, double* __restrict__ norm_out, const int* __restrict__ count) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (count) B = min<int64_t>(B, *count);
     const int64_t w = blockIdx.x;
     if (w >= B) return;
+    constexpr int NW = 4;                     // waves (blockDim 256)
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int na = G.n_a, nb = G.n_bins;
-    const int nch = (na + 255) / 256, nap = nch * 256 + 1;
-    double* buf = reinterpret_cast<double*>(smem);                    // [2 MAXB][4] block_scan totals
-    double* red = buf + 2 * MAXB * 4;                                 // [MAXB][4]
-    double* bc = red + MAXB * 4;                                      // [2 MAXB] next carry (thread 0)
-    double* gcs = bc + 2 * MAXB;                                      // [2 MAXB] sums over the chunks above
-    double* mus = gcs + 2 * MAXB;                                     // [MAXB] n(z) means
-    double* gnx = mus + MAXB;                                         // [2 MAXB] g0, g1 of the node above the chunk
-    double* xw = gnx + 2 * MAXB;                                      // [4][2 MAXB] wave-boundary exchange
-    double* chis = xw + 4 * 2 * MAXB;                                 // [nap]
-    double* lnDs = chis + nap;                                        // [nap]
-    double* EA = lnDs + nap;                                          // [nap] E(a_j)
-    double* GA = EA + nap;                                            // [nap] growth integrand at a_j
+    const int k = (na + 63) >> 6, L = 64 * k;
+    double* S0 = reinterpret_cast<double*>(smem);
+    double* S1 = S0 + L;
+    double* S2 = S1 + L;
+    double* S3 = S2 + L;
+    double* S4 = S3 + L;
+    double* S5 = S4 + L;
 
     auto phys = [&](int slot) { const int ix = pidx[slot]; return ix >= 0 ? theta[w * ld + ix] : pfix[slot]; };
     const double ob = phys(0), oc = phys(1), h = phys(2), w0 = phys(5), wa = phys(6);
     const double Om = (ob + oc) / (h * h);
     const double cH0 = C_KM_S / (100.0 * h), H0c = 1.0 / cH0;
-    auto Efn = [&](double a) {
-        return sqrt(Om / (a * a * a) + (1.0 - Om) * pow(a, -3.0 * (1.0 + w0 + wa)) * exp(-3.0 * wa * (1.0 - a)));
+    const double pde = -3.0 * (1.0 + w0 + wa);
+    // E, f and the growth integrand at scale factor a (ln a given)
+    auto bg = [&](double a, double la, double& E, double& f, double& g) {
+        const double ia = 1.0 / a, ia2 = ia * ia, ia3 = ia2 * ia;
+        const double E2 = Om * ia3 + (1.0 - Om) * exp(pde * la - 3.0 * wa * (1.0 - a));
+        E = sqrt(E2);
+        f = cH0 * ia2 / E;
+        g = exp(GROWTH_INDEX * log(Om * ia3 / E2)) * ia;
     };
-    if (t < MAXB) mus[t] = t < nb ? nz_mean[t] + phys(9 + nb + t) : 0.0;
-    if (t < 2 * MAXB) gnx[t] = gcs[t] = bc[t] = 0.0;
-    if (t == 0) chis[0] = lnDs[0] = 0.0;
-    for (int j = t; j < na; j += 256) {
-        const double a = agrid[j], E = Efn(a);
-        EA[j] = E;
-        GA[j] = pow(Om / (a * a * a) / (E * E), GROWTH_INDEX) / a;
+
+    // (1) S0 E_j, S1 f_j, S2 growth integrand; S3, S4 the Simpson increments
+    // of the interval [j, j+1] (0 for the last node)
+    // (threads walk the positions p = r 64 + l, node j = l k + r; at most
+    // KMAX / 4 per thread, unrolled so that their exp / log chains overlap)
+    constexpr int U = (KMAX + 3) / 4;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = t + 256 * u;
+        const int j = (p & 63) * k + (p >> 6);
+        if (p >= L || j >= na) continue;
+        double E, f, g;
+        bg(agrid[j], lna[j], E, f, g);
+        S0[p] = E;
+        S1[p] = f;
+        S2[p] = g;
     }
     __syncthreads();
-    const double s2 = 2.0 * G.nz_sigma * G.nz_sigma;
-
-    // forward pass: Simpson increments of chi and -ln D on [a_j, a_{j+1}];
-    // chis[j] / lnDs[j] = sums over intervals 0..j-1
-    double carry0 = 0.0, carry1 = 0.0;
-    for (int c = 0; c < nch; ++c) {
-        const int j = c * 256 + t;
-        double inc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = t + 256 * u;
+        const int r = p >> 6, j = (p & 63) * k + r;
+        if (p >= L || j >= na) continue;
+        double ic = 0.0, id = 0.0;
         if (j < na - 1) {
-            const double a = agrid[j], a1 = agrid[j + 1], am = 0.5 * (a + a1);
-            const double Em = Efn(am);
-            const double fm = cH0 / (am * am * Em);
-            const double gm = pow(Om / (am * am * am) / (Em * Em), GROWTH_INDEX) / am;
-            inc[0] = G.da / 6.0 * (cH0 / (a * a * EA[j]) + 4.0 * fm + cH0 / (a1 * a1 * EA[j + 1]));
-            inc[1] = G.da / 6.0 * (GA[j] + 4.0 * gm + GA[j + 1]);
+            double E, f, g;
+            bg(0.5 * (agrid[j] + agrid[j + 1]), lna[na + j], E, f, g);
+            const int p1 = r + 1 < k ? p + 64 : (p & 63) + 1;     // node j + 1
+            ic = G.da / 6.0 * (S1[p] + 4.0 * f + S1[p1]);
+            id = G.da / 6.0 * (S2[p] + 4.0 * g + S2[p1]);
         }
-        block_scan<2>(inc, buf, false);
-        chis[j + 1] = carry0 + inc[0];
-        lnDs[j + 1] = carry1 + inc[1];
-        __syncthreads();
-        carry0 = chis[c * 256 + 256];
-        carry1 = lnDs[c * 256 + 256];
-    }
-
-    // reverse pass over the chunks
-    double nsum[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) nsum[i] = 0.0;
-    for (int c = nch - 1; c >= 0; --c) {
-        const int j = c * 256 + t;
-        const bool node = j < na;
-        const double a = node ? agrid[j] : 1.0;
-        const double Ea = node ? EA[j] : 1.0;
-        const double fa = cH0 / (a * a * Ea);
-        const double chi = node ? chis[j] : 0.0;
-        const double D = exp(-(node ? lnDs[j] : 0.0));
-        const double z = 1.0 / a - 1.0;
-        const double q = (j == 0 || j == na - 1) ? 0.5 * G.da : G.da;
-        // unnormalised n_i(z_j); integrands of G0, G1 at this node
-        double nr[NB], g0[NB], g1[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            if (i >= nb) { nr[i] = g0[i] = g1[i] = 0.0; continue; }
-            const double dz = z - mus[i];
-            nr[i] = (node && j > 0) ? exp(-dz * dz / s2) : 0.0;
-            nsum[i] += q * nr[i] / (a * a);
-            g0[i] = node ? nr[i] / (a * a) : 0.0;
-            g1[i] = (node && j > 0) ? nr[i] / (a * a * chi) : 0.0;
-        }
-        // trapezoid segment [j, j+1]: node j+1 from the next lane, the next
-        // wave (through LDS) or the chunk above (gnx)
-        if (lane == 0)
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                xw[wid * 2 * MAXB + i] = g0[i];
-                xw[wid * 2 * MAXB + MAXB + i] = g1[i];
-            }
-        __syncthreads();
-        double seg[2 * NB];
-        const bool has = node && j < na - 1;
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            double n0 = __shfl_down(g0[i], 1, 64), n1 = __shfl_down(g1[i], 1, 64);
-            if (lane == 63) {
-                const double* src = wid < 3 ? xw + (wid + 1) * 2 * MAXB : gnx;
-                n0 = src[i];
-                n1 = src[MAXB + i];
-            }
-            seg[i] = (has && i < nb) ? 0.5 * G.da * (g0[i] + n0) : 0.0;
-            seg[NB + i] = (has && i < nb) ? 0.5 * G.da * (g1[i] + n1) : 0.0;
-        }
-        __syncthreads();
-        if (t == 0)
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                gnx[i] = g0[i];
-                gnx[MAXB + i] = g1[i];
-            }
-        block_scan<2 * NB>(seg, buf, true);        // sum over the chunk's segments m >= j
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            seg[k] += gcs[k];
-            seg[NB + k] += gcs[MAXB + k];
-        }
-        if (t == 0)
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                bc[k] = seg[k];
-                bc[MAXB + k] = seg[NB + k];
-            }
-        const double pref = 1.5 * Om * H0c * H0c * chi / a;
-        const double sw = (node && j > 0) ? sqrt(q * fa / (chi * chi)) : 0.0;
-        if (node) {
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                if (i >= nb) continue;
-                const double Wg = pref * (seg[i] - chi * seg[NB + i]);
-                const double AIA = phys(9 + i);
-                const double WI = -AIA * C1_RHOCR * Om * nr[i] * H0c * Ea / D;
-                Wout[(w * nb + i) * na + j] = (T)((Wg + WI) * sw);
-            }
-            lchi_out[w * na + j] = j > 0 ? log10(chi) : 0.0;
-        }
-        __syncthreads();
-        if (t == 0)
-#pragma unroll
-            for (int k = 0; k < 2 * MAXB; ++k) gcs[k] = bc[k];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        if (i >= nb) continue;
-        const double v = wave_sum(nsum[i]);
-        if (lane == 0) red[i * 4 + wid] = v;
+        S3[p] = ic;
+        S4[p] = id;
     }
     __syncthreads();
-    if (t < nb) norm_out[w * nb + t] = red[t * 4] + red[t * 4 + 1] + red[t * 4 + 2] + red[t * 4 + 3];
+    // (2) S3 <- chi_j, S4 <- -ln D_j (sums over the intervals below j)
+    if (wid < 2) {
+        double* X = wid == 0 ? S3 : S4;
+        double run = 0.0;
+        for (int r = 0; r < k; ++r)
+            if (lane * k + r < na) {
+                const double x = X[r * 64 + lane];
+                X[r * 64 + lane] = run;
+                run += x;
+            }
+        double inc = run;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
+        }
+        const double up = __shfl_up(inc, 1, 64), ex = lane > 0 ? up : 0.0;
+        for (int r = 0; r < k; ++r)
+            if (lane * k + r < na) X[r * 64 + lane] += ex;
+    }
+    __syncthreads();
+    // (3) per-node factors, in place: S0 z_j, S1 1/a^2, S2 1/(a^2 chi),
+    // S3 sw pref, S4 sw pref chi, S5 sw wI; sw = sqrt(q f / chi^2),
+    // pref = (3/2) Om (H0/c)^2 chi / a, wI = -C1 rho_cr Om (H0/c) E / D
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = t + 256 * u;
+        const int j = (p & 63) * k + (p >> 6);
+        if (p >= L || j >= na) continue;
+        const double a = agrid[j], E = S0[p], f = S1[p], chi = S3[p], D = exp(-S4[p]);
+        const double ia = 1.0 / a, ia2 = ia * ia;
+        const double q = (j == 0 || j == na - 1) ? 0.5 * G.da : G.da;
+        const bool in = j > 0;
+        const double sw = in ? sqrt(q * f / (chi * chi)) : 0.0;
+        const double pref = 1.5 * Om * H0c * H0c * chi * ia;
+        S0[p] = ia - 1.0;
+        S1[p] = ia2;
+        S2[p] = in ? ia2 / chi : 0.0;
+        S3[p] = sw * pref;
+        S4[p] = sw * pref * chi;
+        S5[p] = -sw * C1_RHOCR * Om * H0c * E / D;
+        lchi_out[w * na + j] = in ? log10(chi) : 0.0;
+    }
+    __syncthreads();
+    // (4) one wave per bin; lane l owns nodes l k + r, r < k <= KMAX, its
+    // n_i values held in registers between the two passes
+    const double is2 = 1.0 / (2.0 * G.nz_sigma * G.nz_sigma), hda = 0.5 * G.da;
+    const int j0 = lane * k;
+    for (int i = wid; i < nb; i += NW) {
+        const double mu = nz_mean[i] + phys(9 + nb + i), AIA = phys(9 + i);
+        double nrv[KMAX];
+#pragma unroll
+        for (int r = 0; r < KMAX; ++r) {      // unnormalised n_i(z_j), 0 at z = 0
+            const int j = j0 + r;
+            double v = 0.0;
+            if (r < k && j > 0 && j < na) {
+                const double dz = S0[r * 64 + lane] - mu;
+                v = exp(-dz * dz * is2);
+            }
+            nrv[r] = v;
+        }
+        // integrands at the first node of the next lane
+        const double f0 = j0 < na ? nrv[0] * S1[lane] : 0.0, f1 = j0 < na ? nrv[0] * S2[lane] : 0.0;
+        double n0 = __shfl_down(f0, 1, 64), n1 = __shfl_down(f1, 1, 64);
+        if (lane == 63) n0 = n1 = 0.0;
+        // lane totals of the trapezoid segments [j, j+1], and the normalisation
+        double tot0 = 0.0, tot1 = 0.0, nsum = 0.0, x0 = n0, x1 = n1;
+#pragma unroll
+        for (int r = KMAX - 1; r >= 0; --r) {
+            const int j = j0 + r, p = r * 64 + lane;
+            if (r >= k) continue;
+            double g0 = 0.0, g1 = 0.0;
+            if (j < na) {
+                g0 = nrv[r] * S1[p];
+                g1 = nrv[r] * S2[p];
+                nsum += (j == na - 1 ? hda : G.da) * g0;
+                if (j < na - 1) {
+                    tot0 += hda * (g0 + x0);
+                    tot1 += hda * (g1 + x1);
+                }
+            }
+            x0 = g0;
+            x1 = g1;
+        }
+        // sums over the nodes of the lanes above
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double y0 = __shfl_down(tot0, off, 64), y1 = __shfl_down(tot1, off, 64);
+            if (lane + off < 64) {
+                tot0 += y0;
+                tot1 += y1;
+            }
+        }
+        double c0 = __shfl_down(tot0, 1, 64), c1 = __shfl_down(tot1, 1, 64);
+        if (lane == 63) c0 = c1 = 0.0;
+        T* Wo = Wout + (w * nb + i) * na;
+        x0 = n0;
+        x1 = n1;
+#pragma unroll
+        for (int r = KMAX - 1; r >= 0; --r) {
+            const int j = j0 + r, p = r * 64 + lane;
+            if (r >= k || j >= na) continue;
+            const double nr = nrv[r];
+            const double g0 = nr * S1[p], g1 = nr * S2[p];
+            if (j < na - 1) {
+                c0 += hda * (g0 + x0);
+                c1 += hda * (g1 + x1);
+            }
+            Wo[j] = (T)(S3[p] * c0 - S4[p] * c1 + AIA * S5[p] * nr);
+            x0 = g0;
+            x1 = g1;
+        }
+        const double v = wave_sum(nsum);
+        if (lane == 0) norm_out[w * nb + i] = v;
+    }
 }
 
 // limber_sum_kernel: one workgroup (256 threads) per (walker, chunk of 256
@@ -562,10 +601,7 @@ ShearGeom shear_geom(const ns_model* m) {
     return G;
 }
 
-static size_t windows_smem(const ns_model* m) {
-    const size_t nap = (m->n_a + 255) / 256 * 256 + 1;
-    return (2 * MAXB * 4 + MAXB * 4 + 2 * MAXB + 2 * MAXB + MAXB + 2 * MAXB + 4 * 2 * MAXB + 4 * nap) * sizeof(double);
-}
+static size_t windows_smem(const ns_model* m) { return 6 * 64 * (size_t)((m->n_a + 63) / 64) * sizeof(double); }
 
 static int limber_lb(const ns_model* m) { return m->n_ell <= 20 ? 20 : 32; }
 
@@ -610,10 +646,14 @@ static void launch_limber(ns_model* m, const double* theta, int64_t ld, int64_t 
     NS_CHECK(sm1 <= 160 * 1024 && sm2 <= 160 * 1024, NS_E_UNSUPPORTED, "Limber stage needs more LDS than a workgroup has");
     {
         TraceScope ts(m, s, "shear_windows");
-        auto kern = nb <= 5 ? shear_windows_kernel<T, 5> : shear_windows_kernel<T, MAXB>;
+        // nodes per lane k = ceil(n_a / 64) <= 32, bounded by the kernel's KMAX
+        const int k = (na + 63) / 64;
+        auto kern = k <= 4 ? shear_windows_kernel<T, 4>
+                           : (k <= 8 ? shear_windows_kernel<T, 8>
+                                     : (k <= 20 ? shear_windows_kernel<T, 20> : shear_windows_kernel<T, 32>));
         hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), sm1, s, theta, ld, B, G, m->pidx_d.as<int>(),
-                           m->pfix_d.as<double>(), m->nz_mean_d.as<double>(), m->agrid_d.as<double>(), Win, lchi,
-                           norm, count);
+                           m->pfix_d.as<double>(), m->nz_mean_d.as<double>(), m->agrid_d.as<double>(),
+                           m->lna_d.as<double>(), Win, lchi, norm, count);
         NS_HIP(hipGetLastError());
     }
     TraceScope ts(m, s, "limber");
@@ -637,9 +677,10 @@ double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, i
     const double zmax = 1.0 / m->a_min - 1.0;
     const double hz = zmax / (nz - 1);
     if (!m->shear_attr_set) {   // once per model, outside any stream capture
-        const void* fns[] = {(const void*)shear_windows_kernel<double, 5>, (const void*)shear_windows_kernel<float, 5>,
-                             (const void*)shear_windows_kernel<double, MAXB>,
-                             (const void*)shear_windows_kernel<float, MAXB>,
+        const void* fns[] = {(const void*)shear_windows_kernel<double, 4>, (const void*)shear_windows_kernel<float, 4>,
+                             (const void*)shear_windows_kernel<double, 8>, (const void*)shear_windows_kernel<float, 8>,
+                             (const void*)shear_windows_kernel<double, 20>, (const void*)shear_windows_kernel<float, 20>,
+                             (const void*)shear_windows_kernel<double, 32>, (const void*)shear_windows_kernel<float, 32>,
                              (const void*)limber_sum_kernel<double, false, 20>,
                              (const void*)limber_sum_kernel<double, false, 32>,
                              (const void*)limber_sum_kernel<double, true, 20>,
