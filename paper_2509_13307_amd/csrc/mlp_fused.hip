@@ -65,7 +65,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     constexpr int R = 32 * RT;             // rows per workgroup
     constexpr int HS = H + 8;              // LDS row stride of an activation plane (elements)
     constexpr int KC = H / 16;             // K steps of one GEMM layer
-    static_assert(KC % P == 0, "prefetch depth must divide the K steps");
+    static_assert(KC % P == 0 && P % 2 == 0, "prefetch depth must be even and divide the K steps");
     static_assert(NT % H == 0, "threads must be a multiple of the hidden width");
     extern __shared__ __attribute__((aligned(16))) uint16_t fm_lds[];
     uint16_t* hs = fm_lds;                 // [R][HS] hi (or only) plane
@@ -130,9 +130,10 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
 
     // ---- GEMM stages: hidden layers, then the output layer's H-wide column
     // blocks; stage s = (segment s / KC, K step s % KC).  Loads and MFMAs are
-    // unconditional (stages past the end re-read the last one, waves without
-    // a live unit in an output block compute on valid addresses and store
-    // nothing), so the weight prefetch stays in flight across iterations.
+    // unconditional within the live segments (stages past the end re-read the
+    // last one, the partly live last tile computes on valid addresses and
+    // stores its live units only), so the weight prefetch stays in flight
+    // across iterations.
     const int ncb = (N_out + H - 1) / H;
     const int S = (n_hidden + ncb) * KC;
     // fragment block (kc, nt) of a layer with nt_l 32-unit tiles sits at
@@ -169,11 +170,28 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     // here keeps that order out of the K-step loop's load accounting
     __builtin_amdgcn_s_waitcnt(0x0F70);
 
+    // A operands (activation fragments) of one K step, double-buffered: the
+    // LDS reads of step kc + 1 are issued before the MFMAs of step kc
+    bf16x8_t ah[2][RT], al[2][RT];
+    auto read_a = [&](int kc, bf16x8_t (&xh)[RT], bf16x8_t (&xl)[RT]) {
+        const int koff = kc * 16 + (lane >> 5) * 8;
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            xh[i] = *reinterpret_cast<const bf16x8_t*>(&hs[(i * 32 + (lane & 31)) * HS + koff]);
+            if (X3) xl[i] = *reinterpret_cast<const bf16x8_t*>(&hl[(i * 32 + (lane & 31)) * HS + koff]);
+        }
+    };
+
     // one segment (layer or output column block) per iteration; the K steps
     // run in their own loop, so no epilogue path joins the steady state
     for (int seg = 0; seg < n_hidden + ncb; ++seg) {
         const bool hid = seg < n_hidden;
         const int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
+        // a wave whose units of this output block all lie past N_out has none
+        // in the later blocks either, and no barrier follows the hidden
+        // layers: it stops here and leaves the matrix pipe to the live waves
+        if (!hid && nb >= N_out) break;
+        read_a(0, ah[0], al[0]);
         for (int kc0 = 0; kc0 < KC; kc0 += P) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
@@ -182,28 +200,33 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                 const int kc = kc0 + u;
                 const bf16x8_t (&bh)[CT] = rh[u];
                 const bf16x8_t (&bl)[CT] = rl[u];
-                const int koff = kc * 16 + (lane >> 5) * 8;
-                bf16x8_t ah[RT], al[RT];
-#pragma unroll
-                for (int i = 0; i < RT; ++i) {
-                    ah[i] = *reinterpret_cast<const bf16x8_t*>(&hs[(i * 32 + (lane & 31)) * HS + koff]);
-                    if (X3) al[i] = *reinterpret_cast<const bf16x8_t*>(&hl[(i * 32 + (lane & 31)) * HS + koff]);
-                }
+                // P is even, so kc and u have the same parity; the last step
+                // of a segment re-reads its own fragments (nothing is waiting
+                // for the next segment's input yet)
+                read_a(min(kc + 1, KC - 1), ah[(u + 1) & 1], al[(u + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                const bf16x8_t (&xh)[RT] = ah[u & 1];
+                const bf16x8_t (&xl)[RT] = al[u & 1];
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
 #pragma unroll
                     for (int j = 0; j < CT; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh[j], acc[i][j], 0, 0, 0);
                 if (X3) {
 #pragma unroll
                     for (int i = 0; i < RT; ++i)
 #pragma unroll
                         for (int j = 0; j < CT; ++j) {
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh[j], acc[i][j], 0, 0, 0);
                         }
                 }
                 fetch(seg * KC + kc + P, rh[u], rl[u]);
+                // keep the refill right behind the MFMAs that read the slot:
+                // left to itself the scheduler sinks these loads to the end of
+                // the unrolled steps, next to their first use, and the
+                // prefetch distance collapses to a few instructions
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         // ---- epilogue of a finished segment
