@@ -154,8 +154,7 @@ __global__ void prior_transform_kernel(const double* __restrict__ u, double* __r
     const int64_t row = i / d;
     const int c = (int)(i % d);
     const double x = u[row * ld + c];
-    theta[row * ld + c] = pk[c] == NS_PRIOR_UNIFORM ? pa[c] + (pb[c] - pa[c]) * x
-                                                    : pa[c] + pb[c] * 1.4142135623730950488 * erfinv(2.0 * x - 1.0);
+    theta[row * ld + c] = prior_map(x, pk[c], pa[c], pb[c]);
 }
 
 void prior_transform(ns_model* m, const double* u, double* theta, int64_t ld, int64_t B,

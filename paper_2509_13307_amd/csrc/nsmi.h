@@ -270,6 +270,14 @@ void theory_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doubl
 void prior_transform(ns_model* m, const double* u, double* theta, int64_t ld, int64_t B,
                      const int* count, hipStream_t s);
 
+// Parameter from its unit-cube coordinate x (the priors of Table 1): uniform
+// on [a, b], or normal with mean a and standard deviation b.  Shared by the
+// prior-transform kernel and the slice sampler, which maps its proposals as
+// it writes them.
+__device__ __forceinline__ double prior_map(double x, int kind, double a, double b) {
+    return kind == NS_PRIOR_UNIFORM ? a + (b - a) * x : a + b * 1.4142135623730950488 * erfinv(2.0 * x - 1.0);
+}
+
 // Name of candidate c of the one-kernel forward (width 512 or 128, split form or not).
 const char* fused_cfg_name(int h512, int x3, int c);
 

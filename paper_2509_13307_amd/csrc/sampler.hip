@@ -13,13 +13,19 @@
 //
 // The walkers advance in rounds: slice_advance_kernel applies the previous
 // round's likelihood values and runs every walker forward until it needs a
-// new evaluation, appending that proposal to a compacted batch; the batched
-// likelihood then runs on the compacted rows only.  Every random number is
-// addressed by (walker, step, draw), so the result does not depend on the
-// order of the compacted rows.
+// new evaluation, appending that proposal (in the cube and mapped through the
+// prior) to a compacted batch; the batched likelihood then runs on the
+// compacted rows only.  The batch size and the count of unfinished walkers
+// live in two counter pairs used by rounds of alternating parity, so each
+// round's advance clears the pair of the next round and no separate reset
+// launch is needed.  Every random number is addressed by (walker, step,
+// draw), so the result does not depend on the order of the compacted rows.
 //
-// Nested-sampling bookkeeping (k-deletion, evidence in FP64) runs in
-// single-workgroup kernels; the host only polls a termination flag.
+// Nested-sampling bookkeeping (k-deletion, the running evidence) runs in
+// single-workgroup kernels; the host only polls a termination flag.  The
+// final log Z, H and the replicate log Z for the error bar (FP64) are
+// parallel over the dead points: prefix sums of the log-shrinkages, then a
+// max-shifted sum of exponentials.
 #include "devutil.h"
 #include "nsmi.h"
 
@@ -48,25 +54,22 @@ struct SliceState {
     double* xc;       // [k x d] compacted proposals (unit cube)
     int* cidx;        // [k] walker of each compact slot
     double* llc;      // [k] likelihood of each compact slot
-    int* ccount;      // compact batch size
-    int* active;      // walkers not done after the last advance
+    int* ccount;      // [2] compact batch size of the rounds of even / odd parity
+    int* active;      // [2] walkers not done after the advance of such a round
 };
 
 __global__ void slice_init_kernel(SliceState S, int64_t k) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w == 0) {
+        S.ccount[0] = S.ccount[1] = 0;
+        S.active[0] = S.active[1] = 0;
+    }
     if (w >= k) return;
     S.st[w] = ST_NEWSTEP;
     S.step[w] = 0;
     S.pend[w] = -1;
     S.n_evals[w] = 0;
     S.n_stalls[w] = 0;
-}
-
-__global__ void slice_reset_kernel(SliceState S) {
-    if (threadIdx.x == 0) {
-        *S.ccount = 0;
-        *S.active = 0;
-    }
 }
 
 // One wave per walker, lane i = coordinate i (d <= 64).  The walker's phase
@@ -77,9 +80,18 @@ __global__ void slice_reset_kernel(SliceState S) {
 __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_t k, int d,
                                                             const double* __restrict__ lstar_p,
                                                             const double* __restrict__ L, int n_inner,
-                                                            uint64_t seed, uint64_t iter) {
+                                                            uint64_t seed, uint64_t iter, int par,
+                                                            const int* __restrict__ pk, const double* __restrict__ pa,
+                                                            const double* __restrict__ pb,
+                                                            double* __restrict__ thc) {
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the counters of the other parity were last read by the previous round's
+    // likelihood, which has finished: clear them for the next round
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S.ccount[par ^ 1] = 0;
+        S.active[par ^ 1] = 0;
+    }
     if (w >= k) return;                                   // whole waves
     const bool act = lane < d;
     const double lstar = *lstar_p;
@@ -162,9 +174,12 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             continue;
         }
         int slot = 0;
-        if (lane == 0) slot = atomicAdd(S.ccount, 1);
+        if (lane == 0) slot = atomicAdd(S.ccount + par, 1);
         slot = __shfl(slot, 0, 64);
-        if (act) S.xc[(int64_t)slot * d + lane] = xi;
+        if (act) {
+            S.xc[(int64_t)slot * d + lane] = xi;
+            thc[(int64_t)slot * d + lane] = prior_map(xi, pk[lane], pa[lane], pb[lane]);
+        }
         if (lane == 0) S.cidx[slot] = (int)w;
         pend = slot;
         break;
@@ -177,7 +192,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
         S.st[w] = st; S.step[w] = step; S.q[w] = q; S.ne[w] = ne; S.pend[w] = pend;
         S.n_evals[w] = nev; S.n_stalls[w] = nst;
         S.tl[w] = tl; S.tr[w] = tr; S.tp[w] = tp; S.logl[w] = logl;
-        if (st != ST_DONE) atomicAdd(S.active, 1);
+        if (st != ST_DONE) atomicAdd(S.active + par, 1);
     }
 }
 
@@ -201,7 +216,7 @@ __device__ __forceinline__ double logaddexp(double a, double b) {
 }
 
 // Bitonic sort of (logl, index) for n <= 4096 in one workgroup of 1024 threads;
-// then the k lowest die: evidence update and dead-point records (serial, FP64).
+// then the k lowest die: dead-point records and the running evidence (FP64).
 __global__ __launch_bounds__(1024) void ns_select_kernel(const double* __restrict__ logl,
                                                          const double* __restrict__ u, int n, int k, int d,
                                                          int* __restrict__ order, NSState* __restrict__ S,
@@ -244,19 +259,34 @@ __global__ __launch_bounds__(1024) void ns_select_kernel(const double* __restric
         const int j = e / d, c = e % d;
         if (base + j < dead_cap) dead_u[(base + j) * d + c] = u[(int64_t)idx[j] * d + c];
     }
-    if (threadIdx.x == 0) {
-        double logx = S->logx, logz = S->logz;
-        for (int j = 0; j < k; ++j) {
-            const double nj = (double)(n - j);
-            const double l = key[j];
-            const double logw = logx + log(-expm1(-1.0 / nj));
-            logz = logaddexp(logz, l + logw);
-            logx -= 1.0 / nj;
-            if (base + j < dead_cap) {
-                dead_logl[base + j] = l;
-                dead_n[base + j] = n - j;
-            }
+    for (int j = threadIdx.x; j < k; j += blockDim.x)
+        if (base + j < dead_cap) {
+            dead_logl[base + j] = key[j];
+            dead_n[base + j] = n - j;
         }
+    // The running log Z is the serial chain of log-additions in death order
+    // (the stopping rule reads it).  Its per-death terms 1/n_j and
+    // log(1 - e^{-1/n_j}) depend on the rank only: the workgroup tabulates
+    // them for a block of ranks, then one thread runs the chain over the block.
+    constexpr int QB = 512;
+    __shared__ double qinv[QB], qlog[QB];
+    double logx = S->logx, logz = S->logz;
+    for (int j0 = 0; j0 < k; j0 += QB) {
+        __syncthreads();
+        for (int j = j0 + threadIdx.x; j < min(k, j0 + QB); j += blockDim.x) {
+            const double inv = 1.0 / (double)(n - j);
+            qinv[j - j0] = inv;
+            qlog[j - j0] = log(-expm1(-inv));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int j = j0; j < min(k, j0 + QB); ++j) {
+                const double logw = logx + qlog[j - j0];
+                logz = logaddexp(logz, key[j] + logw);
+                logx -= qinv[j - j0];
+            }
+    }
+    if (threadIdx.x == 0) {
         S->logx = logx;
         S->logz = logz;
         S->lstar = key[k - 1];
@@ -383,45 +413,128 @@ __global__ void ns_final_kernel(const double* __restrict__ logl, const double* _
     if (threadIdx.x == 0) S->n_dead = base + n;
 }
 
-// log Z and H from the expected shrinkage, one workgroup, FP64.
-// out[0] = log Z, out[1] = H
-__global__ __launch_bounds__(256) void ns_evidence_kernel(const double* __restrict__ dl,
-                                                          const int* __restrict__ dn, int64_t M,
-                                                          double* __restrict__ out) {
-    if (threadIdx.x != 0) return;
-    double logx = 0.0, logz = -INFINITY;
-    for (int64_t i = 0; i < M; ++i) {
-        const double inv = 1.0 / dn[i];
-        logz = logaddexp(logz, dl[i] + logx + log(-expm1(-inv)));
-        logx -= inv;
+// Exclusive prefix sum of one value per thread over a workgroup of NT threads
+// (NT a multiple of 64, at most 1024): shuffle scans within the waves, then
+// the totals of the waves before (buf: NT / 64 doubles).
+template <int NT>
+__device__ double block_exclusive_sum(double x, double* buf) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
     }
-    logx = 0.0;
-    double H = 0.0;
-    for (int64_t i = 0; i < M; ++i) {
-        const double inv = 1.0 / dn[i];
-        const double lw = logx + log(-expm1(-inv));
-        if (isfinite(dl[i])) H += exp(dl[i] + lw - logz) * (dl[i] - logz);
-        logx -= inv;
-    }
-    out[0] = logz;
-    out[1] = H;
+    const double up = __shfl_up(inc, 1, 64);
+    __syncthreads();
+    if (lane == 63) buf[wid] = inc;
+    __syncthreads();
+    double pre = 0.0;
+    for (int w = 0; w < wid; ++w) pre += buf[w];
+    return pre + (lane > 0 ? up : 0.0);
 }
 
-// log Z of replicate shrinkage sequences log t_m = log(1 - U_m)/n_m (stream 1).
-__global__ void ns_replicates_kernel(const double* __restrict__ dl, const int* __restrict__ dn, int64_t M,
-                                     int R, uint64_t seed, double* __restrict__ out) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    double logx = 0.0, logz = -INFINITY;
-    for (int64_t m = 0; m < M; m += 4) {
-        const u64x4 b = philox4x64((uint64_t)(m >> 2), (uint64_t)r, 0, 0, seed, 1);
-        for (int e = 0; e < 4 && m + e < M; ++e) {
+// workgroup-wide maximum (buf: blockDim / 64 doubles)
+__device__ double block_max(double v, double* buf) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) buf[wid] = v;
+    __syncthreads();
+    double r = buf[0];
+    for (int w = 1; w < nw; ++w) r = fmax(r, buf[w]);
+    return r;
+}
+
+// log Z and H from the expected shrinkage log X_i = -sum_{m<i} 1/n_m (Eq. (1)
+// with the mean log-shrinkage per death), FP64, one workgroup of 1024
+// threads.  Thread t walks the contiguous run [t c, t c + c) of the M dead
+// points, c = ceil(M / 1024): the runs' sums of 1/n_m are scanned across the
+// workgroup to give log X at the start of each run, then
+// log Z = mx + log sum_i exp(L_i + log w_i - mx) with
+// log w_i = log X_{i-1} + log(1 - e^{-1/n_i}) and mx the largest term, and
+// H = sum_i p_i (L_i - log Z) over the finite L_i, p_i = e^{L_i + log w_i - log Z}.
+// out[0] = log Z, out[1] = H.
+__global__ __launch_bounds__(1024) void ns_evidence_kernel(const double* __restrict__ dl,
+                                                           const int* __restrict__ dn, int64_t M,
+                                                           double* __restrict__ out) {
+    __shared__ double buf[16];
+    const int64_t c = (M + 1023) / 1024;
+    const int64_t i0 = min<int64_t>(M, (int64_t)threadIdx.x * c), i1 = min<int64_t>(M, i0 + c);
+    double s = 0.0;
+    for (int64_t i = i0; i < i1; ++i) s += 1.0 / dn[i];
+    const double x0 = -block_exclusive_sum<1024>(s, buf);
+    // L_i + log w_i, advancing log X past point i
+    auto term = [&](int64_t i, double& logx) {
+        const double inv = 1.0 / dn[i];
+        const double v = dl[i] + (logx + log(-expm1(-inv)));
+        logx -= inv;
+        return v;
+    };
+    double logx = x0, mx = -INFINITY;
+    for (int64_t i = i0; i < i1; ++i) mx = fmax(mx, term(i, logx));
+    mx = block_max(mx, buf);
+    logx = x0;
+    double se = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double v = term(i, logx);
+        if (v > -INFINITY) se += exp(v - mx);
+    }
+    se = block_sum(se, buf);
+    const double logz = mx > -INFINITY ? mx + log(se) : -INFINITY;
+    logx = x0;
+    double h = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double v = term(i, logx);
+        if (isfinite(dl[i])) h += exp(v - logz) * (dl[i] - logz);
+    }
+    h = block_sum(h, buf);
+    if (threadIdx.x == 0) {
+        out[0] = logz;
+        out[1] = h;
+    }
+}
+
+// log Z of replicate shrinkage sequences log t_m = log(1 - U_m)/n_m (draw m
+// of replicate r, stream 1), one workgroup of 256 threads per replicate.
+// Thread t takes the run [t c, t c + c) of the dead points (c a multiple of 4:
+// one Philox block per 4 draws); the runs' sums of log t are scanned for
+// log X at the start of each run, then each thread keeps a running
+// (max, sum of exp) of L_m + log X_{m-1} + log(1 - t_m) and the pairs are
+// combined over the workgroup.
+__global__ __launch_bounds__(256) void ns_replicates_kernel(const double* __restrict__ dl,
+                                                            const int* __restrict__ dn, int64_t M, int R,
+                                                            uint64_t seed, double* __restrict__ out) {
+    __shared__ double buf[4];
+    const int r = blockIdx.x;
+    if (r >= R) return;                                   // whole workgroups
+    const int64_t c = ((M + 255) / 256 + 3) / 4 * 4;
+    const int64_t i0 = min<int64_t>(M, (int64_t)threadIdx.x * c), i1 = min<int64_t>(M, i0 + c);
+    auto draws = [&](int64_t m) { return philox4x64((uint64_t)(m >> 2), (uint64_t)r, 0, 0, seed, 1); };
+    double s = 0.0;
+    for (int64_t m = i0; m < i1; m += 4) {
+        const u64x4 b = draws(m);
+        for (int e = 0; e < 4 && m + e < i1; ++e) s += log1p(-u01(b.x[e])) / (double)dn[m + e];
+    }
+    double logx = block_exclusive_sum<256>(s, buf);
+    double mx = -INFINITY, se = 0.0;
+    for (int64_t m = i0; m < i1; m += 4) {
+        const u64x4 b = draws(m);
+        for (int e = 0; e < 4 && m + e < i1; ++e) {
             const double lt = log1p(-u01(b.x[e])) / (double)dn[m + e];
-            logz = logaddexp(logz, dl[m + e] + logx + log(-expm1(lt)));
+            const double v = dl[m + e] + (logx + log(-expm1(lt)));
             logx += lt;
+            if (v > mx) {
+                se = (mx > -INFINITY ? se * exp(mx - v) : 0.0) + 1.0;
+                mx = v;
+            } else if (v > -INFINITY) {
+                se += exp(v - mx);
+            }
         }
     }
-    out[r] = logz;
+    const double gm = block_max(mx, buf);
+    const double sc = block_sum(mx > -INFINITY ? se * exp(mx - gm) : 0.0, buf);
+    if (threadIdx.x == 0) out[r] = gm > -INFINITY ? gm + log(sc) : -INFINITY;
 }
 
 // ------------------------------------------------------------------ host side
@@ -447,7 +560,7 @@ __global__ __launch_bounds__(256) void ns_count_kernel(const int* __restrict__ n
 
 static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* logl, int* ne, int* ns) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t bytes = al(k * d * 8) * 2 + al(k * 8) * 4 + al(k * 4) * 6 + al(4) * 2;
+    const size_t bytes = al(k * d * 8) * 2 + al(k * 8) * 4 + al(k * 4) * 6 + al(8) * 2;
     m->ws_slice.ensure(bytes);
     char* p = m->ws_slice.as<char>();
     SliceState S;
@@ -464,8 +577,8 @@ static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* 
     S.ne = (int*)p; p += al(k * 4);
     S.pend = (int*)p; p += al(k * 4);
     S.cidx = (int*)p; p += al(k * 4);
-    S.ccount = (int*)p; p += al(4);
-    S.active = (int*)p; p += al(4);
+    S.ccount = (int*)p; p += al(8);
+    S.active = (int*)p; p += al(8);
     return S;
 }
 
@@ -488,19 +601,20 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
     const dim3 gw((unsigned)((k + 255) / 256));
     hipLaunchKernelGGL(slice_init_kernel, gw, dim3(256), 0, s, S, k);
     NS_HIP(hipGetLastError());
-    const int chunk = 16;
+    const int chunk = 16;                     // even: every chunk starts at parity 0
     const int64_t max_rounds = (int64_t)n_inner * (2 * MAX_EXPAND + MAX_SHRINK + 4) + 8;
     int64_t rounds = 0;
     auto rounds_chunk = [&](hipStream_t st) {
         for (int c = 0; c < chunk; ++c) {
+            // round c uses the counters of parity c & 1 (cleared by the round before)
+            const int par = c & 1;
             {
                 TraceScope ts(m, st, "slice_advance");
-                hipLaunchKernelGGL(slice_reset_kernel, dim3(1), dim3(64), 0, st, S);
                 hipLaunchKernelGGL(slice_advance_kernel, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, st, S, k, d,
-                                   lstar_dev, L, n_inner, seed, iter);
+                                   lstar_dev, L, n_inner, seed, iter, par, m->prior_kind.as<int>(),
+                                   m->prior_a.as<double>(), m->prior_b.as<double>(), thc);
             }
-            prior_transform(m, S.xc, thc, d, k, S.ccount, st);
-            loglike_batch(m, thc, d, k, S.llc, prec, S.ccount, st);
+            loglike_batch(m, thc, d, k, S.llc, prec, S.ccount + par, st);
         }
         NS_HIP(hipGetLastError());
     };
@@ -531,7 +645,7 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
             NS_HIP(hipGraphLaunch(exec, run));
         }
         rounds += chunk;
-        NS_HIP(hipMemcpyAsync(flag, S.active, sizeof(int), hipMemcpyDeviceToHost, run));
+        NS_HIP(hipMemcpyAsync(flag, S.active + ((chunk - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, run));
         NS_HIP(hipStreamSynchronize(run));
         if (*flag == 0) break;
         if (rounds >= max_rounds) {
@@ -633,9 +747,9 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
     const int64_t M = n_dead + n;
     const int R = o->n_replicates;
     ev.ensure((size_t)(2 + std::max(R, 1)) * 8);
-    hipLaunchKernelGGL(ns_evidence_kernel, dim3(1), dim3(64), 0, s, dl.as<double>(), dn.as<int>(), M, ev.as<double>());
+    hipLaunchKernelGGL(ns_evidence_kernel, dim3(1), dim3(1024), 0, s, dl.as<double>(), dn.as<int>(), M, ev.as<double>());
     if (R > 0)
-        hipLaunchKernelGGL(ns_replicates_kernel, dim3((unsigned)((R + 63) / 64)), dim3(64), 0, s, dl.as<double>(),
+        hipLaunchKernelGGL(ns_replicates_kernel, dim3((unsigned)R), dim3(256), 0, s, dl.as<double>(),
                            dn.as<int>(), M, R, o->seed, ev.as<double>() + 2);
     NS_HIP(hipGetLastError());
     std::vector<double> evh(2 + std::max(R, 1));
