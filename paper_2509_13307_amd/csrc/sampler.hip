@@ -295,22 +295,53 @@ __global__ __launch_bounds__(1024) void ns_select_kernel(const double* __restric
 }
 
 // Live-point covariance (1/(n-1)), trace jitter, Cholesky (lower, row-major).
+// The live points pass through LDS in chunks of whole points (coalesced
+// loads); each mean and each covariance entry is still one thread's sum over
+// the points in index order.
 __global__ __launch_bounds__(256) void ns_dircov_kernel(const double* __restrict__ u, int n, int d,
                                                         double* __restrict__ L) {
+    constexpr int STAGE = 3072;                            // doubles of staged points
+    constexpr int EPT = MAX_DIM * MAX_DIM / 256;           // covariance entries per thread at most
     __shared__ double mean[MAX_DIM];
     __shared__ double S[MAX_DIM * MAX_DIM];
-    for (int c = threadIdx.x; c < d; c += blockDim.x) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += u[(int64_t)i * d + c];
-        mean[c] = s / n;
+    __shared__ double X[STAGE];
+    const int pc = STAGE / d;                              // points per chunk
+    auto stage = [&](int i0, int i1) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < (i1 - i0) * d; e += blockDim.x) X[e] = u[(int64_t)i0 * d + e];
+        __syncthreads();
+    };
+    double s = 0.0;
+    for (int i0 = 0; i0 < n; i0 += pc) {
+        const int i1 = min(n, i0 + pc);
+        stage(i0, i1);
+        if (threadIdx.x < d)
+            for (int i = i0; i < i1; ++i) s += X[(i - i0) * d + threadIdx.x];
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    if (threadIdx.x < d) mean[threadIdx.x] = s / n;
+    double acc[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) acc[q] = 0.0;
+    for (int i0 = 0; i0 < n; i0 += pc) {
+        const int i1 = min(n, i0 + pc);
+        stage(i0, i1);                                     // its first barrier also publishes mean
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            if (e >= d * d) break;
+            const int a = e / d, b = e % d;
+            if (b > a) continue;
+            const double ma = mean[a], mb = mean[b];
+            for (int i = i0; i < i1; ++i) acc[q] += (X[(i - i0) * d + a] - ma) * (X[(i - i0) * d + b] - mb);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e >= d * d) break;
         const int a = e / d, b = e % d;
         if (b > a) continue;
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += (u[(int64_t)i * d + a] - mean[a]) * (u[(int64_t)i * d + b] - mean[b]);
-        S[a * d + b] = S[b * d + a] = s / (n - 1);
+        S[a * d + b] = S[b * d + a] = acc[q] / (n - 1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
