@@ -92,13 +92,21 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
         S.ccount[par ^ 1] = 0;
         S.active[par ^ 1] = 0;
     }
-    if (w >= k) return;                                   // whole waves
+    // the walker's state is requested first (the idle waves of the last block
+    // read walker k - 1 and leave after the barrier); the direction factor
+    // goes to LDS meanwhile, so that the row products of a new direction
+    // read LDS instead of waiting on one global load per column
+    const int64_t wr = w < k ? w : k - 1;
     const bool act = lane < d;
     const double lstar = *lstar_p;
-    int st = S.st[w], step = S.step[w], q = S.q[w], ne = S.ne[w], pend = S.pend[w];
-    int nev = S.n_evals[w], nst = S.n_stalls[w];
-    double tl = S.tl[w], tr = S.tr[w], tp = S.tp[w], logl = S.logl[w];
-    double ui = act ? S.u[w * d + lane] : 0.0, vi = act ? S.v[w * d + lane] : 0.0;
+    int st = S.st[wr], step = S.step[wr], q = S.q[wr], ne = S.ne[wr], pend = S.pend[wr];
+    int nev = S.n_evals[wr], nst = S.n_stalls[wr];
+    double tl = S.tl[wr], tr = S.tr[wr], tp = S.tp[wr], logl = S.logl[wr];
+    double ui = act ? S.u[wr * d + lane] : 0.0, vi = act ? S.v[wr * d + lane] : 0.0;
+    __shared__ double Ls[MAX_DIM * MAX_DIM];
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) Ls[e] = L[e];
+    __syncthreads();
+    if (w >= k) return;                                   // whole waves
     bool moved = false;
     auto apply = [&](bool inside, double ll) {
         if (st == ST_OUT_L) {
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             double acc = 0.0;
             for (int j = 0; j < d; ++j) {
                 const double zj = __shfl(z, j, 64);
-                if (act && j <= lane) acc = __dadd_rn(acc, __dmul_rn(L[lane * d + j], zj));
+                if (act && j <= lane) acc = __dadd_rn(acc, __dmul_rn(Ls[lane * d + j], zj));
             }
             vi = act ? acc : 0.0;
             const double r = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * d);
