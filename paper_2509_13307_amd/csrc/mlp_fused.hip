@@ -313,8 +313,8 @@ static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, i
 using FusedLaunch = void (*)(ns_model*, const FusedArgs&, const double*, int64_t, int64_t, int, int, const int*,
                              hipStream_t);
 struct FusedCfg { FusedLaunch fn; const char* name; };
-constexpr int FUSED_NCFG = 8;                     // table width; the split form has 6 candidates
-static int fused_ncfg(int x3) { return x3 ? 6 : 8; }
+constexpr int FUSED_NCFG = 8;                     // table width; the split form at width 512 has 6 candidates
+static int fused_ncfg(int h512, int x3) { return x3 && h512 ? 6 : 8; }
 static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
     {   // H = 128
         {{launch_fused<128, 2, false, 4, 2>, "fused 2 waves x 64 units, prefetch 4"},
@@ -330,7 +330,9 @@ static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
          {launch_fused<128, 2, true, 2, 1>, "fused split 4 waves x 32 units, prefetch 2"},
          {launch_fused<128, 2, true, 4, 1>, "fused split 4 waves x 32 units, prefetch 4"},
          {launch_fused<128, 1, true, 2, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 2"},
-         {launch_fused<128, 1, true, 4, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 4"}},
+         {launch_fused<128, 1, true, 4, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 4"},
+         {launch_fused<128, 1, true, 8, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 8"},
+         {launch_fused<128, 2, true, 8, 1>, "fused split 4 waves x 32 units, prefetch 8"}},
     },
     {   // H = 512
         {{launch_fused<512, 2, false, 4, 2>, "fused 8 waves x 64 units, prefetch 4"},
@@ -394,7 +396,7 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
     auto it = m->tune.find(key);
     const char* forced = getenv("NSMI_FUSED_CFG");      // pin one candidate (tests of every shape)
     if (forced != nullptr) {
-        best = std::min(std::max(atoi(forced), 0), fused_ncfg(x3) - 1);
+        best = std::min(std::max(atoi(forced), 0), fused_ncfg(h512, x3) - 1);
     } else if (it != m->tune.end()) {
         best = it->second;
     } else {
@@ -406,7 +408,7 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
             NS_HIP(hipEventCreate(&e1));
             // two interleaved passes over the candidates, the faster pass counts
             // (clock and cache state drift between candidates of one pass)
-            const int ncfg = fused_ncfg(x3);
+            const int ncfg = fused_ncfg(h512, x3);
             float best_ms[FUSED_NCFG];
             for (int c = 0; c < ncfg; ++c) best_ms[c] = 1e30f;
             for (int pass = 0; pass < 2; ++pass)

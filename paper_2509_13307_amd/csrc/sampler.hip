@@ -288,6 +288,7 @@ __global__ __launch_bounds__(1024) void ns_select_kernel(const double* __restric
         }
         __syncthreads();
         if (threadIdx.x == 0)
+#pragma unroll 8
             for (int j = j0; j < min(k, j0 + QB); ++j) {
                 const double logw = logx + qlog[j - j0];
                 logz = logaddexp(logz, key[j] + logw);
