@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--workload", default="cmb4x2500")
     ap.add_argument("--forms", default="bf16,bf16x3,fp32,fp64")
     ap.add_argument("--no-ns", action="store_true")
+    ap.add_argument("--ns-only", action="store_true",
+                    help="run only the nested-sampling leg (one JSON line), e.g. for a kernel trace of ns_run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-shear", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batch-scaling sweep")
@@ -155,6 +157,10 @@ def main():
     if args.shear_paper:
         ns_precs = [p for p in args.sp_ns.split(",") if p]
         print(json.dumps(shear_paper(Model, W, torch, ns_precs, args.mc_live)), flush=True)
+        return
+
+    if args.ns_only:
+        print(json.dumps({"ns": ns_leg(Model, W)}), flush=True)
         return
 
     if args.model_comparison:
