@@ -96,6 +96,77 @@ __global__ __launch_bounds__(64) void zspline_kernel(const T* __restrict__ Y, T*
     mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
 }
 
+// zspline_reg_kernel: the same sweep for n_z <= NZ with the column held in
+// registers (one thread per (walker, k) column, 256 per workgroup): no LDS
+// staging, so more waves per CU hide the serial sweep.  The loops run over
+// the compile-time bound NZ with the run-time n_z as a guard, so the column
+// stays in registers; every value is computed by the expressions of
+// zspline_kernel in the same order.
+template <class T, int NZ>
+__global__ __launch_bounds__(256) void zspline_reg_kernel(const T* __restrict__ Y, T* __restrict__ M, int64_t B,
+                                                          int nz, int nk, double h, const int* __restrict__ count) {
+    __shared__ T cps[NZ];
+    if (threadIdx.x == 0) {
+        T c = T(0);
+        for (int n = 2; n <= nz - 3; ++n) {
+            c = T(1) / (T(4) - (n == 2 ? T(0) : c));
+            cps[n] = c;
+        }
+    }
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (count) B = min<int64_t>(B, *count);
+    if (g >= B * nk) return;
+    const int64_t w = g / nk;
+    const int c = (int)(g % nk);
+    const T* y = Y + w * nz * nk + c;
+    T* mm = M + w * nz * nk + c;
+    T v[NZ];                                            // y_n, then d'_n of the sweep
+#pragma unroll
+    for (int n = 0; n < NZ; ++n) v[n] = n < nz ? y[(int64_t)n * nk] : T(0);
+    T yl0 = T(0), yl1 = T(0), yl2 = T(0);               // y at n_z - 1, n_z - 2, n_z - 3
+#pragma unroll
+    for (int n = 0; n < NZ; ++n) {
+        if (n == nz - 1) yl0 = v[n];
+        if (n == nz - 2) yl1 = v[n];
+        if (n == nz - 3) yl2 = v[n];
+    }
+    const T ih2 = T(1.0 / (h * h));
+    const T M1 = (v[2] - T(2) * v[1] + v[0]) * ih2;
+    const T Mb = (yl0 - T(2) * yl1 + yl2) * ih2;       // M_{N-2}
+    T M2 = Mb, Mc = M1;                                 // n_z = 4: nodes 2 and n_z - 3 are N-2 and 1
+    if (nz > 4) {
+        T dpv = T(0);
+        T ym = v[1], y0 = v[2];
+#pragma unroll
+        for (int n = 2; n < NZ - 1; ++n) {
+            if (n > nz - 3) continue;
+            const T yp = v[n + 1];
+            T rhs = T(6) * (yp - T(2) * y0 + ym) * ih2;
+            if (n == 2) rhs -= M1;
+            if (n == nz - 3) rhs -= Mb;
+            dpv = (rhs - (n == 2 ? T(0) : dpv)) * cps[n];
+            v[n] = dpv;                                 // y_n is held in y0 from here on
+            ym = y0;
+            y0 = yp;
+        }
+        T next = dpv;                                   // M_{nz-3} = d'_{nz-3}
+        mm[(int64_t)(nz - 3) * nk] = next;
+        Mc = next;
+#pragma unroll
+        for (int n = NZ - 1; n >= 2; --n) {
+            if (n > nz - 4) continue;
+            next = v[n] - cps[n] * next;
+            mm[(int64_t)n * nk] = next;
+        }
+        M2 = next;
+    }
+    mm[(int64_t)1 * nk] = M1;
+    mm[(int64_t)(nz - 2) * nk] = Mb;
+    mm[0] = T(2) * M1 - M2;
+    mm[(int64_t)(nz - 1) * nk] = T(2) * Mb - Mc;
+}
+
 // shear_windows_kernel: one workgroup (256 threads) per walker, in four
 // phases over the n_a nodes.  Per-node values live in LDS in lane-major order:
 // with k = ceil(n_a / 64), node j sits at (j mod k) 64 + j / k, so lane l of a
@@ -359,10 +430,18 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
         const T c2 = LINZ ? T(0) : (T)zcoef[zc + 2], c3 = LINZ ? T(0) : (T)zcoef[zc + 3];
         const T* y0 = Ytab + tab + (int64_t)n * G.n_k;
         const T* m0p = LINZ ? y0 : Mtab + tab + (int64_t)n * G.n_k;
-        auto Yz = [&](int col) {
-            if (LINZ) return c0 * y0[col] + c1 * y0[col + G.n_k];
-            return c0 * y0[col] + c1 * y0[col + G.n_k] + c2 * m0p[col] + c3 * m0p[col + G.n_k];
+        // log10 P at z_j from rows n, n + 1 of Y (and of M for cubic z)
+        auto zmix = [&](T ya, T yb, T ma, T mb) {
+            if (LINZ) return c0 * ya + c1 * yb;
+            return c0 * ya + c1 * yb + c2 * ma + c3 * mb;
         };
+        auto Yz = [&](int col) {
+            return zmix(y0[col], y0[col + G.n_k], LINZ ? T(0) : m0p[col], LINZ ? T(0) : m0p[col + G.n_k]);
+        };
+        // the four columns i0 - 1 .. i0 + 2 of one row in one load each (the
+        // rows are only element-aligned; the target allows such vector loads)
+        struct Q4 { T v[4]; };
+        auto row4 = [&](const T* p) { Q4 q; __builtin_memcpy(&q, p, sizeof(q)); return q; };
 #pragma unroll 4
         for (int b = 0; b < LB; ++b) {
             T P = T(0);
@@ -372,9 +451,24 @@ __global__ __launch_bounds__(256) void limber_sum_kernel(
                 int i0 = (int)floor(sv);
                 i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
                 const T tt = (T)(sv - i0);
-                const T p0 = Yz(i0), p1 = Yz(i0 + 1);
-                const T pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
-                const T p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
+                T pm, p0, p1, p2;
+                if (i0 > 0 && i0 + 2 < G.n_k) {
+                    const Q4 ya = row4(y0 + i0 - 1), yb = row4(y0 + G.n_k + i0 - 1);
+                    Q4 ma = {}, mb = {};
+                    if (!LINZ) {
+                        ma = row4(m0p + i0 - 1);
+                        mb = row4(m0p + G.n_k + i0 - 1);
+                    }
+                    pm = zmix(ya.v[0], yb.v[0], ma.v[0], mb.v[0]);
+                    p0 = zmix(ya.v[1], yb.v[1], ma.v[1], mb.v[1]);
+                    p1 = zmix(ya.v[2], yb.v[2], ma.v[2], mb.v[2]);
+                    p2 = zmix(ya.v[3], yb.v[3], ma.v[3], mb.v[3]);
+                } else {
+                    p0 = Yz(i0);
+                    p1 = Yz(i0 + 1);
+                    pm = i0 > 0 ? Yz(i0 - 1) : T(2) * p0 - p1;
+                    p2 = i0 + 2 < G.n_k ? Yz(i0 + 2) : T(2) * p1 - p0;
+                }
                 const T mk0 = T(0.5) * (p1 - pm), mk1 = T(0.5) * (p2 - p0);
                 const T t2 = tt * tt, t3 = t2 * tt;
                 const T lp = (T(2) * t3 - T(3) * t2 + T(1)) * p0 + (t3 - T(2) * t2 + tt) * mk0 +
@@ -706,12 +800,28 @@ double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, i
         dim3 gz((unsigned)((nthr + 63) / 64));
         TraceScope ts(m, s, "zspline");
         const size_t zsm = (size_t)nz * 64 * elem;
-        if (prec == NS_FP64)
-            hipLaunchKernelGGL(zspline_kernel<double>, gz, dim3(64), zsm, s, m->ws_out.as<double>(), (double*)Mtab,
-                               B, nz, nk, hz, count);
-        else
-            hipLaunchKernelGGL(zspline_kernel<float>, gz, dim3(64), zsm, s, m->ws_out.as<float>(), (float*)Mtab, B,
-                               nz, nk, hz, count);
+        const dim3 gr((unsigned)((nthr + 255) / 256));
+        if (prec == NS_FP64) {
+            if (nz <= 16)
+                hipLaunchKernelGGL((zspline_reg_kernel<double, 16>), gr, dim3(256), 0, s, m->ws_out.as<double>(),
+                                   (double*)Mtab, B, nz, nk, hz, count);
+            else if (nz <= 64)
+                hipLaunchKernelGGL((zspline_reg_kernel<double, 64>), gr, dim3(256), 0, s, m->ws_out.as<double>(),
+                                   (double*)Mtab, B, nz, nk, hz, count);
+            else
+                hipLaunchKernelGGL(zspline_kernel<double>, gz, dim3(64), zsm, s, m->ws_out.as<double>(),
+                                   (double*)Mtab, B, nz, nk, hz, count);
+        } else {
+            if (nz <= 16)
+                hipLaunchKernelGGL((zspline_reg_kernel<float, 16>), gr, dim3(256), 0, s, m->ws_out.as<float>(),
+                                   (float*)Mtab, B, nz, nk, hz, count);
+            else if (nz <= 64)
+                hipLaunchKernelGGL((zspline_reg_kernel<float, 64>), gr, dim3(256), 0, s, m->ws_out.as<float>(),
+                                   (float*)Mtab, B, nz, nk, hz, count);
+            else
+                hipLaunchKernelGGL(zspline_kernel<float>, gz, dim3(64), zsm, s, m->ws_out.as<float>(), (float*)Mtab,
+                                   B, nz, nk, hz, count);
+        }
         NS_HIP(hipGetLastError());
     }
     if (prec == NS_FP64)
