@@ -313,15 +313,38 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
             int i0 = (int)floor(s);
             i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
             const double tt = s - i0;
+            // log10 P at z_j from rows nn, nn + 1 of Y (and of M for cubic z)
+            auto zmix = [&](T ya, T yb, T ma, T mb) {
+                if (LINZ) return c0 * (double)ya + c1 * (double)yb;
+                return c0 * (double)ya + c1 * (double)yb + c2 * (double)ma + c3 * (double)mb;
+            };
             auto Yz = [&](int col) {
                 const int64_t o0 = (int64_t)nn * G.n_k + col, o1 = o0 + G.n_k;
-                if (LINZ) return c0 * (double)Yw[o0] + c1 * (double)Yw[o1];
-                return c0 * (double)Yw[o0] + c1 * (double)Yw[o1] + c2 * (double)Mw[o0] + c3 * (double)Mw[o1];
+                return zmix(Yw[o0], Yw[o1], LINZ ? T(0) : Mw[o0], LINZ ? T(0) : Mw[o1]);
             };
             const bool lo_ghost = i0 == 0, hi_ghost = i0 + 2 >= G.n_k;
-            const double p0 = Yz(i0), p1 = Yz(i0 + 1);
-            const double pm = lo_ghost ? 2.0 * p0 - p1 : Yz(i0 - 1);
-            const double p2 = hi_ghost ? 2.0 * p1 - p0 : Yz(i0 + 2);
+            double pm, p0, p1, p2;
+            if (!lo_ghost && !hi_ghost) {
+                // columns i0 - 1 .. i0 + 2 of each row in one (element-aligned) vector load
+                struct Q4 { T v[4]; };
+                auto row4 = [&](const T* q) { Q4 r; __builtin_memcpy(&r, q, sizeof(r)); return r; };
+                const int64_t o = (int64_t)nn * G.n_k + i0 - 1;
+                const Q4 ya = row4(Yw + o), yb = row4(Yw + o + G.n_k);
+                Q4 ma = {}, mb = {};
+                if (!LINZ) {
+                    ma = row4(Mw + o);
+                    mb = row4(Mw + o + G.n_k);
+                }
+                pm = zmix(ya.v[0], yb.v[0], ma.v[0], mb.v[0]);
+                p0 = zmix(ya.v[1], yb.v[1], ma.v[1], mb.v[1]);
+                p1 = zmix(ya.v[2], yb.v[2], ma.v[2], mb.v[2]);
+                p2 = zmix(ya.v[3], yb.v[3], ma.v[3], mb.v[3]);
+            } else {
+                p0 = Yz(i0);
+                p1 = Yz(i0 + 1);
+                pm = lo_ghost ? 2.0 * p0 - p1 : Yz(i0 - 1);
+                p2 = hi_ghost ? 2.0 * p1 - p0 : Yz(i0 + 2);
+            }
             const double m0 = 0.5 * (p1 - pm), m1 = 0.5 * (p2 - p0);
             const double t2 = tt * tt, t3 = t2 * tt;
             const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + tt, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
