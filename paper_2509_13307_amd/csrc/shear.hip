@@ -1,7 +1,9 @@
 // Cosmic-shear likelihood stages after the emulator (App. A of the paper).
 //
-// zspline_kernel   second derivatives M_n(k) of the not-a-knot cubic spline of
-//                  log10 P along the uniform z nodes, one thread per (walker, k):
+// zspline_reg_kernel, zspline_kernel
+//                  second derivatives M_n(k) of the not-a-knot cubic spline of
+//                  log10 P along the uniform z nodes, one thread per (walker, k)
+//                  (the column in registers for n_z <= 64, else in LDS):
 //                  M_1 and M_{N-2} follow directly from the not-a-knot
 //                  conditions on a uniform grid, the interior (1, 4, 1)
 //                  system is solved by a Thomas sweep, M_0 and M_{N-1} are
@@ -14,7 +16,7 @@
 //                      with reverse cumulative trapezoids; NLA window Eq. (A4);
 //                      effective window W = W^g + W^I (the four terms of Eq. (A1)
 //                      share P_dd); all FP64.
-// limber_sum_kernel  one workgroup per walker:
+// limber_sum_kernel  one workgroup per (walker, chunk of 256 nodes):
 //                  (c) P(k = (l+1/2)/chi_j, z_j): spline or linear in z,
 //                      Catmull-Rom in log10 k (linear ghost nodes), zero
 //                      outside [k_min, k_max];
