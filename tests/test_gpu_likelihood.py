@@ -234,11 +234,15 @@ def test_fp64_shear_few_redshift_nodes(built, n_z):
 
 
 SHEAR_GRIDS = [
-    # n_a, n_bins, n_ell, z_interp, n_z: ragged node chunks, 1-10 bins, 1-32 multipoles
+    # n_a, n_bins, n_ell, z_interp, n_z: ragged node chunks, 1-10 bins, 1-32 multipoles;
+    # cubic n_z of 12, 40 and 90 take each z-spline kernel shape (columns in
+    # registers up to 16 or 64 nodes, staged in LDS beyond)
     (300, 3, 25, "linear", 31),
     (3, 1, 1, "linear", 2),
     (700, 7, 32, "cubic", 12),
     (257, 10, 4, "linear", 257),
+    (200, 4, 10, "cubic", 40),
+    (520, 2, 6, "cubic", 90),
 ]
 
 
