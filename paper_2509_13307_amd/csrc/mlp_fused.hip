@@ -44,6 +44,8 @@ struct FusedArgs {
     int n_hidden;        // hidden GEMM layers (network layers - 2)
     int n_in, N_out, mu_rows;
     int64_t ldo;
+    int qg;              // output-block groups (grid z): each runs the hidden layers, then its share of the
+                         // output layer's H-wide column blocks
 };
 
 bool fused_shape(const std::vector<int>& dims) {
@@ -74,11 +76,12 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     __shared__ int zrow[R];                // redshift-node index of each row (row mod mu_rows)
     __shared__ int rowo[R];                // output offset of each row (row ldo), -1 beyond the live rows
 
-    // XCD-aware order: each XCD receives a contiguous run of (network, row block)
-    const int nrb = gridDim.x, total = nrb * gridDim.y;
-    int lin = blockIdx.y * nrb + blockIdx.x;
+    // XCD-aware order: each XCD receives a contiguous run of (output group,
+    // network, row block)
+    const int nrb = gridDim.x, total = nrb * gridDim.y * gridDim.z;
+    int lin = (blockIdx.z * gridDim.y + blockIdx.y) * nrb + blockIdx.x;
     if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
-    const int g = lin / nrb, rb = lin % nrb;
+    const int g = (lin / nrb) % gridDim.y, rb = lin % nrb, q = lin / (nrb * gridDim.y);
     const FusedNet& N = A.net[g];
     int64_t nrows = rows;
     if (count) nrows = min<int64_t>(rows, (int64_t)(*count) * rows_per_walker);
@@ -134,14 +137,21 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     // last one, the partly live last tile computes on valid addresses and
     // stores its live units only), so the weight prefetch stays in flight
     // across iterations.
+    // output group q takes the column blocks [ob0, ob0 + nob); its segments
+    // are the hidden layers, then those blocks (v -> real segment seg_of(v))
     const int ncb = (N_out + H - 1) / H;
-    const int S = (n_hidden + ncb) * KC;
+    const int per = (ncb + A.qg - 1) / A.qg, ob0 = q * per;
+    const int nob = min(ncb, ob0 + per) - ob0;
+    if (nob <= 0) return;
+    const int nseg = n_hidden + nob;
+    auto seg_of = [&](int v) { return v < n_hidden ? v : v + ob0; };
+    const int S = nseg * KC;
     // fragment block (kc, nt) of a layer with nt_l 32-unit tiles sits at
     // (kc nt_l + nt) 512 elements: one K step of a layer is contiguous
     const int nt_out = ncb * H / 32;
     auto frag = [&](int s) -> size_t {
         s = min(s, S - 1);
-        const int seg = s / KC, kc = s - seg * KC;
+        const int v = s / KC, kc = s - v * KC, seg = seg_of(v);
         const bool hid = seg < n_hidden;
         int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
         if (!hid && nb >= N_out) nb = 0;
@@ -184,7 +194,8 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
 
     // one segment (layer or output column block) per iteration; the K steps
     // run in their own loop, so no epilogue path joins the steady state
-    for (int seg = 0; seg < n_hidden + ncb; ++seg) {
+    for (int v = 0; v < nseg; ++v) {
+        const int seg = seg_of(v);
         const bool hid = seg < n_hidden;
         const int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
         // a wave whose units of this output block all lie past N_out has none
@@ -221,7 +232,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh[j], acc[i][j], 0, 0, 0);
                         }
                 }
-                fetch(seg * KC + kc + P, rh[u], rl[u]);
+                fetch(v * KC + kc + P, rh[u], rl[u]);
                 // keep the refill right behind the MFMAs that read the slot:
                 // left to itself the scheduler sinks these loads to the end of
                 // the unrolled steps, next to their first use, and the
@@ -300,7 +311,7 @@ static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, i
         NS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
         m->fused_attr_set[bit] = true;
     }
-    const dim3 grid((unsigned)((rows + R - 1) / R), (unsigned)G);
+    const dim3 grid((unsigned)((rows + R - 1) / R), (unsigned)G, (unsigned)A.qg);
     hipLaunchKernelGGL(kern, grid, dim3(NT), smem, s, theta, ld, rows, rpw, m->emu_src_d.as<int>(),
                        m->emu_fix_d.as<double>(), m->znodes_d.as<double>(), A, count);
 }
@@ -308,13 +319,17 @@ static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, i
 // Candidate launch shapes: 64-row blocks with waves of 32 or 64 output units
 // and 2-8 K steps of weight prefetch, 32-row blocks (twice the workgroups for
 // small batches of one network) and, for plain BF16 (one activation plane),
-// 128-row blocks (half the weight traffic per row).  All candidates give
+// 128-row blocks (half the weight traffic per row); and, for small batches,
+// shapes whose workgroups each take one of the output layer's H-wide column
+// blocks after running the hidden layers themselves ("output blocks split"):
+// more workgroups and a shorter serial chain per workgroup, at the price of
+// the hidden layers computed once per column block.  All candidates give
 // identical results.
 using FusedLaunch = void (*)(ns_model*, const FusedArgs&, const double*, int64_t, int64_t, int, int, const int*,
                              hipStream_t);
-struct FusedCfg { FusedLaunch fn; const char* name; };
-constexpr int FUSED_NCFG = 8;                     // table width; the split form at width 512 has 6 candidates
-static int fused_ncfg(int h512, int x3) { return x3 && h512 ? 6 : 8; }
+struct FusedCfg { FusedLaunch fn; const char* name; bool split_out; };
+constexpr int FUSED_NCFG = 10;                    // table width; the split form at width 512 has 8 candidates
+static int fused_ncfg(int h512, int x3) { return x3 && h512 ? 8 : 10; }
 static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
     {   // H = 128
         {{launch_fused<128, 2, false, 4, 2>, "fused 2 waves x 64 units, prefetch 4"},
@@ -324,7 +339,9 @@ static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
          {launch_fused<128, 1, false, 4, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 4"},
          {launch_fused<128, 1, false, 8, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 8"},
          {launch_fused<128, 4, false, 4, 1>, "fused 4 waves x 32 units, 128 rows, prefetch 4"},
-         {launch_fused<128, 4, false, 4, 2>, "fused 2 waves x 64 units, 128 rows, prefetch 4"}},
+         {launch_fused<128, 4, false, 4, 2>, "fused 2 waves x 64 units, 128 rows, prefetch 4"},
+         {launch_fused<128, 1, false, 4, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 4, output blocks split", true},
+         {launch_fused<128, 1, false, 8, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 8, output blocks split", true}},
         {{launch_fused<128, 2, true, 2, 2>, "fused split 2 waves x 64 units, prefetch 2"},
          {launch_fused<128, 2, true, 4, 2>, "fused split 2 waves x 64 units, prefetch 4"},
          {launch_fused<128, 2, true, 2, 1>, "fused split 4 waves x 32 units, prefetch 2"},
@@ -332,7 +349,9 @@ static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
          {launch_fused<128, 1, true, 2, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 2"},
          {launch_fused<128, 1, true, 4, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 4"},
          {launch_fused<128, 1, true, 8, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 8"},
-         {launch_fused<128, 2, true, 8, 1>, "fused split 4 waves x 32 units, prefetch 8"}},
+         {launch_fused<128, 2, true, 8, 1>, "fused split 4 waves x 32 units, prefetch 8"},
+         {launch_fused<128, 1, true, 2, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 2, output blocks split", true},
+         {launch_fused<128, 1, true, 8, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 8, output blocks split", true}},
     },
     {   // H = 512
         {{launch_fused<512, 2, false, 4, 2>, "fused 8 waves x 64 units, prefetch 4"},
@@ -342,13 +361,17 @@ static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
          {launch_fused<512, 1, false, 4, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 4"},
          {launch_fused<512, 1, false, 8, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 8"},
          {launch_fused<512, 4, false, 4, 1>, "fused 16 waves x 32 units, 128 rows, prefetch 4"},
-         {launch_fused<512, 4, false, 4, 2>, "fused 8 waves x 64 units, 128 rows, prefetch 4"}},
+         {launch_fused<512, 4, false, 4, 2>, "fused 8 waves x 64 units, 128 rows, prefetch 4"},
+         {launch_fused<512, 1, false, 4, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 4, output blocks split", true},
+         {launch_fused<512, 1, false, 8, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 8, output blocks split", true}},
         {{launch_fused<512, 2, true, 2, 2>, "fused split 8 waves x 64 units, prefetch 2"},
          {launch_fused<512, 2, true, 4, 2>, "fused split 8 waves x 64 units, prefetch 4"},
          {launch_fused<512, 2, true, 2, 1>, "fused split 16 waves x 32 units, prefetch 2"},
          {launch_fused<512, 2, true, 4, 1>, "fused split 16 waves x 32 units, prefetch 4"},
          {launch_fused<512, 1, true, 2, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 2"},
-         {launch_fused<512, 1, true, 4, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 4"}},
+         {launch_fused<512, 1, true, 4, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 4"},
+         {launch_fused<512, 1, true, 2, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 2, output blocks split", true},
+         {launch_fused<512, 1, true, 4, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 4, output blocks split", true}},
     },
 };
 
@@ -371,6 +394,7 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
     A.N_out = n0.dims[L];
     A.mu_rows = n0.out_mu_rows;
     A.ldo = ldo;
+    A.qg = 1;
     for (int g = 0; g < G; ++g) {
         const Net& net = *m->nets[nets[g]];
         FusedNet& F = A.net[g];
@@ -391,6 +415,12 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
     // outside stream capture and tracing
     const int h512 = H == 512;
     const FusedCfg* cfgs = FUSED_CFGS[h512][x3];
+    // candidate c with its output-block grouping
+    auto run = [&](int c) {
+        FusedArgs Ac = A;
+        Ac.qg = cfgs[c].split_out ? (A.N_out + H - 1) / H : 1;
+        cfgs[c].fn(m, Ac, theta, ld, rows, rpw, G, count, s);
+    };
     const auto key = std::make_tuple(2 + (int)x3 + 2 * h512, rows, A.N_out, H, G);
     int best = 0;
     auto it = m->tune.find(key);
@@ -413,9 +443,9 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
             for (int c = 0; c < ncfg; ++c) best_ms[c] = 1e30f;
             for (int pass = 0; pass < 2; ++pass)
                 for (int c = 0; c < ncfg; ++c) {
-                    cfgs[c].fn(m, A, theta, ld, rows, rpw, G, count, s);
+                    run(c);
                     NS_HIP(hipEventRecord(e0, s));
-                    for (int r = 0; r < 4; ++r) cfgs[c].fn(m, A, theta, ld, rows, rpw, G, count, s);
+                    for (int r = 0; r < 4; ++r) run(c);
                     NS_HIP(hipEventRecord(e1, s));
                     NS_HIP(hipEventSynchronize(e1));
                     float ms = 0.f;
@@ -430,7 +460,7 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
         }
     }
     TraceScope ts(m, s, x3 ? "mlp_fused_bf16x3" : "mlp_fused_bf16");
-    cfgs[best].fn(m, A, theta, ld, rows, rpw, G, count, s);
+    run(best);
     NS_HIP(hipGetLastError());
     return true;
 }

@@ -210,7 +210,7 @@ def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
     say(f"{name} {prec}: tuned {report}")
     np.testing.assert_array_equal(got, ref)
     width = m["nets"][0]["W"][0].shape[0]          # hidden width: 128 or 512
-    for c in range(8 if prec == "bf16" or width == 128 else 6):
+    for c in range(10 if prec == "bf16" or width == 128 else 8):
         got, _ = run({"NSMI_FUSED_CFG": str(c)})
         np.testing.assert_array_equal(got, ref)
 
