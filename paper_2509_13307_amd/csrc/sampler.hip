@@ -5,7 +5,8 @@
 // cube.  Per step s = 1..n_inner it draws a direction v = L zeta (zeta by
 // Box-Muller from Philox draws 0..2d-1) and an offset r (draw 2d), brackets
 // [t_L, t_R] = [-r, 1-r], steps each end out while it is inside the constraint
-// (at most 10 times per end), then shrinks with draws 2d+1, 2d+2, ... until a
+// (at most 10 times per end; the two ends in the same rounds, since they are
+// independent), then shrinks with draws 2d+1, 2d+2, ... until a
 // point inside is found (accept), the bracket is narrower than 1e-12 or 200
 // shrinks were rejected (stall: the point is kept).  "Inside" means
 // u in [0,1]^d and logL(T(u)) > L*; proposals outside the cube cost no
@@ -31,7 +32,7 @@
 
 namespace nsmi {
 
-enum { ST_NEWSTEP = 0, ST_OUT_L = 1, ST_OUT_R = 2, ST_SHRINK = 3, ST_DONE = 4 };
+enum { ST_NEWSTEP = 0, ST_OUT = 1, ST_SHRINK = 3, ST_DONE = 4 };
 constexpr int MAX_EXPAND = 10;
 constexpr int MAX_SHRINK = 200;
 constexpr double STALL_WIDTH = 1e-12;
@@ -47,13 +48,16 @@ struct SliceState {
     int* st;          // [k] phase
     int* step;        // [k] current step (1-based)
     int* q;           // [k] next draw index
-    int* ne;          // [k] expansions / rejected shrinks in the current phase
-    int* pend;        // [k] compact slot of the pending proposal, -1 none
+    int* ne;          // [k] left-end expansions (stepping out; -1 once that end is final) /
+                      //     rejected shrinks
+    int* ne2;         // [k] right-end expansions (stepping out; -1 once final)
+    int* pend;        // [k] compact slot of the pending (left-end or shrink) proposal, -1 none
+    int* pend2;       // [k] compact slot of the pending right-end proposal, -1 none
     int* n_evals;     // [k]
     int* n_stalls;    // [k]
-    double* xc;       // [k x d] compacted proposals (unit cube)
-    int* cidx;        // [k] walker of each compact slot
-    double* llc;      // [k] likelihood of each compact slot
+    double* xc;       // [2k x d] compacted proposals (unit cube)
+    int* cidx;        // [2k] walker of each compact slot
+    double* llc;      // [2k] likelihood of each compact slot
     int* ccount;      // [2] compact batch size of the rounds of even / odd parity
     int* active;      // [2] walkers not done after the advance of such a round
 };
@@ -68,6 +72,7 @@ __global__ void slice_init_kernel(SliceState S, int64_t k) {
     S.st[w] = ST_NEWSTEP;
     S.step[w] = 0;
     S.pend[w] = -1;
+    S.pend2[w] = -1;
     S.n_evals[w] = 0;
     S.n_stalls[w] = 0;
 }
@@ -100,6 +105,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     const bool act = lane < d;
     const double lstar = *lstar_p;
     int st = S.st[wr], step = S.step[wr], q = S.q[wr], ne = S.ne[wr], pend = S.pend[wr];
+    int ne2 = S.ne2[wr], pend2 = S.pend2[wr];
     int nev = S.n_evals[wr], nst = S.n_stalls[wr];
     double tl = S.tl[wr], tr = S.tr[wr], tp = S.tp[wr], logl = S.logl[wr];
     double ui = act ? S.u[wr * d + lane] : 0.0, vi = act ? S.v[wr * d + lane] : 0.0;
@@ -108,34 +114,57 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     __syncthreads();
     if (w >= k) return;                                   // whole waves
     bool moved = false;
-    auto apply = [&](bool inside, double ll) {
-        if (st == ST_OUT_L) {
-            if (inside) { tl -= 1.0; ne += 1; }
-            else { st = ST_OUT_R; ne = 0; }
-        } else if (st == ST_OUT_R) {
-            if (inside) { tr += 1.0; ne += 1; }
-            else { st = ST_SHRINK; ne = 0; }
-        } else if (st == ST_SHRINK) {
-            if (inside) {
-                ui = __dadd_rn(ui, __dmul_rn(tp, vi));
-                logl = ll;
-                moved = true;
+    // outcome of a shrink proposal at t = tp
+    auto shrink = [&](bool inside, double ll) {
+        if (inside) {
+            ui = __dadd_rn(ui, __dmul_rn(tp, vi));
+            logl = ll;
+            moved = true;
+            st = ST_NEWSTEP;
+        } else {
+            if (tp < 0.0) tl = tp; else tr = tp;
+            ne += 1;
+            if (tr - tl < STALL_WIDTH || ne >= MAX_SHRINK) {
+                nst += 1;
                 st = ST_NEWSTEP;
-            } else {
-                if (tp < 0.0) tl = tp; else tr = tp;
-                ne += 1;
-                if (tr - tl < STALL_WIDTH || ne >= MAX_SHRINK) {
-                    nst += 1;
-                    st = ST_NEWSTEP;
-                }
             }
         }
     };
-    if (pend >= 0) {
+    // the point at t along the direction: its compact slot, or -1 outside the
+    // unit cube (no evaluation: outside the constraint)
+    auto propose = [&](double t) -> int {
+        const double xi = __dadd_rn(ui, __dmul_rn(t, vi));
+        const bool inbox = __ballot(act && !((xi >= 0.0) && (xi <= 1.0))) == 0;
+        if (!inbox) return -1;
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(S.ccount + par, 1);
+        slot = __shfl(slot, 0, 64);
+        if (act) {
+            S.xc[(int64_t)slot * d + lane] = xi;
+            thc[(int64_t)slot * d + lane] = prior_map(xi, pk[lane], pa[lane], pb[lane]);
+        }
+        if (lane == 0) S.cidx[slot] = (int)w;
+        return slot;
+    };
+    // last round's evaluations
+    if (st == ST_OUT) {
+        if (pend >= 0) {
+            const double ll = S.llc[pend];
+            pend = -1;
+            nev += 1;
+            if (ll > lstar) { tl -= 1.0; ne += 1; } else ne = -1;
+        }
+        if (pend2 >= 0) {
+            const double ll = S.llc[pend2];
+            pend2 = -1;
+            nev += 1;
+            if (ll > lstar) { tr += 1.0; ne2 += 1; } else ne2 = -1;
+        }
+    } else if (pend >= 0) {
         const double ll = S.llc[pend];
         pend = -1;
         nev += 1;
-        apply(ll > lstar, ll);
+        shrink(ll > lstar, ll);
     }
     while (true) {
         if (st == ST_DONE) break;
@@ -159,37 +188,36 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             tr = 1.0 - r;
             q = 2 * d + 1;
             ne = 0;
-            st = ST_OUT_L;
+            ne2 = 0;
+            st = ST_OUT;
             continue;
         }
-        double t;
-        if (st == ST_OUT_L) {
-            if (ne >= MAX_EXPAND) { st = ST_OUT_R; ne = 0; continue; }
-            t = tl;
-        } else if (st == ST_OUT_R) {
-            if (ne >= MAX_EXPAND) { st = ST_SHRINK; ne = 0; continue; }
-            t = tr;
-        } else {
-            const int qq = q++;
-            const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)qq);
-            t = __dadd_rn(tl, __dmul_rn(U, __dsub_rn(tr, tl)));
-        }
-        const double xi = __dadd_rn(ui, __dmul_rn(t, vi));
-        const bool inbox = __ballot(act && !((xi >= 0.0) && (xi <= 1.0))) == 0;
-        tp = t;
-        if (!inbox) {
-            apply(false, -INFINITY);
+        if (st == ST_OUT) {
+            // both ends step out at once, each proposing its current end until
+            // that point is outside the slice or the cube or it has expanded
+            // MAX_EXPAND times; the ends do not interact, so the evaluations
+            // and the final bracket are those of stepping out one end after
+            // the other
+            if (ne >= 0) {
+                if (ne >= MAX_EXPAND) ne = -1;
+                else if ((pend = propose(tl)) < 0) ne = -1;
+            }
+            if (ne2 >= 0) {
+                if (ne2 >= MAX_EXPAND) ne2 = -1;
+                else if ((pend2 = propose(tr)) < 0) ne2 = -1;
+            }
+            if (pend >= 0 || pend2 >= 0) break;
+            st = ST_SHRINK;
+            ne = 0;
             continue;
         }
-        int slot = 0;
-        if (lane == 0) slot = atomicAdd(S.ccount + par, 1);
-        slot = __shfl(slot, 0, 64);
-        if (act) {
-            S.xc[(int64_t)slot * d + lane] = xi;
-            thc[(int64_t)slot * d + lane] = prior_map(xi, pk[lane], pa[lane], pb[lane]);
+        const int qq = q++;
+        const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)qq);
+        tp = __dadd_rn(tl, __dmul_rn(U, __dsub_rn(tr, tl)));
+        if ((pend = propose(tp)) < 0) {
+            shrink(false, -INFINITY);
+            continue;
         }
-        if (lane == 0) S.cidx[slot] = (int)w;
-        pend = slot;
         break;
     }
     if (act) {
@@ -198,6 +226,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     }
     if (lane == 0) {
         S.st[w] = st; S.step[w] = step; S.q[w] = q; S.ne[w] = ne; S.pend[w] = pend;
+        S.ne2[w] = ne2; S.pend2[w] = pend2;
         S.n_evals[w] = nev; S.n_stalls[w] = nst;
         S.tl[w] = tl; S.tr[w] = tr; S.tp[w] = tp; S.logl[w] = logl;
         if (st != ST_DONE) atomicAdd(S.active + par, 1);
@@ -600,23 +629,25 @@ __global__ __launch_bounds__(256) void ns_count_kernel(const int* __restrict__ n
 
 static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* logl, int* ne, int* ns) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t bytes = al(k * d * 8) * 2 + al(k * 8) * 4 + al(k * 4) * 6 + al(8) * 2;
+    const size_t bytes = al(k * d * 8) * 3 + al(k * 8) * 5 + al(k * 4) * 9 + al(8) * 2;
     m->ws_slice.ensure(bytes);
     char* p = m->ws_slice.as<char>();
     SliceState S;
     S.u = u; S.logl = logl; S.n_evals = ne; S.n_stalls = ns;
     S.v = (double*)p; p += al(k * d * 8);
-    S.xc = (double*)p; p += al(k * d * 8);
+    S.xc = (double*)p; p += al(2 * k * d * 8);
     S.tl = (double*)p; p += al(k * 8);
     S.tr = (double*)p; p += al(k * 8);
     S.tp = (double*)p; p += al(k * 8);
-    S.llc = (double*)p; p += al(k * 8);
+    S.llc = (double*)p; p += al(2 * k * 8);
     S.st = (int*)p; p += al(k * 4);
     S.step = (int*)p; p += al(k * 4);
     S.q = (int*)p; p += al(k * 4);
     S.ne = (int*)p; p += al(k * 4);
+    S.ne2 = (int*)p; p += al(k * 4);
     S.pend = (int*)p; p += al(k * 4);
-    S.cidx = (int*)p; p += al(k * 4);
+    S.pend2 = (int*)p; p += al(k * 4);
+    S.cidx = (int*)p; p += al(2 * k * 4);
     S.ccount = (int*)p; p += al(8);
     S.active = (int*)p; p += al(8);
     return S;
@@ -635,7 +666,8 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
     NS_CHECK(d <= MAX_DIM, NS_E_UNSUPPORTED, "slice sampler supports d <= 64");
     if (k == 0) return;
     SliceState S = carve_slice(m, k, d, u, logl, n_evals, n_stalls);
-    m->ws_theta.ensure((size_t)k * d * sizeof(double));
+    // up to two proposals per walker and round (both ends while stepping out)
+    m->ws_theta.ensure((size_t)2 * k * d * sizeof(double));
     double* thc = m->ws_theta.as<double>();
     int* flag = host_flag(m);
     const dim3 gw((unsigned)((k + 255) / 256));
@@ -654,7 +686,7 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
                                    lstar_dev, L, n_inner, seed, iter, par, m->prior_kind.as<int>(),
                                    m->prior_a.as<double>(), m->prior_b.as<double>(), thc);
             }
-            loglike_batch(m, thc, d, k, S.llc, prec, S.ccount + par, st);
+            loglike_batch(m, thc, d, 2 * k, S.llc, prec, S.ccount + par, st);
         }
         NS_HIP(hipGetLastError());
     };
