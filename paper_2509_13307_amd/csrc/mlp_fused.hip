@@ -76,17 +76,22 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     __shared__ int zrow[R];                // redshift-node index of each row (row mod mu_rows)
     __shared__ int rowo[R];                // output offset of each row (row ldo), -1 beyond the live rows
 
-    // XCD-aware order: each XCD receives a contiguous run of (output group,
-    // network, row block)
-    const int nrb = gridDim.x, total = nrb * gridDim.y * gridDim.z;
-    int lin = (blockIdx.z * gridDim.y + blockIdx.y) * nrb + blockIdx.x;
-    if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
-    const int g = (lin / nrb) % gridDim.y, rb = lin % nrb, q = lin / (nrb * gridDim.y);
-    const FusedNet& N = A.net[g];
+    // Only the row blocks below the live row count (a device-side count in
+    // the sampler's rounds) carry work: the first nlb G qg workgroups in
+    // launch order take them, the rest leave at once.  Launch order deals
+    // workgroups round-robin to the 8 XCDs, so the live ones span every XCD
+    // however few they are; within them the order is XCD-aware, each XCD
+    // receiving a contiguous run of (output group, network, row block).
     int64_t nrows = rows;
     if (count) nrows = min<int64_t>(rows, (int64_t)(*count) * rows_per_walker);
+    const int nlb = (int)((nrows + R - 1) / R);            // live row blocks per network
+    const int live = nlb * gridDim.y * gridDim.z;
+    int lin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    if (lin >= live) return;
+    if ((live & 7) == 0) lin = (lin & 7) * (live >> 3) + (lin >> 3);
+    const int g = (lin / nlb) % gridDim.y, rb = lin % nlb, q = lin / (nlb * gridDim.y);
+    const FusedNet& N = A.net[g];
     const int64_t r0 = (int64_t)rb * R;
-    if (r0 >= nrows) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_in = A.n_in, n_hidden = A.n_hidden, N_out = A.N_out;
     const int nvalid = (int)min<int64_t>(R, nrows - r0);   // live rows of this block
