@@ -36,6 +36,8 @@ Error: std of log Z over R replicate shrinkage sequences
 log t_m = log(1 - U_m)/n_m (Philox stream 1), and sqrt(H/n) as a cross-check.
 
 Pinned by: the closed-form evidence of a Gaussian likelihood in the unit box;
+a brute-force covariance for the direction factor and a record of which
+points run() hands it;
 the exact quadrature limit for L(X) = exp(-X/s); uniformity of slice draws
 inside a ball constraint; agreement of k = 1 and k = n/2 runs.
 """
@@ -50,7 +52,13 @@ STALL_WIDTH = 1e-12
 
 
 def direction_cholesky(u):
-    """Lower Cholesky of the live-point covariance plus a trace-scaled jitter."""
+    """Lower Cholesky of the live-point covariance plus a trace-scaled jitter.
+
+    Sigma = sum_i (u_i - mean)(u_i - mean)^T / (n - 1) over the rows given
+    (the n live points before deletion, as run() passes them); returns L with
+    L L^T = Sigma + 1e-12 tr(Sigma)/d I.  Pinned by an explicit double loop
+    over points and entries and by a singular point set that only the jitter
+    makes factorisable."""
     d = u.shape[1]
     S = np.cov(u, rowvar=False, ddof=1).reshape(d, d)
     return np.linalg.cholesky(S + 1e-12 * np.trace(S) / d * np.eye(d))

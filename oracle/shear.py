@@ -44,7 +44,9 @@ directly in chi by adaptive quadrature for an EdS background and a power-law
 P; exactness of the z-spline on cubics, of the linear z-interpolation on
 lines, its one-sided error bound on concave tables, and the identity of the
 N_z = n_a table with the emulator evaluated at every node; exactness of the
-k-interpolation on quadratics; identical spectra for identical bins; and
+k-interpolation on quadratics; Limber integrals cut by the emulated k range
+against quadrature over the chi range inside it; identical spectra for
+identical bins; and
 scipy.stats.multivariate_normal for the Gaussian.
 """
 import numpy as np
@@ -234,7 +236,10 @@ def interp_k(Yz, log10k, model):
 
 
 def power_at_limber_k(Y, chi, model):
-    """P(k = (l + 1/2)/chi_j, z_j) [B, n_ell, n_a] from the node table Y."""
+    """P(k = (l + 1/2)/chi_j, z_j) [B, n_ell, n_a] from the node table Y;
+    zero where k lies outside [k_min, k_max] and at chi = 0.  The zero rule is
+    pinned by Limber integrals cut at both ends of the k range against direct
+    quadrature over the chi range inside it."""
     ell = ell_grid(model)
     Yz = interp_z(Y, model)
     chi_safe = np.where(np.arange(chi.shape[1]) == 0, 1.0, chi)

@@ -25,6 +25,31 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _on_device(t, device):
+    return t.is_cuda and (t.device.index if t.device.index is not None else torch.cuda.current_device()) == device
+
+
+def check_rows(t, d, device, name="theta"):
+    """Rows handed to the library as a device pointer with a leading dimension:
+    a float64 tensor on the model's device, [B, ld >= d], unit column stride."""
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 tensor")
+    if not _on_device(t, device):
+        raise TypeError(f"{name} must live on HIP device {device}")
+    if t.dim() != 2 or t.shape[1] < d or t.stride(1) != 1 or (t.shape[0] > 1 and t.stride(0) < d):
+        raise ValueError(f"{name} must be [B, ld >= d] with unit column stride")
+
+
+def check_vector(t, n, dtype, device, name):
+    """A contiguous length-n vector of `dtype` on `device` (a torch.device)."""
+    if not (isinstance(t, torch.Tensor) and t.dtype == dtype):
+        raise TypeError(f"{name} must be a {dtype} tensor")
+    if t.device != device:
+        raise TypeError(f"{name} must live on {device}")
+    if t.dim() != 1 or t.shape[0] != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous vector of length {n}")
+
+
 class Model:
     """A likelihood model resident on one HIP device.
 
@@ -122,11 +147,8 @@ class Model:
         return nd
 
     # ----------------------------------------------------------------- calls
-    def _check_theta(self, theta):
-        if not (isinstance(theta, torch.Tensor) and theta.is_cuda and theta.dtype == torch.float64):
-            raise TypeError("theta must be a float64 tensor on the HIP device")
-        if theta.dim() != 2 or theta.shape[1] < self.d or theta.stride(1) != 1:
-            raise ValueError("theta must be [B, ld >= d] with unit column stride")
+    def _check_theta(self, theta, name="theta"):
+        check_rows(theta, self.d, self.device, name)
 
     def loglike(self, theta, precision="fp64", out=None):
         """logL [B] (float64 device tensor) of theta [B, >= d]."""
@@ -134,6 +156,8 @@ class Model:
         B = theta.shape[0]
         if out is None:
             out = torch.empty(B, dtype=torch.float64, device=theta.device)
+        else:
+            check_vector(out, B, torch.float64, theta.device, "out")
         C.check(C.lib().ns_loglike_batch(self._h, _ptr(theta), theta.stride(0), B, _ptr(out),
                                          C.PRECISIONS[precision], _stream()))
         return out
@@ -158,16 +182,24 @@ class Model:
         return logl, grad
 
     def prior_transform(self, u):
-        self._check_theta(u)
-        theta = torch.empty_like(u)
-        C.check(C.lib().ns_prior_transform(self._h, _ptr(u), _ptr(theta), u.stride(0), u.shape[0], _stream()))
-        return theta
+        """theta [B, d] of unit-cube points u [B, >= d].  The library reads u and
+        writes theta with one leading dimension, so theta is allocated with
+        u's row stride and its first d columns are returned."""
+        self._check_theta(u, "u")
+        B, ld = u.shape[0], u.stride(0)
+        theta = torch.empty((B, ld), dtype=torch.float64, device=u.device)
+        C.check(C.lib().ns_prior_transform(self._h, _ptr(u), _ptr(theta), ld, B, _stream()))
+        return theta[:, :self.d]
 
     def slice_step(self, u, logl, logl_star, dir_chol, n_inner, seed, it, precision="fp64"):
         """In-place slice steps of walkers u [k, d], logl [k]; returns (n_evals, n_stalls)."""
+        check_rows(u, self.d, self.device, "u")
         k = u.shape[0]
         if u.shape[1] != self.d or not u.is_contiguous():
             raise ValueError("u must be contiguous [k, d]")
+        check_vector(logl, k, torch.float64, u.device, "logl")
+        if tuple(dir_chol.shape) != (self.d, self.d):
+            raise ValueError("dir_chol must be [d, d]")
         ne = torch.empty(k, dtype=torch.int32, device=u.device)
         ns = torch.empty(k, dtype=torch.int32, device=u.device)
         L = dir_chol.to(device=u.device, dtype=torch.float64).contiguous()
@@ -198,8 +230,13 @@ class Model:
         """Hamiltonian Monte Carlo chains from theta0 [chains, d] (device tensor);
         returns (samples [n_iter, chains, d], logp [n_iter, chains], result dict,
         last state)."""
-        theta = theta0.to(torch.float64).contiguous().clone()
+        dev = torch.device("cuda", self.device)
+        theta = theta0.to(device=dev, dtype=torch.float64).contiguous().clone()
+        if theta.dim() != 2 or theta.shape[1] != self.d:
+            raise ValueError("theta0 must be [chains, d]")
         n_ch, d = theta.shape
+        if inv_mass.numel() != d:
+            raise ValueError("inv_mass must hold d values")
         minv = inv_mass.to(device=theta.device, dtype=torch.float64).contiguous()
         samples = logp = None
         if keep_samples:

@@ -61,3 +61,25 @@ def test_module_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _capi.lib()
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding refuses host, wrong-dtype, mis-shaped and strided tensors
+    before any pointer reaches the library (no device needed: every tensor
+    here is a host tensor or fails a shape check first)."""
+    import torch
+    from paper_2509_13307_amd.model import check_rows, check_vector
+    with pytest.raises(TypeError, match="float64"):
+        check_rows(torch.zeros(4, 6, dtype=torch.float32), 6, 0, "u")
+    with pytest.raises(TypeError, match="device"):
+        check_rows(torch.zeros(4, 6, dtype=torch.float64), 6, 0, "u")
+    with pytest.raises(TypeError, match="float64"):
+        check_rows([[0.0] * 6], 6, 0, "u")
+    with pytest.raises(TypeError, match="float64"):
+        check_vector(torch.zeros(4, dtype=torch.float32), 4, torch.float64, torch.device("cpu"), "logl")
+    with pytest.raises(TypeError, match="live on"):
+        check_vector(torch.zeros(4, dtype=torch.float64), 4, torch.float64, torch.device("cuda", 0), "logl")
+    with pytest.raises(ValueError, match="length 5"):
+        check_vector(torch.zeros(4, dtype=torch.float64), 5, torch.float64, torch.device("cpu"), "logl")
+    with pytest.raises(ValueError, match="contiguous"):
+        check_vector(torch.zeros(8, dtype=torch.float64)[::2], 4, torch.float64, torch.device("cpu"), "logl")

@@ -34,6 +34,14 @@ def test_prior_transform_matches_oracle():
     g = mk(W.load_model("shear10"))
     th = g.prior_transform(torch.tensor(u, device=DEV)).cpu().numpy()
     np.testing.assert_allclose(th, prior_transform(u, m), rtol=1e-14, atol=1e-15)
+    # a column view of a wider buffer: theta takes u's row stride, and the
+    # guard column past the view is left alone
+    wide = torch.full((u.shape[0], m["d"] + 5), 7.0, dtype=torch.float64, device=DEV)
+    wide[:, :m["d"]] = torch.tensor(u, device=DEV)
+    th2 = g.prior_transform(wide[:, :m["d"]])
+    assert tuple(th2.shape) == (u.shape[0], m["d"])
+    np.testing.assert_allclose(th2.cpu().numpy(), prior_transform(u, m), rtol=1e-14, atol=1e-15)
+    assert bool((wide[:, m["d"]:] == 7.0).all())
 
 
 def walkers_above(model, n, seed):

@@ -85,3 +85,64 @@ def test_replicates_reproducible_and_centered():
     again = nested.evidence_replicates(res["dead_logl"], res["dead_n"], seed=5, n_rep=300, chunk=7)
     assert np.array_equal(reps, again)
     assert abs(reps.mean() - res["logZ"]) < 0.5 * reps.std() + 0.05
+
+
+def brute_covariance(u):
+    """Sample covariance (1/(n-1)) by explicit loops over points and entries."""
+    n, d = u.shape
+    mean = [sum(u[i][c] for i in range(n)) / n for c in range(d)]
+    S = np.zeros((d, d))
+    for a in range(d):
+        for b in range(d):
+            S[a, b] = sum((u[i][a] - mean[a]) * (u[i][b] - mean[b]) for i in range(n)) / (n - 1)
+    return S
+
+
+def test_direction_cholesky_brute_force():
+    """L L^T = Sigma + 1e-12 tr(Sigma)/d I, Sigma with the 1/(n-1) normalisation;
+    L lower-triangular with a positive diagonal."""
+    rng = np.random.default_rng(17)
+    for n, d in ((7, 3), (40, 6)):
+        u = rng.uniform(size=(n, d)) * rng.uniform(0.1, 1.0, size=d)
+        S = brute_covariance(u)
+        L = nested.direction_cholesky(u)
+        assert np.array_equal(L, np.tril(L)) and np.all(np.diag(L) > 0)
+        want = S + 1e-12 * np.trace(S) / d * np.eye(d)
+        np.testing.assert_allclose(L @ L.T, want, rtol=1e-12, atol=1e-15)
+        # the 1/n normalisation differs by n/(n-1): far outside the tolerance
+        assert np.max(np.abs(S * (n - 1) / n - S)) > 1e-3 * np.max(np.abs(S))
+
+
+def test_direction_cholesky_jitter_on_a_singular_set():
+    """d points in d dimensions have a singular covariance: the trace-scaled
+    jitter alone makes it factorisable, and L L^T - Sigma is that jitter."""
+    rng = np.random.default_rng(18)
+    d = 4
+    u = rng.uniform(size=(d, d))
+    S = brute_covariance(u)
+    assert np.min(np.linalg.eigvalsh(S)) < 1e-14 * np.trace(S)
+    L = nested.direction_cholesky(u)
+    jit = 1e-12 * np.trace(S) / d
+    np.testing.assert_allclose(np.diag(L @ L.T - S), jit, rtol=1e-2)
+    off = (L @ L.T - S)[~np.eye(d, dtype=bool)]
+    assert np.max(np.abs(off)) < 1e-2 * jit
+
+
+def test_run_takes_directions_from_the_live_set_before_deletion(monkeypatch):
+    """Each iteration's direction covariance is that of all n live points,
+    the k about to be replaced included (iteration 1: the initial draws)."""
+    from oracle.philox import uniforms
+    seen = []
+    orig = nested.direction_cholesky
+
+    def spy(u):
+        seen.append(np.array(u, copy=True))
+        return orig(u)
+
+    monkeypatch.setattr(nested, "direction_cholesky", spy)
+    loglike_u, _ = gauss_box([0.4, 0.6], [0.1, 0.1])
+    nested.run(loglike_u, 2, 20, 10, 4, seed=31, max_iter=2, n_rep=0)
+    assert len(seen) == 2
+    init = uniforms(31, 0, np.arange(20), 0, 0, np.arange(2))
+    assert seen[0].shape == (20, 2)
+    np.testing.assert_array_equal(seen[0], init)

@@ -107,8 +107,10 @@ def test_k_interpolation_exact_on_quadratics_and_lines():
     assert du > 0
 
 
-def direct_limber(model, theta, A, n_pk, pairs_ells):
-    """Eqs. (A2)-(A4) integrated in chi by adaptive quadrature (EdS, P = A k^n)."""
+def direct_limber(model, theta, A, n_pk, pairs_ells, k_range=None):
+    """Eqs. (A2)-(A4) integrated in chi by adaptive quadrature (EdS, P = A k^n).
+    With k_range = (k_lo, k_hi), P is zero where (l + 1/2)/chi leaves it, so
+    the integral runs over chi in [(l + 1/2)/k_hi, (l + 1/2)/k_lo] only."""
     cos = shear.unpack(shear.physical(theta, model), model["n_bins"])
     h = float(cos["h"][0, 0])
     c_H0 = C_KM_S / (100 * h)
@@ -133,7 +135,10 @@ def direct_limber(model, theta, A, n_pk, pairs_ells):
     out = []
     for (i, j), ell in pairs_ells:
         f = lambda chi: window(i, chi) * window(j, chi) / chi ** 2 * A * ((ell + 0.5) / chi) ** n_pk
-        val = integrate.quad(f, 1e-6, chiH, epsabs=0, epsrel=1e-10, limit=400)[0]
+        lo, hi = 1e-6, chiH
+        if k_range is not None:
+            lo, hi = max(lo, (ell + 0.5) / k_range[1]), min(hi, (ell + 0.5) / k_range[0])
+        val = integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-10, limit=400)[0] if hi > lo else 0.0
         out.append((1 + cos["m"][0, i]) * (1 + cos["m"][0, j]) * val)
     return np.array(out)
 
@@ -166,6 +171,37 @@ def test_windows_and_limber_match_direct_integration(n_a_list):
     assert np.all(errs[0] < 2e-4), errs
     ratio = errs[0] / errs[1]
     assert np.all((ratio > 3.0) & (ratio < 5.0)), (errs, ratio)
+
+
+def test_limber_power_is_zero_outside_the_emulated_k_range():
+    """P = 0 where k = (l + 1/2)/chi leaves [k_min, k_max]: with a range that
+    cuts the chi integral at both ends (k_max at small chi for every l, k_min
+    at large chi for the lowest l) the spectra equal the direct integral over
+    the chi range inside and are far from the uncut integral; where the whole
+    range lies outside (l = 3000 needs chi > chi_H for k <= k_max) the
+    spectrum is exactly zero."""
+    A, n_pk = 2e3, -1.3
+    k_range = (0.03, 0.5)
+    m = W.shear_structure(n_z=6, n_bins=2, n_extra=0, hidden=(4,), n_a=1021, n_k=200)
+    m["nz_mean"] = np.array([1.0, 1.5])
+    m["k_min"], m["k_max"] = k_range
+    th = eds_theta(m)
+    u = shear.log10k_grid(m)
+    Y = np.broadcast_to(np.log10(A) + n_pk * u, (1, m["n_z"], m["n_k"])).copy()
+    C = shear.spectra(th, m, Y=Y)[0][0]
+    ells = shear.ell_grid(m)
+    cases = [((0, 0), 0), ((0, 1), 12), ((1, 1), 15)]
+    got = np.array([C[shear.pairs(2).index(pq) * m["n_ell"] + b] for pq, b in cases])
+    pe = [(pq, ells[b]) for pq, b in cases]
+    cut = direct_limber(m, th, A, n_pk, pe, k_range=k_range)
+    uncut = direct_limber(m, th, A, n_pk, pe)
+    # the cut is a step in the integrand: first-order trapezoid error (measured
+    # 1.4e-3 at most on this grid)
+    np.testing.assert_allclose(got, cut, rtol=5e-3)
+    assert np.all(np.abs(uncut / cut - 1) > 0.3), uncut / cut
+    top = C[shear.pairs(2).index((0, 1)) * m["n_ell"] + m["n_ell"] - 1]
+    chi_H = 2 * C_KM_S / 70.0 * (1 - np.sqrt(m["a_min"]))
+    assert ells[-1] + 0.5 > k_range[1] * chi_H and top == 0.0
 
 
 def test_multiplicative_bias_and_photoz_shift():
