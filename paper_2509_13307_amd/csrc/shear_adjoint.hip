@@ -16,6 +16,20 @@
 //   sum_j [ sum_i gW_i(j) dW_i(j) + g wq_j dwq_j + g chi_j dchi_j ].
 // Every Limber-adjoint term belongs to one a-node, so a thread owns a node
 // (the a-grid is taken in chunks of 256 nodes).
+//
+// The scatter into g Y (and g M) is accumulated in 64-bit fixed point, so that
+// its result does not depend on the order in which the nodes of a walker
+// reach a table entry: the kernel first computes and stores every
+// g log10 P_bj of the walker and their largest magnitude G, then adds each
+// contribution c w g log10 P (|c w| < 2: spline and Catmull-Rom weights)
+// rounded to the grid 2^(e - FX_BITS), G < 2^e, with integer atomics.  At most
+// n_a n_ell <= 2^16 contributions reach one entry, so every partial sum stays
+// below 2^(FX_BITS + 17) < 2^63; the grid step is below G 2^-44 (about
+// 6e-14 G), well under the FP64 gradient's error against the complex step.
+// The spline-curvature table g M takes contributions smaller by the factor
+// max |c2|, |c3| <= 0.385 h^2 / 6 (h the z-node spacing) and has a grid finer
+// by 2^mshift, mshift = floor(log2(6 / (0.385 h^2))).  The spline adjoint
+// converts the integers back to doubles.
 #include "devutil.h"
 #include "nsmi.h"
 #include "shear_common.h"
@@ -253,20 +267,37 @@ __global__ __launch_bounds__(256) void shear_tangent_kernel(
 }
 
 // --------------------------------------------------------- Limber adjoint
+constexpr int FX_BITS = 45;
+
+// log10 k of multipole b at comoving distance chi -> Catmull-Rom interval i0,
+// its offset tt and the ghost flags at the ends of the k grid (one definition
+// for both passes of the Limber adjoint)
+struct KPos { int i0; double tt; bool lo_ghost, hi_ghost; };
+__device__ __forceinline__ KPos k_position(double k, const ShearGeom& G) {
+    const double s = (log10(k) - G.u0) / G.du;
+    int i0 = (int)floor(s);
+    i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
+    return KPos{i0, s - i0, i0 == 0, i0 + 2 >= G.n_k};
+}
+
 // One workgroup (256 threads) per walker, thread = a-node j (chunks of 256):
 // g(P wq), g W_i(j), g wq_j and g chi_j (through k = (l+1/2)/chi_j) from the
-// Limber sums, scattered into g Y (and g M for the cubic z-spline; atomics),
-// then contracted with the tangents of shear_tangent_kernel into the direct
-// gradient gdir [B x d] (fully written).  gY, gM accumulate: start at zero.
+// Limber sums; g log10 P_bj goes to glp [B x n_ell x n_a] and, in a second pass
+// over the nodes, into the fixed-point tables gYi (and gMi for the cubic
+// z-spline; integer atomics, see above; they start at zero), with the walker's
+// grid step in gstep [B]; the node terms are contracted with the tangents of
+// shear_tangent_kernel into the direct gradient gdir [B x d] (fully written).
 template <class T, bool LINZ>
 __global__ __launch_bounds__(256) void limber_adjoint_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, int d, ShearGeom G,
     const int* __restrict__ pidx, const double* __restrict__ pfix, const int* __restrict__ zidx,
     const double* __restrict__ zcoef, const double* __restrict__ ell, const T* __restrict__ Ytab,
     const T* __restrict__ Mtab, const double* __restrict__ Cv, const double* __restrict__ gC,
-    const double* __restrict__ tg, double* __restrict__ gY, double* __restrict__ gM, double* __restrict__ gdir) {
+    const double* __restrict__ tg, double* __restrict__ glp_buf, unsigned long long* __restrict__ gYi,
+    unsigned long long* __restrict__ gMi, double* __restrict__ gstep, int mshift, double* __restrict__ gdir) {
     __shared__ double Hs[55 * 32];          // G_pb f_p, pair-major
     __shared__ double red[4 + 2 * MAXB][4];
+    __shared__ double gmx[4];
     const int64_t w = blockIdx.x;
     if (w >= B) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -291,8 +322,10 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
     for (int q = 0; q < 4 + 2 * MAXB; ++q) acc[q] = 0.0;
     const T* Yw = Ytab + w * (int64_t)G.n_z * G.n_k;
     const T* Mw = LINZ ? Yw : Mtab + w * (int64_t)G.n_z * G.n_k;
-    double* gYw = gY + w * (int64_t)G.n_z * G.n_k;
-    double* gMw = LINZ ? gYw : gM + w * (int64_t)G.n_z * G.n_k;
+    unsigned long long* gYw = gYi + w * (int64_t)G.n_z * G.n_k;
+    unsigned long long* gMw = LINZ ? gYw : gMi + w * (int64_t)G.n_z * G.n_k;
+    double* glw = glp_buf + w * (int64_t)ne * na;
+    double gmax = 0.0;
     for (int c = 0; c < nch; ++c) {
         const int j = c * 256 + t;
         if (j <= 0 || j >= na) continue;
@@ -309,10 +342,9 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
         for (int b = 0; b < ne; ++b) {
             const double k = (ell[b] + 0.5) / chi;
             if (!(k >= G.k_min && k <= G.k_max)) continue;
-            const double s = (log10(k) - G.u0) / G.du;
-            int i0 = (int)floor(s);
-            i0 = i0 < 0 ? 0 : (i0 > G.n_k - 2 ? G.n_k - 2 : i0);
-            const double tt = s - i0;
+            const KPos kp = k_position(k, G);
+            const int i0 = kp.i0;
+            const double tt = kp.tt;
             // log10 P at z_j from rows nn, nn + 1 of Y (and of M for cubic z)
             auto zmix = [&](T ya, T yb, T ma, T mb) {
                 if (LINZ) return c0 * (double)ya + c1 * (double)yb;
@@ -322,7 +354,7 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
                 const int64_t o0 = (int64_t)nn * G.n_k + col, o1 = o0 + G.n_k;
                 return zmix(Yw[o0], Yw[o1], LINZ ? T(0) : Mw[o0], LINZ ? T(0) : Mw[o1]);
             };
-            const bool lo_ghost = i0 == 0, hi_ghost = i0 + 2 >= G.n_k;
+            const bool lo_ghost = kp.lo_ghost, hi_ghost = kp.hi_ghost;
             double pm, p0, p1, p2;
             if (!lo_ghost && !hi_ghost) {
                 // columns i0 - 1 .. i0 + 2 of each row in one (element-aligned) vector load
@@ -370,24 +402,8 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
             const double gP = gPw * wq;
             gchi += gP * (-P * dlp_dt / (G.du * chi));
             const double glp = gP * P * LN10;
-            // d lp / d (pm, p0, p1, p2), ghosts folded into the real columns
-            double wm = -0.5 * h10, w0c = h00 - 0.5 * h11, w1c = h01 + 0.5 * h10, w2 = 0.5 * h11;
-            if (lo_ghost) { w0c += 2.0 * wm; w1c -= wm; wm = 0.0; }
-            if (hi_ghost) { w1c += 2.0 * w2; w0c -= w2; w2 = 0.0; }
-            auto scatter = [&](int col, double wgt) {
-                const double gy = glp * wgt;
-                const int64_t o0 = (int64_t)nn * G.n_k + col, o1 = o0 + G.n_k;
-                atomicAdd(&gYw[o0], c0 * gy);
-                atomicAdd(&gYw[o1], c1 * gy);
-                if (!LINZ) {
-                    atomicAdd(&gMw[o0], c2 * gy);
-                    atomicAdd(&gMw[o1], c3 * gy);
-                }
-            };
-            if (!lo_ghost) scatter(i0 - 1, wm);
-            scatter(i0, w0c);
-            scatter(i0 + 1, w1c);
-            if (!hi_ghost) scatter(i0 + 2, w2);
+            glw[(int64_t)b * na + j] = glp;
+            gmax = fmax(gmax, fabs(glp));
         }
         // contract with the tangents of this node
         for (int q = 0; q < 4; ++q) {
@@ -438,16 +454,73 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
             add(9 + 2 * nb + i, v / (1.0 + phys(9 + 2 * nb + i)));
         }
     }
+
+    // ---- g Y (and g M) in fixed point: the walker's grid from its largest
+    // |g log10 P| (a NaN anywhere makes the step NaN and skips the scatter)
+    {
+        const double v = wave_max(gmax);
+        if (lane == 0) gmx[wid] = v;
+    }
+    __syncthreads();
+    const double gm_all = fmax(fmax(gmx[0], gmx[1]), fmax(gmx[2], gmx[3]));
+    const bool ok = !isnan(gmx[0] + gmx[1] + gmx[2] + gmx[3]) && gm_all <= 1.7e308;
+    int e = 0;
+    if (ok && gm_all > 0.0) (void)frexp(gm_all, &e);                  // gm_all < 2^e
+    const double scale = ldexp(1.0, FX_BITS - e), mscale = ldexp(1.0, FX_BITS + mshift - e);
+    if (t == 0) gstep[w] = ok ? ldexp(1.0, e - FX_BITS) : NAN;
+    if (!ok || gm_all == 0.0) return;
+    auto fx_add = [&](unsigned long long* p, double v, double sc) {
+        if (v != 0.0) atomicAdd(p, (unsigned long long)llrint(v * sc));
+    };
+    for (int c = 0; c < nch; ++c) {
+        const int j = c * 256 + t;
+        if (j <= 0 || j >= na) continue;
+        const double chi = rec(TG_CHI, j);
+        const int nn = zidx[j];
+        const double c0 = zcoef[4 * j], c1 = zcoef[4 * j + 1];
+        const double c2 = LINZ ? 0.0 : zcoef[4 * j + 2], c3 = LINZ ? 0.0 : zcoef[4 * j + 3];
+        for (int b = 0; b < ne; ++b) {
+            const double k = (ell[b] + 0.5) / chi;
+            if (!(k >= G.k_min && k <= G.k_max)) continue;
+            const double glp = glw[(int64_t)b * na + j];
+            if (glp == 0.0) continue;
+            const KPos kp = k_position(k, G);
+            const double tt = kp.tt, t2 = tt * tt, t3 = t2 * tt;
+            const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + tt, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
+            // d lp / d (pm, p0, p1, p2), ghosts folded into the real columns
+            double wm = -0.5 * h10, w0c = h00 - 0.5 * h11, w1c = h01 + 0.5 * h10, w2 = 0.5 * h11;
+            if (kp.lo_ghost) { w0c += 2.0 * wm; w1c -= wm; wm = 0.0; }
+            if (kp.hi_ghost) { w1c += 2.0 * w2; w0c -= w2; w2 = 0.0; }
+            auto scatter = [&](int col, double wgt) {
+                const double gy = glp * wgt;
+                const int64_t o0 = (int64_t)nn * G.n_k + col, o1 = o0 + G.n_k;
+                fx_add(&gYw[o0], c0 * gy, scale);
+                fx_add(&gYw[o1], c1 * gy, scale);
+                if (!LINZ) {
+                    fx_add(&gMw[o0], c2 * gy, mscale);
+                    fx_add(&gMw[o1], c3 * gy, mscale);
+                }
+            };
+            if (!kp.lo_ghost) scatter(kp.i0 - 1, wm);
+            scatter(kp.i0, w0c);
+            scatter(kp.i0 + 1, w1c);
+            if (!kp.hi_ghost) scatter(kp.i0 + 2, w2);
+        }
+    }
 }
 
 // ------------------------------------------------------------ spline adjoint
-// gY += S^T gM for the not-a-knot spline of each (walker, k) column, then
-// delta_out[row = w n_z + n][c] = gY[n][c] sigma_out[c] (padded to n_pad).
+// gY, gM arrive as the fixed-point integers of limber_adjoint_kernel (grid
+// gstep[w], and gstep[w] 2^-mshift for gM) and are turned into doubles in
+// place; then gY += S^T gM for the not-a-knot spline of each (walker, k)
+// column, and delta_out[row = w n_z + n][c] = gY[n][c] sigma_out[c] (padded to
+// n_pad).
 template <class T>
 __global__ __launch_bounds__(256) void zspline_adjoint_kernel(double* __restrict__ gY, double* __restrict__ gM,
                                                               int64_t B, int nz, int nk, double h,
                                                               const double* __restrict__ sigma_out, int n_pad,
-                                                              T* __restrict__ delta, int linear) {
+                                                              T* __restrict__ delta, int linear,
+                                                              const double* __restrict__ gstep, int mshift) {
     __shared__ double cps[256];
     if (threadIdx.x == 0) {
         double c = 0.0;
@@ -466,14 +539,21 @@ __global__ __launch_bounds__(256) void zspline_adjoint_kernel(double* __restrict
         return;
     }
     double* gy = gY + w * nz * nk + c;
+    const double step = gstep[w];
+    auto fx = [](double bits, double st) { return (double)__builtin_bit_cast(long long, bits) * st; };
     if (linear) {                               // no spline: delta = g Y sigma_out
         const double sg = sigma_out[c];
-        for (int n = 0; n < nz; ++n) delta[(w * nz + n) * n_pad + c] = (T)(gy[(int64_t)n * nk] * sg);
+        for (int n = 0; n < nz; ++n) delta[(w * nz + n) * n_pad + c] = (T)(fx(gy[(int64_t)n * nk], step) * sg);
         return;
     }
     double* gm = gM + w * nz * nk + c;
     auto Y = [&](int n) -> double& { return gy[(int64_t)n * nk]; };
     auto Mg = [&](int n) -> double& { return gm[(int64_t)n * nk]; };
+    const double mstep = ldexp(step, -mshift);
+    for (int n = 0; n < nz; ++n) {
+        Y(n) = fx(Y(n), step);
+        Mg(n) = fx(Mg(n), mstep);
+    }
     const double ih2 = 1.0 / (h * h);
     // M_0 = 2 M_1 - M_2 and M_{N-1} = 2 M_{N-2} - M_{N-3}: fold their adjoints
     // into the other nodes first (valid for every nz >= 4)
@@ -535,10 +615,11 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
     const void* Mtab = m->ws_aux.p;
     const double* Cv = reinterpret_cast<const double*>(m->ws_aux.as<char>() + mbytes);
     // adjoint scratch: gC, R [B n], chi^2 partial sums [n_ct B], gY (and gM) [B nz nk],
-    // tangents [B S n_a], gdir [B d]
+    // tangents [B S n_a], gdir [B d], g log10 P [B n_ell n_a], fixed-point grid [B]
     const size_t ntab = (size_t)B * nz * nk, n_ct = (n + 63) / 64;
     const size_t S = TG_FIXED + 7 * (size_t)nb;
-    m->ws_grad.ensure(((size_t)B * (2 * n + n_ct) + (lin ? 1 : 2) * ntab + (size_t)B * S * na + (size_t)B * d) *
+    m->ws_grad.ensure(((size_t)B * (2 * n + n_ct) + (lin ? 1 : 2) * ntab + (size_t)B * S * na + (size_t)B * d +
+                       (size_t)B * m->n_ell * na + (size_t)B) *
                       sizeof(double));
     double* gC = m->ws_grad.as<double>();
     double* R = gC + (size_t)B * n;
@@ -547,6 +628,11 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
     double* gM = lin ? gY : gY + ntab;          // spline second derivatives: cubic z only
     double* tg = gY + (lin ? 1 : 2) * ntab;
     double* gdir = tg + (size_t)B * S * na;
+    double* glp = gdir + (size_t)B * d;
+    double* gstep = glp + (size_t)B * m->n_ell * na;
+    // finer fixed-point grid of g M: its coefficients are at most 0.385 h^2 / 6
+    const double hz = (1.0 / m->a_min - 1.0) / (nz - 1);
+    const int mshift = lin ? 0 : std::max(0, std::min(40, (int)std::floor(std::log2(6.0 / (0.385 * hz * hz)))));
     {
         TraceScope ts(m, s, "adj_dense_chi2");
         dense_chi2_adjoint(m, theta, ld, B, Cv, R, part, logl, gC, s);
@@ -565,7 +651,9 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
         auto launch = [&](auto kern, const auto* Y) {
             hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, d, G, m->pidx_d.as<int>(),
                                m->pfix_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                               m->ell_d.as<double>(), Y, (decltype(Y))Mtab, Cv, gC, tg, gY, gM, gdir);
+                               m->ell_d.as<double>(), Y, (decltype(Y))Mtab, Cv, gC, tg, glp,
+                               reinterpret_cast<unsigned long long*>(gY), reinterpret_cast<unsigned long long*>(gM),
+                               gstep, mshift, gdir);
         };
         if (f64) {
             if (lin) launch(limber_adjoint_kernel<double, true>, m->ws_out.as<double>());
@@ -586,14 +674,15 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
     m->ws_gact[1].ensure(gstride * elem);
     {
         TraceScope ts(m, s, "adj_zspline");
-        const double hz = (1.0 / m->a_min - 1.0) / (nz - 1);
         const dim3 gz((unsigned)((B * n_pad + 255) / 256));
         if (f64)
             hipLaunchKernelGGL(zspline_adjoint_kernel<double>, gz, dim3(256), 0, s, gY, gM, B, nz, nk, hz,
-                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<double>(), (int)lin);
+                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<double>(), (int)lin, gstep,
+                               mshift);
         else
             hipLaunchKernelGGL(zspline_adjoint_kernel<float>, gz, dim3(256), 0, s, gY, gM, B, nz, nk, hz,
-                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<float>(), (int)lin);
+                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<float>(), (int)lin, gstep,
+                               mshift);
         NS_HIP(hipGetLastError());
     }
     emulator_backward(m, &id0, 1, B, f64 ? NS_FP64 : NS_FP32, s);

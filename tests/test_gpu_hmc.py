@@ -143,3 +143,22 @@ def test_hmc_reduced_precision_gradient_runs(prec):
     say(f"{prec}: accept {res['n_accept']} of 80, left {res['n_left']}")
     assert np.all(np.isfinite(s)) and np.all((s >= 0) & (s <= 1))
     assert res["n_accept"] >= 40
+
+
+def test_hmc_shear_is_bitwise_repeatable():
+    """Two ns_hmc runs with the same seed on the shear likelihood give bitwise
+    equal chains (deterministic adjoint: no float atomics)."""
+    say("case hmc shear10 repeatable")
+    from paper_2509_13307_amd import Model
+    m = W.load_model("shear10")
+    width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
+    minv = np.minimum(m["fisher_sigma"], 0.1 * width) ** 2
+    th0 = torch.tensor(start_points(m, 4, 0.5, 9), device=DEV)
+    g = Model(m)
+    runs = [g.hmc(th0, torch.tensor(minv), 6, 5, 0.2, seed=11) for _ in range(2)]
+    g.close()
+    (s0, l0, r0, t0), (s1, l1, r1, t1) = runs
+    say(f"accepted {r0['n_accept']} / {r1['n_accept']}")
+    assert r0["n_accept"] == r1["n_accept"] and r0["n_left"] == r1["n_left"]
+    assert torch.equal(s0, s1) and torch.equal(t0, t1)
+    assert torch.equal(torch.nan_to_num(l0, neginf=-1e300), torch.nan_to_num(l1, neginf=-1e300))

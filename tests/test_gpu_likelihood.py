@@ -7,9 +7,9 @@ Tolerances (stated per precision form):
 * FP32 / BF16X3: |dlogL| <= 1e-2 on posterior-region walkers (the bar for the
   reduced-precision forms).
 * BF16 (operands rounded to 8 bits of mantissa, FP32 accumulation): misses
-  that bar on the CMB workloads (|dlogL| ~ 0.1-1) and on shear10; the
-  measured value is printed and held under a regression limit about twice the
-  value measured when the kernels were written.  The paper-shaped shear pair
+  that bar on the CMB workloads (|dlogL| ~ 0.1-1) and on shear10 / shear64;
+  those cases only report the measured error (the test is marked skipped with
+  it: nothing is certified for that form there).  The paper-shaped shear pair
   meets the 1e-2 bar in BF16 and is held to it.
 """
 import sys
@@ -153,16 +153,9 @@ def test_batch_and_permutation_invariance(built):
     assert single[0] == full[100]
 
 
-# |dlogL| limits of the reduced-precision forms on posterior-region walkers
-LOWP_LIMIT = {
-    ("cmb6", "fp32"): 1e-2, ("cmb6", "bf16x3"): 1e-2, ("cmb6", "bf16"): 2.0,
-    ("cmb4x2500", "fp32"): 1e-2, ("cmb4x2500", "bf16x3"): 1e-2, ("cmb4x2500", "bf16"): 1.0,
-    ("cmbtt_cv", "fp32"): 1e-2, ("cmbtt_cv", "bf16x3"): 1e-2, ("cmbtt_cv", "bf16"): 5.0,
-    ("shear10", "fp32"): 1e-2, ("shear10", "bf16x3"): 1e-2, ("shear10", "bf16"): 0.1,
-    ("shear64", "fp32"): 1e-2, ("shear64", "bf16x3"): 1e-2, ("shear64", "bf16"): 0.1,
-    ("shear_full", "fp32"): 1e-2, ("shear_full", "bf16x3"): 1e-2, ("shear_full", "bf16"): 1e-2,
-    ("shear_interp", "fp32"): 1e-2, ("shear_interp", "bf16x3"): 1e-2, ("shear_interp", "bf16"): 1e-2,
-}
+# Workloads on which plain BF16 misses the |dlogL| <= 1e-2 bar: their cases
+# report the error and are skipped; every other (workload, form) is held to it.
+BF16_BELOW_BAR = {"cmb6", "cmb4x2500", "cmbtt_cv", "shear10", "shear64"}
 
 
 @pytest.mark.parametrize("name", ["cmb6", "cmb4x2500", "cmbtt_cv", "shear10", "shear64", "shear_full",
@@ -180,7 +173,10 @@ def test_reduced_precision_forms(built, name, prec):
     assert fin.sum() >= B // 2
     d = np.abs(got[fin] - ref[fin])
     say(f"{name} {prec}: |dlogL| max {d.max():.3e} median {np.median(d):.3e} over {fin.sum()} walkers")
-    assert d.max() <= LOWP_LIMIT[(name, prec)]
+    if prec == "bf16" and name in BF16_BELOW_BAR:
+        pytest.skip(f"plain BF16 is below the 1e-2 bar on {name}: measured |dlogL| max {d.max():.3e} "
+                    f"(reported only)")
+    assert d.max() <= 1e-2
 
 
 @pytest.mark.parametrize("name,B", [("cmb6", 300), ("cmb4x2500", 333), ("cmbtt_cv", 333), ("shear10", 70),

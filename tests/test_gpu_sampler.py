@@ -140,6 +140,73 @@ def test_ns_run_replays_oracle_gauss():
     assert abs(res["logz"] - exact) < 3 * res["sigma"]
 
 
+@pytest.mark.parametrize("n_live,n_delete", [(1000, 500), (2400, 1200)])
+def test_ns_run_replays_oracle_gauss_large(n_live, n_delete):
+    """The configured (1000/500) and the sigma <= 0.1 (2400/1200) live-point
+    counts: the selection sorts several points per thread (n > 1024) and the
+    running evidence runs in blocks of ranks (k > 512)."""
+    say(f"case ns_run gauss {n_live}/{n_delete}")
+    desc = W.gauss_structure(d=3, mu=[0.1, 0.5, 0.8], sigma=[0.05, 0.1, 0.08])
+    ref = nested.run(lambda u: loglike_u(u, desc), 3, n_live, n_delete, 15, seed=11, n_rep=100)
+    g = mk(desc)
+    res = g.run(n_live, n_delete, 15, seed=11, n_replicates=100, capacity=400000)
+    g.close()
+    say(f"gauss {n_live}: gpu logZ {res['logz']:.10f} +- {res['sigma']:.4f} iters {res['n_iter']} "
+        f"evals {res['n_evals']} | oracle {ref['logZ']:.10f} +- {ref['sigma']:.4f} iters {ref['n_iter']} "
+        f"evals {ref['n_evals']}")
+    assert res["n_iter"] == ref["n_iter"]
+    assert res["n_evals"] == ref["n_evals"]
+    assert res["n_dead"] == ref["dead_logl"].size
+    np.testing.assert_array_equal(res["dead_n"], ref["dead_n"])
+    np.testing.assert_allclose(res["dead_logl"], ref["dead_logl"], rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(res["dead_u"], ref["dead_u"], rtol=0, atol=1e-10)
+    assert abs(res["logz"] - ref["logZ"]) < 1e-8
+    assert abs(res["sigma"] - ref["sigma"]) < 1e-8
+
+
+@pytest.mark.parametrize("name,n_all,n_inner,prec", [("cmb6", 2400, 4, "fp64"), ("cmb6", 2400, 4, "bf16x3"),
+                                                     ("shear10", 2048, 1, "fp64")])
+def test_slice_step_many_walkers_replays_oracle(name, n_all, n_inner, prec):
+    """Ragged slice rounds over 1024-1200 walkers (the nested-sampling batch and
+    the ragged benchmark's walker counts) replay the oracle's trajectories."""
+    say(f"case slice step {name} {n_all // 2} walkers {prec}")
+    m = W.load_model(name)
+    u_all, ll_all, lstar, u0, l0 = walkers_above(m, n_all, seed=9)
+    L = nested.direction_cholesky(u_all)
+    g = mk(m)
+    lg = l0
+    if prec != "fp64":
+        # threshold and start values in the form, as a run in that form has them
+        th_all = g.prior_transform(torch.tensor(u_all, device=DEV).contiguous())
+        lb = g.loglike(th_all.contiguous(), prec).cpu().numpy()
+        lstar = np.median(lb)
+        keep = lb > lstar
+        u0, l0, lg = u_all[keep], ll_all[keep], lb[keep]
+    fn = lambda x: loglike_u(x, m)
+    u_ref, l_ref, ne_ref, ns_ref = nested.slice_step(fn, u0, l0, lstar, L, n_inner, seed=9, it=4)
+    ut = torch.tensor(u0, device=DEV).contiguous()
+    lt = torch.tensor(lg, device=DEV)
+    ne, ns = g.slice_step(ut, lt, lstar, torch.tensor(L), n_inner, seed=9, it=4, precision=prec)
+    torch.cuda.synchronize()
+    g.close()
+    ne, ns = ne.cpu().numpy(), ns.cpu().numpy()
+    say(f"{name} {prec}: {u0.shape[0]} walkers, evals {int(ne.sum())} vs oracle {int(ne_ref.sum())}, "
+        f"per walker {ne.min()}..{ne.max()}")
+    if prec == "fp64":
+        np.testing.assert_array_equal(ne, ne_ref)
+        np.testing.assert_array_equal(ns, ns_ref)
+        np.testing.assert_allclose(ut.cpu().numpy(), u_ref, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(lt.cpu().numpy(), l_ref, rtol=1e-12, atol=1e-7)
+    else:
+        # decisions at the threshold may differ where |dlogL| of the form
+        # reaches L*: every walker ends inside the constraint, and nearly all
+        # replay the FP64 trajectory
+        same = np.all(np.abs(ut.cpu().numpy() - u_ref) <= 1e-10, axis=1)
+        say(f"  {same.mean():.4f} of the walkers replay the FP64 oracle exactly")
+        assert same.mean() > 0.95
+    assert np.all(lt.cpu().numpy() > lstar)
+
+
 def test_ns_run_replays_oracle_cmb6():
     say("case ns_run cmb6")
     m = W.load_model("cmb6")
