@@ -7,9 +7,12 @@
  * GPU-accelerated Nested Sampling and Neural Emulators" (Lovick et al.,
  * arXiv:2509.13307) and runs nested slice sampling on them:
  *
- *   - neural-emulator likelihoods of CMB spectra with a Gaussian chi^2
- *     (Sec. 2.3),
- *   - the tomographic cosmic-shear likelihood of App. A: emulated P(k, z),
+ *   - neural-emulator likelihoods of CMB spectra (Sec. 2.3-2.4): the
+ *     cosmic-variance-limited TT likelihood of Sec. 2.4 and Gaussian chi^2
+ *     forms of the same emulators,
+ *   - the tomographic cosmic-shear likelihood of Sec. 2.5 and App. A:
+ *     emulated P(k, z) (on every redshift node, or on a coarser grid
+ *     interpolated in z as in App. B),
  *     extended Limber projection Eq. (A2) with lensing and intrinsic-alignment
  *     windows Eqs. (A3)-(A4), summed as in Eq. (A1), multiplicative shear bias
  *     and photo-z shifts, and a dense-covariance Gaussian,
@@ -52,6 +55,10 @@ typedef enum {
     NS_E_NOT_SPD = -5,     /* covariance not symmetric positive definite      */
     NS_E_UNSUPPORTED = -6  /* valid request this build does not implement     */
 } ns_status;
+/* A slice step whose bracket collapses without finding a point inside the
+ * constraint keeps its walker where it was and is counted (n_stalls of
+ * ns_slice_step, ns_run_result.n_stalls); it is not an error, so there is no
+ * stall status code. */
 
 /* Arithmetic of the emulator and projection stages.  The final Gaussian
  * chi^2 (Cholesky whitening, reductions) and all sampler bookkeeping are FP64
@@ -68,15 +75,15 @@ typedef enum {
 typedef enum {
     NS_MODEL_CMB_DIAG = 0,   /* one emulator, Gaussian with diagonal covariance */
     NS_MODEL_CMB_BLOCK = 1,  /* TT, TE, EE, PP emulators; 3x3 block + diagonal  */
-    NS_MODEL_SHEAR = 2,      /* cosmic shear, App. A                            */
+    NS_MODEL_SHEAR = 2,      /* cosmic shear, Sec. 2.5 and App. A               */
     NS_MODEL_GAUSS = 3,      /* diagonal Gaussian in theta (closed-form evidence) */
     NS_MODEL_CMB_CV = 4      /* TT emulator, cosmic-variance-limited likelihood:
-                                (2l+1) Ch_l / C_l ~ chi^2 with 2l+1 d.o.f. (Sec. 2.3) */
+                                (2l+1) Ch_l / C_l ~ chi^2 with 2l+1 d.o.f. (Sec. 2.4) */
 } ns_model_kind;
 
 enum { NS_PRIOR_UNIFORM = 0, NS_PRIOR_NORMAL = 1 };
 
-/* One emulator network (Sec. 2.2 and 2.4: CosmoPower-style MLP):
+/* One emulator network (Sec. 2.2, 2.4 and 2.5: CosmoPower-style MLP):
  *   x   = (inputs - in_shift) / in_scale
  *   h_l = f_l(W_l h_{l-1} + b_l),  f_l(t) = (gamma_l + (1 - gamma_l) sigmoid(beta_l t)) t
  *   y   = out_mu + out_sigma * (W_L h_{L-1} + b_L)
@@ -148,8 +155,12 @@ typedef struct ns_model_desc {
 
 typedef struct ns_model ns_model; /* opaque, library-owned */
 
-/* Create a model on HIP device `device`: copies weights, data and grids to the
- * device and factorises the covariance in FP64 on the host.
+/* Create a model on HIP device `device`: the likelihood L(theta) and prior
+ * pi(theta) of the evidence integral Eq. (1) -- priors of Table 1, emulator
+ * networks (Sec. 2.2), the CMB likelihoods (Sec. 2.3-2.4) or the cosmic-shear
+ * likelihood (Sec. 2.5, App. A-B).  Copies weights, data and grids to the
+ * device and factorises the covariance in FP64 on the host.  *out receives a
+ * library-owned handle (release with ns_model_free).
  * Errors: NS_E_INVALID / NS_E_SHAPE for bad descriptions, NS_E_NOT_SPD when a
  * covariance (block) has no Cholesky factor, NS_E_HIP / NS_E_NOMEM. */
 ns_status ns_model_create(const ns_model_desc* desc, int32_t device, ns_model** out);
@@ -166,9 +177,14 @@ ns_status ns_model_dim(const ns_model* model, int32_t* d);
 ns_status ns_prior_transform(ns_model* model, const double* u, double* theta, int64_t ld,
                              int64_t B, void* stream);
 
-/* Batched log-likelihood logL(theta_b), b < B (the hot path: emulator ->
- * [Limber + nuisances] -> Gaussian chi^2).
- * theta: device [B x ld]; logl: device [B].  Asynchronous on stream.
+/* Batched log-likelihood logL(theta_b), b < B: the likelihood of Eq. (1)
+ * evaluated for many parameter points at once, which Sec. 2.2 names the
+ * bottleneck of the parallel sampler (emulator -> [Limber projection Eqs.
+ * (A1)-(A4) + nuisances] -> Gaussian chi^2, or the cosmic-variance sum of
+ * Sec. 2.4).  All constants are included (logL is a normalised density of the
+ * data), so log Z from it is a normalised evidence.
+ * theta: device [B x ld] (caller-owned, read only); logl: device [B]
+ * (caller-owned, written).  Asynchronous on stream.
  * B = 0 is a no-op.  NS_E_UNSUPPORTED for precisions a model kind lacks. */
 ns_status ns_loglike_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
                            double* logl, int32_t precision, void* stream);
@@ -176,7 +192,7 @@ ns_status ns_loglike_batch(ns_model* model, const double* theta, int64_t ld, int
 /* Theory vector of every walker: the prediction the likelihood compares with
  * the data, in the data's order, after every stage before the chi^2 (or the
  * cosmic-variance sum), by the same kernels as ns_loglike_batch.
- *   CMB_DIAG: the emulator outputs y (Sec. 3.1); CMB_BLOCK: C^TT | C^TE |
+ *   CMB_DIAG: the emulator outputs y (Sec. 2.3); CMB_BLOCK: C^TT | C^TE |
  *   C^EE | C^pp, each n_ell long, C = 10^y where spec_log is 1; CMB_CV:
  *   C^TT_l = 10^y; SHEAR: C_ij(l_b) after the multiplicative bias
  *   (Eqs. (A1)-(A4)), pairs i <= j in lexicographic order, then l_b.
@@ -188,8 +204,14 @@ ns_status ns_loglike_batch(ns_model* model, const double* theta, int64_t ld, int
 ns_status ns_theory_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
                           double* out, int64_t ldo, int32_t precision, void* stream);
 
-/* As ns_loglike_batch, plus grad: device [B x d], d logL / d theta by the
- * hand-written adjoint of every stage (input gradients only). */
+/* As ns_loglike_batch, plus grad: device [B x d] (caller-owned, written),
+ * d logL / d theta by the hand-written adjoint of every stage (input
+ * gradients only): the gradients that Sec. 2.2 notes an automatically
+ * differentiable likelihood makes available to gradient-based samplers
+ * (Sec. 4.2).  Rows outside the prior support get logL = -inf and grad = 0.
+ * FP64 form: every stage in double; the reduced forms run the forward pass in
+ * their form and the adjoint in FP32.  Deterministic: repeated calls give
+ * bitwise equal results.  Asynchronous on stream. */
 ns_status ns_loglike_grad_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
                                 double* logl, double* grad, int32_t precision, void* stream);
 

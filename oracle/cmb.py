@@ -1,7 +1,8 @@
-"""Gaussian CMB-style likelihoods (Sec. 2.3 of the paper; Gaussian form).
+"""CMB likelihoods: Gaussian forms and the cosmic-variance-limited TT likelihood
+(Sec. 2.3-2.4 of the paper).
 
 The paper's CMB analysis emulates C_l and evaluates them against mock data
-(Sec. 2.3).  The workloads here use a Gaussian chi^2 of the emulated model
+(Sec. 2.4).  The workloads here use a Gaussian chi^2 of the emulated model
 vector against a synthetic data vector:
 
 * diagonal covariance (one emulator, raw outputs):
@@ -15,7 +16,7 @@ vector against a synthetic data vector:
   with L_l the lower Cholesky factor of Sigma_l.
 
 Cosmic-variance-limited temperature likelihood (the paper's CMB analysis,
-Sec. 2.3): with no noise, (2l+1) Ch_l / C_l follows a chi^2 distribution with
+Sec. 2.4): with no noise, (2l+1) Ch_l / C_l follows a chi^2 distribution with
 k = 2l+1 degrees of freedom, so the density of the observed Ch_l given the
 emulated C_l = 10^y_l is p(Ch_l | C_l) = (k / C_l) f_k(k Ch_l / C_l), with
       log f_k(x) = (k/2 - 1) log x - x/2 - (k/2) log 2 - log Gamma(k/2),

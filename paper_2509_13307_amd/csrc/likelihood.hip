@@ -1,5 +1,5 @@
-// Gaussian chi^2 stages of the CMB-style likelihoods (Sec. 2.3 of the paper,
-// Gaussian form), the diagonal-Gaussian test likelihood, the prior transform
+// Gaussian chi^2 stages of the CMB likelihoods (Gaussian forms of the
+// emulated spectra of Sec. 2.3-2.4), the diagonal-Gaussian test likelihood, the prior transform
 // (Table 1) and the per-kind dispatch of the batched likelihood.
 //
 // All chi^2 arithmetic is FP64 whatever the emulator precision: the model

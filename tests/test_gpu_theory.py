@@ -1,5 +1,5 @@
 """Element-by-element parity of the theory vector (ns_theory_batch) with the
-FP64 oracle: the CMB spectra after the output transform (Sec. 3.1) and the
+FP64 oracle: the CMB spectra after the output transform (Sec. 2.4) and the
 tomographic shear spectra after the multiplicative bias (Eqs. (A1)-(A4)),
 entry by entry, at every workload shape.
 
