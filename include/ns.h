@@ -235,7 +235,7 @@ ns_status ns_slice_step(ns_model* model, double* u, double* logl, int32_t* n_eva
                         void* stream);
 
 typedef struct ns_run_opts {
-    int32_t n_live;          /* live points n                                  */
+    int32_t n_live;          /* live points n (2 .. 4096)                       */
     int32_t n_delete;        /* k deleted and evolved in parallel per iteration */
     int32_t n_inner;         /* slice steps per walker per iteration            */
     int32_t precision;       /* ns_precision of the likelihood                  */
@@ -243,6 +243,11 @@ typedef struct ns_run_opts {
     uint64_t seed;
     int32_t max_iter;
     int32_t n_replicates;    /* shrinkage replicates for sigma(log Z)           */
+    const char* checkpoint_path; /* host, NUL-terminated file name, or NULL    */
+    int32_t checkpoint_every;    /* > 0: write the run's state after every
+                                    iteration that is a multiple of this       */
+    int32_t resume;              /* 1: continue from checkpoint_path if that
+                                    file exists (else start afresh)            */
 } ns_run_opts;
 
 typedef struct ns_run_result {
@@ -254,7 +259,8 @@ typedef struct ns_run_result {
     int64_t n_evals;
     int64_t n_stalls;
     int64_t n_dead;
-    double wall_s;
+    double wall_s;           /* wall time of this call                          */
+    int64_t resumed_iter;    /* iteration the run continued from (0: fresh)     */
 } ns_run_result;
 
 /* Nested slice sampling to convergence (Sec. 2.1-2.2): k-deletion, slice
@@ -262,7 +268,17 @@ typedef struct ns_run_result {
  * Optional outputs (host, may be NULL): dead_logl [capacity], dead_n
  * [capacity], dead_u [capacity x d]; if the run produces more than `capacity`
  * dead points only the first `capacity` are written (result->n_dead has the
- * total).  Synchronous. */
+ * total).  Synchronous.
+ * Checkpoints: with checkpoint_path set, the state at the end of an iteration
+ * (live points, dead points, evidence accumulators, iteration index) is
+ * written to that file after every checkpoint_every-th iteration and when
+ * max_iter ends the run (written to "<path>.tmp", then renamed).  A call with
+ * resume = 1 and the same model and options (n_live, n_delete, n_inner,
+ * precision, seed, frac_remain; max_iter may grow) continues from the file:
+ * every random number is addressed by (seed, iteration, walker, step, draw)
+ * and every reduction has a fixed order, so the continued run gives bitwise
+ * the result of an uninterrupted one.  NS_E_INVALID if the file is not a
+ * checkpoint of this library or belongs to other options. */
 ns_status ns_run(ns_model* model, const ns_run_opts* opts, ns_run_result* result,
                  double* dead_logl, int32_t* dead_n, double* dead_u, int64_t capacity,
                  void* stream);

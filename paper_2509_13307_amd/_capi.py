@@ -80,6 +80,9 @@ class RunOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("max_iter", ctypes.c_int32),
         ("n_replicates", ctypes.c_int32),
+        ("checkpoint_path", ctypes.c_char_p),
+        ("checkpoint_every", ctypes.c_int32),
+        ("resume", ctypes.c_int32),
     ]
 
 
@@ -94,6 +97,7 @@ class RunResult(ctypes.Structure):
         ("n_stalls", ctypes.c_int64),
         ("n_dead", ctypes.c_int64),
         ("wall_s", ctypes.c_double),
+        ("resumed_iter", ctypes.c_int64),
     ]
 
 

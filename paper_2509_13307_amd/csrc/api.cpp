@@ -210,6 +210,22 @@ static Net* build_net(const ns_net_desc& nd, int mu_rows) {
                 upload(ly->gamma32, ga.data(), (size_t)N);
             }
         }
+        net->narrow64 = narrow_f64_shape(net->dims);
+        if (net->narrow64) {
+            std::vector<double> f64;
+            for (int l = 1; l < nd.n_layers; ++l) {
+                const int K = net->dims[l], N = net->dims[l + 1], NT = (N + 15) / 16, K4 = K / 4;
+                const size_t base = f64.size();
+                f64.resize(base + (size_t)K4 * NT * 64, 0.0);
+                for (int kq = 0; kq < K4; ++kq)
+                    for (int nt = 0; nt < NT; ++nt)
+                        for (int q = 0; q < 64; ++q) {
+                            const int n = nt * 16 + q % 16, k = kq * 4 + q / 16;
+                            if (n < N) f64[base + ((size_t)kq * NT + nt) * 64 + q] = nd.W[l][(size_t)n * K + k];
+                        }
+            }
+            upload(net->Wf64, f64.data(), f64.size());
+        }
         if (net->fused) {
             upload(net->Wf, fh.data(), fh.size());
             upload(net->Wfl, fl.data(), fl.size());
@@ -253,6 +269,8 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
             NS_CHECK(D->prior_b[i] > 0.0, NS_E_INVALID, "normal prior needs sigma > 0");
     }
     upload(m->prior_kind, D->prior_kind, (size_t)D->d);
+    m->any_normal_prior = false;
+    for (int i = 0; i < D->d; ++i) m->any_normal_prior = m->any_normal_prior || D->prior_kind[i] == NS_PRIOR_NORMAL;
     upload(m->prior_a, D->prior_a, (size_t)D->d);
     upload(m->prior_b, D->prior_b, (size_t)D->d);
 
@@ -524,7 +542,6 @@ static void check_prec(int p) {
 
 ns_model::~ns_model() {
     for (auto* n : nets) delete n;
-    if (host_pinned) (void)hipHostFree(host_pinned);
     for (auto& r : trace_recs) {
         (void)hipEventDestroy(r.e0);
         (void)hipEventDestroy(r.e1);

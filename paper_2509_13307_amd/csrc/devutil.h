@@ -93,11 +93,23 @@ __device__ __forceinline__ u64x4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c
 
 __device__ __forceinline__ double u01(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
 
-// draw q of the sequence (c1, c2, c3) under key (seed, stream)
+// draw q of the sequence (c1, c2, c3) under key (seed, stream): word q mod 4
+// of Philox block q / 4 (picked by selects, not by a run-time array index,
+// which would put the block in scratch memory)
 __device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t stream, uint64_t c1,
                                                  uint64_t c2, uint64_t c3, uint64_t q) {
-    u64x4 b = philox4x64(q >> 2, c1, c2, c3, seed, stream);
-    return u01(b.x[q & 3]);
+    const u64x4 b = philox4x64(q >> 2, c1, c2, c3, seed, stream);
+    const int r = (int)(q & 3);
+    return u01(r == 0 ? b.x[0] : r == 1 ? b.x[1] : r == 2 ? b.x[2] : b.x[3]);
+}
+
+// draws q and q + 1 (q even) of the sequence: one Philox block
+__device__ __forceinline__ void philox_uniform_pair(uint64_t seed, uint64_t stream, uint64_t c1, uint64_t c2,
+                                                    uint64_t c3, uint64_t q, double& a, double& b) {
+    const u64x4 x = philox4x64(q >> 2, c1, c2, c3, seed, stream);
+    const bool hi = (q & 2) != 0;
+    a = u01(hi ? x.x[2] : x.x[0]);
+    b = u01(hi ? x.x[3] : x.x[1]);
 }
 
 }  // namespace nsmi

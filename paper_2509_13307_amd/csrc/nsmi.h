@@ -103,6 +103,12 @@ struct Net {
     // GEMM layer (3H floats each) followed by the output bias.
     bool fused = false;
     DevBuf Wf, Wfl, fvec;
+    // One-kernel FP64 forward (networks that pass narrow_f64_shape): weights
+    // of GEMM layers 2..L in v_mfma_f64_16x16x4f64 fragment order, layer after
+    // layer; block (kq, nt) of a layer with NT = ceil(N / 16) column tiles at
+    // (kq NT + nt) 64, lane q holding W[16 nt + q % 16][4 kq + q / 16] (0 past N)
+    bool narrow64 = false;
+    DevBuf Wf64;
     ~Net();
 };
 
@@ -116,6 +122,7 @@ enum { SRC_FIXED = -1, SRC_ZNODE = -2 };
 struct ns_model {
     int kind = 0, d = 0, device = 0;
     nsmi::DevBuf prior_kind, prior_a, prior_b;
+    bool any_normal_prior = false;   // some parameter has a normal prior (its map needs erfinv)
     std::vector<nsmi::Net*> nets;
     std::vector<int> spec_log;
     int n_data = 0;
@@ -171,8 +178,7 @@ struct ns_model {
     nsmi::DevBuf ws_gact[2];         // adjoint activations ping-pong [G x rows x n_pad]
     nsmi::DevBuf ws_gx;              // input gradients [G x rows x n_in]
     nsmi::DevBuf ws_hmc;             // HMC chain state
-    void* host_pinned = nullptr;     // pinned host flag for completion polling
-    hipStream_t graph_stream = nullptr;  // stream the captured slice-step graphs replay on
+    hipStream_t graph_stream = nullptr;  // stream the captured sampler graphs replay on
     hipEvent_t graph_event = nullptr;
     bool shear_attr_set = false;     // hipFuncSetAttribute done for the Limber kernels
     std::bitset<96> fused_attr_set;  // ... and per instance of the one-kernel emulator
@@ -277,6 +283,25 @@ void prior_transform(ns_model* m, const double* u, double* theta, int64_t ld, in
 __device__ __forceinline__ double prior_map(double x, int kind, double a, double b) {
     return kind == NS_PRIOR_UNIFORM ? a + (b - a) * x : a + b * 1.4142135623730950488 * erfinv(2.0 * x - 1.0);
 }
+
+// theta outside a uniform prior's [a, b] -> false (NaN compares false: kept)
+__device__ __forceinline__ bool in_support(const double* th, int d, const int* kind, const double* a,
+                                           const double* b) {
+    bool ok = true;
+    for (int i = 0; i < d; ++i)
+        if (kind[i] == NS_PRIOR_UNIFORM && (th[i] < a[i] || th[i] > b[i])) ok = false;
+    return ok;
+}
+
+// Networks the one-kernel FP64 forward supports: 3..8 layers, <= 16 inputs,
+// every hidden width 64 or 128, <= 256 outputs.
+bool narrow_f64_shape(const std::vector<int>& dims);
+// One-kernel FP64 forward of a model's single narrow network (rows = B,
+// outputs [B x ldo] in out), or with logl != nullptr the diagonal-Gaussian
+// logL of a CMB_DIAG model instead of the outputs; false without launching
+// when the model does not fit it.
+bool emulator_forward_f64_narrow(ns_model* m, const double* theta, int64_t ld, int64_t B, double* out,
+                                 int64_t ldo, int is_log, double* logl, const int* count, hipStream_t s);
 
 // Name of candidate c of the one-kernel forward (width 512 or 128, split form or not).
 const char* fused_cfg_name(int h512, int x3, int c);

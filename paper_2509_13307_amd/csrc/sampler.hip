@@ -16,17 +16,28 @@
 // round's likelihood values and runs every walker forward until it needs a
 // new evaluation, appending that proposal (in the cube and mapped through the
 // prior) to a compacted batch; the batched likelihood then runs on the
-// compacted rows only.  The batch size and the count of unfinished walkers
-// live in two counter pairs used by rounds of alternating parity, so each
-// round's advance clears the pair of the next round and no separate reset
-// launch is needed.  Every random number is addressed by (walker, step,
-// draw), so the result does not depend on the order of the compacted rows.
+// compacted rows only.  Round c uses counter slot c mod 3 (batch size and
+// unfinished walkers): it reads slot c-1 (all walkers finished there: the
+// round returns at once, and so does the likelihood on its empty batch),
+// fills slot c and clears slot c+1 for the next round, so a fixed sequence of
+// rounds can be replayed without host work in between.  Every random number
+// is addressed by (walker, step, draw), so the result does not depend on the
+// order of the compacted rows.
 //
-// Nested-sampling bookkeeping (k-deletion, the running evidence) runs in
-// single-workgroup kernels; the host only polls a termination flag.  The
-// final log Z, H and the replicate log Z for the error bar (FP64) are
+// A nested-sampling run is driven from the device: one captured graph of 24
+// rounds with a control kernel before every 8th round, launched again and
+// again.  The control kernel (one workgroup) finishes an iteration once its
+// walkers have all stopped (replacement, live term, stopping rule) and begins
+// the next one (selection of the k lowest, dead records, running evidence,
+// direction factor, spawn of the walkers); between those points it does
+// nothing.  The host keeps one graph launch ahead and reads a small control
+// block after each, so it only acts at checkpoints, buffer growth and the end.
+// The final log Z, H and the replicate log Z for the error bar (FP64) are
 // parallel over the dead points: prefix sums of the log-shrinkages, then a
 // max-shifted sum of exponentials.
+#include <cstdio>
+#include <memory>
+
 #include "devutil.h"
 #include "nsmi.h"
 
@@ -58,15 +69,19 @@ struct SliceState {
     double* xc;       // [2k x d] compacted proposals (unit cube)
     int* cidx;        // [2k] walker of each compact slot
     double* llc;      // [2k] likelihood of each compact slot
-    int* ccount;      // [2] compact batch size of the rounds of even / odd parity
-    int* active;      // [2] walkers not done after the advance of such a round
+    int* ccount;      // [3] compact batch size of the rounds of slot c mod 3
+    int* active;      // [3] walkers not done after the advance of such a round
 };
 
-__global__ void slice_init_kernel(SliceState S, int64_t k) {
+// Walkers at their first step; counters for a first round in slot 0 (slot 2,
+// "the round before", marked unfinished); the walk's iteration index.
+__global__ void slice_init_kernel(SliceState S, int64_t k, int64_t* iter_p, uint64_t iter) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w == 0) {
-        S.ccount[0] = S.ccount[1] = 0;
+        S.ccount[0] = S.ccount[1] = S.ccount[2] = 0;
         S.active[0] = S.active[1] = 0;
+        S.active[2] = 1;
+        *iter_p = (int64_t)iter;
     }
     if (w >= k) return;
     S.st[w] = ST_NEWSTEP;
@@ -77,42 +92,61 @@ __global__ void slice_init_kernel(SliceState S, int64_t k) {
     S.n_stalls[w] = 0;
 }
 
-// One wave per walker, lane i = coordinate i (d <= 64).  The walker's phase
-// state is uniform across the wave and kept in registers; the direction draw
-// (lane i: Box-Muller of draws 2i, 2i+1), the product with L (lane i sums row
-// i in column order, as a serial loop would) and the proposal are spread over
-// the lanes, so every value is bitwise that of one thread per walker.
+// A group of GS lanes per walker (GS the power of two >= d, at least 8, so a
+// wave carries 64 / GS walkers), lane i of the group = coordinate i.  The
+// walker's phase state is uniform across its group and kept in registers;
+// the direction draw (lane i: Box-Muller of draws 2i, 2i+1), the product with
+// L (lane i sums row i in column order, as a serial loop would) and the
+// proposals are spread over the group's lanes, so every value is bitwise that
+// of one thread per walker.  A walker stops at its next needed evaluation(s):
+// at most two proposals (both ends while stepping out, or one shrink point),
+// written after its state machine has run, with compact slots taken by one
+// atomic per wave.  NORMAL: some prior is normal (its map needs erfinv, whose
+// FP64 form alone takes more than half the registers; without it the kernel
+// fits four waves per SIMD).
+template <int GS, bool NORMAL>
 __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_t k, int d,
                                                             const double* __restrict__ lstar_p,
                                                             const double* __restrict__ L, int n_inner,
-                                                            uint64_t seed, uint64_t iter, int par,
+                                                            uint64_t seed, const int64_t* __restrict__ iter_p,
+                                                            int round,
                                                             const int* __restrict__ pk, const double* __restrict__ pa,
                                                             const double* __restrict__ pb,
                                                             double* __restrict__ thc) {
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    // the counters of the other parity were last read by the previous round's
-    // likelihood, which has finished: clear them for the next round
+    constexpr int WPW = 64 / GS;
+    const int lane = threadIdx.x & 63, lg = lane & (GS - 1), gb = lane - lg;
+    const int64_t w = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * WPW + lane / GS;
+    const int slot = round % 3, prev = (round + 2) % 3, next = (round + 1) % 3;
+    // slot c+1 was last read by round c-1, which has finished: clear it for
+    // the next round; if no walker was left after the round before, there is
+    // nothing to do (this round's slot is already clear)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        S.ccount[par ^ 1] = 0;
-        S.active[par ^ 1] = 0;
+        S.ccount[next] = 0;
+        S.active[next] = 0;
     }
-    // the walker's state is requested first (the idle waves of the last block
-    // read walker k - 1 and leave after the barrier); the direction factor
-    // goes to LDS meanwhile, so that the row products of a new direction
-    // read LDS instead of waiting on one global load per column
-    const int64_t wr = w < k ? w : k - 1;
-    const bool act = lane < d;
+    if (S.active[prev] == 0) return;
+    const uint64_t iter = (uint64_t)*iter_p;
+    // the walker's state is requested first (groups past the last walker read
+    // walker k - 1 and take no part); the direction factor goes to LDS
+    // meanwhile, so that the row products of a new direction read LDS
+    // instead of waiting on one global load per column
+    const bool live = w < k;
+    const int64_t wr = live ? w : k - 1;
+    const bool act = lg < d;
     const double lstar = *lstar_p;
     int st = S.st[wr], step = S.step[wr], q = S.q[wr], ne = S.ne[wr], pend = S.pend[wr];
     int ne2 = S.ne2[wr], pend2 = S.pend2[wr];
     int nev = S.n_evals[wr], nst = S.n_stalls[wr];
     double tl = S.tl[wr], tr = S.tr[wr], tp = S.tp[wr], logl = S.logl[wr];
-    double ui = act ? S.u[wr * d + lane] : 0.0, vi = act ? S.v[wr * d + lane] : 0.0;
+    double ui = act ? S.u[wr * d + lg] : 0.0, vi = act ? S.v[wr * d + lg] : 0.0;
     __shared__ double Ls[MAX_DIM * MAX_DIM];
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) Ls[e] = L[e];
     __syncthreads();
-    if (w >= k) return;                                   // whole waves
+    if (!live) {
+        st = ST_DONE;
+        pend = pend2 = -1;
+    }
+    const uint64_t gmask = GS == 64 ? ~0ull : (((1ull << GS) - 1) << gb);
     bool moved = false;
     // outcome of a shrink proposal at t = tp
     auto shrink = [&](bool inside, double ll) {
@@ -130,21 +164,11 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             }
         }
     };
-    // the point at t along the direction: its compact slot, or -1 outside the
-    // unit cube (no evaluation: outside the constraint)
-    auto propose = [&](double t) -> int {
+    // the point at t along the direction lies in the unit cube (outside it
+    // needs no evaluation: it is outside the constraint)
+    auto inbox = [&](double t) {
         const double xi = __dadd_rn(ui, __dmul_rn(t, vi));
-        const bool inbox = __ballot(act && !((xi >= 0.0) && (xi <= 1.0))) == 0;
-        if (!inbox) return -1;
-        int slot = 0;
-        if (lane == 0) slot = atomicAdd(S.ccount + par, 1);
-        slot = __shfl(slot, 0, 64);
-        if (act) {
-            S.xc[(int64_t)slot * d + lane] = xi;
-            thc[(int64_t)slot * d + lane] = prior_map(xi, pk[lane], pa[lane], pb[lane]);
-        }
-        if (lane == 0) S.cidx[slot] = (int)w;
-        return slot;
+        return (__ballot(act && !((xi >= 0.0) && (xi <= 1.0))) & gmask) == 0;
     };
     // last round's evaluations
     if (st == ST_OUT) {
@@ -166,6 +190,8 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
         nev += 1;
         shrink(ll > lstar, ll);
     }
+    bool e0 = false, e1 = false;       // proposals: e0 at t0 (left end or shrink point), e1 at tr
+    double t0 = 0.0;
     while (true) {
         if (st == ST_DONE) break;
         if (st == ST_NEWSTEP) {
@@ -173,17 +199,17 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             const int s = ++step;
             double z = 0.0;
             if (act) {
-                const double u1 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * lane);
-                const double u2 = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * lane + 1);
+                double u1, u2;
+                philox_uniform_pair(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)lg, u1, u2);
                 z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
             }
             double acc = 0.0;
             for (int j = 0; j < d; ++j) {
-                const double zj = __shfl(z, j, 64);
-                if (act && j <= lane) acc = __dadd_rn(acc, __dmul_rn(Ls[lane * d + j], zj));
+                const double zj = __shfl(z, gb + j, 64);
+                if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
             }
             vi = act ? acc : 0.0;
-            const double r = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * d);
+            const double r = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)d);
             tl = -r;
             tr = 1.0 - r;
             q = 2 * d + 1;
@@ -199,14 +225,14 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             // and the final bracket are those of stepping out one end after
             // the other
             if (ne >= 0) {
-                if (ne >= MAX_EXPAND) ne = -1;
-                else if ((pend = propose(tl)) < 0) ne = -1;
+                if (ne < MAX_EXPAND && inbox(tl)) { e0 = true; t0 = tl; }
+                else ne = -1;
             }
             if (ne2 >= 0) {
-                if (ne2 >= MAX_EXPAND) ne2 = -1;
-                else if ((pend2 = propose(tr)) < 0) ne2 = -1;
+                if (ne2 < MAX_EXPAND && inbox(tr)) e1 = true;
+                else ne2 = -1;
             }
-            if (pend >= 0 || pend2 >= 0) break;
+            if (e0 || e1) break;
             st = ST_SHRINK;
             ne = 0;
             continue;
@@ -214,23 +240,50 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
         const int qq = q++;
         const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)qq);
         tp = __dadd_rn(tl, __dmul_rn(U, __dsub_rn(tr, tl)));
-        if ((pend = propose(tp)) < 0) {
-            shrink(false, -INFINITY);
-            continue;
+        if (inbox(tp)) { e0 = true; t0 = tp; break; }
+        shrink(false, -INFINITY);
+    }
+    // compact slots: exclusive prefix of the walkers' proposal counts over the
+    // wave (group leaders hold them), one atomic for the wave
+    const int nemit = (lg == 0) ? (int)e0 + (int)e1 : 0;
+    int inc = nemit;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    const int total = __shfl(inc, 63, 64);
+    int base = 0;
+    if (lane == 0 && total > 0) base = atomicAdd(S.ccount + slot, total);
+    base = __shfl(base, 0, 64) + __shfl(inc - nemit, gb, 64);
+#pragma unroll 1
+    for (int e = 0; e < 2; ++e) {
+        if (!(e == 0 ? e0 : e1)) continue;
+        const int cs = base + (e == 1 && e0 ? 1 : 0);
+        const double xi = __dadd_rn(ui, __dmul_rn(e == 0 ? t0 : tr, vi));
+        if (act) {
+            S.xc[(int64_t)cs * d + lg] = xi;
+            thc[(int64_t)cs * d + lg] = NORMAL ? prior_map(xi, pk[lg], pa[lg], pb[lg]) : pa[lg] + (pb[lg] - pa[lg]) * xi;
         }
-        break;
+        if (lg == 0) S.cidx[cs] = (int)w;
+        if (e == 0) pend = cs;
+        else pend2 = cs;
     }
-    if (act) {
-        if (moved) S.u[w * d + lane] = ui;
-        S.v[w * d + lane] = vi;
+    if (live) {
+        if (act) {
+            if (moved) S.u[w * d + lg] = ui;
+            S.v[w * d + lg] = vi;
+        }
+        if (lg == 0) {
+            S.st[w] = st; S.step[w] = step; S.q[w] = q; S.ne[w] = ne; S.pend[w] = pend;
+            S.ne2[w] = ne2; S.pend2[w] = pend2;
+            S.n_evals[w] = nev; S.n_stalls[w] = nst;
+            S.tl[w] = tl; S.tr[w] = tr; S.tp[w] = tp; S.logl[w] = logl;
+        }
     }
-    if (lane == 0) {
-        S.st[w] = st; S.step[w] = step; S.q[w] = q; S.ne[w] = ne; S.pend[w] = pend;
-        S.ne2[w] = ne2; S.pend2[w] = pend2;
-        S.n_evals[w] = nev; S.n_stalls[w] = nst;
-        S.tl[w] = tl; S.tr[w] = tr; S.tp[w] = tp; S.logl[w] = logl;
-        if (st != ST_DONE) atomicAdd(S.active + par, 1);
-    }
+    // unfinished walkers: one atomic for the wave
+    const uint64_t busy = __ballot(live && lg == 0 && st != ST_DONE);
+    if (lane == 0 && busy) atomicAdd(S.active + slot, (int)__popcll(busy));
 }
 
 // ------------------------------------------------------------- NS kernels
@@ -245,241 +298,34 @@ struct NSState {
     int stop;
 };
 
+// Control block of a run (device memory): where the device-driven iteration
+// stands and why it stopped, read by the host after each graph launch.
+struct NSCtl {
+    int64_t it;          // iteration of the walkers (1-based); between iterations the last finished one
+    int64_t max_iter;
+    int64_t ckpt_every;  // > 0: pause after iterations that are multiples of it
+    int need_begin;      // the next control point begins iteration it + 1
+    int walking;         // the walkers of iteration it are stepping
+    int pause;           // stopped at an iteration boundary for a checkpoint
+    int grow;            // stopped at an iteration boundary: dead-point storage too small
+    int done;            // 1: stopping rule met, 2: max_iter reached
+    int pad;
+};
+
+// Dead-point storage of a run (device memory, so that it can grow between
+// launches of a captured graph).
+struct DeadBuf {
+    double* dl;       // [cap] logL
+    int* dn;          // [cap] live points at death
+    double* du;       // [cap x d] unit-cube position
+    int64_t cap;
+};
+
 __device__ __forceinline__ double logaddexp(double a, double b) {
     if (a == -INFINITY) return b;
     if (b == -INFINITY) return a;
     const double m = fmax(a, b);
     return m + log1p(exp(-fabs(a - b)));
-}
-
-// Bitonic sort of (logl, index) for n <= 4096 in one workgroup of 1024 threads;
-// then the k lowest die: dead-point records and the running evidence (FP64).
-__global__ __launch_bounds__(1024) void ns_select_kernel(const double* __restrict__ logl,
-                                                         const double* __restrict__ u, int n, int k, int d,
-                                                         int* __restrict__ order, NSState* __restrict__ S,
-                                                         double* __restrict__ dead_logl, int* __restrict__ dead_n,
-                                                         double* __restrict__ dead_u, int64_t dead_cap,
-                                                         int record) {
-    __shared__ double key[4096];
-    __shared__ int idx[4096];
-    int N2 = 1;
-    while (N2 < n) N2 <<= 1;
-    for (int i = threadIdx.x; i < N2; i += blockDim.x) {
-        key[i] = i < n ? logl[i] : INFINITY;
-        idx[i] = i < n ? i : 0x7fffffff;
-    }
-    __syncthreads();
-    for (int size = 2; size <= N2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < N2; i += blockDim.x) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const bool up = (i & size) == 0;
-                    const double ki = key[i], kj = key[j];
-                    const int ii = idx[i], ij = idx[j];
-                    // (logl, index) lexicographic; NaN sorts after +inf
-                    const bool gt = (ki > kj) || (ki == kj && ii > ij) || (isnan(ki) && !isnan(kj));
-                    if (gt == up) {
-                        key[i] = kj; key[j] = ki;
-                        idx[i] = ij; idx[j] = ii;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = idx[i];
-    __syncthreads();
-    if (!record) return;
-    const int64_t base = S->n_dead;
-    for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
-        const int j = e / d, c = e % d;
-        if (base + j < dead_cap) dead_u[(base + j) * d + c] = u[(int64_t)idx[j] * d + c];
-    }
-    for (int j = threadIdx.x; j < k; j += blockDim.x)
-        if (base + j < dead_cap) {
-            dead_logl[base + j] = key[j];
-            dead_n[base + j] = n - j;
-        }
-    // The running log Z is the serial chain of log-additions in death order
-    // (the stopping rule reads it).  Its per-death terms 1/n_j and
-    // log(1 - e^{-1/n_j}) depend on the rank only: the workgroup tabulates
-    // them for a block of ranks, then one thread runs the chain over the block.
-    constexpr int QB = 512;
-    __shared__ double qinv[QB], qlog[QB];
-    double logx = S->logx, logz = S->logz;
-    for (int j0 = 0; j0 < k; j0 += QB) {
-        __syncthreads();
-        for (int j = j0 + threadIdx.x; j < min(k, j0 + QB); j += blockDim.x) {
-            const double inv = 1.0 / (double)(n - j);
-            qinv[j - j0] = inv;
-            qlog[j - j0] = log(-expm1(-inv));
-        }
-        __syncthreads();
-        if (threadIdx.x == 0)
-#pragma unroll 8
-            for (int j = j0; j < min(k, j0 + QB); ++j) {
-                const double logw = logx + qlog[j - j0];
-                logz = logaddexp(logz, key[j] + logw);
-                logx -= qinv[j - j0];
-            }
-    }
-    if (threadIdx.x == 0) {
-        S->logx = logx;
-        S->logz = logz;
-        S->lstar = key[k - 1];
-        S->n_dead = base + k;
-    }
-}
-
-// Live-point covariance (1/(n-1)), trace jitter, Cholesky (lower, row-major).
-// The live points pass through LDS in chunks of whole points (coalesced
-// loads); each mean and each covariance entry is still one thread's sum over
-// the points in index order.
-__global__ __launch_bounds__(256) void ns_dircov_kernel(const double* __restrict__ u, int n, int d,
-                                                        double* __restrict__ L) {
-    constexpr int STAGE = 3072;                            // doubles of staged points
-    constexpr int EPT = MAX_DIM * MAX_DIM / 256;           // covariance entries per thread at most
-    __shared__ double mean[MAX_DIM];
-    __shared__ double S[MAX_DIM * MAX_DIM];
-    __shared__ double X[STAGE];
-    const int pc = STAGE / d;                              // points per chunk
-    auto stage = [&](int i0, int i1) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < (i1 - i0) * d; e += blockDim.x) X[e] = u[(int64_t)i0 * d + e];
-        __syncthreads();
-    };
-    double s = 0.0;
-    for (int i0 = 0; i0 < n; i0 += pc) {
-        const int i1 = min(n, i0 + pc);
-        stage(i0, i1);
-        if (threadIdx.x < d)
-            for (int i = i0; i < i1; ++i) s += X[(i - i0) * d + threadIdx.x];
-    }
-    if (threadIdx.x < d) mean[threadIdx.x] = s / n;
-    double acc[EPT];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) acc[q] = 0.0;
-    for (int i0 = 0; i0 < n; i0 += pc) {
-        const int i1 = min(n, i0 + pc);
-        stage(i0, i1);                                     // its first barrier also publishes mean
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            if (e >= d * d) break;
-            const int a = e / d, b = e % d;
-            if (b > a) continue;
-            const double ma = mean[a], mb = mean[b];
-            for (int i = i0; i < i1; ++i) acc[q] += (X[(i - i0) * d + a] - ma) * (X[(i - i0) * d + b] - mb);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        if (e >= d * d) break;
-        const int a = e / d, b = e % d;
-        if (b > a) continue;
-        S[a * d + b] = S[b * d + a] = acc[q] / (n - 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tr = 0.0;
-        for (int a = 0; a < d; ++a) tr += S[a * d + a];
-        const double jit = 1e-12 * tr / d;
-        for (int a = 0; a < d; ++a) S[a * d + a] += jit;
-        for (int j = 0; j < d; ++j) {
-            double s = S[j * d + j];
-            for (int p = 0; p < j; ++p) s -= S[j * d + p] * S[j * d + p];
-            const double djj = sqrt(fmax(s, 0.0));
-            S[j * d + j] = djj;
-            for (int i = j + 1; i < d; ++i) {
-                double t = S[i * d + j];
-                for (int p = 0; p < j; ++p) t -= S[i * d + p] * S[j * d + p];
-                S[i * d + j] = djj > 0.0 ? t / djj : 0.0;
-            }
-        }
-        for (int a = 0; a < d; ++a)
-            for (int b = 0; b < d; ++b) L[a * d + b] = b <= a ? S[a * d + b] : 0.0;
-    }
-}
-
-// Walker w starts at survivor floor(U (n-k)) (draw 0 of step 0).
-__global__ void ns_spawn_kernel(const double* __restrict__ u, const double* __restrict__ logl,
-                                const int* __restrict__ order, int n, int k, int d, uint64_t seed,
-                                uint64_t iter, double* __restrict__ wu, double* __restrict__ wl) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= k) return;
-    const double U = philox_uniform(seed, 0, (uint64_t)w, 0, iter, 0);
-    int pick = (int)floor(U * (double)(n - k));
-    pick = pick > n - k - 1 ? n - k - 1 : pick;
-    const int src = order[k + pick];
-    for (int c = 0; c < d; ++c) wu[(int64_t)w * d + c] = u[(int64_t)src * d + c];
-    wl[w] = logl[src];
-}
-
-__global__ void ns_replace_kernel(double* __restrict__ u, double* __restrict__ logl,
-                                  const int* __restrict__ order, int k, int d, const double* __restrict__ wu,
-                                  const double* __restrict__ wl) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= k) return;
-    const int dst = order[w];
-    for (int c = 0; c < d; ++c) u[(int64_t)dst * d + c] = wu[(int64_t)w * d + c];
-    logl[dst] = wl[w];
-}
-
-// live term log(X mean_live L) and the stopping rule
-__global__ __launch_bounds__(256) void ns_term_kernel(const double* __restrict__ logl, int n,
-                                                      NSState* __restrict__ S, double log_frac) {
-    __shared__ double red[4];
-    double m = -INFINITY;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, logl[i]);
-    m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    __syncthreads();
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += exp(logl[i] - mx);
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double tot = red[0] + red[1] + red[2] + red[3];
-        const double live = mx + log(tot) - log((double)n) + S->logx;
-        S->live_term = live;
-        S->stop = (live - logaddexp(S->logz, live)) < log_frac ? 1 : 0;
-    }
-}
-
-// initial live points: u[i][c] = draw c of (walker i, step 0, iteration 0)
-__global__ void ns_init_kernel(double* __restrict__ u, int n, int d, uint64_t seed, NSState* S) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) {
-        S->logx = 0.0; S->logz = -INFINITY; S->lstar = -INFINITY; S->live_term = 0.0;
-        S->n_dead = 0; S->n_evals = n; S->n_stalls = 0; S->stop = 0;
-    }
-    if (e >= (int64_t)n * d) return;
-    const int i = (int)(e / d), c = (int)(e % d);
-    u[e] = philox_uniform(seed, 0, (uint64_t)i, 0, 0, (uint64_t)c);
-}
-
-// final: live points die in ascending order with counts n, n-1, ..., 1
-__global__ void ns_final_kernel(const double* __restrict__ logl, const double* __restrict__ u,
-                                const int* __restrict__ order, int n, int d, NSState* __restrict__ S,
-                                double* __restrict__ dead_logl, int* __restrict__ dead_n,
-                                double* __restrict__ dead_u, int64_t dead_cap) {
-    const int64_t base = S->n_dead;
-    for (int e = threadIdx.x; e < n * d; e += blockDim.x) {
-        const int j = e / d, c = e % d;
-        if (base + j < dead_cap) dead_u[(base + j) * d + c] = u[(int64_t)order[j] * d + c];
-    }
-    for (int j = threadIdx.x; j < n; j += blockDim.x)
-        if (base + j < dead_cap) {
-            dead_logl[base + j] = logl[order[j]];
-            dead_n[base + j] = n - j;
-        }
-    __syncthreads();
-    if (threadIdx.x == 0) S->n_dead = base + n;
 }
 
 // Exclusive prefix sum of one value per thread over a workgroup of NT threads
@@ -513,6 +359,338 @@ __device__ double block_max(double v, double* buf) {
     double r = buf[0];
     for (int w = 1; w < nw; ++w) r = fmax(r, buf[w]);
     return r;
+}
+
+// Bitonic sort of (logl, index) for n <= 4096 by one workgroup: key [N2]
+// doubles and idx [N2] ints in LDS, N2 = n rounded up to a power of two
+// (padding +inf, index 2^31 - 1); ties by index, NaN after +inf.
+__device__ void sort_live(const double* __restrict__ logl, int n, double* key, int* idx) {
+    int N2 = 1;
+    while (N2 < n) N2 <<= 1;
+    for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+        key[i] = i < n ? logl[i] : INFINITY;
+        idx[i] = i < n ? i : 0x7fffffff;
+    }
+    __syncthreads();
+    for (int size = 2; size <= N2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const double ki = key[i], kj = key[j];
+                    const int ii = idx[i], ij = idx[j];
+                    const bool gt = (ki > kj) || (ki == kj && ii > ij) || (isnan(ki) && !isnan(kj));
+                    if (gt == up) {
+                        key[i] = kj; key[j] = ki;
+                        idx[i] = ij; idx[j] = ii;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+constexpr int CTL_NT = 1024;
+constexpr int CTL_LDS = 4096 + 2080 + MAX_DIM;   // doubles: sort keys + indices, or dircov's regions
+
+// Direction factor by one workgroup of CTL_NT threads: live-point covariance
+// (1/(n-1)), trace jitter 1e-12 tr/d, lower Cholesky factor L (row-major).
+// Each mean and each covariance entry is a sum over the points split into a
+// fixed number of strided parts (part p takes points p, p + P, ..., in index
+// order), and the parts are added in order.  lds: CTL_LDS doubles.
+__device__ void dircov_block(const double* __restrict__ u, int n, int d, double* __restrict__ L, double* lds) {
+    constexpr int NT = CTL_NT, STAGE = 4096;
+    double* X = lds;                                   // staged points, then the covariance [d x d]
+    double* P = lds + STAGE;                           // partial sums (<= 2080)
+    double* mean = P + 2080;                           // [d]
+    const int t = threadIdx.x;
+    {
+        const int spm = NT / d, c = t % d, sp = t / d;
+        double s = 0.0;
+        if (sp < spm)
+            for (int i = sp; i < n; i += spm) s += u[(int64_t)i * d + c];
+        __syncthreads();
+        if (sp < spm) P[sp * d + c] = s;
+        __syncthreads();
+        if (t < d) {
+            double m = 0.0;
+            for (int q = 0; q < spm; ++q) m += P[q * d + t];
+            mean[t] = m / n;
+        }
+        __syncthreads();
+    }
+    const int ne = d * (d + 1) / 2;
+    const int spc = ne <= NT ? NT / ne : 1;            // parts per entry
+    constexpr int EPT = (MAX_DIM * (MAX_DIM + 1) / 2 + NT - 1) / NT;
+    int ea[EPT], eb[EPT], sp = 0;
+    double acc[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        int e = -1;
+        if (ne <= NT) {
+            if (q == 0 && t < spc * ne) { e = t % ne; sp = t / ne; }
+        } else if (t + NT * q < ne) {
+            e = t + NT * q;
+        }
+        int a = 0;
+        if (e >= 0)
+            while ((a + 1) * (a + 2) / 2 <= e) ++a;
+        ea[q] = e >= 0 ? a : -1;
+        eb[q] = e >= 0 ? e - a * (a + 1) / 2 : 0;
+        acc[q] = 0.0;
+    }
+    const int pc = STAGE / d;                          // points per staged chunk
+    for (int i0 = 0; i0 < n; i0 += pc) {
+        const int i1 = min(n, i0 + pc);
+        __syncthreads();
+        for (int x = t; x < (i1 - i0) * d; x += NT) X[x] = u[(int64_t)i0 * d + x];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            if (ea[q] < 0) continue;
+            const int a = ea[q], b = eb[q];
+            const double ma = mean[a], mb = mean[b];
+            const int first = i0 + (((sp - i0) % spc) + spc) % spc;
+            for (int i = first; i < i1; i += spc) acc[q] += (X[(i - i0) * d + a] - ma) * (X[(i - i0) * d + b] - mb);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+        if (ea[q] >= 0) P[ne <= NT ? sp * ne + (ea[q] * (ea[q] + 1) / 2 + eb[q]) : t + NT * q] = acc[q];
+    __syncthreads();
+    for (int e = t; e < ne; e += NT) {
+        double v = 0.0;
+        for (int q = 0; q < spc; ++q) v += P[q * ne + e];
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= e) ++a;
+        const int b = e - a * (a + 1) / 2;
+        X[a * d + b] = X[b * d + a] = v / (n - 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+        double tr = 0.0;
+        for (int a = 0; a < d; ++a) tr += X[a * d + a];
+        const double jit = 1e-12 * tr / d;
+        for (int a = 0; a < d; ++a) X[a * d + a] += jit;
+        for (int j = 0; j < d; ++j) {
+            double s = X[j * d + j];
+            for (int p = 0; p < j; ++p) s -= X[j * d + p] * X[j * d + p];
+            const double djj = sqrt(fmax(s, 0.0));
+            X[j * d + j] = djj;
+            for (int i = j + 1; i < d; ++i) {
+                double v = X[i * d + j];
+                for (int p = 0; p < j; ++p) v -= X[i * d + p] * X[j * d + p];
+                X[i * d + j] = djj > 0.0 ? v / djj : 0.0;
+            }
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) L[a * d + b] = b <= a ? X[a * d + b] : 0.0;
+    }
+}
+
+// Control point of a run, placed before slice round `round` of the graph (one
+// workgroup of CTL_NT threads).
+//  Finish: if iteration `it` is walking and no walker was left after the
+//   round before, add the walkers' evaluation and stall counts, put the
+//   walkers in the dead points' slots, compute the live term
+//   log(X mean_live L) and the stopping rule, and decide: done (rule or
+//   max_iter), grow (dead storage cannot take k more), pause (checkpoint
+//   due) or begin the next iteration.
+//  Begin (iteration it + 1): order the live points by (logL, index); the k
+//   lowest die with live counts n, ..., n-k+1 (dead records; log X shrinks
+//   by 1/n_j per death; running log Z += the log-sum-exp of
+//   logL_j + log X_{j-1} + log(1 - e^{-1/n_j}), each term formed as a serial
+//   chain would form it); L* = the largest dead logL; walker w starts at
+//   survivor floor(U (n-k)) (draw 0 of step 0 of the iteration); the
+//   direction factor from the live points before the deletion.
+// Between those points it returns at once.
+__global__ __launch_bounds__(CTL_NT) void ns_control_kernel(NSCtl* __restrict__ ctl, NSState* __restrict__ S,
+                                                            const DeadBuf* __restrict__ db, SliceState W,
+                                                            double* __restrict__ live_u, double* __restrict__ live_l,
+                                                            int* __restrict__ order, double* __restrict__ L, int n,
+                                                            int k, int d, uint64_t seed, double log_frac, int round) {
+    __shared__ double lds[CTL_LDS];
+    __shared__ double red[CTL_NT / 64];
+    __shared__ double s_logx;
+    __shared__ int s_begin;
+    const int t = threadIdx.x;
+    const int prev = (round + 2) % 3;
+    const int64_t it0 = ctl->it;
+    const int walking = ctl->walking, need_begin = ctl->need_begin;
+    const int left = W.active[prev];
+    __syncthreads();                                  // every thread has read ctl before it changes
+    int begin = need_begin;
+    if (walking && left == 0) {
+        long long a = 0, b = 0;
+        for (int w = t; w < k; w += CTL_NT) {
+            a += W.n_evals[w];
+            b += W.n_stalls[w];
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        for (int e = t; e < k * d; e += CTL_NT) {
+            const int w = e / d, c = e - w * d;
+            live_u[(int64_t)order[w] * d + c] = W.u[e];
+        }
+        for (int w = t; w < k; w += CTL_NT) live_l[order[w]] = W.logl[w];
+        __syncthreads();
+        double mx = -INFINITY;
+        for (int i = t; i < n; i += CTL_NT) mx = fmax(mx, live_l[i]);
+        mx = block_max(mx, red);
+        double se = 0.0;
+        for (int i = t; i < n; i += CTL_NT) se += exp(live_l[i] - mx);
+        se = block_sum(se, red);
+        __shared__ long long cnt[2][CTL_NT / 64];
+        if ((t & 63) == 0) {
+            cnt[0][t >> 6] = a;
+            cnt[1][t >> 6] = b;
+        }
+        __syncthreads();
+        if (t == 0) {
+            long long ta = 0, tb = 0;
+            for (int q = 0; q < CTL_NT / 64; ++q) {
+                ta += cnt[0][q];
+                tb += cnt[1][q];
+            }
+            S->n_evals += ta;
+            S->n_stalls += tb;
+            const double live = mx + log(se) - log((double)n) + S->logx;
+            S->live_term = live;
+            S->stop = (live - logaddexp(S->logz, live)) < log_frac ? 1 : 0;
+            ctl->walking = 0;
+            int nb = 0;
+            if (S->stop) ctl->done = 1;
+            else if (it0 >= ctl->max_iter) ctl->done = 2;
+            else if (S->n_dead + k > db->cap) ctl->grow = 1;
+            else if (ctl->ckpt_every > 0 && it0 % ctl->ckpt_every == 0) ctl->pause = 1;
+            else nb = 1;
+            s_begin = nb;
+        }
+        __syncthreads();
+        begin = s_begin;
+    }
+    if (!begin) return;
+
+    const int64_t it1 = it0 + 1;
+    double* key = lds;
+    int* idx = reinterpret_cast<int*>(lds + 4096);
+    sort_live(live_l, n, key, idx);
+    const DeadBuf D = *db;
+    const int64_t base = S->n_dead;
+    const double logx0 = S->logx, logz0 = S->logz;
+    for (int e = t; e < k * d; e += CTL_NT) {
+        const int j = e / d, c = e - j * d;
+        D.du[(base + j) * d + c] = live_u[(int64_t)idx[j] * d + c];
+    }
+    for (int j = t; j < k; j += CTL_NT) {
+        D.dl[base + j] = key[j];
+        D.dn[base + j] = n - j;
+    }
+    // running evidence: thread t takes ranks [4t, 4t + 4) (k < 4096)
+    constexpr int RPT = 4;
+    const int j0 = min(k, t * RPT), j1 = min(k, j0 + RPT);
+    double sinv = 0.0;
+    for (int j = j0; j < j1; ++j) sinv += 1.0 / (double)(n - j);
+    double lx = logx0 - block_exclusive_sum<CTL_NT>(sinv, red);
+    double v[RPT], mloc = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        v[r] = -INFINITY;
+        const int j = j0 + r;
+        if (j < j1) {
+            const double inv = 1.0 / (double)(n - j);
+            v[r] = key[j] + (lx + log(-expm1(-inv)));
+            lx -= inv;
+            mloc = fmax(mloc, v[r]);
+        }
+    }
+    if (j0 < j1 && j1 == k) s_logx = lx;               // log X after the k deaths
+    const double mall = block_max(mloc, red);
+    double se = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+        if (v[r] > -INFINITY) se += exp(v[r] - mall);
+    se = block_sum(se, red);
+    if (t == 0) {
+        S->logz = logaddexp(logz0, mall > -INFINITY ? mall + log(se) : -INFINITY);
+        S->logx = s_logx;
+        S->lstar = key[k - 1];
+        S->n_dead = base + k;
+    }
+    for (int i = t; i < n; i += CTL_NT) order[i] = idx[i];
+    // spawn: survivor floor(U (n - k)), U = draw 0 of (walker, step 0, iteration it + 1);
+    // the source index waits in W.pend until the copy
+    for (int w = t; w < k; w += CTL_NT) {
+        const double U = philox_uniform(seed, 0, (uint64_t)w, 0, (uint64_t)it1, 0);
+        int pick = (int)floor(U * (double)(n - k));
+        pick = pick > n - k - 1 ? n - k - 1 : pick;
+        W.pend[w] = idx[k + pick];
+        W.logl[w] = key[k + pick];
+    }
+    __syncthreads();
+    for (int e = t; e < k * d; e += CTL_NT) {
+        const int w = e / d, c = e - w * d;
+        W.u[e] = live_u[(int64_t)W.pend[w] * d + c];
+    }
+    __syncthreads();
+    for (int w = t; w < k; w += CTL_NT) {
+        W.st[w] = ST_NEWSTEP;
+        W.step[w] = 0;
+        W.pend[w] = -1;
+        W.pend2[w] = -1;
+        W.n_evals[w] = 0;
+        W.n_stalls[w] = 0;
+    }
+    dircov_block(live_u, n, d, L, lds);                // its first barrier ends the sort's use of lds
+    if (t == 0) {
+        W.active[prev] = 1;                            // the next round runs
+        ctl->it = it1;
+        ctl->walking = 1;
+        ctl->need_begin = 0;
+    }
+}
+
+// order of the live points by (logL, index), one workgroup
+__global__ __launch_bounds__(CTL_NT) void ns_sort_kernel(const double* __restrict__ logl, int n,
+                                                         int* __restrict__ order) {
+    __shared__ double key[4096];
+    __shared__ int idx[4096];
+    sort_live(logl, n, key, idx);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = idx[i];
+}
+
+// initial live points: u[i][c] = draw c of (walker i, step 0, iteration 0)
+__global__ void ns_init_kernel(double* __restrict__ u, int n, int d, uint64_t seed, NSState* S) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        S->logx = 0.0; S->logz = -INFINITY; S->lstar = -INFINITY; S->live_term = 0.0;
+        S->n_dead = 0; S->n_evals = n; S->n_stalls = 0; S->stop = 0;
+    }
+    if (e >= (int64_t)n * d) return;
+    const int i = (int)(e / d), c = (int)(e % d);
+    u[e] = philox_uniform(seed, 0, (uint64_t)i, 0, 0, (uint64_t)c);
+}
+
+// final: live points die in ascending order with counts n, n-1, ..., 1
+__global__ void ns_final_kernel(const double* __restrict__ logl, const double* __restrict__ u,
+                                const int* __restrict__ order, int n, int d, NSState* __restrict__ S,
+                                double* __restrict__ dead_logl, int* __restrict__ dead_n,
+                                double* __restrict__ dead_u, int64_t dead_cap) {
+    const int64_t base = S->n_dead;
+    for (int e = threadIdx.x; e < n * d; e += blockDim.x) {
+        const int j = e / d, c = e % d;
+        if (base + j < dead_cap) dead_u[(base + j) * d + c] = u[(int64_t)order[j] * d + c];
+    }
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        if (base + j < dead_cap) {
+            dead_logl[base + j] = logl[order[j]];
+            dead_n[base + j] = n - j;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) S->n_dead = base + n;
 }
 
 // log Z and H from the expected shrinkage log X_i = -sum_{m<i} 1/n_m (Eq. (1)
@@ -611,25 +789,14 @@ __global__ void set_scalar_kernel(double* p, double v) {
     if (threadIdx.x == 0) *p = v;
 }
 
-// add the per-walker evaluation and stall counts of one slice step to the run totals
-__global__ __launch_bounds__(256) void ns_count_kernel(const int* __restrict__ ne, const int* __restrict__ ns,
-                                                       int k, NSState* __restrict__ S) {
-    __shared__ long long red[2][4];
-    long long a = 0, b = 0;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) { a += ne[i]; b += ns[i]; }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = a; red[1][threadIdx.x >> 6] = b; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        S->n_evals += red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        S->n_stalls += red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    }
+__global__ void zero_ints_kernel(int* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* logl, int* ne, int* ns) {
+static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* logl, int* ne, int* ns,
+                              int64_t** iter_p) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t bytes = al(k * d * 8) * 3 + al(k * 8) * 5 + al(k * 4) * 9 + al(8) * 2;
+    const size_t bytes = al(k * d * 8) * 3 + al(k * 8) * 5 + al(k * 4) * 9 + al(16) * 3;
     m->ws_slice.ensure(bytes);
     char* p = m->ws_slice.as<char>();
     SliceState S;
@@ -648,15 +815,113 @@ static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* 
     S.pend = (int*)p; p += al(k * 4);
     S.pend2 = (int*)p; p += al(k * 4);
     S.cidx = (int*)p; p += al(2 * k * 4);
-    S.ccount = (int*)p; p += al(8);
-    S.active = (int*)p; p += al(8);
+    S.ccount = (int*)p; p += al(16);
+    S.active = (int*)p; p += al(16);
+    if (iter_p) *iter_p = (int64_t*)p;
     return S;
 }
 
-// host flag buffer: pinned, one per model
-static int* host_flag(ns_model* m) {
-    if (!m->host_pinned) NS_HIP(hipHostMalloc(&m->host_pinned, 256, hipHostMallocDefault));
-    return static_cast<int*>(m->host_pinned);
+// Owning handles for the graph objects and pinned host memory of one call, so
+// that every error path ends a capture and releases what it made.
+struct Capture {
+    hipStream_t s = nullptr;
+    bool on = false;
+    void begin(hipStream_t st) {
+        s = st;
+        NS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        on = true;
+    }
+    hipGraph_t end() {
+        hipGraph_t g = nullptr;
+        on = false;
+        NS_HIP(hipStreamEndCapture(s, &g));
+        return g;
+    }
+    ~Capture() {
+        if (on) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    }
+};
+struct GraphExec {
+    hipGraphExec_t e = nullptr;
+    ~GraphExec() {
+        if (e) (void)hipGraphExecDestroy(e);
+    }
+};
+struct PinnedHost {
+    void* p = nullptr;
+    explicit PinnedHost(size_t n) { NS_HIP(hipHostMalloc(&p, n, hipHostMallocDefault)); }
+    ~PinnedHost() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+struct EventPair {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    explicit EventPair(unsigned flags) {
+        NS_HIP(hipEventCreateWithFlags(&e[0], flags));
+        NS_HIP(hipEventCreateWithFlags(&e[1], flags));
+    }
+    ~EventPair() {
+        for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// Capture the launches of `body` on stream st into an executable graph.
+template <class F>
+static void capture_graph(hipStream_t st, GraphExec& ge, F&& body) {
+    Capture cap;
+    cap.begin(st);
+    body(st);
+    hipGraph_t g = cap.end();
+    const hipError_t ie = hipGraphInstantiate(&ge.e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    NS_HIP(ie);
+}
+
+// the model's own stream for captured graphs (capture needs a stream other
+// than the null stream), ordered after the caller's stream s
+static hipStream_t graph_stream_after(ns_model* m, hipStream_t s) {
+    if (!m->graph_stream) NS_HIP(hipStreamCreateWithFlags(&m->graph_stream, hipStreamNonBlocking));
+    if (!m->graph_event) NS_HIP(hipEventCreateWithFlags(&m->graph_event, hipEventDisableTiming));
+    NS_HIP(hipEventRecord(m->graph_event, s));
+    NS_HIP(hipStreamWaitEvent(m->graph_stream, m->graph_event, 0));
+    return m->graph_stream;
+}
+
+static bool graphs_enabled(const ns_model* m) { return !m->trace && getenv("NSMI_NO_GRAPH") == nullptr; }
+
+constexpr int GRAPH_ROUNDS = 24;      // slice rounds per captured graph (a multiple of 3)
+constexpr int CTL_EVERY = 8;          // rounds between control points of a nested-sampling graph
+
+static void advance_round(ns_model* m, const SliceState& S, int64_t k, const double* lstar_dev, const double* L,
+                          int n_inner, uint64_t seed, const int64_t* iter_p, int round, int prec, hipStream_t st) {
+    const int d = m->d;
+    double* thc = m->ws_theta.as<double>();
+    {
+        TraceScope ts(m, st, "slice_advance");
+        auto launch = [&](auto kern, int gs) {
+            const int64_t per_block = 4 * (64 / gs);
+            hipLaunchKernelGGL(kern, dim3((unsigned)((k + per_block - 1) / per_block)), dim3(256), 0, st, S, k, d,
+                               lstar_dev, L, n_inner, seed, iter_p, round, m->prior_kind.as<int>(),
+                               m->prior_a.as<double>(), m->prior_b.as<double>(), thc);
+        };
+        if (m->any_normal_prior) {
+            if (d <= 8) launch(slice_advance_kernel<8, true>, 8);
+            else if (d <= 16) launch(slice_advance_kernel<16, true>, 16);
+            else if (d <= 32) launch(slice_advance_kernel<32, true>, 32);
+            else launch(slice_advance_kernel<64, true>, 64);
+        } else {
+            if (d <= 8) launch(slice_advance_kernel<8, false>, 8);
+            else if (d <= 16) launch(slice_advance_kernel<16, false>, 16);
+            else if (d <= 32) launch(slice_advance_kernel<32, false>, 32);
+            else launch(slice_advance_kernel<64, false>, 64);
+        }
+    }
+    loglike_batch(m, thc, d, 2 * k, S.llc, prec, S.ccount + round % 3, st);
 }
 
 void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
@@ -665,67 +930,41 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
     const int d = m->d;
     NS_CHECK(d <= MAX_DIM, NS_E_UNSUPPORTED, "slice sampler supports d <= 64");
     if (k == 0) return;
-    SliceState S = carve_slice(m, k, d, u, logl, n_evals, n_stalls);
+    int64_t* iter_p = nullptr;
+    SliceState S = carve_slice(m, k, d, u, logl, n_evals, n_stalls, &iter_p);
     // up to two proposals per walker and round (both ends while stepping out)
     m->ws_theta.ensure((size_t)2 * k * d * sizeof(double));
-    double* thc = m->ws_theta.as<double>();
-    int* flag = host_flag(m);
-    const dim3 gw((unsigned)((k + 255) / 256));
-    hipLaunchKernelGGL(slice_init_kernel, gw, dim3(256), 0, s, S, k);
+    PinnedHost flag(64);
+    int* hflag = static_cast<int*>(flag.p);
+    hipLaunchKernelGGL(slice_init_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, S, k, iter_p, iter);
     NS_HIP(hipGetLastError());
-    const int chunk = 16;                     // even: every chunk starts at parity 0
     const int64_t max_rounds = (int64_t)n_inner * (2 * MAX_EXPAND + MAX_SHRINK + 4) + 8;
-    int64_t rounds = 0;
-    auto rounds_chunk = [&](hipStream_t st) {
-        for (int c = 0; c < chunk; ++c) {
-            // round c uses the counters of parity c & 1 (cleared by the round before)
-            const int par = c & 1;
-            {
-                TraceScope ts(m, st, "slice_advance");
-                hipLaunchKernelGGL(slice_advance_kernel, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, st, S, k, d,
-                                   lstar_dev, L, n_inner, seed, iter, par, m->prior_kind.as<int>(),
-                                   m->prior_a.as<double>(), m->prior_b.as<double>(), thc);
-            }
-            loglike_batch(m, thc, d, 2 * k, S.llc, prec, S.ccount + par, st);
-        }
+    auto chunk = [&](hipStream_t st) {
+        for (int c = 0; c < GRAPH_ROUNDS; ++c) advance_round(m, S, k, lstar_dev, L, n_inner, seed, iter_p, c, prec, st);
         NS_HIP(hipGetLastError());
     };
-    // First chunk eagerly on the caller's stream (sizes every workspace); the
-    // following chunks replay one captured graph of `chunk` rounds on the
-    // model's own stream, which is ordered after the caller's work.
-    const bool graphs = !m->trace && getenv("NSMI_NO_GRAPH") == nullptr;
-    hipGraphExec_t exec = nullptr;
+    // first chunk eagerly on the caller's stream (sizes every workspace, tunes
+    // launch shapes); the following chunks replay one captured graph on the
+    // model's own stream, ordered after the caller's work
+    GraphExec ge;
     hipStream_t run = s;
+    int64_t rounds = 0;
     while (true) {
-        if (rounds == 0 || !graphs) {
-            rounds_chunk(run);
+        if (rounds == 0 || !graphs_enabled(m)) {
+            chunk(run);
         } else {
-            if (!exec) {
-                if (!m->graph_stream) NS_HIP(hipStreamCreateWithFlags(&m->graph_stream, hipStreamNonBlocking));
-                if (!m->graph_event) NS_HIP(hipEventCreateWithFlags(&m->graph_event, hipEventDisableTiming));
-                NS_HIP(hipEventRecord(m->graph_event, s));
-                NS_HIP(hipStreamWaitEvent(m->graph_stream, m->graph_event, 0));
-                run = m->graph_stream;
-                hipGraph_t graph;
-                NS_HIP(hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
-                rounds_chunk(run);
-                NS_HIP(hipStreamEndCapture(run, &graph));
-                const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                NS_HIP(ie);
+            if (!ge.e) {
+                run = graph_stream_after(m, s);
+                capture_graph(run, ge, chunk);
             }
-            NS_HIP(hipGraphLaunch(exec, run));
+            NS_HIP(hipGraphLaunch(ge.e, run));
         }
-        rounds += chunk;
-        NS_HIP(hipMemcpyAsync(flag, S.active + ((chunk - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, run));
+        rounds += GRAPH_ROUNDS;
+        NS_HIP(hipMemcpyAsync(hflag, S.active + (GRAPH_ROUNDS - 1) % 3, sizeof(int), hipMemcpyDeviceToHost, run));
         NS_HIP(hipStreamSynchronize(run));
-        if (*flag == 0) break;
-        if (rounds >= max_rounds) {
-            if (exec) (void)hipGraphExecDestroy(exec);
-            throw Error{NS_E_INVALID, "slice sampler did not terminate"};
-        }
+        if (*hflag == 0) break;
+        NS_CHECK(rounds < max_rounds, NS_E_INVALID, "slice sampler did not terminate");
     }
-    if (exec) NS_HIP(hipGraphExecDestroy(exec));
 }
 
 void slice_step_host_lstar(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
@@ -738,6 +977,73 @@ void slice_step_host_lstar(ns_model* m, double* u, double* logl, int* n_evals, i
     slice_step(m, u, logl, n_evals, n_stalls, k, lp, L, n_inner, seed, iter, prec, s);
 }
 
+// ------------------------------------------------------------ checkpoints
+// File layout (native byte order): CkptHeader, then live u [n x d] and live
+// logL [n] (double), dead logL [n_dead] (double), dead live counts [n_dead]
+// (int32), dead u [n_dead x d] (double).
+struct CkptHeader {
+    char magic[8];                // "NSMICKP1"
+    int32_t kind, d, n_data, n_live, n_delete, n_inner, precision, stop;
+    uint64_t seed;
+    double frac_remain;
+    int64_t it, n_dead, n_evals, n_stalls;
+    double logx, logz, lstar, live_term;
+};
+
+static void write_checkpoint(const char* path, const CkptHeader& h, const std::vector<double>& lu,
+                             const std::vector<double>& ll, const std::vector<double>& dl,
+                             const std::vector<int>& dn, const std::vector<double>& du) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    NS_CHECK(f != nullptr, NS_E_INVALID, std::string("cannot write checkpoint ") + tmp);
+    bool ok = fwrite(&h, sizeof(h), 1, f) == 1;
+    auto put = [&](const void* p, size_t bytes) {
+        if (bytes) ok = ok && fwrite(p, 1, bytes, f) == bytes;
+    };
+    put(lu.data(), lu.size() * 8);
+    put(ll.data(), ll.size() * 8);
+    put(dl.data(), dl.size() * 8);
+    put(dn.data(), dn.size() * 4);
+    put(du.data(), du.size() * 8);
+    ok = (fclose(f) == 0) && ok;
+    NS_CHECK(ok, NS_E_INVALID, std::string("short write of checkpoint ") + tmp);
+    NS_CHECK(rename(tmp.c_str(), path) == 0, NS_E_INVALID, std::string("cannot rename checkpoint to ") + path);
+}
+
+static bool read_checkpoint(const char* path, CkptHeader& h, std::vector<double>& lu, std::vector<double>& ll,
+                            std::vector<double>& dl, std::vector<int>& dn, std::vector<double>& du) {
+    FILE* f = fopen(path, "rb");
+    if (!f) return false;
+    std::unique_ptr<FILE, int (*)(FILE*)> guard(f, fclose);
+    NS_CHECK(fread(&h, sizeof(h), 1, f) == 1 && memcmp(h.magic, "NSMICKP1", 8) == 0, NS_E_INVALID,
+             std::string("not a checkpoint of this library: ") + path);
+    NS_CHECK(h.d >= 1 && h.d <= MAX_DIM && h.n_live >= 2 && h.n_live <= 4096 && h.n_dead >= 0 &&
+                 h.n_dead <= ((int64_t)1 << 40),
+             NS_E_INVALID, std::string("corrupt checkpoint header: ") + path);
+    lu.resize((size_t)h.n_live * h.d);
+    ll.resize(h.n_live);
+    dl.resize(h.n_dead);
+    dn.resize(h.n_dead);
+    du.resize((size_t)h.n_dead * h.d);
+    bool ok = true;
+    auto get = [&](void* p, size_t bytes) {
+        if (bytes) ok = ok && fread(p, 1, bytes, f) == bytes;
+    };
+    get(lu.data(), lu.size() * 8);
+    get(ll.data(), ll.size() * 8);
+    get(dl.data(), dl.size() * 8);
+    get(dn.data(), dn.size() * 4);
+    get(du.data(), du.size() * 8);
+    NS_CHECK(ok, NS_E_INVALID, std::string("truncated checkpoint: ") + path);
+    return true;
+}
+
+// ------------------------------------------------------------------- ns_run
+struct RunSnap {
+    NSCtl ctl;
+    NSState st;
+};
+
 void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, int* dn_h, double* du_h,
          int64_t cap, hipStream_t s) {
     const int n = o->n_live, k = o->n_delete, d = m->d;
@@ -748,11 +1054,15 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
     NS_CHECK(o->frac_remain > 0.0 && o->frac_remain < 1.0, NS_E_INVALID, "frac_remain must be in (0, 1)");
     NS_CHECK(o->max_iter >= 1, NS_E_INVALID, "max_iter must be >= 1");
     NS_CHECK(o->n_replicates >= 0, NS_E_INVALID, "n_replicates must be >= 0");
-    hipEvent_t ev0, ev1;
-    NS_HIP(hipEventCreate(&ev0));
-    NS_HIP(hipEventCreate(&ev1));
-    NS_HIP(hipEventRecord(ev0, s));
-    DevBuf live_u, live_l, order, wu, wl, wne, wns, L, state, th, dl, dn, du, ev;
+    NS_CHECK(o->checkpoint_every >= 0, NS_E_INVALID, "checkpoint_every must be >= 0");
+    NS_CHECK(o->resume == 0 || o->resume == 1, NS_E_INVALID, "resume must be 0 or 1");
+    const char* ckpt = (o->checkpoint_path && o->checkpoint_path[0]) ? o->checkpoint_path : nullptr;
+    NS_CHECK(ckpt || (o->checkpoint_every == 0 && o->resume == 0), NS_E_INVALID,
+             "checkpoint_every and resume need a checkpoint_path");
+    EventPair tev(hipEventDefault);
+    NS_HIP(hipEventRecord(tev.e[0], s));
+    DevBuf live_u, live_l, order, wu, wl, wne, wns, L, state, ctlb, dbuf, th, ev;
+    DevBuf dl, dn, du;
     live_u.ensure((size_t)n * d * 8);
     live_l.ensure((size_t)n * 8);
     order.ensure((size_t)n * 4);
@@ -762,77 +1072,206 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
     wns.ensure((size_t)k * 4);
     L.ensure((size_t)d * d * 8);
     state.ensure(sizeof(NSState));
+    ctlb.ensure(sizeof(NSCtl));
+    dbuf.ensure(sizeof(DeadBuf));
     th.ensure((size_t)n * d * 8);
-    int64_t dcap = std::max<int64_t>(4 * (int64_t)n, 1024);
-    dl.ensure(dcap * 8); dn.ensure(dcap * 4); du.ensure(dcap * d * 8);
     NSState* S = state.as<NSState>();
-    NSState hs;
-    hipLaunchKernelGGL(ns_init_kernel, dim3((unsigned)(((int64_t)n * d + 255) / 256)), dim3(256), 0, s,
-                       live_u.as<double>(), n, d, o->seed, S);
-    NS_HIP(hipGetLastError());
-    prior_transform(m, live_u.as<double>(), th.as<double>(), d, n, nullptr, s);
-    loglike_batch(m, th.as<double>(), d, n, live_l.as<double>(), o->precision, nullptr, s);
-    const double log_frac = log(o->frac_remain);
-    int64_t it = 0;
-    int64_t n_dead = 0;
-    const double* lstar_dev = reinterpret_cast<const double*>(reinterpret_cast<const char*>(S) + offsetof(NSState, lstar));
-    while (it < o->max_iter) {
-        ++it;
-        if (n_dead + k + n > dcap) {
-            const int64_t ncap = std::max<int64_t>(2 * dcap, n_dead + k + n);
-            DevBuf dl2, dn2, du2;
-            dl2.ensure(ncap * 8); dn2.ensure(ncap * 4); du2.ensure(ncap * d * 8);
-            NS_HIP(hipMemcpyAsync(dl2.p, dl.p, n_dead * 8, hipMemcpyDeviceToDevice, s));
-            NS_HIP(hipMemcpyAsync(dn2.p, dn.p, n_dead * 4, hipMemcpyDeviceToDevice, s));
-            NS_HIP(hipMemcpyAsync(du2.p, du.p, n_dead * d * 8, hipMemcpyDeviceToDevice, s));
-            NS_HIP(hipStreamSynchronize(s));
-            std::swap(dl.p, dl2.p); std::swap(dl.bytes, dl2.bytes);
-            std::swap(dn.p, dn2.p); std::swap(dn.bytes, dn2.bytes);
-            std::swap(du.p, du2.p); std::swap(du.bytes, du2.bytes);
-            dcap = ncap;
+    NSCtl* ctl = ctlb.as<NSCtl>();
+    int64_t dcap = 0;
+    // (re)allocate the dead-point storage for at least `need` points, keeping the first n_keep
+    auto grow_dead = [&](int64_t need, int64_t n_keep, hipStream_t st) {
+        if (need <= dcap) return;
+        const int64_t ncap = std::max<int64_t>(std::max<int64_t>(2 * dcap, need), 1024);
+        DevBuf dl2, dn2, du2;
+        dl2.ensure(ncap * 8);
+        dn2.ensure(ncap * 4);
+        du2.ensure(ncap * d * 8);
+        if (n_keep > 0) {
+            NS_HIP(hipMemcpyAsync(dl2.p, dl.p, n_keep * 8, hipMemcpyDeviceToDevice, st));
+            NS_HIP(hipMemcpyAsync(dn2.p, dn.p, n_keep * 4, hipMemcpyDeviceToDevice, st));
+            NS_HIP(hipMemcpyAsync(du2.p, du.p, n_keep * d * 8, hipMemcpyDeviceToDevice, st));
         }
-        hipLaunchKernelGGL(ns_select_kernel, dim3(1), dim3(1024), 0, s, live_l.as<double>(), live_u.as<double>(), n,
-                           k, d, order.as<int>(), S, dl.as<double>(), dn.as<int>(), du.as<double>(), dcap, 1);
-        hipLaunchKernelGGL(ns_dircov_kernel, dim3(1), dim3(256), 0, s, live_u.as<double>(), n, d, L.as<double>());
-        hipLaunchKernelGGL(ns_spawn_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, live_u.as<double>(),
-                           live_l.as<double>(), order.as<int>(), n, k, d, o->seed, (uint64_t)it, wu.as<double>(),
-                           wl.as<double>());
-        NS_HIP(hipGetLastError());
-        slice_step(m, wu.as<double>(), wl.as<double>(), wne.as<int>(), wns.as<int>(), k, lstar_dev, L.as<double>(),
-                   o->n_inner, o->seed, (uint64_t)it, o->precision, s);
-        hipLaunchKernelGGL(ns_count_kernel, dim3(1), dim3(256), 0, s, wne.as<int>(), wns.as<int>(), k, S);
-        hipLaunchKernelGGL(ns_replace_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s,
-                           live_u.as<double>(), live_l.as<double>(), order.as<int>(), k, d, wu.as<double>(),
-                           wl.as<double>());
-        hipLaunchKernelGGL(ns_term_kernel, dim3(1), dim3(256), 0, s, live_l.as<double>(), n, S, log_frac);
-        NS_HIP(hipGetLastError());
-        NS_HIP(hipMemcpyAsync(&hs, S, sizeof(NSState), hipMemcpyDeviceToHost, s));
-        NS_HIP(hipStreamSynchronize(s));
-        n_dead = hs.n_dead;
-        if (hs.stop) break;
+        NS_HIP(hipStreamSynchronize(st));
+        std::swap(dl.p, dl2.p); std::swap(dl.bytes, dl2.bytes);
+        std::swap(dn.p, dn2.p); std::swap(dn.bytes, dn2.bytes);
+        std::swap(du.p, du2.p); std::swap(du.bytes, du2.bytes);
+        dcap = ncap;
+        const DeadBuf hb{dl.as<double>(), dn.as<int>(), du.as<double>(), dcap};
+        NS_HIP(hipMemcpy(dbuf.p, &hb, sizeof(hb), hipMemcpyHostToDevice));
+    };
+
+    // ---- start: fresh live points, or the state of a checkpoint
+    CkptHeader hdr{};
+    std::vector<double> c_lu, c_ll, c_dl, c_du;
+    std::vector<int> c_dn;
+    bool resumed = false;
+    if (ckpt && o->resume && read_checkpoint(ckpt, hdr, c_lu, c_ll, c_dl, c_dn, c_du)) {
+        NS_CHECK(hdr.kind == m->kind && hdr.d == d && hdr.n_data == m->n_data && hdr.n_live == n &&
+                     hdr.n_delete == k && hdr.n_inner == o->n_inner && hdr.precision == o->precision &&
+                     hdr.seed == o->seed && hdr.frac_remain == o->frac_remain,
+                 NS_E_INVALID, std::string("checkpoint ") + ckpt + " belongs to another model or other run options");
+        resumed = true;
     }
-    // final: live points in ascending order
-    hipLaunchKernelGGL(ns_select_kernel, dim3(1), dim3(1024), 0, s, live_l.as<double>(), live_u.as<double>(), n, k,
-                       d, order.as<int>(), S, dl.as<double>(), dn.as<int>(), du.as<double>(), dcap, 0);
-    hipLaunchKernelGGL(ns_final_kernel, dim3(1), dim3(256), 0, s, live_l.as<double>(), live_u.as<double>(),
+    NSCtl hc{};
+    hc.max_iter = o->max_iter;
+    hc.ckpt_every = ckpt ? o->checkpoint_every : 0;
+    if (resumed) {
+        grow_dead(std::max<int64_t>(4 * (int64_t)n, hdr.n_dead + k + n), 0, s);
+        NS_HIP(hipMemcpy(live_u.p, c_lu.data(), c_lu.size() * 8, hipMemcpyHostToDevice));
+        NS_HIP(hipMemcpy(live_l.p, c_ll.data(), c_ll.size() * 8, hipMemcpyHostToDevice));
+        if (hdr.n_dead > 0) {
+            NS_HIP(hipMemcpy(dl.p, c_dl.data(), c_dl.size() * 8, hipMemcpyHostToDevice));
+            NS_HIP(hipMemcpy(dn.p, c_dn.data(), c_dn.size() * 4, hipMemcpyHostToDevice));
+            NS_HIP(hipMemcpy(du.p, c_du.data(), c_du.size() * 8, hipMemcpyHostToDevice));
+        }
+        NSState hs{hdr.logx, hdr.logz, hdr.lstar, hdr.live_term, hdr.n_dead, hdr.n_evals, hdr.n_stalls, hdr.stop};
+        NS_HIP(hipMemcpy(S, &hs, sizeof(hs), hipMemcpyHostToDevice));
+        hc.it = hdr.it;
+        hc.need_begin = hdr.stop ? 0 : 1;
+        hc.done = hdr.stop ? 1 : (hdr.it >= o->max_iter ? 2 : 0);
+        if (hc.done) hc.need_begin = 0;
+    } else {
+        grow_dead(std::max<int64_t>(4 * (int64_t)n, 1024), 0, s);
+        hipLaunchKernelGGL(ns_init_kernel, dim3((unsigned)(((int64_t)n * d + 255) / 256)), dim3(256), 0, s,
+                           live_u.as<double>(), n, d, o->seed, S);
+        NS_HIP(hipGetLastError());
+        prior_transform(m, live_u.as<double>(), th.as<double>(), d, n, nullptr, s);
+        loglike_batch(m, th.as<double>(), d, n, live_l.as<double>(), o->precision, nullptr, s);
+        hc.it = 0;
+        hc.need_begin = 1;
+    }
+    NS_HIP(hipMemcpyAsync(ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+    NS_HIP(hipStreamSynchronize(s));
+
+    // ---- the device-driven iteration
+    int64_t* iter_unused = nullptr;
+    SliceState W = carve_slice(m, k, d, wu.as<double>(), wl.as<double>(), wne.as<int>(), wns.as<int>(),
+                               &iter_unused);
+    m->ws_theta.ensure((size_t)2 * k * d * sizeof(double));
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, W.ccount, 3);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, W.active, 3);
+    NS_HIP(hipGetLastError());
+    const double log_frac = log(o->frac_remain);
+    const double* lstar_dev = reinterpret_cast<const double*>(reinterpret_cast<const char*>(S) + offsetof(NSState, lstar));
+    const int64_t* it_dev = reinterpret_cast<const int64_t*>(reinterpret_cast<const char*>(ctl) + offsetof(NSCtl, it));
+    auto block = [&](hipStream_t st) {
+        for (int c = 0; c < GRAPH_ROUNDS; ++c) {
+            if (c % CTL_EVERY == 0) {
+                TraceScope ts(m, st, "ns_control");
+                hipLaunchKernelGGL(ns_control_kernel, dim3(1), dim3(CTL_NT), 0, st, ctl, S, dbuf.as<DeadBuf>(), W,
+                                   live_u.as<double>(), live_l.as<double>(), order.as<int>(), L.as<double>(), n, k,
+                                   d, o->seed, log_frac, c);
+            }
+            advance_round(m, W, k, lstar_dev, L.as<double>(), o->n_inner, o->seed, it_dev, c, o->precision, st);
+        }
+        NS_HIP(hipGetLastError());
+    };
+    hipStream_t st = graphs_enabled(m) ? graph_stream_after(m, s) : s;
+    PinnedHost pin(2 * sizeof(RunSnap));
+    RunSnap* snap = static_cast<RunSnap*>(pin.p);
+    EventPair sev(hipEventDisableTiming);
+    GraphExec ge;
+    auto launch = [&]() {
+        if (ge.e) NS_HIP(hipGraphLaunch(ge.e, st));
+        else block(st);
+    };
+    auto snapshot = [&](int i) {
+        NS_HIP(hipMemcpyAsync(&snap[i].ctl, ctl, sizeof(NSCtl), hipMemcpyDeviceToHost, st));
+        NS_HIP(hipMemcpyAsync(&snap[i].st, S, sizeof(NSState), hipMemcpyDeviceToHost, st));
+        NS_HIP(hipEventRecord(sev.e[i], st));
+    };
+    // the first launch runs eagerly: it sizes every workspace and tunes the
+    // likelihood's launch shapes before anything is captured
+    block(st);
+    snapshot(0);
+    NS_HIP(hipEventSynchronize(sev.e[0]));
+    if (graphs_enabled(m)) capture_graph(st, ge, block);
+    const int64_t max_graphs_per_iter =
+        ((int64_t)o->n_inner * (2 * MAX_EXPAND + MAX_SHRINK + 4) + 8) / GRAPH_ROUNDS + 3;
+    int64_t last_it = -1, same_it = 0;
+    int cur = 0;
+    RunSnap h = snap[0];
+    auto write_ckpt = [&](const RunSnap& hs) {
+        CkptHeader w{};
+        memcpy(w.magic, "NSMICKP1", 8);
+        w.kind = m->kind; w.d = d; w.n_data = m->n_data; w.n_live = n; w.n_delete = k;
+        w.n_inner = o->n_inner; w.precision = o->precision; w.stop = hs.st.stop;
+        w.seed = o->seed; w.frac_remain = o->frac_remain;
+        w.it = hs.ctl.it; w.n_dead = hs.st.n_dead; w.n_evals = hs.st.n_evals; w.n_stalls = hs.st.n_stalls;
+        w.logx = hs.st.logx; w.logz = hs.st.logz; w.lstar = hs.st.lstar; w.live_term = hs.st.live_term;
+        std::vector<double> lu((size_t)n * d), ll(n), dlv(hs.st.n_dead), duv((size_t)hs.st.n_dead * d);
+        std::vector<int> dnv(hs.st.n_dead);
+        NS_HIP(hipMemcpy(lu.data(), live_u.p, lu.size() * 8, hipMemcpyDeviceToHost));
+        NS_HIP(hipMemcpy(ll.data(), live_l.p, ll.size() * 8, hipMemcpyDeviceToHost));
+        if (hs.st.n_dead > 0) {
+            NS_HIP(hipMemcpy(dlv.data(), dl.p, dlv.size() * 8, hipMemcpyDeviceToHost));
+            NS_HIP(hipMemcpy(dnv.data(), dn.p, dnv.size() * 4, hipMemcpyDeviceToHost));
+            NS_HIP(hipMemcpy(duv.data(), du.p, duv.size() * 8, hipMemcpyDeviceToHost));
+        }
+        write_checkpoint(ckpt, w, lu, ll, dlv, dnv, duv);
+    };
+    while (true) {
+        if (!h.ctl.done && !h.ctl.pause && !h.ctl.grow) {
+            // one launch in flight beyond the state being read
+            launch();
+            snapshot(cur ^ 1);
+            NS_HIP(hipEventSynchronize(sev.e[cur]));
+            h = snap[cur];
+            cur ^= 1;
+            if (!(h.ctl.done || h.ctl.pause || h.ctl.grow)) {
+                if (h.ctl.it == last_it && h.ctl.walking) {
+                    NS_CHECK(++same_it <= max_graphs_per_iter, NS_E_INVALID, "slice sampler did not terminate");
+                } else {
+                    last_it = h.ctl.it;
+                    same_it = 0;
+                }
+                continue;
+            }
+            // the launch in flight started nothing new: wait for it
+            NS_HIP(hipEventSynchronize(sev.e[cur]));
+            h = snap[cur];
+        }
+        if (h.ctl.done) break;
+        if (h.ctl.pause) {
+            write_ckpt(h);
+            h.ctl.pause = 0;
+        }
+        if (h.ctl.grow) {
+            grow_dead(h.st.n_dead + k + n, h.st.n_dead, st);
+            h.ctl.grow = 0;
+        }
+        h.ctl.need_begin = 1;
+        NS_HIP(hipMemcpy(ctl, &h.ctl, sizeof(NSCtl), hipMemcpyHostToDevice));
+        launch();
+        snapshot(cur);
+        NS_HIP(hipEventSynchronize(sev.e[cur]));
+        h = snap[cur];
+    }
+    NS_HIP(hipStreamSynchronize(st));
+    if (ckpt && h.ctl.done == 2) write_ckpt(h);        // a run ended by max_iter can be continued
+
+    // ---- final: live points in ascending order, then log Z, H and the replicates
+    int64_t n_dead = h.st.n_dead;
+    grow_dead(n_dead + n, n_dead, st);
+    hipLaunchKernelGGL(ns_sort_kernel, dim3(1), dim3(CTL_NT), 0, st, live_l.as<double>(), n, order.as<int>());
+    hipLaunchKernelGGL(ns_final_kernel, dim3(1), dim3(256), 0, st, live_l.as<double>(), live_u.as<double>(),
                        order.as<int>(), n, d, S, dl.as<double>(), dn.as<int>(), du.as<double>(), dcap);
     const int64_t M = n_dead + n;
     const int R = o->n_replicates;
     ev.ensure((size_t)(2 + std::max(R, 1)) * 8);
-    hipLaunchKernelGGL(ns_evidence_kernel, dim3(1), dim3(1024), 0, s, dl.as<double>(), dn.as<int>(), M, ev.as<double>());
+    hipLaunchKernelGGL(ns_evidence_kernel, dim3(1), dim3(1024), 0, st, dl.as<double>(), dn.as<int>(), M,
+                       ev.as<double>());
     if (R > 0)
-        hipLaunchKernelGGL(ns_replicates_kernel, dim3((unsigned)R), dim3(256), 0, s, dl.as<double>(),
+        hipLaunchKernelGGL(ns_replicates_kernel, dim3((unsigned)R), dim3(256), 0, st, dl.as<double>(),
                            dn.as<int>(), M, R, o->seed, ev.as<double>() + 2);
     NS_HIP(hipGetLastError());
     std::vector<double> evh(2 + std::max(R, 1));
-    NS_HIP(hipMemcpyAsync(evh.data(), ev.p, evh.size() * 8, hipMemcpyDeviceToHost, s));
-    NS_HIP(hipMemcpyAsync(&hs, S, sizeof(NSState), hipMemcpyDeviceToHost, s));
-    NS_HIP(hipEventRecord(ev1, s));
-    NS_HIP(hipStreamSynchronize(s));
+    NS_HIP(hipMemcpyAsync(evh.data(), ev.p, evh.size() * 8, hipMemcpyDeviceToHost, st));
+    NS_HIP(hipStreamSynchronize(st));
+    NS_HIP(hipEventRecord(tev.e[1], s));
+    NS_HIP(hipEventSynchronize(tev.e[1]));
     float ms = 0.f;
-    NS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
+    NS_HIP(hipEventElapsedTime(&ms, tev.e[0], tev.e[1]));
     const int64_t ncopy = std::min<int64_t>(M, cap);
     if (dl_h && ncopy > 0) NS_HIP(hipMemcpy(dl_h, dl.p, ncopy * 8, hipMemcpyDeviceToHost));
     if (dn_h && ncopy > 0) NS_HIP(hipMemcpy(dn_h, dn.p, ncopy * 4, hipMemcpyDeviceToHost));
@@ -845,11 +1284,12 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
     for (int r = 0; r < R; ++r) var += (evh[2 + r] - mean) * (evh[2 + r] - mean);
     res->sigma = R > 0 ? sqrt(var / R) : 0.0;
     res->sigma_skilling = sqrt(std::max(evh[1], 0.0) / n);
-    res->n_iter = it;
-    res->n_evals = hs.n_evals;
-    res->n_stalls = hs.n_stalls;
+    res->n_iter = h.ctl.it;
+    res->n_evals = h.st.n_evals;
+    res->n_stalls = h.st.n_stalls;
     res->n_dead = M;
     res->wall_s = ms * 1e-3;
+    res->resumed_iter = resumed ? hdr.it : 0;
 }
 
 }  // namespace nsmi

@@ -270,3 +270,30 @@ def test_fused_emulator_slice_step_matches_layer_by_layer(monkeypatch, name, n, 
     say(f"{name} {prec}: evals {outs[0][2].sum()} (min {outs[0][2].min()}, max {outs[0][2].max()})")
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_ns_run_resume_is_bitwise(tmp_path, prec):
+    """A run cut short by max_iter (checkpoints every 3 iterations and at its
+    end) and continued from the file gives bitwise the uninterrupted run."""
+    say(f"case ns_run checkpoint/resume cmb6 {prec}")
+    m = W.load_model("cmb6")
+    g = mk(m)
+    full = g.run(100, 50, 30, precision=prec, seed=4, n_replicates=100, capacity=100000)
+    path = tmp_path / "run.ckpt"
+    part = g.run(100, 50, 30, precision=prec, seed=4, n_replicates=100, capacity=100000, max_iter=7,
+                 checkpoint_path=path, checkpoint_every=3)
+    assert part["n_iter"] == 7 and path.exists()
+    rest = g.run(100, 50, 30, precision=prec, seed=4, n_replicates=100, capacity=100000,
+                 checkpoint_path=path, resume=True)
+    # a checkpoint of other options is refused
+    with pytest.raises(RuntimeError, match="other run options"):
+        g.run(100, 50, 30, precision=prec, seed=5, n_replicates=100, checkpoint_path=path, resume=True)
+    g.close()
+    say(f"full: logZ {full['logz']!r} iters {full['n_iter']} evals {full['n_evals']}; resumed from "
+        f"{rest['resumed_iter']}: logZ {rest['logz']!r} iters {rest['n_iter']} evals {rest['n_evals']}")
+    assert rest["resumed_iter"] == 7
+    for key in ("logz", "sigma", "h", "n_iter", "n_evals", "n_stalls", "n_dead"):
+        assert rest[key] == full[key], key
+    for key in ("dead_logl", "dead_n", "dead_u"):
+        np.testing.assert_array_equal(rest[key], full[key])
