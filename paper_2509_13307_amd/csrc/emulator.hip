@@ -646,6 +646,10 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
     if (!save_t && getenv("NSMI_NO_FUSED_MLP") == nullptr &&
         emulator_forward_fused(m, nets, G, theta, ld, B, outs, ldo, is_log, prec, count, s))
         return;
+    if (!save_t && prec == NS_FP64 && G == 1 && nets[0] == 0 &&
+        emulator_forward_f64_narrow(m, theta, ld, B, static_cast<double*>(outs[0]), ldo, is_log[0], nullptr, count,
+                                    s))
+        return;
     const size_t act_elem = prec == NS_FP64 ? 8 : (prec == NS_BF16 ? 2 : 4);
     size_t max_w = 0;
     for (int l = 1; l < L; ++l) max_w = std::max(max_w, (size_t)net0.dims[l]);

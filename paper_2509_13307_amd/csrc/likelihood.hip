@@ -9,15 +9,6 @@
 
 namespace nsmi {
 
-// theta outside a uniform prior's [a, b] -> false (NaN compares false: kept)
-__device__ __forceinline__ bool in_support(const double* th, int d, const int* kind, const double* a,
-                                           const double* b) {
-    bool ok = true;
-    for (int i = 0; i < d; ++i)
-        if (kind[i] == NS_PRIOR_UNIFORM && (th[i] < a[i] || th[i] > b[i])) ok = false;
-    return ok;
-}
-
 // ------------------------------------------------------------ diagonal chi^2
 // One wave per walker; lanes stride over the n data points.
 template <class T>
@@ -307,6 +298,10 @@ void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
             ids[g] = g;
             outs[g] = m->ws_out.as<char>() + g * sp * elem;
         }
+        // narrow FP64 networks: emulator and diagonal chi^2 in one launch
+        if (m->kind == NS_MODEL_CMB_DIAG && prec == NS_FP64 &&
+            emulator_forward_f64_narrow(m, theta, ld, B, nullptr, 0, m->spec_log[0], logl, count, s))
+            return;
         // the cosmic-variance stage reads log10 C_l itself
         static const int raw[4] = {0, 0, 0, 0};
         emulator_forward(m, ids, G, theta, ld, B, outs, n, m->kind == NS_MODEL_CMB_CV ? raw : m->spec_log.data(),

@@ -332,3 +332,30 @@ def test_full_and_interpolated_shear_share_their_data(built):
     assert np.mean(Ci < Cf) > 0.95
 
 
+
+
+def test_fp64_one_kernel_narrow_emulator_matches_layer_by_layer(built, monkeypatch):
+    """The one-kernel FP64 forward of the narrow cmb6 network (with the
+    diagonal chi^2 in the same launch) gives bitwise the layer-by-layer
+    GEMMs plus the separate chi^2 kernel, and its theory vector bitwise the
+    layer-by-layer outputs; a batch with a partial last row tile, prior draws
+    outside the support and batch 1 included."""
+    say("case fp64 one-kernel narrow cmb6")
+    from paper_2509_13307_amd import Model
+    m = W.load_model("cmb6")
+    th = W.prior_draws(m, 333, tag=21)
+    th[:80] = W.posterior_draws(m["theta_fid"], post_scale(m), 80, tag=21)
+    th[5, 1] = 1.2                              # outside U(0,1): -inf
+    t = torch.tensor(th, device=DEV)
+    outs = []
+    for env in ({}, {"NSMI_NO_FUSED_MLP": "1"}):
+        monkeypatch.delenv("NSMI_NO_FUSED_MLP", raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g = Model(m)
+        outs.append((g.loglike(t).cpu().numpy(), g.theory(t).cpu().numpy(), g.loglike(t[:1]).cpu().numpy()))
+        g.close()
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    assert outs[0][0][5] == -np.inf
+    check_fp64(oracle_loglike(th, m, chunk=64), outs[0][0], "cmb6 one-kernel fp64")
