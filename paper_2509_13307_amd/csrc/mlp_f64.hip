@@ -62,12 +62,17 @@ __device__ __forceinline__ void mf_layer_gemm(const double* __restrict__ act, co
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[t][r] = 0.0;
-    auto fetch = [&](int kq, double (&b)[TPW]) {
+    // loads and MFMAs are unconditional (a branch around either makes the
+    // compiler wait for every load in flight): tiles past NT recompute tile
+    // NT - 1 and steps past the layer re-read its last step; neither result
+    // is stored
+    int ntc[TPW];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
-            const int nt = wave + 4 * t;
-            b[t] = (nt < NT && kq < K4) ? Wl[((size_t)kq * NT + nt) * 64 + lane] : 0.0;
-        }
+    for (int t = 0; t < TPW; ++t) ntc[t] = min(wave + 4 * t, NT - 1);
+    auto fetch = [&](int kq, double (&b)[TPW]) {
+        kq = min(kq, K4 - 1);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) b[t] = Wl[((size_t)kq * NT + ntc[t]) * 64 + lane];
     };
 #pragma unroll
     for (int u = 0; u < MF_PF; ++u) fetch(u, bq[u]);
@@ -77,8 +82,7 @@ __device__ __forceinline__ void mf_layer_gemm(const double* __restrict__ act, co
             const int kq = kq0 + u;
             const double a = act[(lane & 15) * LDA + kq * 4 + (lane >> 4)];
 #pragma unroll
-            for (int t = 0; t < TPW; ++t)
-                if (wave + 4 * t < NT) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[u][t], acc[t], 0, 0, 0);
+            for (int t = 0; t < TPW; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[u][t], acc[t], 0, 0, 0);
             fetch(kq + MF_PF, bq[u]);
         }
     }
@@ -146,11 +150,11 @@ __global__ __launch_bounds__(256, 2) void mlp_f64_kernel(const double* __restric
     if (r0 >= nrows) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_in = A.n_in, N_out = A.N_out;
-    for (int e = tid; e < MF_R * n_in; e += 256) {
-        const int rr = e / n_in, k = e % n_in;
+    for (int e = tid; e < MF_R * 16; e += 256) {
+        const int rr = e / 16, k = e % 16;
         const int64_t r = r0 + rr;
         double v = 0.0;
-        if (r < nrows) {
+        if (r < nrows && k < n_in) {
             const int s = src[k];
             const double t = s >= 0 ? theta[r * ld + s] : fix[k];
             v = (t - A.shift[k]) / A.scale[k];
@@ -165,10 +169,13 @@ __global__ __launch_bounds__(256, 2) void mlp_f64_kernel(const double* __restric
         for (int k = 0; k < 16; ++k) w1[k] = k < n_in ? A.W1[c * n_in + k] : 0.0;
         const double b1 = A.b1[c], be1 = A.be1[c], ga1 = A.ga1[c];
         for (int rr = tid / H; rr < MF_R; rr += 256 / H) {
+            double x[16];                              // the row's inputs in registers first
+#pragma unroll
+            for (int k = 0; k < 16; ++k) x[k] = xs[rr][k];
             double acc = b1;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (k < n_in) acc += w1[k] * xs[rr][k];
+                if (k < n_in) acc += w1[k] * x[k];
             act[rr * LDA + c] = gated<double>(acc, be1, ga1);
         }
     }
