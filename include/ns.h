@@ -189,6 +189,28 @@ ns_status ns_prior_transform(ns_model* model, const double* u, double* theta, in
 ns_status ns_loglike_batch(ns_model* model, const double* theta, int64_t ld, int64_t B,
                            double* logl, int32_t precision, void* stream);
 
+/* ns_loglike_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same results, bitwise, with the
+ * emulator's model vector in a library-owned device array of 64 MiB per GPU
+ * (set up when the first model is created on that GPU and held until the
+ * process ends) instead of the model's grow-on-demand workspace; no
+ * allocation, no launch-shape tuning runs (the shape tuned by an earlier
+ * ns_loglike_batch call of the same batch size, else the first candidate) and
+ * no trace events.
+ * Covers the CMB model kinds in the NS_BF16 / NS_BF16X3 forms of one-kernel
+ * emulator networks (hidden widths 128 or 512), and NS_FP64 on a narrow
+ * CMB_DIAG model (hidden width 128: emulator and chi^2 in one kernel, no
+ * scratch); NS_E_UNSUPPORTED otherwise.  The array holds the model vectors of
+ * at most 64 MiB / (4 x row length) walkers (1 658 for the four-spectrum
+ * 2 x 2500-multipole model); larger B is NS_E_SHAPE, nothing launched.
+ * All calls on one GPU share the array: calls that overlap in time on one GPU
+ * (any models, any streams) race and must be ordered by the caller.
+ * theta: device [B x ld]; logl: device [B]; both caller-owned.  Asynchronous
+ * on stream. */
+ns_status ns_loglike_batch_noalloc(ns_model* model, const double* theta, int64_t ld, int64_t B,
+                                   double* logl, int32_t precision, void* stream);
+
 /* Theory vector of every walker: the prediction the likelihood compares with
  * the data, in the data's order, after every stage before the chi^2 (or the
  * cosmic-variance sum), by the same kernels as ns_loglike_batch.

@@ -53,7 +53,7 @@ static hipEvent_t pool_event(ns_model* m) {
 }
 
 TraceScope::TraceScope(ns_model* m_, hipStream_t s_, const char* name) : m(m_), s(s_) {
-    if (!m->trace) return;
+    if (!m->trace || m->noalloc_call) return;
     ns_model::TraceRec r{name, pool_event(m), pool_event(m)};
     NS_HIP(hipEventRecord(r.e0, s));
     m->trace_recs.push_back(r);
@@ -564,6 +564,7 @@ ns_status ns_model_create(const ns_model_desc* desc, int32_t device, ns_model** 
         NS_HIP(hipGetDeviceCount(&n));
         NS_CHECK(device >= 0 && device < n, NS_E_INVALID, "no such HIP device");
         NS_HIP(hipSetDevice(device));
+        scratch_init(device);                   // address of the allocation-free path's array on this device
         ns_model* m = new ns_model();
         m->device = device;
         try {
@@ -638,6 +639,21 @@ ns_status ns_theory_batch(ns_model* model, const double* theta, int64_t ld, int6
         check_ptr(out, "out");
         bind_device(model);
         theory_batch(model, theta, ld, B, out, ldo, precision, (hipStream_t)stream);
+    });
+}
+
+ns_status ns_loglike_batch_noalloc(ns_model* model, const double* theta, int64_t ld, int64_t B, double* logl,
+                                   int32_t precision, void* stream) {
+    return (ns_status)guard([&] {
+        check_ptr(model, "model");
+        check_prec(precision);
+        NS_CHECK(B >= 0 && ld >= model->d, NS_E_SHAPE, "B must be >= 0 and ld >= d");
+        if (B > 0) {
+            check_ptr(theta, "theta");
+            check_ptr(logl, "logl");
+        }
+        bind_device(model);
+        loglike_batch_noalloc(model, theta, ld, B, logl, precision, (hipStream_t)stream);
     });
 }
 

@@ -437,7 +437,7 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
     } else {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         NS_HIP(hipStreamIsCapturing(s, &cs));
-        if (cs == hipStreamCaptureStatusNone && !m->trace && getenv("NSMI_NO_AUTOTUNE") == nullptr) {
+        if (cs == hipStreamCaptureStatusNone && !m->trace && !m->noalloc_call && getenv("NSMI_NO_AUTOTUNE") == nullptr) {
             hipEvent_t e0, e1;
             NS_HIP(hipEventCreate(&e0));
             NS_HIP(hipEventCreate(&e1));

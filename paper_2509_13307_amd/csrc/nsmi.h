@@ -187,6 +187,7 @@ struct ns_model {
 
     // per-kernel tracing: HIP events bracketing each launch on its stream
     bool trace = false;
+    bool noalloc_call = false;       // inside ns_loglike_batch_noalloc: no tuning runs, no trace events
     struct TraceRec { const char* name; hipEvent_t e0, e1; };
     std::vector<TraceRec> trace_recs;
     std::vector<hipEvent_t> trace_pool;
@@ -321,6 +322,14 @@ void slice_step_host_lstar(ns_model* m, double* u, double* logl, int* n_evals, i
 // Hamiltonian Monte Carlo chains (synchronises s).
 void hmc_run(ns_model* m, const ns_hmc_opts* o, const double* minv, double* theta, double* samples, double* logp,
              ns_hmc_result* res, hipStream_t s);
+
+// Allocation-free likelihood: the scratch array's device address, taken once
+// per device with that device current (at the first model created on it),
+// and the batched CMB likelihood with its model vector in that array.
+void scratch_init(int device);
+size_t scratch_bytes();
+void loglike_batch_noalloc(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, int prec,
+                           hipStream_t s);
 
 // Nested slice sampling to convergence.
 void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, int* dn_h, double* du_h,

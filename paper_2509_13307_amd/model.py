@@ -162,6 +162,16 @@ class Model:
                                          C.PRECISIONS[precision], _stream()))
         return out
 
+    def loglike_noalloc(self, theta, out, precision="bf16x3"):
+        """logL into `out` [B] by the allocation-free entry point
+        (ns_loglike_batch_noalloc): the caller provides every buffer."""
+        self._check_theta(theta)
+        B = theta.shape[0]
+        check_vector(out, B, torch.float64, theta.device, "out")
+        C.check(C.lib().ns_loglike_batch_noalloc(self._h, _ptr(theta), theta.stride(0), B, _ptr(out),
+                                                 C.PRECISIONS[precision], _stream()))
+        return out
+
     def theory(self, theta, precision="fp64"):
         """Theory vector [B, n_data] (float64 device tensor) of theta [B, >= d]:
         the prediction the likelihood compares with the data, in data order."""

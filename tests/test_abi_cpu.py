@@ -45,6 +45,7 @@ def test_argument_validation_without_device(capi):
     assert b"desc" in lib.ns_last_error()
     assert lib.ns_loglike_batch(None, None, 6, 10, None, 0, None) == capi.NS_E_INVALID
     assert lib.ns_theory_batch(None, None, 6, 10, None, 100, 0, None) == capi.NS_E_INVALID
+    assert lib.ns_loglike_batch_noalloc(None, None, 6, 10, None, 3, None) == capi.NS_E_INVALID
     assert lib.ns_model_free(None) == capi.NS_OK
     assert lib.ns_last_error() == b""
     assert lib.ns_run(None, None, None, None, None, None, 0, None) == capi.NS_E_INVALID
