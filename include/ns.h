@@ -250,6 +250,14 @@ ns_status ns_loglike_grad_batch(ns_model* model, const double* theta, int64_t ld
  * 0..2d-1 give d Box-Muller normals, draw 2d the bracket offset, then one
  * draw per shrink.  Step-out at most 10 per end, stall when the bracket is
  * narrower than 1e-12 or after 200 shrinks.
+ * The walkers advance in rounds of one batched likelihood call.  A walker may
+ * propose several of its next points in one round: the stepping-out points
+ * of an end and the chain of shrink points that follow one another if each
+ * is rejected are fixed before any evaluation, so the results are applied in
+ * the serial order and u, logl, n_evals and n_stalls are exactly those of
+ * one proposal at a time (evaluations past the deciding one are not counted).
+ * The number per end and round is the library's choice (environment
+ * NSMI_SPEC = 1..4 sets it).
  * Synchronises `stream` (the host polls a completion flag). */
 ns_status ns_slice_step(ns_model* model, double* u, double* logl, int32_t* n_evals,
                         int32_t* n_stalls, int64_t k, double logl_star, const double* dir_chol,
@@ -270,6 +278,9 @@ typedef struct ns_run_opts {
                                     iteration that is a multiple of this       */
     int32_t resume;              /* 1: continue from checkpoint_path if that
                                     file exists (else start afresh)            */
+    int32_t speculate;           /* slice proposals per bracket end and round,
+                                    1..4 (0: the library's choice); any value
+                                    gives the same result, see ns_slice_step   */
 } ns_run_opts;
 
 typedef struct ns_run_result {

@@ -83,6 +83,7 @@ class RunOpts(ctypes.Structure):
         ("checkpoint_path", ctypes.c_char_p),
         ("checkpoint_every", ctypes.c_int32),
         ("resume", ctypes.c_int32),
+        ("speculate", ctypes.c_int32),
     ]
 
 

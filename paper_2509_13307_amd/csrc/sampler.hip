@@ -49,26 +49,28 @@ constexpr int MAX_SHRINK = 200;
 constexpr double STALL_WIDTH = 1e-12;
 constexpr int MAX_DIM = 64;
 
+constexpr int MAX_SPEC = 4;      // speculative proposals per bracket end and round
+
 struct SliceState {
     double* u;        // [k x d] walker positions (caller buffer)
     double* logl;     // [k]
     double* v;        // [k x d] current direction
     double* tl;       // [k]
     double* tr;       // [k]
-    double* tp;       // [k] t of the pending proposal
     int* st;          // [k] phase
     int* step;        // [k] current step (1-based)
     int* q;           // [k] next draw index
     int* ne;          // [k] left-end expansions (stepping out; -1 once that end is final) /
                       //     rejected shrinks
     int* ne2;         // [k] right-end expansions (stepping out; -1 once final)
-    int* pend;        // [k] compact slot of the pending (left-end or shrink) proposal, -1 none
-    int* pend2;       // [k] compact slot of the pending right-end proposal, -1 none
+    int* pend;        // [k] first compact slot of the pending proposals, -1 none
+    int* npl;         // [k] pending left-end (or shrink) proposals, in slots pend ..
+    int* npr;         // [k] pending right-end proposals, in the slots after those
     int* n_evals;     // [k]
     int* n_stalls;    // [k]
-    double* xc;       // [2k x d] compacted proposals (unit cube)
-    int* cidx;        // [2k] walker of each compact slot
-    double* llc;      // [2k] likelihood of each compact slot
+    double* xc;       // [2 spec k x d] compacted proposals (unit cube)
+    int* cidx;        // [2 spec k] walker of each compact slot
+    double* llc;      // [2 spec k] likelihood of each compact slot
     int* ccount;      // [3] compact batch size of the rounds of slot c mod 3
     int* active;      // [3] walkers not done after the advance of such a round
 };
@@ -87,7 +89,8 @@ __global__ void slice_init_kernel(SliceState S, int64_t k, int64_t* iter_p, uint
     S.st[w] = ST_NEWSTEP;
     S.step[w] = 0;
     S.pend[w] = -1;
-    S.pend2[w] = -1;
+    S.npl[w] = 0;
+    S.npr[w] = 0;
     S.n_evals[w] = 0;
     S.n_stalls[w] = 0;
 }
@@ -98,9 +101,17 @@ __global__ void slice_init_kernel(SliceState S, int64_t k, int64_t* iter_p, uint
 // the direction draw (lane i: Box-Muller of draws 2i, 2i+1), the product with
 // L (lane i sums row i in column order, as a serial loop would) and the
 // proposals are spread over the group's lanes, so every value is bitwise that
-// of one thread per walker.  A walker stops at its next needed evaluation(s):
-// at most two proposals (both ends while stepping out, or one shrink point),
-// written after its state machine has run, with compact slots taken by one
+// of one thread per walker.
+//
+// Speculation (spec proposals per bracket end and round): the stepping-out
+// points t_L, t_L - 1, ... of an end, and the shrink points that follow one
+// another if each is rejected (the next bracket, hence the next point, is
+// known from the sign of t before any evaluation), are all fixed in advance;
+// a walker proposes up to spec of them at once and applies the results in
+// the serial algorithm's order, so every decision, draw and counted
+// evaluation is that algorithm's (results past the deciding one are not
+// used).  spec = 1 is the plain one-proposal-per-round walk.  Proposals are
+// written after the state machine has run, with compact slots taken by one
 // atomic per wave.  NORMAL: some prior is normal (its map needs erfinv, whose
 // FP64 form alone takes more than half the registers; without it the kernel
 // fits four waves per SIMD).
@@ -109,7 +120,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
                                                             const double* __restrict__ lstar_p,
                                                             const double* __restrict__ L, int n_inner,
                                                             uint64_t seed, const int64_t* __restrict__ iter_p,
-                                                            int round,
+                                                            int round, int spec,
                                                             const int* __restrict__ pk, const double* __restrict__ pa,
                                                             const double* __restrict__ pb,
                                                             double* __restrict__ thc) {
@@ -134,64 +145,78 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     const int64_t wr = live ? w : k - 1;
     const bool act = lg < d;
     const double lstar = *lstar_p;
-    int st = S.st[wr], step = S.step[wr], q = S.q[wr], ne = S.ne[wr], pend = S.pend[wr];
-    int ne2 = S.ne2[wr], pend2 = S.pend2[wr];
+    int st = S.st[wr], step = S.step[wr], q = S.q[wr], ne = S.ne[wr], ne2 = S.ne2[wr];
+    int pend = S.pend[wr], npl = S.npl[wr], npr = S.npr[wr];
     int nev = S.n_evals[wr], nst = S.n_stalls[wr];
-    double tl = S.tl[wr], tr = S.tr[wr], tp = S.tp[wr], logl = S.logl[wr];
+    double tl = S.tl[wr], tr = S.tr[wr], logl = S.logl[wr];
     double ui = act ? S.u[wr * d + lg] : 0.0, vi = act ? S.v[wr * d + lg] : 0.0;
     __shared__ double Ls[MAX_DIM * MAX_DIM];
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) Ls[e] = L[e];
     __syncthreads();
-    if (!live) {
+    if (!live) {                        // walker k - 1's state was read: none of it is this group's
         st = ST_DONE;
-        pend = pend2 = -1;
+        pend = -1;
+        npl = npr = 0;
     }
     const uint64_t gmask = GS == 64 ? ~0ull : (((1ull << GS) - 1) << gb);
     bool moved = false;
-    // outcome of a shrink proposal at t = tp
-    auto shrink = [&](bool inside, double ll) {
-        if (inside) {
-            ui = __dadd_rn(ui, __dmul_rn(tp, vi));
-            logl = ll;
-            moved = true;
-            st = ST_NEWSTEP;
-        } else {
-            if (tp < 0.0) tl = tp; else tr = tp;
-            ne += 1;
-            if (tr - tl < STALL_WIDTH || ne >= MAX_SHRINK) {
-                nst += 1;
-                st = ST_NEWSTEP;
-            }
-        }
-    };
     // the point at t along the direction lies in the unit cube (outside it
     // needs no evaluation: it is outside the constraint)
     auto inbox = [&](double t) {
         const double xi = __dadd_rn(ui, __dmul_rn(t, vi));
         return (__ballot(act && !((xi >= 0.0) && (xi <= 1.0))) & gmask) == 0;
     };
-    // last round's evaluations
-    if (st == ST_OUT) {
-        if (pend >= 0) {
-            const double ll = S.llc[pend];
-            pend = -1;
-            nev += 1;
-            if (ll > lstar) { tl -= 1.0; ne += 1; } else ne = -1;
+    // shrink point from the bracket and draw qq
+    auto shrink_point = [&](double a, double b, int qq) {
+        const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)qq);
+        return __dadd_rn(a, __dmul_rn(U, __dsub_rn(b, a)));
+    };
+    // last round's evaluations, in the serial order
+    if (pend >= 0) {
+        if (st == ST_OUT) {
+            for (int i = 0; i < npl; ++i) {            // left end at t_L, t_L - 1, ...
+                const double ll = S.llc[pend + i];
+                nev += 1;
+                if (ll > lstar) { tl -= 1.0; ne += 1; } else { ne = -1; break; }
+            }
+            for (int i = 0; i < npr; ++i) {            // right end at t_R, t_R + 1, ...
+                const double ll = S.llc[pend + npl + i];
+                nev += 1;
+                if (ll > lstar) { tr += 1.0; ne2 += 1; } else { ne2 = -1; break; }
+            }
+        } else {
+            // the shrink chain again from its start: points outside the cube are
+            // rejected without evaluation, the evaluated ones take their results
+            int kk = 0;
+            while (true) {
+                const double t = shrink_point(tl, tr, q);
+                ++q;
+                if (inbox(t)) {
+                    const double ll = S.llc[pend + kk];
+                    ++kk;
+                    nev += 1;
+                    if (ll > lstar) {
+                        ui = __dadd_rn(ui, __dmul_rn(t, vi));
+                        logl = ll;
+                        moved = true;
+                        st = ST_NEWSTEP;
+                        break;
+                    }
+                }
+                if (t < 0.0) tl = t; else tr = t;
+                ne += 1;
+                if (tr - tl < STALL_WIDTH || ne >= MAX_SHRINK) {
+                    nst += 1;
+                    st = ST_NEWSTEP;
+                    break;
+                }
+                if (kk == npl) break;
+            }
         }
-        if (pend2 >= 0) {
-            const double ll = S.llc[pend2];
-            pend2 = -1;
-            nev += 1;
-            if (ll > lstar) { tr += 1.0; ne2 += 1; } else ne2 = -1;
-        }
-    } else if (pend >= 0) {
-        const double ll = S.llc[pend];
         pend = -1;
-        nev += 1;
-        shrink(ll > lstar, ll);
+        npl = npr = 0;
     }
-    bool e0 = false, e1 = false;       // proposals: e0 at t0 (left end or shrink point), e1 at tr
-    double t0 = 0.0;
+    double tq[2 * MAX_SPEC];            // this round's proposals: npl left-end / shrink points, then npr right-end
     while (true) {
         if (st == ST_DONE) break;
         if (st == ST_NEWSTEP) {
@@ -219,33 +244,57 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             continue;
         }
         if (st == ST_OUT) {
-            // both ends step out at once, each proposing its current end until
-            // that point is outside the slice or the cube or it has expanded
-            // MAX_EXPAND times; the ends do not interact, so the evaluations
-            // and the final bracket are those of stepping out one end after
-            // the other
+            // both ends step out at once, each proposing its next points until
+            // one is outside the cube or the end has expanded MAX_EXPAND times;
+            // the ends do not interact, so the evaluations and the final
+            // bracket are those of stepping out one end after the other
             if (ne >= 0) {
-                if (ne < MAX_EXPAND && inbox(tl)) { e0 = true; t0 = tl; }
-                else ne = -1;
+                double t = tl;
+                while (npl < spec && ne + npl < MAX_EXPAND) {
+                    if (npl > 0) t -= 1.0;
+                    if (!inbox(t)) break;
+                    tq[npl++] = t;
+                }
+                if (npl == 0) ne = -1;
             }
             if (ne2 >= 0) {
-                if (ne2 < MAX_EXPAND && inbox(tr)) e1 = true;
-                else ne2 = -1;
+                double t = tr;
+                while (npr < spec && ne2 + npr < MAX_EXPAND) {
+                    if (npr > 0) t += 1.0;
+                    if (!inbox(t)) break;
+                    tq[npl + npr++] = t;
+                }
+                if (npr == 0) ne2 = -1;
             }
-            if (e0 || e1) break;
+            if (npl + npr > 0) break;
             st = ST_SHRINK;
             ne = 0;
             continue;
         }
-        const int qq = q++;
-        const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)qq);
-        tp = __dadd_rn(tl, __dmul_rn(U, __dsub_rn(tr, tl)));
-        if (inbox(tp)) { e0 = true; t0 = tp; break; }
-        shrink(false, -INFINITY);
+        // shrink: the next spec points in the cube, each on the bracket the
+        // rejections before it leave; the state stays at the chain's start
+        double ca = tl, cb = tr;
+        int cne = ne, cq = q;
+        bool stall = false;
+        while (npl < spec) {
+            const double t = shrink_point(ca, cb, cq);
+            ++cq;
+            if (inbox(t)) tq[npl++] = t;
+            if (t < 0.0) ca = t; else cb = t;
+            ++cne;
+            if (cb - ca < STALL_WIDTH || cne >= MAX_SHRINK) { stall = true; break; }
+        }
+        if (npl > 0) break;
+        // the bracket collapsed with no point in the cube: the step stalls now
+        (void)stall;
+        tl = ca; tr = cb; ne = cne; q = cq;
+        nst += 1;
+        st = ST_NEWSTEP;
     }
     // compact slots: exclusive prefix of the walkers' proposal counts over the
     // wave (group leaders hold them), one atomic for the wave
-    const int nemit = (lg == 0) ? (int)e0 + (int)e1 : 0;
+    const int nmine = npl + npr;
+    const int nemit = (lg == 0) ? nmine : 0;
     int inc = nemit;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -257,28 +306,26 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     if (lane == 0 && total > 0) base = atomicAdd(S.ccount + slot, total);
     base = __shfl(base, 0, 64) + __shfl(inc - nemit, gb, 64);
 #pragma unroll 1
-    for (int e = 0; e < 2; ++e) {
-        if (!(e == 0 ? e0 : e1)) continue;
-        const int cs = base + (e == 1 && e0 ? 1 : 0);
-        const double xi = __dadd_rn(ui, __dmul_rn(e == 0 ? t0 : tr, vi));
+    for (int e = 0; e < nmine; ++e) {
+        const int cs = base + e;
+        const double xi = __dadd_rn(ui, __dmul_rn(tq[e], vi));
         if (act) {
             S.xc[(int64_t)cs * d + lg] = xi;
             thc[(int64_t)cs * d + lg] = NORMAL ? prior_map(xi, pk[lg], pa[lg], pb[lg]) : pa[lg] + (pb[lg] - pa[lg]) * xi;
         }
         if (lg == 0) S.cidx[cs] = (int)w;
-        if (e == 0) pend = cs;
-        else pend2 = cs;
     }
+    if (nmine > 0) pend = base;
     if (live) {
         if (act) {
             if (moved) S.u[w * d + lg] = ui;
             S.v[w * d + lg] = vi;
         }
         if (lg == 0) {
-            S.st[w] = st; S.step[w] = step; S.q[w] = q; S.ne[w] = ne; S.pend[w] = pend;
-            S.ne2[w] = ne2; S.pend2[w] = pend2;
+            S.st[w] = st; S.step[w] = step; S.q[w] = q; S.ne[w] = ne; S.ne2[w] = ne2;
+            S.pend[w] = pend; S.npl[w] = npl; S.npr[w] = npr;
             S.n_evals[w] = nev; S.n_stalls[w] = nst;
-            S.tl[w] = tl; S.tr[w] = tr; S.tp[w] = tp; S.logl[w] = logl;
+            S.tl[w] = tl; S.tr[w] = tr; S.logl[w] = logl;
         }
     }
     // unfinished walkers: one atomic for the wave
@@ -640,7 +687,8 @@ __global__ __launch_bounds__(CTL_NT) void ns_control_kernel(NSCtl* __restrict__ 
         W.st[w] = ST_NEWSTEP;
         W.step[w] = 0;
         W.pend[w] = -1;
-        W.pend2[w] = -1;
+        W.npl[w] = 0;
+        W.npr[w] = 0;
         W.n_evals[w] = 0;
         W.n_stalls[w] = 0;
     }
@@ -793,28 +841,30 @@ __global__ void zero_ints_kernel(int* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-static SliceState carve_slice(ns_model* m, int64_t k, int d, double* u, double* logl, int* ne, int* ns,
+static SliceState carve_slice(ns_model* m, int64_t k, int d, int spec, double* u, double* logl, int* ne, int* ns,
                               int64_t** iter_p) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t bytes = al(k * d * 8) * 3 + al(k * 8) * 5 + al(k * 4) * 9 + al(16) * 3;
+    const int64_t kc = 2 * (int64_t)spec * k;          // compact slots
+    const size_t bytes = al(k * d * 8) + al(kc * d * 8) + al(k * 8) * 2 + al(kc * 8) + al(k * 4) * 8 +
+                         al(kc * 4) + al(16) * 3;
     m->ws_slice.ensure(bytes);
     char* p = m->ws_slice.as<char>();
     SliceState S;
     S.u = u; S.logl = logl; S.n_evals = ne; S.n_stalls = ns;
     S.v = (double*)p; p += al(k * d * 8);
-    S.xc = (double*)p; p += al(2 * k * d * 8);
+    S.xc = (double*)p; p += al(kc * d * 8);
     S.tl = (double*)p; p += al(k * 8);
     S.tr = (double*)p; p += al(k * 8);
-    S.tp = (double*)p; p += al(k * 8);
-    S.llc = (double*)p; p += al(2 * k * 8);
+    S.llc = (double*)p; p += al(kc * 8);
     S.st = (int*)p; p += al(k * 4);
     S.step = (int*)p; p += al(k * 4);
     S.q = (int*)p; p += al(k * 4);
     S.ne = (int*)p; p += al(k * 4);
     S.ne2 = (int*)p; p += al(k * 4);
     S.pend = (int*)p; p += al(k * 4);
-    S.pend2 = (int*)p; p += al(k * 4);
-    S.cidx = (int*)p; p += al(2 * k * 4);
+    S.npl = (int*)p; p += al(k * 4);
+    S.npr = (int*)p; p += al(k * 4);
+    S.cidx = (int*)p; p += al(kc * 4);
     S.ccount = (int*)p; p += al(16);
     S.active = (int*)p; p += al(16);
     if (iter_p) *iter_p = (int64_t*)p;
@@ -897,8 +947,9 @@ static bool graphs_enabled(const ns_model* m) { return !m->trace && getenv("NSMI
 constexpr int GRAPH_ROUNDS = 24;      // slice rounds per captured graph (a multiple of 3)
 constexpr int CTL_EVERY = 8;          // rounds between control points of a nested-sampling graph
 
-static void advance_round(ns_model* m, const SliceState& S, int64_t k, const double* lstar_dev, const double* L,
-                          int n_inner, uint64_t seed, const int64_t* iter_p, int round, int prec, hipStream_t st) {
+static void advance_round(ns_model* m, const SliceState& S, int64_t k, int spec, const double* lstar_dev,
+                          const double* L, int n_inner, uint64_t seed, const int64_t* iter_p, int round, int prec,
+                          hipStream_t st) {
     const int d = m->d;
     double* thc = m->ws_theta.as<double>();
     {
@@ -906,7 +957,7 @@ static void advance_round(ns_model* m, const SliceState& S, int64_t k, const dou
         auto launch = [&](auto kern, int gs) {
             const int64_t per_block = 4 * (64 / gs);
             hipLaunchKernelGGL(kern, dim3((unsigned)((k + per_block - 1) / per_block)), dim3(256), 0, st, S, k, d,
-                               lstar_dev, L, n_inner, seed, iter_p, round, m->prior_kind.as<int>(),
+                               lstar_dev, L, n_inner, seed, iter_p, round, spec, m->prior_kind.as<int>(),
                                m->prior_a.as<double>(), m->prior_b.as<double>(), thc);
         };
         if (m->any_normal_prior) {
@@ -921,7 +972,23 @@ static void advance_round(ns_model* m, const SliceState& S, int64_t k, const dou
             else launch(slice_advance_kernel<64, false>, 64);
         }
     }
-    loglike_batch(m, thc, d, 2 * k, S.llc, prec, S.ccount + round % 3, st);
+    loglike_batch(m, thc, d, 2 * spec * k, S.llc, prec, S.ccount + round % 3, st);
+}
+
+// Speculative proposals per bracket end and round (1 .. MAX_SPEC): the
+// request, else NSMI_SPEC, else the library's choice -- for the CMB and test
+// likelihoods as many as keep a round within 4096 rows (up to that size a
+// batch costs about what one row does, so proposals that turn out unneeded
+// are nearly free while the rounds fall), for the shear likelihood 1 (its
+// cost grows with the rows from small batches on).
+static int slice_spec(const ns_model* m, int64_t k, int requested) {
+    int spec = requested;
+    if (spec <= 0) {
+        const char* e = getenv("NSMI_SPEC");
+        spec = e ? atoi(e) : 0;
+    }
+    if (spec <= 0) spec = m->kind == NS_MODEL_SHEAR ? 1 : (int)std::max<int64_t>(1, 4096 / (2 * std::max<int64_t>(k, 1)));
+    return std::min(std::max(spec, 1), MAX_SPEC);
 }
 
 void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stalls, int64_t k,
@@ -931,16 +998,18 @@ void slice_step(ns_model* m, double* u, double* logl, int* n_evals, int* n_stall
     NS_CHECK(d <= MAX_DIM, NS_E_UNSUPPORTED, "slice sampler supports d <= 64");
     if (k == 0) return;
     int64_t* iter_p = nullptr;
-    SliceState S = carve_slice(m, k, d, u, logl, n_evals, n_stalls, &iter_p);
-    // up to two proposals per walker and round (both ends while stepping out)
-    m->ws_theta.ensure((size_t)2 * k * d * sizeof(double));
+    const int spec = slice_spec(m, k, 0);
+    SliceState S = carve_slice(m, k, d, spec, u, logl, n_evals, n_stalls, &iter_p);
+    // up to 2 spec proposals per walker and round (both ends while stepping out)
+    m->ws_theta.ensure((size_t)2 * spec * k * d * sizeof(double));
     PinnedHost flag(64);
     int* hflag = static_cast<int*>(flag.p);
     hipLaunchKernelGGL(slice_init_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, S, k, iter_p, iter);
     NS_HIP(hipGetLastError());
     const int64_t max_rounds = (int64_t)n_inner * (2 * MAX_EXPAND + MAX_SHRINK + 4) + 8;
     auto chunk = [&](hipStream_t st) {
-        for (int c = 0; c < GRAPH_ROUNDS; ++c) advance_round(m, S, k, lstar_dev, L, n_inner, seed, iter_p, c, prec, st);
+        for (int c = 0; c < GRAPH_ROUNDS; ++c)
+            advance_round(m, S, k, spec, lstar_dev, L, n_inner, seed, iter_p, c, prec, st);
         NS_HIP(hipGetLastError());
     };
     // first chunk eagerly on the caller's stream (sizes every workspace, tunes
@@ -1056,6 +1125,7 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
     NS_CHECK(o->n_replicates >= 0, NS_E_INVALID, "n_replicates must be >= 0");
     NS_CHECK(o->checkpoint_every >= 0, NS_E_INVALID, "checkpoint_every must be >= 0");
     NS_CHECK(o->resume == 0 || o->resume == 1, NS_E_INVALID, "resume must be 0 or 1");
+    NS_CHECK(o->speculate >= 0 && o->speculate <= MAX_SPEC, NS_E_INVALID, "speculate must be in [0, 4]");
     const char* ckpt = (o->checkpoint_path && o->checkpoint_path[0]) ? o->checkpoint_path : nullptr;
     NS_CHECK(ckpt || (o->checkpoint_every == 0 && o->resume == 0), NS_E_INVALID,
              "checkpoint_every and resume need a checkpoint_path");
@@ -1145,9 +1215,10 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
 
     // ---- the device-driven iteration
     int64_t* iter_unused = nullptr;
-    SliceState W = carve_slice(m, k, d, wu.as<double>(), wl.as<double>(), wne.as<int>(), wns.as<int>(),
+    const int spec = slice_spec(m, k, o->speculate);
+    SliceState W = carve_slice(m, k, d, spec, wu.as<double>(), wl.as<double>(), wne.as<int>(), wns.as<int>(),
                                &iter_unused);
-    m->ws_theta.ensure((size_t)2 * k * d * sizeof(double));
+    m->ws_theta.ensure((size_t)2 * spec * k * d * sizeof(double));
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, W.ccount, 3);
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, W.active, 3);
     NS_HIP(hipGetLastError());
@@ -1162,7 +1233,7 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
                                    live_u.as<double>(), live_l.as<double>(), order.as<int>(), L.as<double>(), n, k,
                                    d, o->seed, log_frac, c);
             }
-            advance_round(m, W, k, lstar_dev, L.as<double>(), o->n_inner, o->seed, it_dev, c, o->precision, st);
+            advance_round(m, W, k, spec, lstar_dev, L.as<double>(), o->n_inner, o->seed, it_dev, c, o->precision, st);
         }
         NS_HIP(hipGetLastError());
     };

@@ -219,14 +219,15 @@ class Model:
         return ne, ns
 
     def run(self, n_live, n_delete, n_inner, precision="fp64", frac_remain=1e-3, seed=1, max_iter=100000,
-            n_replicates=1000, capacity=0, checkpoint_path=None, checkpoint_every=0, resume=False):
+            n_replicates=1000, capacity=0, checkpoint_path=None, checkpoint_every=0, resume=False, speculate=0):
         """Nested slice sampling; returns a dict (logz, sigma, h, ..., and dead points if capacity > 0).
         With checkpoint_path the state is written every checkpoint_every
         iterations and when max_iter ends the run; resume=True continues from
-        that file if it exists."""
+        that file if it exists.  speculate: slice proposals per bracket end and
+        round (1-4, 0 = the library's choice); the result does not depend on it."""
         path = None if checkpoint_path is None else str(checkpoint_path).encode()
         o = C.RunOpts(n_live, n_delete, n_inner, C.PRECISIONS[precision], frac_remain, seed, max_iter, n_replicates,
-                      path, int(checkpoint_every), 1 if resume else 0)
+                      path, int(checkpoint_every), 1 if resume else 0, int(speculate))
         r = C.RunResult()
         dl = np.zeros(capacity)
         dn = np.zeros(capacity, dtype=np.int32)

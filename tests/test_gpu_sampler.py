@@ -53,9 +53,13 @@ def walkers_above(model, n, seed):
     return u, ll, lstar, u[keep], ll[keep]
 
 
+@pytest.mark.parametrize("spec", ["1", "3"])
 @pytest.mark.parametrize("name,k_live,n_inner", [("cmb6", 100, 6), ("cmbtt_cv", 64, 3), ("shear10", 40, 2)])
-def test_slice_step_replays_oracle(name, k_live, n_inner):
-    say(f"case slice step {name}")
+def test_slice_step_replays_oracle(name, k_live, n_inner, spec, monkeypatch):
+    """One proposal per walker and round, and three (speculative stepping-out
+    and shrink chains): both replay the oracle's serial trajectories."""
+    monkeypatch.setenv("NSMI_SPEC", spec)
+    say(f"case slice step {name} spec {spec}")
     m = W.load_model(name)
     u_all, _, lstar, u0, l0 = walkers_above(m, k_live, seed=9)
     L = nested.direction_cholesky(u_all)
@@ -297,3 +301,23 @@ def test_ns_run_resume_is_bitwise(tmp_path, prec):
         assert rest[key] == full[key], key
     for key in ("dead_logl", "dead_n", "dead_u"):
         np.testing.assert_array_equal(rest[key], full[key])
+
+
+@pytest.mark.parametrize("name,n_live,n_inner,prec", [("gauss", 2400, 15, "fp64"), ("cmb6", 100, 30, "fp64"),
+                                                      ("cmbtt_cv", 200, 6, "bf16x3")])
+def test_ns_run_does_not_depend_on_speculation(name, n_live, n_inner, prec):
+    """Speculative proposals (1, 2 or 4 per bracket end and round) change the
+    rounds a run takes, not its result: every output is bitwise equal."""
+    say(f"case ns_run speculation {name}")
+    m = W.gauss_structure(d=3, mu=[0.1, 0.5, 0.8], sigma=[0.05, 0.1, 0.08]) if name == "gauss" else W.load_model(name)
+    g = mk(m)
+    runs = [g.run(n_live, n_live // 2, n_inner, precision=prec, seed=8, n_replicates=50, capacity=400000,
+                  speculate=sp, max_iter=12 if name == "cmbtt_cv" else 100000) for sp in (1, 2, 4)]
+    g.close()
+    for sp, r in zip((1, 2, 4), runs):
+        say(f"  speculate {sp}: logZ {r['logz']!r} iters {r['n_iter']} evals {r['n_evals']} wall {r['wall_s']:.3f}s")
+    for r in runs[1:]:
+        for key in ("logz", "sigma", "h", "n_iter", "n_evals", "n_stalls", "n_dead"):
+            assert r[key] == runs[0][key], key
+        for key in ("dead_logl", "dead_n", "dead_u"):
+            np.testing.assert_array_equal(r[key], runs[0][key])
