@@ -420,12 +420,14 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
     // outside stream capture and tracing
     const int h512 = H == 512;
     const FusedCfg* cfgs = FUSED_CFGS[h512][x3];
-    // candidate c with its output-block grouping
-    auto run = [&](int c) {
+    // candidate c with its output-block grouping, on `nr` rows given on the
+    // host (tuning) or on the launch's rows and device count
+    auto run_rows = [&](int c, int64_t nr, const int* cnt) {
         FusedArgs Ac = A;
         Ac.qg = cfgs[c].split_out ? (A.N_out + H - 1) / H : 1;
-        cfgs[c].fn(m, Ac, theta, ld, rows, rpw, G, count, s);
+        cfgs[c].fn(m, Ac, theta, ld, nr, rpw, G, cnt, s);
     };
+    auto run = [&](int c) { run_rows(c, rows, count); };
     const auto key = std::make_tuple(2 + (int)x3 + 2 * h512, rows, A.N_out, H, G);
     int best = 0;
     auto it = m->tune.find(key);
@@ -442,23 +444,36 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
             NS_HIP(hipEventCreate(&e0));
             NS_HIP(hipEventCreate(&e1));
             // two interleaved passes over the candidates, the faster pass counts
-            // (clock and cache state drift between candidates of one pass)
+            // (clock and cache state drift between candidates of one pass).  A
+            // launch whose live rows are a device count (the sampler's rounds,
+            // whose batches vary from round to round below the maximum `rows`)
+            // is timed at a quarter, half and all of `rows` and ranked by the
+            // sum: the rows those launches carry are rarely the maximum.
             const int ncfg = fused_ncfg(h512, x3);
-            float best_ms[FUSED_NCFG];
-            for (int c = 0; c < ncfg; ++c) best_ms[c] = 1e30f;
-            for (int pass = 0; pass < 2; ++pass)
-                for (int c = 0; c < ncfg; ++c) {
-                    run(c);
-                    NS_HIP(hipEventRecord(e0, s));
-                    for (int r = 0; r < 4; ++r) run(c);
-                    NS_HIP(hipEventRecord(e1, s));
-                    NS_HIP(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    NS_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    best_ms[c] = std::min(best_ms[c], ms);
-                }
+            const int64_t sizes[3] = {std::max<int64_t>(rpw, rows / 4 / rpw * rpw),
+                                      std::max<int64_t>(rpw, rows / 2 / rpw * rpw), rows};
+            const int nsz = count ? 3 : 1;
+            float tot_ms[FUSED_NCFG];
+            for (int c = 0; c < ncfg; ++c) tot_ms[c] = 0.f;
+            for (int z = 0; z < nsz; ++z) {
+                const int64_t nr = count ? sizes[z] : rows;
+                float best_ms[FUSED_NCFG];
+                for (int c = 0; c < ncfg; ++c) best_ms[c] = 1e30f;
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int c = 0; c < ncfg; ++c) {
+                        run_rows(c, nr, count ? nullptr : count);
+                        NS_HIP(hipEventRecord(e0, s));
+                        for (int r = 0; r < 4; ++r) run_rows(c, nr, count ? nullptr : count);
+                        NS_HIP(hipEventRecord(e1, s));
+                        NS_HIP(hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        NS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        best_ms[c] = std::min(best_ms[c], ms);
+                    }
+                for (int c = 0; c < ncfg; ++c) tot_ms[c] += best_ms[c];
+            }
             for (int c = 1; c < ncfg; ++c)
-                if (best_ms[c] < best_ms[best]) best = c;
+                if (tot_ms[c] < tot_ms[best]) best = c;
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             m->tune[key] = best;

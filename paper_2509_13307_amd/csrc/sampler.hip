@@ -976,18 +976,19 @@ static void advance_round(ns_model* m, const SliceState& S, int64_t k, int spec,
 }
 
 // Speculative proposals per bracket end and round (1 .. MAX_SPEC): the
-// request, else NSMI_SPEC, else the library's choice -- for the CMB and test
-// likelihoods as many as keep a round within 4096 rows (up to that size a
-// batch costs about what one row does, so proposals that turn out unneeded
-// are nearly free while the rounds fall), for the shear likelihood 1 (its
-// cost grows with the rows from small batches on).
+// request, else NSMI_SPEC, else the library's choice -- 2 for the CMB and
+// test likelihoods while a round stays within 8192 rows (two proposals per end
+// take the rounds per iteration from about 140 to 90 on the CMB workloads,
+// more take them to about 75 while the batches, hence the likelihood's cost,
+// grow), 1 for the shear likelihood (its cost grows with the rows from small
+// batches on).
 static int slice_spec(const ns_model* m, int64_t k, int requested) {
     int spec = requested;
     if (spec <= 0) {
         const char* e = getenv("NSMI_SPEC");
         spec = e ? atoi(e) : 0;
     }
-    if (spec <= 0) spec = m->kind == NS_MODEL_SHEAR ? 1 : (int)std::max<int64_t>(1, 4096 / (2 * std::max<int64_t>(k, 1)));
+    if (spec <= 0) spec = (m->kind == NS_MODEL_SHEAR || 4 * k > 8192) ? 1 : 2;
     return std::min(std::max(spec, 1), MAX_SPEC);
 }
 
