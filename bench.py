@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-shear", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batch-scaling sweep")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the per-workload |dlogL| leg")
     ap.add_argument("--model-comparison", action="store_true",
                     help="only run the LCDM vs w0wa nested-sampling comparison and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -235,6 +237,12 @@ def main():
         "roofline": roofline,
         "bf16_tiles": g.tuning_report(),
     }
+    if "fp64" in traces and head != "fp64":
+        # the paper's own arithmetic: roofline of the FP64 form's dominant kernel
+        tr64 = traces["fp64"]
+        dom64 = max(tr64, key=lambda k: tr64[k][1])
+        n64, t64 = tr64[dom64]
+        out["roofline_fp64"] = roofline_of(dom64, t64 / n64 * 1e-3, "fp64", m, B, args.workload)
 
     # per-call distribution of the headline form: 50 calls, each between its own events
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
@@ -258,10 +266,87 @@ def main():
     if not args.no_shear:
         out["shear"] = shear_leg(Model, W, torch, dev)
 
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(Model, W, torch, dev)
+
     if not args.no_cpu:
         out["cpu_baseline"], out["accuracy"] = cpu_leg(m, g, forms, torch, dev)
+        if not args.no_accuracy:
+            out["accuracy"]["per_workload"] = accuracy_leg(Model, W, torch, dev)
 
     print(json.dumps(out), flush=True)
+
+
+def accuracy_leg(Model, W, torch, dev):
+    """max |dlogL| of every form against the FP64 oracle on posterior-region
+    walkers (theta_fid plus Fisher-scaled Gaussian draws, capped at a tenth of
+    a uniform prior's width), per workload; the bars are 1e-6 (FP64) and
+    1e-2 (reduced forms)."""
+    from oracle.likelihood import loglike as oracle_loglike
+    plan = [("cmb6", 64), ("cmb4x2500", 64), ("cmbtt_cv", 64), ("shear10", 32), ("shear64", 32),
+            ("shear_full", 16), ("shear_interp", 16)]
+    out = {}
+    for name, B in plan:
+        m = W.load_model(name)
+        g = Model(m)
+        width = np.where(m["prior_kind"] == 0, m["prior_b"] - m["prior_a"], 1.0)
+        th = W.posterior_draws(m["theta_fid"], np.minimum(m["fisher_sigma"], 0.1 * width), B, tag=19)
+        ref = oracle_loglike(th, m, chunk=64)
+        fin = np.isfinite(ref)
+        t = torch.tensor(th, dtype=torch.float64, device=dev)
+        row = {"walkers": int(fin.sum())}
+        for p in ("fp64", "fp32", "bf16x3", "bf16"):
+            got = g.loglike(t, p).cpu().numpy()
+            row[p] = float(np.max(np.abs(got[fin] - ref[fin])))
+        row["meets_bar"] = {p: bool(row[p] <= (1e-6 if p == "fp64" else 1e-2)) for p in ("fp64", "fp32", "bf16x3", "bf16")}
+        out[name] = row
+        g.close()
+        print(f"# accuracy {name}: {json.dumps(row)}", file=sys.stderr, flush=True)
+    return out
+
+
+def adjoint_leg(Model, W, torch, dev):
+    """ns_loglike_grad_batch (logL and d logL / d theta by the hand-written
+    adjoint) at batch 4096: gradients per second and the rate of the
+    emulator's backward GEMMs (input gradients only: the multiply-adds of its
+    forward GEMM layers once more), against the peak of their arithmetic
+    (FP64 for the FP64 form; the reduced forms run the adjoint in FP32)."""
+    B = 4096
+    out = {}
+    for name, precs in (("cmb4x2500", ("fp64", "bf16x3")), ("shear64", ("fp64",))):
+        m = W.load_model(name)
+        g = Model(m)
+        th = torch.tensor(W.prior_draws(m, B, tag=22), dtype=torch.float64, device=dev)
+        rows = B * int(m.get("n_z", 1))
+        back_flops = sum(2.0 * rows * Wl.shape[0] * Wl.shape[1] for net in m["nets"] for Wl in net["W"][1:])
+        for prec in precs:
+            g.loglike_grad(th, prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 3
+            e0.record()
+            for _ in range(reps):
+                g.loglike_grad(th, prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            g.trace(True)
+            g.loglike_grad(th, prec)
+            tr = g.trace_report()
+            g.trace(False)
+            key = "adj_gemm_f64" if prec == "fp64" else "adj_gemm_f32"
+            n_adj, t_adj = tr.get(key, (0, 0.0))
+            peak = MI355X_PEAK["fp64" if prec == "fp64" else "fp32"]
+            achieved = back_flops / (t_adj * 1e-3) / 1e12 if t_adj > 0 else None
+            out[f"{name}_{prec}"] = dict(
+                batch=B, ms_per_call=round(ms, 3), grads_per_s=round(B / (ms * 1e-3), 1),
+                backward_gemm=dict(kernel=key, launches=n_adj, total_us=round(t_adj * 1e3, 1),
+                                   work_flop=back_flops, achieved_tflops=None if achieved is None else round(achieved, 2),
+                                   peak_tflops=peak, frac=None if achieved is None else round(achieved / peak, 4)),
+                kernels_us={k: round(t / n * 1e3, 2) for k, (n, t) in tr.items()})
+            print(f"# adjoint {name} {prec}: {json.dumps(out[f'{name}_{prec}'])}", file=sys.stderr, flush=True)
+        g.close()
+    return out
 
 
 def environment(torch):
@@ -333,6 +418,11 @@ def ns_leg(Model, W):
     g = Model(m)
     torch.cuda.synchronize()
     out = {}
+    # one untimed iteration per form and live-point count first: the
+    # likelihood's launch shapes are tuned on first use (a one-time cost of a
+    # model, kept out of the timed runs)
+    for n, prec in ((100, "fp64"), (2400, "fp64"), (2400, "bf16x3")):
+        g.run(n, n // 2, 30, precision=prec, seed=1, n_replicates=0, max_iter=1)
     r = g.run(100, 50, 30, precision="fp64", seed=1, n_replicates=1000)
     out["as_configured"] = dict(n_live=100, n_delete=50, logz=r["logz"], sigma=r["sigma"], wall_s=r["wall_s"],
                                 n_iter=r["n_iter"], n_evals=r["n_evals"])
@@ -346,6 +436,7 @@ def ns_leg(Model, W):
     m = W.load_model("cmbtt_cv")
     g = Model(m)
     for prec in ("fp64", "bf16x3"):
+        g.run(1000, 500, 30, precision=prec, seed=3, n_replicates=0, max_iter=1)
         r = g.run(1000, 500, 30, precision=prec, seed=3, n_replicates=1000)
         out[f"cmbtt_cv_{prec}"] = dict(n_live=1000, n_delete=500, logz=r["logz"], sigma=r["sigma"],
                                        wall_s=r["wall_s"], n_iter=r["n_iter"], n_evals=r["n_evals"])
