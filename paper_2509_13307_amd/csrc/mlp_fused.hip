@@ -28,6 +28,7 @@
 namespace nsmi {
 
 constexpr int FM_MAXHID = 6;   // hidden GEMM layers supported
+constexpr int FM_SLACK = 64;   // bytes behind the activation planes (read-ahead past a layer's last K step)
 
 struct FusedNet {
     const float* W1; const float* b1; const float* be1; const float* ga1;   // first layer (FP32)
@@ -70,8 +71,10 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     static_assert(KC % P == 0 && P % 2 == 0, "prefetch depth must be even and divide the K steps");
     static_assert(NT % H == 0, "threads must be a multiple of the hidden width");
     extern __shared__ __attribute__((aligned(16))) uint16_t fm_lds[];
-    uint16_t* hs = fm_lds;                 // [R][HS] hi (or only) plane
-    uint16_t* hl = fm_lds + R * HS;        // [R][HS] lo plane (split form)
+    // [R][HS] hi (or only) plane, then the lo plane (split form), then
+    // FM_SLACK bytes that the read-ahead of a layer's last K step may touch
+    uint16_t* hs = fm_lds;
+    uint16_t* hl = fm_lds + R * HS;
     __shared__ float xs[R][16];
     __shared__ int zrow[R];                // redshift-node index of each row (row mod mu_rows)
     __shared__ int rowo[R];                // output offset of each row (row ldo), -1 beyond the live rows
@@ -90,9 +93,10 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     if (lin >= live) return;
     if ((live & 7) == 0) lin = (lin & 7) * (live >> 3) + (lin >> 3);
     const int g = (lin / nlb) % gridDim.y, rb = lin % nlb, q = lin / (nlb * gridDim.y);
-    const FusedNet& N = A.net[g];
+    const FusedNet N = A.net[g];           // by value: the fields live in scalar registers
     const int64_t r0 = (int64_t)rb * R;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_in = A.n_in, n_hidden = A.n_hidden, N_out = A.N_out;
     const int nvalid = (int)min<int64_t>(R, nrows - r0);   // live rows of this block
     if (tid < R) {
@@ -150,26 +154,29 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     if (nob <= 0) return;
     const int nseg = n_hidden + nob;
     auto seg_of = [&](int v) { return v < n_hidden ? v : v + ob0; };
-    const int S = nseg * KC;
     // fragment block (kc, nt) of a layer with nt_l 32-unit tiles sits at
-    // (kc nt_l + nt) 512 elements: one K step of a layer is contiguous
+    // (kc nt_l + nt) 512 elements: one K step of a layer is contiguous.  The
+    // wave's fragments of K step 0 of segment v start at the (wave-uniform)
+    // element offset seg_frag(v); successive K steps lie `stride` apart, and
+    // lane l reads elements 8 l .. 8 l + 7 of each 512-element block.
     const int nt_out = ncb * H / 32;
-    auto frag = [&](int s) -> size_t {
-        s = min(s, S - 1);
-        const int v = s / KC, kc = s - v * KC, seg = seg_of(v);
+    auto seg_frag = [&](int v, int& stride) -> size_t {
+        const int seg = seg_of(v);
         const bool hid = seg < n_hidden;
         int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
         if (!hid && nb >= N_out) nb = 0;
-        const int ntl = hid ? H / 32 : nt_out;
-        return (size_t)min(seg, n_hidden) * H * H + ((size_t)kc * ntl + nb / 32) * 512 + (size_t)lane * 8;
+        stride = (hid ? H / 32 : nt_out) * 512;
+        return (size_t)min(seg, n_hidden) * H * H + (size_t)(nb / 32) * 512;
     };
+    const unsigned lane8 = (unsigned)lane * 8u;
     bf16x8_t rh[P][CT], rl[P][CT];
-    auto fetch = [&](int s, bf16x8_t (&bh)[CT], bf16x8_t (&bl)[CT]) {
-        const size_t off = frag(s);
+    auto fetch = [&](size_t off, bf16x8_t (&bh)[CT], bf16x8_t (&bl)[CT]) {
+        const uint16_t* wh = N.Wf + off;
+        const uint16_t* wl = N.Wfl + off;
 #pragma unroll
         for (int j = 0; j < CT; ++j) {
-            bh[j] = *reinterpret_cast<const bf16x8_t*>(N.Wf + off + (size_t)j * 512);
-            if (X3) bl[j] = *reinterpret_cast<const bf16x8_t*>(N.Wfl + off + (size_t)j * 512);
+            bh[j] = *reinterpret_cast<const bf16x8_t*>(wh + j * 512 + lane8);
+            if (X3) bl[j] = *reinterpret_cast<const bf16x8_t*>(wl + j * 512 + lane8);
         }
     };
     f32x16_t acc[RT][CT];
@@ -179,21 +186,27 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         for (int j = 0; j < CT; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    int scur;
+    size_t cur = seg_frag(0, scur);
 #pragma unroll
-    for (int u = 0; u < P; ++u) fetch(u, rh[u], rl[u]);
+    for (int u = 0; u < P; ++u) fetch(cur + (size_t)u * scur, rh[u], rl[u]);
     // the compiler may issue these first loads in any order; waiting for them
     // here keeps that order out of the K-step loop's load accounting
     __builtin_amdgcn_s_waitcnt(0x0F70);
 
     // A operands (activation fragments) of one K step, double-buffered: the
-    // LDS reads of step kc + 1 are issued before the MFMAs of step kc
+    // LDS reads of step kc + 1 are issued before the MFMAs of step kc.  The
+    // read-ahead past a layer's last step (kc = KC) lands in the next row's
+    // first elements or, for the last row, in the slack behind the planes; it
+    // is never used.
+    const int abase = (lane & 31) * HS + (lane >> 5) * 8;
     bf16x8_t ah[2][RT], al[2][RT];
     auto read_a = [&](int kc, bf16x8_t (&xh)[RT], bf16x8_t (&xl)[RT]) {
-        const int koff = kc * 16 + (lane >> 5) * 8;
+        const int koff = abase + kc * 16;
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
-            xh[i] = *reinterpret_cast<const bf16x8_t*>(&hs[(i * 32 + (lane & 31)) * HS + koff]);
-            if (X3) xl[i] = *reinterpret_cast<const bf16x8_t*>(&hl[(i * 32 + (lane & 31)) * HS + koff]);
+            xh[i] = *reinterpret_cast<const bf16x8_t*>(&hs[i * 32 * HS + koff]);
+            if (X3) xl[i] = *reinterpret_cast<const bf16x8_t*>(&hl[i * 32 * HS + koff]);
         }
     };
 
@@ -207,8 +220,29 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         // in the later blocks either, and no barrier follows the hidden
         // layers: it stops here and leaves the matrix pipe to the live waves
         if (!hid && nb >= N_out) break;
+        // the stage P steps past the last K step is in the next segment, or,
+        // after the last segment, the last stage again
+        int snext = 0;
+        const size_t nxt = v + 1 < nseg ? seg_frag(v + 1, snext) : cur + (size_t)(KC - 1) * scur;
+        // epilogue vectors of this segment, loaded while its K steps run
+        const float* vb = N.vec + (size_t)seg * 3 * H;             // hidden: b, beta, gamma
+        const float* bo = N.vec + (size_t)n_hidden * 3 * H;        // output: bias
+        float e0[CT], e1[CT], e2[CT];
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            const int c = nb + j * 32 + (lane & 31);
+            if (hid) {
+                e0[j] = vb[c]; e1[j] = vb[H + c]; e2[j] = vb[2 * H + c];
+            } else {
+                const int cc = min(c, N_out - 1);
+                e0[j] = bo[cc]; e1[j] = N.sigma[cc]; e2[j] = N.mu[cc];
+            }
+        }
         read_a(0, ah[0], al[0]);
         for (int kc0 = 0; kc0 < KC; kc0 += P) {
+            const bool last = kc0 + P >= KC;
+            const size_t fb = last ? nxt : cur + (size_t)(kc0 + P) * scur;
+            const int fs = last ? snext : scur;
 #pragma unroll
             for (int u = 0; u < P; ++u) {
                 // slot u feeds this step's MFMAs first and is then refilled with
@@ -216,10 +250,8 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                 const int kc = kc0 + u;
                 const bf16x8_t (&bh)[CT] = rh[u];
                 const bf16x8_t (&bl)[CT] = rl[u];
-                // P is even, so kc and u have the same parity; the last step
-                // of a segment re-reads its own fragments (nothing is waiting
-                // for the next segment's input yet)
-                read_a(min(kc + 1, KC - 1), ah[(u + 1) & 1], al[(u + 1) & 1]);
+                // P is even, so kc and u have the same parity
+                read_a(kc + 1, ah[(u + 1) & 1], al[(u + 1) & 1]);
                 __builtin_amdgcn_sched_barrier(0);
                 const bf16x8_t (&xh)[RT] = ah[u & 1];
                 const bf16x8_t (&xl)[RT] = al[u & 1];
@@ -237,7 +269,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh[j], acc[i][j], 0, 0, 0);
                         }
                 }
-                fetch(v * KC + kc + P, rh[u], rl[u]);
+                fetch(fb + (size_t)u * fs, rh[u], rl[u]);
                 // keep the refill right behind the MFMAs that read the slot:
                 // left to itself the scheduler sinks these loads to the end of
                 // the unrolled steps, next to their first use, and the
@@ -245,49 +277,66 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+        cur = nxt;
+        scur = snext;
         // ---- epilogue of a finished segment
         if (hid) {
-            const float* vb = N.vec + (size_t)seg * 3 * H;
             __syncthreads();                               // every wave done reading this layer's input
 #pragma unroll
             for (int j = 0; j < CT; ++j) {
                 const int c = wave * WC + j * 32 + (lane & 31);
-                const float bb = vb[c], be = vb[H + c], ga = vb[2 * H + c];
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int row = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
-                        const float v = gated<float>(acc[i][j][r] + bb, be, ga);
+                        const float v = gated<float>(acc[i][j][r] + e0[j], e1[j], e2[j]);
                         const uint16_t hi = f2bf(v);
                         hs[row * HS + c] = hi;
                         if (X3) hl[row * HS + c] = bf16_lo(v, hi);
                     }
             }
             __syncthreads();                               // next layer's input complete
-        } else if (nb < N_out) {
-            const float* bo = N.vec + (size_t)n_hidden * 3 * H;
+        } else {
             const bool zdep = A.mu_rows > 1, is_log = N.is_log;
+            // every row of the block live and one mean row: row addresses are
+            // wave-uniform, the lane adds its column and its 4-row group
+            const bool plain = nvalid == R && !zdep;
+            const int64_t ldo = A.ldo;
 #pragma unroll
             for (int j = 0; j < CT; ++j) {
                 const int c = nb + j * 32 + (lane & 31);
                 if (c >= N_out) continue;
-                const float bb = bo[c], sg = N.sigma[c], mu0 = N.mu[c];
-                float* ob = N.out + r0 * A.ldo + c;
+                const float bb = e0[j], sg = e1[j], mu0 = e2[j];
+                if (plain) {
+                    const unsigned lofs = (unsigned)((lane >> 5) * 4 * ldo + c);
+                    float* ob = N.out + r0 * ldo;
 #pragma unroll
-                for (int i = 0; i < RT; ++i)
+                    for (int i = 0; i < RT; ++i)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        // row offsets come from LDS: kept in registers they would
-                        // hold 64-bit addresses live across the whole stage loop
-                        const int lr = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
-                        const int ro = rowo[lr];
-                        if (ro < 0) continue;
-                        const float m = zdep ? N.mu[zrow[lr] * N_out + c] : mu0;
-                        float y = m + sg * (acc[i][j][r] + bb);
-                        if (is_log) y = exp10_of<float>(y);
-                        ob[ro] = y;
-                    }
+                        for (int r = 0; r < 16; ++r) {
+                            float* rowp = ob + (int64_t)(i * 32 + (r >> 2) * 8 + (r & 3)) * ldo;
+                            float y = mu0 + sg * (acc[i][j][r] + bb);
+                            if (is_log) y = exp10_of<float>(y);
+                            rowp[lofs] = y;
+                        }
+                } else {
+                    float* ob = N.out + r0 * ldo + c;
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            // row offsets come from LDS: kept in registers they would
+                            // hold 64-bit addresses live across the whole stage loop
+                            const int lr = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
+                            const int ro = rowo[lr];
+                            if (ro < 0) continue;
+                            const float m = zdep ? N.mu[zrow[lr] * N_out + c] : mu0;
+                            float y = m + sg * (acc[i][j][r] + bb);
+                            if (is_log) y = exp10_of<float>(y);
+                            ob[ro] = y;
+                        }
+                }
             }
         }
         // drain this segment's loads here (vmcnt(0) only), so that the next
@@ -308,7 +357,7 @@ static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, i
                          int G, const int* count, hipStream_t s) {
     constexpr int R = 32 * RT;
     constexpr int NT = 64 * (H / (32 * CT));
-    const size_t smem = (size_t)(X3 ? 2 : 1) * R * (H + 8) * sizeof(uint16_t);
+    const size_t smem = (size_t)(X3 ? 2 : 1) * R * (H + 8) * sizeof(uint16_t) + FM_SLACK;
     const auto kern = mlp_fused_kernel<H, RT, X3, P, CT>;
     const int rtc = RT == 2 ? 0 : (RT == 1 ? 1 : 2);
     const int bit = (((rtc * 2 + (H == 512)) * 2 + X3) * 2 + (CT == 1)) * 4 + (P == 2 ? 0 : (P == 4 ? 1 : 2));
