@@ -99,12 +99,19 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_in = A.n_in, n_hidden = A.n_hidden, N_out = A.N_out;
     const int nvalid = (int)min<int64_t>(R, nrows - r0);   // live rows of this block
+    // output group q takes the column blocks [ob0, ob0 + nob); its segments
+    // are the hidden layers, then those blocks (v -> real segment seg_of(v))
+    const int ncb = (N_out + H - 1) / H;
+    const int per = (ncb + A.qg - 1) / A.qg, ob0 = q * per;
+    const int nob = min(ncb, ob0 + per) - ob0;
+    if (nob <= 0) return;
+    const int nseg = n_hidden + nob;
     if (tid < R) {
         zrow[tid] = A.mu_rows > 1 ? (int)((r0 + tid) % A.mu_rows) : 0;
         rowo[tid] = tid < nvalid ? tid * (int)A.ldo : -1;
     }
 
-    // ---- layer 1 into LDS (FP32 VALU, the arithmetic of the layer-by-layer path)
+    // ---- layer-1 inputs (normalised parameters) into LDS
     for (int e = tid; e < R * n_in; e += NT) {
         const int rr = e / n_in, k = e % n_in;
         const int64_t r = r0 + rr;
@@ -118,10 +125,11 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         }
         xs[rr][k] = v;
     }
-    __syncthreads();
-    {
-        // NT is a multiple of H: each thread keeps one unit c (weights in
-        // registers) for rows tid / H, tid / H + NT / H, ...
+
+    // ---- layer 1 (FP32 VALU, the arithmetic of the layer-by-layer path).  NT
+    // is a multiple of H: each thread keeps one unit c (weights in registers)
+    // for rows tid / H, tid / H + NT / H, ...
+    auto first_layer = [&]() {
         const int c = tid % H;
         float w1[16];
 #pragma unroll
@@ -137,22 +145,14 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
             hs[rr * HS + c] = hi;
             if (X3) hl[rr * HS + c] = bf16_lo(v, hi);
         }
-    }
-    __syncthreads();
+    };
 
     // ---- GEMM stages: hidden layers, then the output layer's H-wide column
     // blocks; stage s = (segment s / KC, K step s % KC).  Loads and MFMAs are
     // unconditional within the live segments (stages past the end re-read the
     // last one, the partly live last tile computes on valid addresses and
     // stores its live units only), so the weight prefetch stays in flight
-    // across iterations.
-    // output group q takes the column blocks [ob0, ob0 + nob); its segments
-    // are the hidden layers, then those blocks (v -> real segment seg_of(v))
-    const int ncb = (N_out + H - 1) / H;
-    const int per = (ncb + A.qg - 1) / A.qg, ob0 = q * per;
-    const int nob = min(ncb, ob0 + per) - ob0;
-    if (nob <= 0) return;
-    const int nseg = n_hidden + nob;
+    // across segments, epilogues and barriers.
     auto seg_of = [&](int v) { return v < n_hidden ? v : v + ob0; };
     // fragment block (kc, nt) of a layer with nt_l 32-unit tiles sits at
     // (kc nt_l + nt) 512 elements: one K step of a layer is contiguous.  The
@@ -180,54 +180,63 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         }
     };
     f32x16_t acc[RT][CT];
+    auto zero_acc = [&]() {
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < CT; ++j)
+            for (int j = 0; j < CT; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    int scur;
-    size_t cur = seg_frag(0, scur);
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    };
+    zero_acc();
+    // segment state of this wave: v, its fragments (cur, scur), the next
+    // segment's (nxt, snext) and the epilogue vectors of v
+    int v = 0, scur = 0, snext = 0;
+    size_t cur = seg_frag(0, scur), nxt = 0;
+    // the first stages' weights, requested behind layer 1 (in flight across
+    // it they would hold registers that layer 1 needs)
+    auto prefetch = [&]() {
 #pragma unroll
-    for (int u = 0; u < P; ++u) fetch(cur + (size_t)u * scur, rh[u], rl[u]);
-    // the compiler may issue these first loads in any order; waiting for them
-    // here keeps that order out of the K-step loop's load accounting
-    __builtin_amdgcn_s_waitcnt(0x0F70);
+        for (int u = 0; u < P; ++u) fetch(cur + (size_t)u * scur, rh[u], rl[u]);
+    };
 
     // A operands (activation fragments) of one K step, double-buffered: the
     // LDS reads of step kc + 1 are issued before the MFMAs of step kc.  The
-    // read-ahead past a layer's last step (kc = KC) lands in the next row's
-    // first elements or, for the last row, in the slack behind the planes; it
-    // is never used.
-    const int abase = (lane & 31) * HS + (lane >> 5) * 8;
+    // read-ahead past the end of a run of K steps is discarded (the next run
+    // reads its first step again); past a layer's last step it lands in the
+    // next row's first elements or, for the last row, in the slack behind the
+    // planes.
+    // Element offsets of this lane's A rows, one per row tile and plane.  The
+    // empty asm makes them opaque: folded into each read, the lo plane's
+    // offset (beyond the 64 KiB immediate range of an LDS read) would need a
+    // register per K step, which the compiler precomputes and spills.
+    int aoff[RT][2];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        aoff[i][0] = i * 32 * HS + (lane & 31) * HS + (lane >> 5) * 8;
+        aoff[i][1] = aoff[i][0] + R * HS;
+        asm volatile("" : "+v"(aoff[i][0]), "+v"(aoff[i][1]));
+    }
     bf16x8_t ah[2][RT], al[2][RT];
     auto read_a = [&](int kc, bf16x8_t (&xh)[RT], bf16x8_t (&xl)[RT]) {
-        const int koff = abase + kc * 16;
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
-            xh[i] = *reinterpret_cast<const bf16x8_t*>(&hs[i * 32 * HS + koff]);
-            if (X3) xl[i] = *reinterpret_cast<const bf16x8_t*>(&hl[i * 32 * HS + koff]);
+            xh[i] = *reinterpret_cast<const bf16x8_t*>(&fm_lds[aoff[i][0] + kc * 16]);
+            if (X3) xl[i] = *reinterpret_cast<const bf16x8_t*>(&fm_lds[aoff[i][1] + kc * 16]);
         }
     };
-
-    // one segment (layer or output column block) per iteration; the K steps
-    // run in their own loop, so no epilogue path joins the steady state
-    for (int v = 0; v < nseg; ++v) {
+    float e0[CT], e1[CT], e2[CT];
+    // start of segment v: the next segment's fragments (the stage P steps past
+    // the last K step is in the next segment, or, after the last segment, the
+    // last stage again) and the epilogue vectors, loaded while the K steps run
+    auto seg_begin = [&]() {
+        snext = 0;
+        nxt = v + 1 < nseg ? seg_frag(v + 1, snext) : cur + (size_t)(KC - 1) * scur;
         const int seg = seg_of(v);
         const bool hid = seg < n_hidden;
         const int nb = (hid ? 0 : (seg - n_hidden) * H) + wave * WC;
-        // a wave whose units of this output block all lie past N_out has none
-        // in the later blocks either, and no barrier follows the hidden
-        // layers: it stops here and leaves the matrix pipe to the live waves
-        if (!hid && nb >= N_out) break;
-        // the stage P steps past the last K step is in the next segment, or,
-        // after the last segment, the last stage again
-        int snext = 0;
-        const size_t nxt = v + 1 < nseg ? seg_frag(v + 1, snext) : cur + (size_t)(KC - 1) * scur;
-        // epilogue vectors of this segment, loaded while its K steps run
         const float* vb = N.vec + (size_t)seg * 3 * H;             // hidden: b, beta, gamma
         const float* bo = N.vec + (size_t)n_hidden * 3 * H;        // output: bias
-        float e0[CT], e1[CT], e2[CT];
 #pragma unroll
         for (int j = 0; j < CT; ++j) {
             const int c = nb + j * 32 + (lane & 31);
@@ -238,8 +247,11 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                 e0[j] = bo[cc]; e1[j] = N.sigma[cc]; e2[j] = N.mu[cc];
             }
         }
-        read_a(0, ah[0], al[0]);
-        for (int kc0 = 0; kc0 < KC; kc0 += P) {
+    };
+    // K steps [k0, k1) of segment v
+    auto ksteps = [&](int k0, int k1) {
+        read_a(k0, ah[0], al[0]);
+        for (int kc0 = k0; kc0 < k1; kc0 += P) {
             const bool last = kc0 + P >= KC;
             const size_t fb = last ? nxt : cur + (size_t)(kc0 + P) * scur;
             const int fs = last ? snext : scur;
@@ -250,7 +262,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                 const int kc = kc0 + u;
                 const bf16x8_t (&bh)[CT] = rh[u];
                 const bf16x8_t (&bl)[CT] = rl[u];
-                // P is even, so kc and u have the same parity
+                // k0 and P are even, so kc and u have the same parity
                 read_a(kc + 1, ah[(u + 1) & 1], al[(u + 1) & 1]);
                 __builtin_amdgcn_sched_barrier(0);
                 const bf16x8_t (&xh)[RT] = ah[u & 1];
@@ -277,78 +289,103 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+    };
+    auto seg_end = [&]() {
         cur = nxt;
         scur = snext;
-        // ---- epilogue of a finished segment
-        if (hid) {
-            __syncthreads();                               // every wave done reading this layer's input
+        ++v;
+        zero_acc();
+    };
+    // epilogue of hidden segment v: gated activation of this wave's units, the
+    // BF16 (hi, lo) split into LDS
+    auto hidden_epi = [&]() {
 #pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                const int c = wave * WC + j * 32 + (lane & 31);
+        for (int j = 0; j < CT; ++j) {
+            const int c = wave * WC + j * 32 + (lane & 31);
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
+                    const float v = gated<float>(acc[i][j][r] + e0[j], e1[j], e2[j]);
+                    const uint16_t hi = f2bf(v);
+                    hs[row * HS + c] = hi;
+                    if (X3) hl[row * HS + c] = bf16_lo(v, hi);
+                }
+        }
+    };
+    // epilogue of output segment v (units nb + ...): mean + sigma y, 10^ for
+    // log-emulated outputs, stored to the live rows
+    auto output_epi = [&](int nb) {
+        const bool zdep = A.mu_rows > 1, is_log = N.is_log;
+        // every row of the block live and one mean row: row addresses are
+        // wave-uniform, the lane adds its column and its 4-row group
+        const bool plain = nvalid == R && !zdep;
+        const int64_t ldo = A.ldo;
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            const int c = nb + j * 32 + (lane & 31);
+            if (c >= N_out) continue;
+            const float bb = e0[j], sg = e1[j], mu0 = e2[j];
+            if (plain) {
+                const unsigned lofs = (unsigned)((lane >> 5) * 4 * ldo + c);
+                float* ob = N.out + r0 * ldo;
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const int row = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
-                        const float v = gated<float>(acc[i][j][r] + e0[j], e1[j], e2[j]);
-                        const uint16_t hi = f2bf(v);
-                        hs[row * HS + c] = hi;
-                        if (X3) hl[row * HS + c] = bf16_lo(v, hi);
+                        float* rowp = ob + (int64_t)(i * 32 + (r >> 2) * 8 + (r & 3)) * ldo;
+                        float y = mu0 + sg * (acc[i][j][r] + bb);
+                        if (is_log) y = exp10_of<float>(y);
+                        rowp[lofs] = y;
+                    }
+            } else {
+                float* ob = N.out + r0 * ldo + c;
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        // row offsets come from LDS: kept in registers they would
+                        // hold 64-bit addresses live across the whole stage loop
+                        const int lr = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
+                        const int ro = rowo[lr];
+                        if (ro < 0) continue;
+                        const float m = zdep ? N.mu[zrow[lr] * N_out + c] : mu0;
+                        float y = m + sg * (acc[i][j][r] + bb);
+                        if (is_log) y = exp10_of<float>(y);
+                        ob[ro] = y;
                     }
             }
-            __syncthreads();                               // next layer's input complete
-        } else {
-            const bool zdep = A.mu_rows > 1, is_log = N.is_log;
-            // every row of the block live and one mean row: row addresses are
-            // wave-uniform, the lane adds its column and its 4-row group
-            const bool plain = nvalid == R && !zdep;
-            const int64_t ldo = A.ldo;
-#pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                const int c = nb + j * 32 + (lane & 31);
-                if (c >= N_out) continue;
-                const float bb = e0[j], sg = e1[j], mu0 = e2[j];
-                if (plain) {
-                    const unsigned lofs = (unsigned)((lane >> 5) * 4 * ldo + c);
-                    float* ob = N.out + r0 * ldo;
-#pragma unroll
-                    for (int i = 0; i < RT; ++i)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            float* rowp = ob + (int64_t)(i * 32 + (r >> 2) * 8 + (r & 3)) * ldo;
-                            float y = mu0 + sg * (acc[i][j][r] + bb);
-                            if (is_log) y = exp10_of<float>(y);
-                            rowp[lofs] = y;
-                        }
-                } else {
-                    float* ob = N.out + r0 * ldo + c;
-#pragma unroll
-                    for (int i = 0; i < RT; ++i)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            // row offsets come from LDS: kept in registers they would
-                            // hold 64-bit addresses live across the whole stage loop
-                            const int lr = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
-                            const int ro = rowo[lr];
-                            if (ro < 0) continue;
-                            const float m = zdep ? N.mu[zrow[lr] * N_out + c] : mu0;
-                            float y = m + sg * (acc[i][j][r] + bb);
-                            if (is_log) y = exp10_of<float>(y);
-                            ob[ro] = y;
-                        }
-                }
-            }
         }
-        // drain this segment's loads here (vmcnt(0) only), so that the next
-        // K-step loop starts with nothing but the weight prefetch in flight and
+        // drain this segment's stores here (vmcnt(0) only), so that the next
+        // K-step run starts with nothing but the weight prefetch in flight and
         // its waits can count just those loads
         __builtin_amdgcn_s_waitcnt(0x0F70);
-#pragma unroll
-        for (int i = 0; i < RT; ++i)
-#pragma unroll
-            for (int j = 0; j < CT; ++j)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    };
+    // output unit base of segment v for this wave; a wave whose units of an
+    // output block all lie past N_out has none in the later blocks either
+    auto out_nb = [&]() { return (seg_of(v) - n_hidden) * H + wave * WC; };
+
+    __syncthreads();
+    first_layer();
+    prefetch();
+    __syncthreads();
+    for (; v < n_hidden; ) {
+        seg_begin();
+        ksteps(0, KC);
+        __syncthreads();                                   // every wave done reading this layer's input
+        hidden_epi();
+        __syncthreads();                                   // next layer's input complete
+        seg_end();
+    }
+    // output column blocks: no barriers, the waves run free
+    for (; v < nseg; ) {
+        const int nb = out_nb();
+        if (nb >= N_out) break;
+        seg_begin();
+        ksteps(0, KC);
+        output_epi(nb);
+        seg_end();
     }
 }
 
