@@ -341,13 +341,18 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
                     }
             } else {
                 float* ob = N.out + r0 * ldo + c;
+                // row offsets come from LDS: kept in registers they would hold
+                // 64-bit addresses live across the whole stage loop.  The lane's
+                // first row is opaque to the compiler, so that the reads use one
+                // base register and immediate offsets instead of an address per
+                // row that it would precompute and spill.
+                int lr0 = (lane >> 5) * 4;
+                asm volatile("" : "+v"(lr0));
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        // row offsets come from LDS: kept in registers they would
-                        // hold 64-bit addresses live across the whole stage loop
-                        const int lr = i * 32 + (lane >> 5) * 4 + (r >> 2) * 8 + (r & 3);
+                        const int lr = lr0 + i * 32 + (r >> 2) * 8 + (r & 3);
                         const int ro = rowo[lr];
                         if (ro < 0) continue;
                         const float m = zdep ? N.mu[zrow[lr] * N_out + c] : mu0;
