@@ -367,15 +367,19 @@ ns_status ns_trace_enable(ns_model* model, int32_t enable);
  * NUL-terminated; NS_E_SHAPE if it does not fit).  Clears the records. */
 ns_status ns_trace_report(ns_model* model, char* buf, int64_t buf_len);
 
-/* Launch shapes the library's autotuner has chosen for this model so far:
- * BF16 GEMM tiles of the layer-by-layer path and launch shapes of the
- * one-kernel BF16 / BF16X3 emulator forward, as JSON
- * {"<kind> M=.. N=.. K=.. networks=..": "<shape>"} (host buf, NUL-terminated;
- * NS_E_SHAPE if it does not fit).  Every candidate accumulates in the same
- * order, so the choice never changes a result.  Environment: NSMI_NO_AUTOTUNE
- * keeps the first candidate; NSMI_FUSED_CFG=c pins candidate c (0-7 for
- * BF16, 0-5 for BF16X3) of the one-kernel forward; NSMI_NO_FUSED_MLP selects
- * the layer-by-layer forward. */
+/* Launch shapes the library's autotuner has chosen for this model so far
+ * (measured or read from the on-disk cache): BF16 GEMM tiles of the
+ * layer-by-layer path and launch shapes of the one-kernel BF16 / BF16X3
+ * emulator forward, as JSON {"<kind> M=.. N=.. K=.. networks=..": "<shape>"}
+ * (host buf, NUL-terminated; NS_E_SHAPE if it does not fit).  Every
+ * candidate accumulates in the same order, so the choice never changes a
+ * result.  Environment: NSMI_NO_AUTOTUNE keeps the first candidate;
+ * NSMI_FUSED_CFG=c pins candidate c (0-9 at hidden width 128 and for BF16 at
+ * 512, 0-7 for BF16X3 at 512) of the one-kernel forward; NSMI_NO_FUSED_MLP
+ * selects the layer-by-layer forward; NSMI_TUNE_CACHE names the on-disk
+ * cache of choices ("off": none; default $XDG_CACHE_HOME/nsmi/tune.txt or
+ * $HOME/.cache/nsmi/tune.txt), read by ns_model_create for the device's GPU
+ * architecture and appended to on every new choice. */
 ns_status ns_tuning_report(ns_model* model, char* buf, int64_t buf_len);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libnsmi.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "emulator.hip", "mlp_fused.hip", "mlp_f64.hip", "likelihood.hip", "shear.hip", "shear_adjoint.hip", "sampler.hip", "adjoint.hip", "hmc.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "emulator.hip", "mlp_fused.hip", "mlp_f64.hip", "likelihood.hip", "shear.hip", "shear_adjoint.hip", "sampler.hip", "adjoint.hip", "hmc.hip", "noalloc.hip", "tune_cache.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

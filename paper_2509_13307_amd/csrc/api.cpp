@@ -568,6 +568,7 @@ ns_status ns_model_create(const ns_model_desc* desc, int32_t device, ns_model** 
         ns_model* m = new ns_model();
         m->device = device;
         try {
+            tune_cache_load(m);                 // launch shapes measured before on this GPU architecture
             build_model(m, desc);
         } catch (...) {
             delete m;

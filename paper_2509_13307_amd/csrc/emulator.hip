@@ -567,10 +567,15 @@ static void launch_bf16_tuned(ns_model* m, int kind, const Group<Epi>& P, int64_
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            m->tune[key] = best;
+            tune_cache_store(m, key, best);
         }
     }
     bf16_candidate<Epi>(best)(P, M, N, K, G, count, rpw, s);
+}
+
+int tune_ncfg(int kind) { return kind < 2 ? BF16_NCFG : fused_ncfg_of(kind >= 4, kind & 1); }
+const char* tune_cfg_name(int kind, int c) {
+    return kind < 2 ? BF16_CFG_NAMES[c] : fused_cfg_name(kind >= 4, kind & 1, c);
 }
 
 std::string bf16_tuning_report(const ns_model* m) {

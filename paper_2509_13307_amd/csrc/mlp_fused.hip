@@ -472,6 +472,7 @@ static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
 };
 
 const char* fused_cfg_name(int h512, int x3, int c) { return FUSED_CFGS[h512][x3][c].name; }
+int fused_ncfg_of(int h512, int x3) { return fused_ncfg(h512, x3); }
 
 // Returns false (and launches nothing) when the networks have no fragment-
 // ordered weights (shape outside fused_shape) or the form is not BF16-operand.
@@ -567,7 +568,7 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
                 if (tot_ms[c] < tot_ms[best]) best = c;
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            m->tune[key] = best;
+            tune_cache_store(m, key, best);
         }
     }
     TraceScope ts(m, s, x3 ? "mlp_fused_bf16x3" : "mlp_fused_bf16");

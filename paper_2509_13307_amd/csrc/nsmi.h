@@ -183,7 +183,10 @@ struct ns_model {
     bool shear_attr_set = false;     // hipFuncSetAttribute done for the Limber kernels
     std::bitset<96> fused_attr_set;  // ... and per instance of the one-kernel emulator
     // BF16 tile / fused launch-shape choice per (kind, M, N, K, networks), measured at first use
+    // or read from the on-disk cache (tune_path, entries of this GPU architecture only)
     std::map<std::tuple<int, int64_t, int, int, int>, int> tune;
+    std::string arch;                // gcnArchName of the model's device
+    std::string tune_path;           // on-disk tuning cache ("" when off)
 
     // per-kernel tracing: HIP events bracketing each launch on its stream
     bool trace = false;
@@ -304,11 +307,22 @@ bool narrow_f64_shape(const std::vector<int>& dims);
 bool emulator_forward_f64_narrow(ns_model* m, const double* theta, int64_t ld, int64_t B, double* out,
                                  int64_t ldo, int is_log, double* logl, const int* count, hipStream_t s);
 
-// Name of candidate c of the one-kernel forward (width 512 or 128, split form or not).
+// Name of candidate c of the one-kernel forward (width 512 or 128, split form
+// or not), and the number of candidates.
 const char* fused_cfg_name(int h512, int x3, int c);
+int fused_ncfg_of(int h512, int x3);
 
 // JSON of the BF16 tile configurations the autotuner chose so far.
 std::string bf16_tuning_report(const ns_model* m);
+
+// Autotuner tables: candidates of tuning kind `kind` (0 BF16 hidden GEMM,
+// 1 BF16 output GEMM, 2 + split + 2 wide: one-kernel emulator) and their names.
+int tune_ncfg(int kind);
+const char* tune_cfg_name(int kind, int c);
+// On-disk tuning cache: load the entries of the model's GPU architecture into
+// m->tune (at creation), record a new choice in m->tune and the file.
+void tune_cache_load(ns_model* m);
+void tune_cache_store(ns_model* m, const std::tuple<int, int64_t, int, int, int>& key, int cfg);
 
 // Slice steps for k walkers with the threshold in device memory (lstar_dev)
 // or given on the host; synchronises s.

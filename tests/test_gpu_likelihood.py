@@ -211,6 +211,46 @@ def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
         np.testing.assert_array_equal(got, ref)
 
 
+def test_tuning_cache_round_trip(built, tmp_path, monkeypatch):
+    """The autotuner's choices go to the on-disk cache; a new model on the same
+    GPU architecture starts with them (no timing runs, same results), and
+    entries of another architecture, another candidate table, an out-of-range
+    candidate or a malformed line are ignored."""
+    say("case tuning cache")
+    from paper_2509_13307_amd import Model
+    path = tmp_path / "tune.txt"
+    for k in ("NSMI_NO_FUSED_MLP", "NSMI_FUSED_CFG", "NSMI_NO_AUTOTUNE"):
+        monkeypatch.delenv(k, raising=False)
+    monkeypatch.setenv("NSMI_TUNE_CACHE", str(path))
+    m = W.load_model("cmb6")
+    th = torch.tensor(W.prior_draws(m, 300, tag=5), device=DEV)
+    g = Model(m)
+    assert g.tuning_report() == {}
+    ref = g.loglike(th, "bf16x3").cpu().numpy()
+    rep = g.tuning_report()
+    g.close()
+    lines = path.read_text().splitlines()
+    assert len(rep) >= 1 and len(lines) == len(rep)
+    f = lines[0].split()
+    assert len(f) == 8
+    bogus = [" ".join(["gfx000:other"] + f[1:3] + ["999"] + f[4:]),          # another architecture
+             " ".join(f[:1] + ["0"] + f[2:3] + ["998"] + f[4:]),            # another candidate table
+             " ".join(f[:3] + ["997"] + f[4:7] + ["99"]),                   # candidate out of range
+             "not a cache line"]
+    with open(path, "a") as fh:
+        fh.write("\n".join(bogus) + "\n")
+    g2 = Model(m)
+    assert g2.tuning_report() == rep                    # loaded at creation, before any launch
+    got = g2.loglike(th, "bf16x3").cpu().numpy()
+    g2.close()
+    np.testing.assert_array_equal(got, ref)
+    assert len(path.read_text().splitlines()) == len(lines) + len(bogus)   # nothing tuned again
+    monkeypatch.setenv("NSMI_TUNE_CACHE", "off")
+    g3 = Model(m)
+    assert g3.tuning_report() == {}
+    g3.close()
+
+
 @pytest.mark.parametrize("n_z", [4, 5, 7])
 def test_fp64_shear_few_redshift_nodes(built, n_z):
     """Shear likelihood with the smallest redshift-node tables the spline
