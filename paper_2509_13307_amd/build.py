@@ -23,10 +23,23 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-u
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
 
+def _source_id():
+    """Hash of every source and header of the library: keys the on-disk
+    autotuning cache to this build's kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, os.path.join(os.path.dirname(HERE), "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".cpp", ".h")):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src):
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, src + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", path, "-o", obj]
+    cmd = [HIPCC, *FLAGS, f"-DNSMI_SRC_ID=\"{_source_id()}\"", "-x", "hip", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

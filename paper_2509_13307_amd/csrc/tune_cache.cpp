@@ -4,10 +4,11 @@
 //
 // One line per choice: `<arch> <table signature> <kind> <M> <N> <K> <networks>
 // <candidate>`.  The architecture is the device's gcnArchName; the table
-// signature is a 64-bit FNV-1a hash of the names of the candidates of that
-// kind, so that entries written by a build with another candidate list are
-// ignored rather than read as the wrong shape.  Choices never change a
-// result (every candidate gives identical outputs), only the speed.
+// signature is a 64-bit FNV-1a hash of the build's source hash (NSMI_SRC_ID,
+// set by the build script) and the names of the candidates of that kind, so
+// that entries written by another build (other kernels, another candidate
+// list) are ignored rather than read as timings of this one.  Choices never
+// change a result (every candidate gives identical outputs), only the speed.
 //
 // The file is NSMI_TUNE_CACHE if that is set (empty or "off": no cache),
 // else $XDG_CACHE_HOME/nsmi/tune.txt, else $HOME/.cache/nsmi/tune.txt.  It is
@@ -32,8 +33,12 @@ static uint64_t fnv1a(const char* s, uint64_t h) {
     return h;
 }
 
-uint64_t tune_table_sig(int kind) {
-    uint64_t h = 1469598103934665603ull;
+#ifndef NSMI_SRC_ID
+#define NSMI_SRC_ID "unversioned"
+#endif
+
+static uint64_t tune_table_sig(int kind) {
+    uint64_t h = fnv1a(NSMI_SRC_ID, 1469598103934665603ull);
     const int n = tune_ncfg(kind);
     for (int c = 0; c < n; ++c) h = fnv1a(tune_cfg_name(kind, c), fnv1a("|", h));
     return h;
