@@ -150,6 +150,8 @@ struct ns_model {
     nsmi::DevBuf agrid_d;            // a_j [n_a]
     nsmi::DevBuf lna_d;              // ln a_j [n_a], then ln of the interval midpoints [n_a - 1]
     nsmi::DevBuf zsp_idx_d;          // int [n_a]: spline interval of z_j
+    nsmi::DevBuf lslab_d;            // int4 [n_lslab]: Limber-adjoint scatter slabs (first node, end node, first row, last row)
+    int n_lslab = 0, lslab_rows = 0; // slab count, z rows held in LDS per slab
     nsmi::DevBuf zsp_coef_d;         // double [n_a x 4]: (1-t, t, h^2/6((1-t)^3-(1-t)), h^2/6(t^3-t));
                                      // linear z: (1-t, t, 0, 0)
     nsmi::DevBuf ws_win;             // shear windows [B][nb][n_a] (form type), log10 chi, n(z) normalisations

@@ -19,10 +19,13 @@
 //
 // The scatter into g Y (and g M) is accumulated in 64-bit fixed point, so that
 // its result does not depend on the order in which the nodes of a walker
-// reach a table entry: the kernel first computes and stores every
-// g log10 P_bj of the walker and their largest magnitude G, then adds each
-// contribution c w g log10 P (|c w| < 2: spline and Catmull-Rom weights)
-// rounded to the grid 2^(e - FX_BITS), G < 2^e, with integer atomics.  At most
+// reach a table entry: limber_adjoint_kernel computes and stores every
+// g log10 P_bj of the walker and their largest magnitude G; then
+// limber_scatter_kernel adds each contribution c w g log10 P (|c w| < 2:
+// spline and Catmull-Rom weights) rounded to the grid 2^(e - FX_BITS),
+// G < 2^e, as integers: slab by slab (runs of nodes whose z rows fit in LDS)
+// with LDS atomics, each slab's rows then stored to (or, for the row it
+// shares with the slab before, added to) the walker's table.  At most
 // n_a n_ell <= 2^16 contributions reach one entry, so every partial sum stays
 // below 2^(FX_BITS + 17) < 2^63; the grid step is below G 2^-44 (about
 // 6e-14 G), well under the FP64 gradient's error against the complex step.
@@ -293,8 +296,8 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
     const int* __restrict__ pidx, const double* __restrict__ pfix, const int* __restrict__ zidx,
     const double* __restrict__ zcoef, const double* __restrict__ ell, const T* __restrict__ Ytab,
     const T* __restrict__ Mtab, const double* __restrict__ Cv, const double* __restrict__ gC,
-    const double* __restrict__ tg, double* __restrict__ glp_buf, unsigned long long* __restrict__ gYi,
-    unsigned long long* __restrict__ gMi, double* __restrict__ gstep, int mshift, double* __restrict__ gdir) {
+    const double* __restrict__ tg, double* __restrict__ glp_buf, double* __restrict__ gstep,
+    double* __restrict__ gdir) {
     __shared__ double Hs[55 * 32];          // G_pb f_p, pair-major
     __shared__ double red[4 + 2 * MAXB][4];
     __shared__ double gmx[4];
@@ -322,8 +325,6 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
     for (int q = 0; q < 4 + 2 * MAXB; ++q) acc[q] = 0.0;
     const T* Yw = Ytab + w * (int64_t)G.n_z * G.n_k;
     const T* Mw = LINZ ? Yw : Mtab + w * (int64_t)G.n_z * G.n_k;
-    unsigned long long* gYw = gYi + w * (int64_t)G.n_z * G.n_k;
-    unsigned long long* gMw = LINZ ? gYw : gMi + w * (int64_t)G.n_z * G.n_k;
     double* glw = glp_buf + w * (int64_t)ne * na;
     double gmax = 0.0;
     for (int c = 0; c < nch; ++c) {
@@ -466,47 +467,102 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
     const bool ok = !isnan(gmx[0] + gmx[1] + gmx[2] + gmx[3]) && gm_all <= 1.7e308;
     int e = 0;
     if (ok && gm_all > 0.0) (void)frexp(gm_all, &e);                  // gm_all < 2^e
-    const double scale = ldexp(1.0, FX_BITS - e), mscale = ldexp(1.0, FX_BITS + mshift - e);
     if (t == 0) gstep[w] = ok ? ldexp(1.0, e - FX_BITS) : NAN;
-    if (!ok || gm_all == 0.0) return;
+}
+
+// Fixed-point scatter of g log10 P_bj (limber_adjoint_kernel's glp_buf and
+// grid step gstep) into gYi (and gMi for the cubic z-spline), one workgroup
+// per walker.  Slab s = (first node, end node, first row, last row) of
+// `slabs`: the contributions of its nodes go to LDS tables of its rows
+// (integer atomics), which are then written to the walker's tables; a row the
+// slab shares with earlier slabs is added to, rows no slab reaches are set to
+// zero.  Every entry of the walker's tables is written, so they need no
+// clearing before.  A walker whose grid step is NaN (a non-finite gradient)
+// gets zero tables.
+template <bool LINZ>
+__global__ __launch_bounds__(256) void limber_scatter_kernel(
+    int64_t B, ShearGeom G, const int* __restrict__ zidx, const double* __restrict__ zcoef,
+    const double* __restrict__ ell, const double* __restrict__ tg, const double* __restrict__ glp_buf,
+    const int4* __restrict__ slabs, int n_slabs, int rmax, const double* __restrict__ gstep, int mshift,
+    unsigned long long* __restrict__ gYi, unsigned long long* __restrict__ gMi) {
+    extern __shared__ unsigned long long sl[];          // [tables][rmax][n_k]
+    const int64_t w = blockIdx.x;
+    if (w >= B) return;
+    const int t = threadIdx.x;
+    const int na = G.n_a, ne = G.n_ell, nk = G.n_k, nz = G.n_z;
+    const int S = TG_FIXED + 7 * G.n_bins;
+    const double step = gstep[w];
+    const bool ok = !isnan(step);
+    const double scale = 1.0 / step, mscale = ldexp(scale, mshift);     // powers of two: exact
+    const int tab = rmax * nk;
+    unsigned long long* gYw = gYi + w * (int64_t)nz * nk;
+    unsigned long long* gMw = LINZ ? gYw : gMi + w * (int64_t)nz * nk;
+    const double* glw = glp_buf + w * (int64_t)ne * na;
+    const double* chiw = tg + ((int64_t)w * S + TG_CHI) * na;
+    auto zero_rows = [&](int r0, int r1) {
+        for (int64_t e = (int64_t)r0 * nk + t; e < (int64_t)r1 * nk; e += 256) {
+            gYw[e] = 0ull;
+            if (!LINZ) gMw[e] = 0ull;
+        }
+    };
     auto fx_add = [&](unsigned long long* p, double v, double sc) {
         if (v != 0.0) atomicAdd(p, (unsigned long long)llrint(v * sc));
     };
-    for (int c = 0; c < nch; ++c) {
-        const int j = c * 256 + t;
-        if (j <= 0 || j >= na) continue;
-        const double chi = rec(TG_CHI, j);
-        const int nn = zidx[j];
-        const double c0 = zcoef[4 * j], c1 = zcoef[4 * j + 1];
-        const double c2 = LINZ ? 0.0 : zcoef[4 * j + 2], c3 = LINZ ? 0.0 : zcoef[4 * j + 3];
-        for (int b = 0; b < ne; ++b) {
-            const double k = (ell[b] + 0.5) / chi;
-            if (!(k >= G.k_min && k <= G.k_max)) continue;
-            const double glp = glw[(int64_t)b * na + j];
-            if (glp == 0.0) continue;
-            const KPos kp = k_position(k, G);
-            const double tt = kp.tt, t2 = tt * tt, t3 = t2 * tt;
-            const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + tt, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
-            // d lp / d (pm, p0, p1, p2), ghosts folded into the real columns
-            double wm = -0.5 * h10, w0c = h00 - 0.5 * h11, w1c = h01 + 0.5 * h10, w2 = 0.5 * h11;
-            if (kp.lo_ghost) { w0c += 2.0 * wm; w1c -= wm; wm = 0.0; }
-            if (kp.hi_ghost) { w1c += 2.0 * w2; w0c -= w2; w2 = 0.0; }
-            auto scatter = [&](int col, double wgt) {
-                const double gy = glp * wgt;
-                const int64_t o0 = (int64_t)nn * G.n_k + col, o1 = o0 + G.n_k;
-                fx_add(&gYw[o0], c0 * gy, scale);
-                fx_add(&gYw[o1], c1 * gy, scale);
-                if (!LINZ) {
-                    fx_add(&gMw[o0], c2 * gy, mscale);
-                    fx_add(&gMw[o1], c3 * gy, mscale);
-                }
-            };
-            if (!kp.lo_ghost) scatter(kp.i0 - 1, wm);
-            scatter(kp.i0, w0c);
-            scatter(kp.i0 + 1, w1c);
-            if (!kp.hi_ghost) scatter(kp.i0 + 2, w2);
+    int rnext = 0;                                      // rows below are written
+    for (int s = 0; s < n_slabs; ++s) {
+        const int4 sb = slabs[s];
+        const int lo = sb.z, nr = sb.w - sb.z + 1, nj = sb.y - sb.x;
+        for (int e = t; e < nr * nk; e += 256) {
+            sl[e] = 0ull;
+            if (!LINZ) sl[tab + e] = 0ull;
         }
+        __syncthreads();
+        if (ok)
+            for (int it = t; it < nj * ne; it += 256) {
+                const int j = sb.x + it % nj, b = it / nj;
+                const double chi = chiw[j];
+                const double k = (ell[b] + 0.5) / chi;
+                if (!(k >= G.k_min && k <= G.k_max)) continue;
+                const double glp = glw[(int64_t)b * na + j];
+                if (glp == 0.0) continue;
+                const int nn = zidx[j] - lo;
+                const double c0 = zcoef[4 * j], c1 = zcoef[4 * j + 1];
+                const double c2 = LINZ ? 0.0 : zcoef[4 * j + 2], c3 = LINZ ? 0.0 : zcoef[4 * j + 3];
+                const KPos kp = k_position(k, G);
+                const double tt = kp.tt, t2 = tt * tt, t3 = t2 * tt;
+                const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + tt, h01 = -2 * t3 + 3 * t2,
+                             h11 = t3 - t2;
+                // d lp / d (pm, p0, p1, p2), ghosts folded into the real columns
+                double wm = -0.5 * h10, w0c = h00 - 0.5 * h11, w1c = h01 + 0.5 * h10, w2 = 0.5 * h11;
+                if (kp.lo_ghost) { w0c += 2.0 * wm; w1c -= wm; wm = 0.0; }
+                if (kp.hi_ghost) { w1c += 2.0 * w2; w0c -= w2; w2 = 0.0; }
+                auto scatter = [&](int col, double wgt) {
+                    const double gy = glp * wgt;
+                    const int o0 = nn * nk + col, o1 = o0 + nk;
+                    fx_add(&sl[o0], c0 * gy, scale);
+                    fx_add(&sl[o1], c1 * gy, scale);
+                    if (!LINZ) {
+                        fx_add(&sl[tab + o0], c2 * gy, mscale);
+                        fx_add(&sl[tab + o1], c3 * gy, mscale);
+                    }
+                };
+                if (!kp.lo_ghost) scatter(kp.i0 - 1, wm);
+                scatter(kp.i0, w0c);
+                scatter(kp.i0 + 1, w1c);
+                if (!kp.hi_ghost) scatter(kp.i0 + 2, w2);
+            }
+        __syncthreads();
+        if (rnext < lo) zero_rows(rnext, lo);
+        const int64_t g0 = (int64_t)lo * nk;
+        for (int e = t; e < nr * nk; e += 256) {
+            const bool seen = lo + e / nk < rnext;
+            gYw[g0 + e] = (seen ? gYw[g0 + e] : 0ull) + sl[e];
+            if (!LINZ) gMw[g0 + e] = (seen ? gMw[g0 + e] : 0ull) + sl[tab + e];
+        }
+        rnext = max(rnext, sb.w + 1);
+        __syncthreads();                                // LDS reused by the next slab
     }
+    zero_rows(rnext, nz);
 }
 
 // ------------------------------------------------------------ spline adjoint
@@ -593,11 +649,6 @@ __global__ __launch_bounds__(256) void zspline_adjoint_kernel(double* __restrict
     for (int n = 0; n < nz; ++n) delta[(w * nz + n) * n_pad + c] = (T)(Y(n) * sg);
 }
 
-__global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
-}
-
 // ------------------------------------------------------------------ driver
 void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, double* grad, int prec,
                 hipStream_t s) {
@@ -647,13 +698,10 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
     }
     {
         TraceScope ts(m, s, "adj_limber");
-        hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, gY, (int64_t)((lin ? 1 : 2) * ntab));
         auto launch = [&](auto kern, const auto* Y) {
             hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, d, G, m->pidx_d.as<int>(),
                                m->pfix_d.as<double>(), m->zsp_idx_d.as<int>(), m->zsp_coef_d.as<double>(),
-                               m->ell_d.as<double>(), Y, (decltype(Y))Mtab, Cv, gC, tg, glp,
-                               reinterpret_cast<unsigned long long*>(gY), reinterpret_cast<unsigned long long*>(gM),
-                               gstep, mshift, gdir);
+                               m->ell_d.as<double>(), Y, (decltype(Y))Mtab, Cv, gC, tg, glp, gstep, gdir);
         };
         if (f64) {
             if (lin) launch(limber_adjoint_kernel<double, true>, m->ws_out.as<double>());
@@ -662,6 +710,18 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
             if (lin) launch(limber_adjoint_kernel<float, true>, m->ws_out.as<float>());
             else launch(limber_adjoint_kernel<float, false>, m->ws_out.as<float>());
         }
+        NS_HIP(hipGetLastError());
+    }
+    {
+        TraceScope ts(m, s, "adj_limber_scatter");
+        const size_t smem = (size_t)(lin ? 1 : 2) * m->lslab_rows * nk * sizeof(unsigned long long);
+        const auto kern = lin ? limber_scatter_kernel<true> : limber_scatter_kernel<false>;
+        if (smem > 64 * 1024)
+            NS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), smem, s, B, G, m->zsp_idx_d.as<int>(),
+                           m->zsp_coef_d.as<double>(), m->ell_d.as<double>(), tg, glp, m->lslab_d.as<int4>(),
+                           m->n_lslab, m->lslab_rows, gstep, mshift, reinterpret_cast<unsigned long long*>(gY),
+                           reinterpret_cast<unsigned long long*>(gM));
         NS_HIP(hipGetLastError());
     }
     // spline adjoint -> delta for the emulator's raw outputs
