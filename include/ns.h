@@ -376,7 +376,10 @@ ns_status ns_trace_report(ns_model* model, char* buf, int64_t buf_len);
  * result.  Environment: NSMI_NO_AUTOTUNE keeps the first candidate;
  * NSMI_FUSED_CFG=c pins candidate c (0-9 at hidden width 128 and for BF16 at
  * 512, 0-7 for BF16X3 at 512) of the one-kernel forward; NSMI_NO_FUSED_MLP
- * selects the layer-by-layer forward; NSMI_TUNE_CACHE names the on-disk
+ * selects the layer-by-layer forward; NSMI_NO_FUSED_CHI2 stages the chi^2 of
+ * the one-network CMB models after the one-kernel forward instead of adding
+ * it in the forward's epilogue (results equal to 1e-12 relative: the same
+ * terms summed in another order); NSMI_TUNE_CACHE names the on-disk
  * cache of choices ("off": none; default $XDG_CACHE_HOME/nsmi/tune.txt or
  * $HOME/.cache/nsmi/tune.txt), read by ns_model_create for the device's GPU
  * architecture and appended to on every new choice. */

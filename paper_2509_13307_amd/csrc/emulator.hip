@@ -573,9 +573,10 @@ static void launch_bf16_tuned(ns_model* m, int kind, const Group<Epi>& P, int64_
     bf16_candidate<Epi>(best)(P, M, N, K, G, count, rpw, s);
 }
 
-int tune_ncfg(int kind) { return kind < 2 ? BF16_NCFG : fused_ncfg_of(kind >= 4, kind & 1); }
+// kinds 2 .. 9: one-kernel forward, 2 + split + 2 wide + 4 chi^2 mode
+int tune_ncfg(int kind) { return kind < 2 ? BF16_NCFG : fused_ncfg_of(((kind - 2) >> 1) & 1, (kind - 2) & 1); }
 const char* tune_cfg_name(int kind, int c) {
-    return kind < 2 ? BF16_CFG_NAMES[c] : fused_cfg_name(kind >= 4, kind & 1, c);
+    return kind < 2 ? BF16_CFG_NAMES[c] : fused_cfg_name(((kind - 2) >> 1) & 1, (kind - 2) & 1, c);
 }
 
 std::string bf16_tuning_report(const ns_model* m) {
@@ -584,9 +585,10 @@ std::string bf16_tuning_report(const ns_model* m) {
     for (const auto& kv : m->tune) {
         char tmp[256];
         const int kind = std::get<0>(kv.first);
-        static const char* kinds[6] = {"bf16_hidden", "bf16_out", "fused_bf16", "fused_bf16x3", "fused_bf16",
-                                       "fused_bf16x3"};
-        const char* cfg = kind < 2 ? BF16_CFG_NAMES[kv.second] : fused_cfg_name(kind >= 4, kind & 1, kv.second);
+        static const char* kinds[10] = {"bf16_hidden", "bf16_out", "fused_bf16", "fused_bf16x3", "fused_bf16",
+                                        "fused_bf16x3", "fused_chi2_bf16", "fused_chi2_bf16x3", "fused_chi2_bf16",
+                                        "fused_chi2_bf16x3"};
+        const char* cfg = tune_cfg_name(kind, kv.second);
         snprintf(tmp, sizeof tmp, "%s\"%s M=%lld N=%d K=%d networks=%d\": \"%s\"", first ? "" : ", ", kinds[kind],
                  (long long)std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
                  std::get<4>(kv.first), cfg);

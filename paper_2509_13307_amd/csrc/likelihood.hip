@@ -302,6 +302,8 @@ void loglike_batch(ns_model* m, const double* theta, int64_t ld, int64_t B, doub
         if (m->kind == NS_MODEL_CMB_DIAG && prec == NS_FP64 &&
             emulator_forward_f64_narrow(m, theta, ld, B, nullptr, 0, m->spec_log[0], logl, count, s))
             return;
+        // one network in a BF16-operand form: the chi^2 in the emulator's epilogue
+        if (emulator_chi2_fused(m, theta, ld, B, logl, prec, count, s)) return;
         // the cosmic-variance stage reads log10 C_l itself
         static const int raw[4] = {0, 0, 0, 0};
         emulator_forward(m, ids, G, theta, ld, B, outs, n, m->kind == NS_MODEL_CMB_CV ? raw : m->spec_log.data(),

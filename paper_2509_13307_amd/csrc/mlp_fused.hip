@@ -47,7 +47,59 @@ struct FusedArgs {
     int64_t ldo;
     int qg;              // output-block groups (grid z): each runs the hidden layers, then its share of the
                          // output layer's H-wide column blocks
+    // chi^2 in the output epilogue instead of stored outputs (one network):
+    // chi = 1 diagonal Gaussian, 2 cosmic-variance TT (see chi2_term)
+    int chi;
+    const double* cdata; const double* cw;  // data vector and inverse sigma (1) or (2l+1)/2 (2)
+    double cst;                             // logL constant
+    double* logl;                           // [rows] (one output group) ...
+    double* part;                           // ... or [n_cb][H/32][rows] tile partials (several groups)
+    const double* theta_s; int64_t ld_s; int d;   // support check of each walker
+    const int* pk; const double* pa; const double* pb;
 };
+
+// One chi^2 term of output c with model value y (the FP32 output the store
+// path would write): diagonal Gaussian ((data - y) / sigma)^2, or the
+// cosmic-variance TT term (2l+1)/2 (ln C + data / C) with C = 10^y (Sec. 2.4
+// of the paper); the same expressions as the staged kernels chi2_diag_kernel
+// and cv_loglike_kernel.
+__device__ __forceinline__ double chi2_term(int chi, double y, double data, double w) {
+    if (chi == 1) {
+        const double r = (data - y) * w;
+        return r * r;
+    }
+    const double lc = 2.302585092994045684 * y;
+    return w * (lc + data * exp(-lc));
+}
+
+// Sum of v[0..7] over the 32 lanes of each half wave, one row per value:
+// afterwards lane l (l % 4 == 0) holds the sum for value (l & 31) >> 2.
+// Partial sums of lanes c and c ^ m are added for m = 16, 8, 4, 2, 1 in this
+// order, so every row's sum is the same tree over its 32 columns wherever
+// the row sits.
+__device__ __forceinline__ double tile_row_sums(const double (&v)[8], int lane) {
+    // scalars and value selects (a select of two array elements can become a
+    // select of their addresses, which keeps the array out of registers)
+    double a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3], a4 = v[4], a5 = v[5], a6 = v[6], a7 = v[7];
+    bool up = lane & 16;                                // 8 values -> 4
+    double s0 = up ? a0 : a4, s1 = up ? a1 : a5, s2 = up ? a2 : a6, s3 = up ? a3 : a7;
+    double k0 = up ? a4 : a0, k1 = up ? a5 : a1, k2 = up ? a6 : a2, k3 = up ? a7 : a3;
+    a0 = k0 + __shfl_xor(s0, 16, 64);
+    a1 = k1 + __shfl_xor(s1, 16, 64);
+    a2 = k2 + __shfl_xor(s2, 16, 64);
+    a3 = k3 + __shfl_xor(s3, 16, 64);
+    up = lane & 8;                                      // 4 -> 2
+    s0 = up ? a0 : a2; s1 = up ? a1 : a3;
+    k0 = up ? a2 : a0; k1 = up ? a3 : a1;
+    a0 = k0 + __shfl_xor(s0, 8, 64);
+    a1 = k1 + __shfl_xor(s1, 8, 64);
+    up = lane & 4;                                      // 2 -> 1
+    s0 = up ? a0 : a1;
+    k0 = up ? a1 : a0;
+    a0 = k0 + __shfl_xor(s0, 4, 64);
+    const double x = a0 + __shfl_xor(a0, 2, 64);
+    return x + __shfl_xor(x, 1, 64);
+}
 
 bool fused_shape(const std::vector<int>& dims) {
     const int L = (int)dims.size() - 1;
@@ -59,7 +111,7 @@ bool fused_shape(const std::vector<int>& dims) {
     return true;
 }
 
-template <int H, int RT, bool X3, int P, int CT>
+template <int H, int RT, bool X3, int P, int CT, bool CHI>
 __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t rows, int rows_per_walker, const int* __restrict__ src,
     const double* __restrict__ fix, const double* __restrict__ znodes, FusedArgs A, const int* __restrict__ count) {
@@ -75,6 +127,9 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     // FM_SLACK bytes that the read-ahead of a layer's last K step may touch
     uint16_t* hs = fm_lds;
     uint16_t* hl = fm_lds + R * HS;
+    // chi^2 mode: [R][H / 32] row sums per 32-unit tile, behind the slack
+    constexpr int NTILE = H / 32;
+    double* csl = reinterpret_cast<double*>(fm_lds + (X3 ? 2 : 1) * R * HS + FM_SLACK / 2);
     __shared__ float xs[R][16];
     __shared__ int zrow[R];                // redshift-node index of each row (row mod mu_rows)
     __shared__ int rowo[R];                // output offset of each row (row ldo), -1 beyond the live rows
@@ -110,6 +165,8 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         zrow[tid] = A.mu_rows > 1 ? (int)((r0 + tid) % A.mu_rows) : 0;
         rowo[tid] = tid < nvalid ? tid * (int)A.ldo : -1;
     }
+    if (CHI)
+        for (int e = tid; e < R * NTILE; e += NT) csl[e] = 0.0;
 
     // ---- layer-1 inputs (normalised parameters) into LDS
     for (int e = tid; e < R * n_in; e += NT) {
@@ -316,6 +373,38 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     };
     // epilogue of output segment v (units nb + ...): mean + sigma y, 10^ for
     // log-emulated outputs, stored to the live rows
+    // chi^2 mode: per 32-unit tile, the row sums of the terms (tile_row_sums)
+    // are added to the tile's LDS slot of the row, block after block
+    auto chi_epi = [&](int nb) {
+        const bool is_log = N.is_log;
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            const int c = nb + j * 32 + (lane & 31);
+            const bool live_c = c < N_out;
+            const int cc = min(c, N_out - 1);
+            const float bb = e0[j], sg = e1[j], mu0 = e2[j];
+            const double dat = A.cdata[cc], cw = A.cw[cc];
+            const int tile = (wave * WC + j * 32) / 32;
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf) {                // accumulator rows r = 8 hf .. 8 hf + 7
+                    double v[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        float y = mu0 + sg * (acc[i][j][8 * hf + k] + bb);
+                        if (is_log) y = exp10_of<float>(y);
+                        v[k] = live_c ? chi2_term(A.chi, (double)y, dat, cw) : 0.0;
+                    }
+                    const double sum = tile_row_sums(v, lane);
+                    if ((lane & 3) == 0) {
+                        const int rr = 8 * hf + ((lane & 31) >> 2);
+                        const int row = i * 32 + (lane >> 5) * 4 + (rr >> 2) * 8 + (rr & 3);
+                        csl[row * NTILE + tile] += sum;
+                    }
+                }
+        }
+    };
     auto output_epi = [&](int nb) {
         const bool zdep = A.mu_rows > 1, is_log = N.is_log;
         // every row of the block live and one mean row: row addresses are
@@ -389,20 +478,61 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         if (nb >= N_out) break;
         seg_begin();
         ksteps(0, KC);
-        output_epi(nb);
+        if (CHI) chi_epi(nb);
+        else output_epi(nb);
         seg_end();
+    }
+    if (!CHI) return;
+    // chi^2 mode: every wave's tile sums are in LDS; per row, tiles in order
+    // (one output group: logL), or each tile's sum as a partial of its block
+    __syncthreads();
+    for (int t = tid; t < R * NTILE; t += NT) {
+        const int rr = t / NTILE, tile = t % NTILE;
+        if (rr >= nvalid || A.qg == 1) continue;
+        A.part[((int64_t)ob0 * NTILE + tile) * nrows + r0 + rr] = csl[t];
+    }
+    if (A.qg == 1 && tid < nvalid) {
+        double sum = csl[tid * NTILE];
+        for (int tile = 1; tile < NTILE; ++tile) sum += csl[tid * NTILE + tile];
+        const int64_t w = (r0 + tid) / rows_per_walker;
+        const bool ok = in_support(A.theta_s + w * A.ld_s, A.d, A.pk, A.pa, A.pb);
+        A.logl[r0 + tid] = !ok ? -INFINITY : (A.chi == 1 ? -0.5 * sum + A.cst : A.cst - sum);
     }
 }
 
-template <int H, int RT, bool X3, int P, int CT>
+// Several output groups: logL of each row from the tile partials of every
+// output block, tiles outer and blocks inner, in the order of one group's
+// LDS slots (each slot adds its tile's block sums in block order, then the
+// tiles are summed), so the value does not depend on the launch shape.
+__global__ __launch_bounds__(256) void chi2_fused_finish_kernel(const double* __restrict__ part, int nblk,
+                                                                int ntile, int64_t rows, FusedArgs A,
+                                                                const int* __restrict__ count) {
+    int64_t nr = rows;
+    if (count) nr = min<int64_t>(rows, (int64_t)(*count));
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    double sum = 0.0;
+    for (int tile = 0; tile < ntile; ++tile) {
+        double ts = part[(int64_t)tile * nr + r];
+        for (int b = 1; b < nblk; ++b) ts += part[((int64_t)b * ntile + tile) * nr + r];
+        sum = tile == 0 ? ts : sum + ts;
+    }
+    const bool ok = in_support(A.theta_s + r * A.ld_s, A.d, A.pk, A.pa, A.pb);
+    A.logl[r] = !ok ? -INFINITY : (A.chi == 1 ? -0.5 * sum + A.cst : A.cst - sum);
+}
+
+template <int H, int RT, bool X3, int P, int CT, bool CHI>
 static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, int64_t ld, int64_t rows, int rpw,
                          int G, const int* count, hipStream_t s) {
     constexpr int R = 32 * RT;
     constexpr int NT = 64 * (H / (32 * CT));
-    const size_t smem = (size_t)(X3 ? 2 : 1) * R * (H + 8) * sizeof(uint16_t) + FM_SLACK;
-    const auto kern = mlp_fused_kernel<H, RT, X3, P, CT>;
+    const size_t base = (size_t)(X3 ? 2 : 1) * R * (H + 8) * sizeof(uint16_t) + FM_SLACK;
+    const size_t slots = (size_t)R * (H / 32) * sizeof(double);     // chi^2 mode's row sums
+    const size_t smem = base + (CHI ? slots : 0);
+    const auto kern = mlp_fused_kernel<H, RT, X3, P, CT, CHI>;
     const int rtc = RT == 2 ? 0 : (RT == 1 ? 1 : 2);
-    const int bit = (((rtc * 2 + (H == 512)) * 2 + X3) * 2 + (CT == 1)) * 4 + (P == 2 ? 0 : (P == 4 ? 1 : 2));
+    const int bit = ((((int)CHI * 3 + rtc) * 2 + (H == 512)) * 2 + X3) * 8 + (CT == 1) * 4 +
+                    (P == 2 ? 0 : (P == 4 ? 1 : 2));
     if (smem > 64 * 1024 && !m->fused_attr_set[bit]) {
         NS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
         m->fused_attr_set[bit] = true;
@@ -423,51 +553,55 @@ static void launch_fused(ns_model* m, const FusedArgs& A, const double* theta, i
 // identical results.
 using FusedLaunch = void (*)(ns_model*, const FusedArgs&, const double*, int64_t, int64_t, int, int, const int*,
                              hipStream_t);
-struct FusedCfg { FusedLaunch fn; const char* name; bool split_out; };
+struct FusedCfg { FusedLaunch fn, fn_chi; const char* name; bool split_out; };
+template <int H, int RT, bool X3, int P, int CT>
+constexpr FusedCfg fcfg(const char* name, bool split_out = false) {
+    return {launch_fused<H, RT, X3, P, CT, false>, launch_fused<H, RT, X3, P, CT, true>, name, split_out};
+}
 constexpr int FUSED_NCFG = 10;                    // table width; the split form at width 512 has 8 candidates
 static int fused_ncfg(int h512, int x3) { return x3 && h512 ? 8 : 10; }
 static const FusedCfg FUSED_CFGS[2][2][FUSED_NCFG] = {
     {   // H = 128
-        {{launch_fused<128, 2, false, 4, 2>, "fused 2 waves x 64 units, prefetch 4"},
-         {launch_fused<128, 2, false, 8, 2>, "fused 2 waves x 64 units, prefetch 8"},
-         {launch_fused<128, 2, false, 4, 1>, "fused 4 waves x 32 units, prefetch 4"},
-         {launch_fused<128, 2, false, 8, 1>, "fused 4 waves x 32 units, prefetch 8"},
-         {launch_fused<128, 1, false, 4, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 4"},
-         {launch_fused<128, 1, false, 8, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 8"},
-         {launch_fused<128, 4, false, 4, 1>, "fused 4 waves x 32 units, 128 rows, prefetch 4"},
-         {launch_fused<128, 4, false, 4, 2>, "fused 2 waves x 64 units, 128 rows, prefetch 4"},
-         {launch_fused<128, 1, false, 4, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 4, output blocks split", true},
-         {launch_fused<128, 1, false, 8, 1>, "fused 4 waves x 32 units, 32 rows, prefetch 8, output blocks split", true}},
-        {{launch_fused<128, 2, true, 2, 2>, "fused split 2 waves x 64 units, prefetch 2"},
-         {launch_fused<128, 2, true, 4, 2>, "fused split 2 waves x 64 units, prefetch 4"},
-         {launch_fused<128, 2, true, 2, 1>, "fused split 4 waves x 32 units, prefetch 2"},
-         {launch_fused<128, 2, true, 4, 1>, "fused split 4 waves x 32 units, prefetch 4"},
-         {launch_fused<128, 1, true, 2, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 2"},
-         {launch_fused<128, 1, true, 4, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 4"},
-         {launch_fused<128, 1, true, 8, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 8"},
-         {launch_fused<128, 2, true, 8, 1>, "fused split 4 waves x 32 units, prefetch 8"},
-         {launch_fused<128, 1, true, 2, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 2, output blocks split", true},
-         {launch_fused<128, 1, true, 8, 1>, "fused split 4 waves x 32 units, 32 rows, prefetch 8, output blocks split", true}},
+        {fcfg<128, 2, false, 4, 2>("fused 2 waves x 64 units, prefetch 4"),
+         fcfg<128, 2, false, 8, 2>("fused 2 waves x 64 units, prefetch 8"),
+         fcfg<128, 2, false, 4, 1>("fused 4 waves x 32 units, prefetch 4"),
+         fcfg<128, 2, false, 8, 1>("fused 4 waves x 32 units, prefetch 8"),
+         fcfg<128, 1, false, 4, 1>("fused 4 waves x 32 units, 32 rows, prefetch 4"),
+         fcfg<128, 1, false, 8, 1>("fused 4 waves x 32 units, 32 rows, prefetch 8"),
+         fcfg<128, 4, false, 4, 1>("fused 4 waves x 32 units, 128 rows, prefetch 4"),
+         fcfg<128, 4, false, 4, 2>("fused 2 waves x 64 units, 128 rows, prefetch 4"),
+         fcfg<128, 1, false, 4, 1>("fused 4 waves x 32 units, 32 rows, prefetch 4, output blocks split", true),
+         fcfg<128, 1, false, 8, 1>("fused 4 waves x 32 units, 32 rows, prefetch 8, output blocks split", true)},
+        {fcfg<128, 2, true, 2, 2>("fused split 2 waves x 64 units, prefetch 2"),
+         fcfg<128, 2, true, 4, 2>("fused split 2 waves x 64 units, prefetch 4"),
+         fcfg<128, 2, true, 2, 1>("fused split 4 waves x 32 units, prefetch 2"),
+         fcfg<128, 2, true, 4, 1>("fused split 4 waves x 32 units, prefetch 4"),
+         fcfg<128, 1, true, 2, 1>("fused split 4 waves x 32 units, 32 rows, prefetch 2"),
+         fcfg<128, 1, true, 4, 1>("fused split 4 waves x 32 units, 32 rows, prefetch 4"),
+         fcfg<128, 1, true, 8, 1>("fused split 4 waves x 32 units, 32 rows, prefetch 8"),
+         fcfg<128, 2, true, 8, 1>("fused split 4 waves x 32 units, prefetch 8"),
+         fcfg<128, 1, true, 2, 1>("fused split 4 waves x 32 units, 32 rows, prefetch 2, output blocks split", true),
+         fcfg<128, 1, true, 8, 1>("fused split 4 waves x 32 units, 32 rows, prefetch 8, output blocks split", true)},
     },
     {   // H = 512
-        {{launch_fused<512, 2, false, 4, 2>, "fused 8 waves x 64 units, prefetch 4"},
-         {launch_fused<512, 2, false, 8, 2>, "fused 8 waves x 64 units, prefetch 8"},
-         {launch_fused<512, 2, false, 4, 1>, "fused 16 waves x 32 units, prefetch 4"},
-         {launch_fused<512, 2, false, 8, 1>, "fused 16 waves x 32 units, prefetch 8"},
-         {launch_fused<512, 1, false, 4, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 4"},
-         {launch_fused<512, 1, false, 8, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 8"},
-         {launch_fused<512, 4, false, 4, 1>, "fused 16 waves x 32 units, 128 rows, prefetch 4"},
-         {launch_fused<512, 4, false, 4, 2>, "fused 8 waves x 64 units, 128 rows, prefetch 4"},
-         {launch_fused<512, 1, false, 4, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 4, output blocks split", true},
-         {launch_fused<512, 1, false, 8, 1>, "fused 16 waves x 32 units, 32 rows, prefetch 8, output blocks split", true}},
-        {{launch_fused<512, 2, true, 2, 2>, "fused split 8 waves x 64 units, prefetch 2"},
-         {launch_fused<512, 2, true, 4, 2>, "fused split 8 waves x 64 units, prefetch 4"},
-         {launch_fused<512, 2, true, 2, 1>, "fused split 16 waves x 32 units, prefetch 2"},
-         {launch_fused<512, 2, true, 4, 1>, "fused split 16 waves x 32 units, prefetch 4"},
-         {launch_fused<512, 1, true, 2, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 2"},
-         {launch_fused<512, 1, true, 4, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 4"},
-         {launch_fused<512, 1, true, 2, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 2, output blocks split", true},
-         {launch_fused<512, 1, true, 4, 1>, "fused split 16 waves x 32 units, 32 rows, prefetch 4, output blocks split", true}},
+        {fcfg<512, 2, false, 4, 2>("fused 8 waves x 64 units, prefetch 4"),
+         fcfg<512, 2, false, 8, 2>("fused 8 waves x 64 units, prefetch 8"),
+         fcfg<512, 2, false, 4, 1>("fused 16 waves x 32 units, prefetch 4"),
+         fcfg<512, 2, false, 8, 1>("fused 16 waves x 32 units, prefetch 8"),
+         fcfg<512, 1, false, 4, 1>("fused 16 waves x 32 units, 32 rows, prefetch 4"),
+         fcfg<512, 1, false, 8, 1>("fused 16 waves x 32 units, 32 rows, prefetch 8"),
+         fcfg<512, 4, false, 4, 1>("fused 16 waves x 32 units, 128 rows, prefetch 4"),
+         fcfg<512, 4, false, 4, 2>("fused 8 waves x 64 units, 128 rows, prefetch 4"),
+         fcfg<512, 1, false, 4, 1>("fused 16 waves x 32 units, 32 rows, prefetch 4, output blocks split", true),
+         fcfg<512, 1, false, 8, 1>("fused 16 waves x 32 units, 32 rows, prefetch 8, output blocks split", true)},
+        {fcfg<512, 2, true, 2, 2>("fused split 8 waves x 64 units, prefetch 2"),
+         fcfg<512, 2, true, 4, 2>("fused split 8 waves x 64 units, prefetch 4"),
+         fcfg<512, 2, true, 2, 1>("fused split 16 waves x 32 units, prefetch 2"),
+         fcfg<512, 2, true, 4, 1>("fused split 16 waves x 32 units, prefetch 4"),
+         fcfg<512, 1, true, 2, 1>("fused split 16 waves x 32 units, 32 rows, prefetch 2"),
+         fcfg<512, 1, true, 4, 1>("fused split 16 waves x 32 units, 32 rows, prefetch 4"),
+         fcfg<512, 1, true, 2, 1>("fused split 16 waves x 32 units, 32 rows, prefetch 2, output blocks split", true),
+         fcfg<512, 1, true, 4, 1>("fused split 16 waves x 32 units, 32 rows, prefetch 4, output blocks split", true)},
     },
 };
 
@@ -476,21 +610,16 @@ int fused_ncfg_of(int h512, int x3) { return fused_ncfg(h512, x3); }
 
 // Returns false (and launches nothing) when the networks have no fragment-
 // ordered weights (shape outside fused_shape) or the form is not BF16-operand.
-bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
-                            void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
-                            hipStream_t s) {
-    if (prec != NS_BF16 && prec != NS_BF16X3) return false;
+// Shared by the store and chi^2 modes: the one-kernel arguments of networks
+// nets[0..G) (outputs and flags filled in by the caller).
+static FusedArgs fused_args(ns_model* m, const int* nets, int G) {
     const Net& n0 = *m->nets[nets[0]];
-    if (!n0.fused) return false;
-    const bool x3 = prec == NS_BF16X3;
     const int L = n0.n_layers;
-    const int H = n0.dims[1];
     FusedArgs A{};
     A.n_hidden = L - 2;
     A.n_in = n0.dims[0];
     A.N_out = n0.dims[L];
     A.mu_rows = n0.out_mu_rows;
-    A.ldo = ldo;
     A.qg = 1;
     for (int g = 0; g < G; ++g) {
         const Net& net = *m->nets[nets[g]];
@@ -503,24 +632,34 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
         F.Wfl = net.Wfl.as<uint16_t>();
         F.vec = net.fvec.as<float>();
         F.mu = net.out_mu32.as<float>(); F.sigma = net.out_sigma32.as<float>();
-        F.out = static_cast<float*>(outs[g]);
-        F.is_log = is_log[g];
     }
+    return A;
+}
+
+// Launch shape (measured once per (form, mode, rows, outputs, width, networks)
+// outside stream capture and tracing, or pinned / read from the cache), then
+// the launch; in chi^2 mode with the output blocks split over workgroups, the
+// finishing sum of the tile partials.
+static void fused_run(ns_model* m, const FusedArgs& A, int H, bool x3, int G, const double* theta, int64_t ld,
+                      int64_t B, const int* count, hipStream_t s) {
+    const Net& n0 = *m->nets[0];
     const int rpw = n0.out_mu_rows;
     const int64_t rows = B * rpw;
-    // launch shape: measured once per (form, rows, outputs, width, networks),
-    // outside stream capture and tracing
     const int h512 = H == 512;
     const FusedCfg* cfgs = FUSED_CFGS[h512][x3];
+    const int ncb = (A.N_out + H - 1) / H;
     // candidate c with its output-block grouping, on `nr` rows given on the
     // host (tuning) or on the launch's rows and device count
     auto run_rows = [&](int c, int64_t nr, const int* cnt) {
         FusedArgs Ac = A;
-        Ac.qg = cfgs[c].split_out ? (A.N_out + H - 1) / H : 1;
-        cfgs[c].fn(m, Ac, theta, ld, nr, rpw, G, cnt, s);
+        Ac.qg = cfgs[c].split_out ? ncb : 1;
+        (Ac.chi ? cfgs[c].fn_chi : cfgs[c].fn)(m, Ac, theta, ld, nr, rpw, G, cnt, s);
+        if (Ac.chi && Ac.qg > 1)
+            hipLaunchKernelGGL(chi2_fused_finish_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s,
+                               (const double*)Ac.part, ncb, H / 32, nr, Ac, cnt);
     };
     auto run = [&](int c) { run_rows(c, rows, count); };
-    const auto key = std::make_tuple(2 + (int)x3 + 2 * h512, rows, A.N_out, H, G);
+    const auto key = std::make_tuple(2 + (int)x3 + 2 * h512 + (A.chi ? 4 : 0), rows, A.N_out, H, G);
     int best = 0;
     auto it = m->tune.find(key);
     const char* forced = getenv("NSMI_FUSED_CFG");      // pin one candidate (tests of every shape)
@@ -571,9 +710,76 @@ bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* t
             tune_cache_store(m, key, best);
         }
     }
-    TraceScope ts(m, s, x3 ? "mlp_fused_bf16x3" : "mlp_fused_bf16");
+    TraceScope ts(m, s, A.chi ? (x3 ? "mlp_fused_chi2_bf16x3" : "mlp_fused_chi2_bf16")
+                              : (x3 ? "mlp_fused_bf16x3" : "mlp_fused_bf16"));
     run(best);
     NS_HIP(hipGetLastError());
+}
+
+// Returns false (and launches nothing) when the networks have no fragment-
+// ordered weights (shape outside fused_shape) or the form is not BF16-operand.
+bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
+                            void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
+                            hipStream_t s) {
+    if (prec != NS_BF16 && prec != NS_BF16X3) return false;
+    const Net& n0 = *m->nets[nets[0]];
+    if (!n0.fused) return false;
+    FusedArgs A = fused_args(m, nets, G);
+    A.ldo = ldo;
+    for (int g = 0; g < G; ++g) {
+        A.net[g].out = static_cast<float*>(outs[g]);
+        A.net[g].is_log = is_log[g];
+    }
+    fused_run(m, A, n0.dims[1], prec == NS_BF16X3, G, theta, ld, B, count, s);
+    return true;
+}
+
+size_t chi2_fused_part_bytes(const ns_model* m, int64_t B) {
+    const Net& n0 = *m->nets[0];
+    const int H = n0.dims[1], ncb = (n0.dims[n0.n_layers] + H - 1) / H;
+    return (size_t)ncb * (H / 32) * std::max<int64_t>(B, 1) * sizeof(double);
+}
+
+bool emulator_chi2_fused(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, int prec,
+                         const int* count, hipStream_t s, double* part) {
+    if (prec != NS_BF16 && prec != NS_BF16X3) return false;
+    if (m->kind != NS_MODEL_CMB_DIAG && m->kind != NS_MODEL_CMB_CV) return false;
+    if (m->nets.size() != 1 || !m->nets[0]->fused || m->nets[0]->out_mu_rows != 1) return false;
+    // staged chi^2 (tests compare the two), or the layer-by-layer forward
+    if (getenv("NSMI_NO_FUSED_CHI2") != nullptr || getenv("NSMI_NO_FUSED_MLP") != nullptr) return false;
+    // The cosmic-variance terms take an FP64 exp each, which in the epilogue
+    // lengthens every workgroup's serial path by about 10 us, against a staged
+    // kernel that spreads them over the whole GPU in 10 us (1 000 rows) to
+    // 20 us (4 096 rows): fused only from FUSED_CV_MIN_ROWS rows (measured:
+    // 4 096 rows 104 instead of 111 us, 1 000 rows 79 instead of 66 us).  A
+    // fixed rule, not a timing, so that which sum a batch gets (they differ
+    // in the last bits) does not depend on the machine.
+    constexpr int64_t FUSED_CV_MIN_ROWS = 3072;
+    if (m->kind == NS_MODEL_CMB_CV && B < FUSED_CV_MIN_ROWS) return false;
+    const int id0 = 0;
+    const Net& n0 = *m->nets[0];
+    const int H = n0.dims[1];
+    FusedArgs A = fused_args(m, &id0, 1);
+    const bool cv = m->kind == NS_MODEL_CMB_CV;
+    A.net[0].out = nullptr;
+    A.net[0].is_log = cv ? 0 : m->spec_log[0];             // the cosmic-variance terms take log10 C_l
+    A.chi = cv ? 2 : 1;
+    A.cdata = m->data.as<double>();
+    A.cw = cv ? m->cv_halfk.as<double>() : m->inv_sigma.as<double>();
+    A.cst = m->logl_const;
+    A.logl = logl;
+    if (!part) {
+        m->ws_chi.ensure(chi2_fused_part_bytes(m, B));
+        part = m->ws_chi.as<double>();
+    }
+    A.part = part;
+    A.theta_s = theta;
+    A.ld_s = ld;
+    A.d = m->d;
+    A.pk = m->prior_kind.as<int>();
+    A.pa = m->prior_a.as<double>();
+    A.pb = m->prior_b.as<double>();
+    fused_run(m, A, H, prec == NS_BF16X3, 1, theta, ld, B, count, s);
     return true;
 }
 

@@ -1,9 +1,10 @@
 // Batched CMB log-likelihood without any device allocation, for callers that
 // cannot allocate (code under HIP graph capture, tight serving loops): the
-// emulator's model vector, the only device memory the one-kernel BF16 /
-// split-BF16 path needs beyond the caller's theta and logL, lives in a
-// file-scope device array of SCRATCH_BYTES per GPU instead of the model's
-// grow-on-demand workspace.
+// only device memory the one-kernel BF16 / split-BF16 path needs beyond the
+// caller's theta and logL (the emulator's model vector, or, for the
+// one-network models whose chi^2 runs in the emulator's epilogue, its tile
+// partials) lives in a file-scope device array of SCRATCH_BYTES per GPU
+// instead of the model's grow-on-demand workspace.
 //
 // The array's address on each device is taken once, with that device current,
 // when the first model is created on it (hipGetSymbolAddress); host code only
@@ -78,6 +79,12 @@ void loglike_batch_noalloc(ns_model* m, const double* theta, int64_t ld, int64_t
     static const int raw[4] = {0, 0, 0, 0};
     m->noalloc_call = true;
     try {
+        // the same launches as ns_loglike_batch: chi^2 in the epilogue where it applies
+        if (chi2_fused_part_bytes(m, B) <= SCRATCH_BYTES &&
+            emulator_chi2_fused(m, theta, ld, B, logl, prec, nullptr, s, reinterpret_cast<double*>(base))) {
+            m->noalloc_call = false;
+            return;
+        }
         const bool ok = emulator_forward_fused(m, ids, G, theta, ld, B, outs, n,
                                                m->kind == NS_MODEL_CMB_CV ? raw : m->spec_log.data(), prec, nullptr,
                                                s);

@@ -180,10 +180,11 @@ struct ns_model {
     nsmi::DevBuf ws_gact[2];         // adjoint activations ping-pong [G x rows x n_pad]
     nsmi::DevBuf ws_gx;              // input gradients [G x rows x n_in]
     nsmi::DevBuf ws_hmc;             // HMC chain state
+    nsmi::DevBuf ws_chi;             // chi^2 tile partials of the one-kernel emulator [blocks x tiles x B]
     hipStream_t graph_stream = nullptr;  // stream the captured sampler graphs replay on
     hipEvent_t graph_event = nullptr;
     bool shear_attr_set = false;     // hipFuncSetAttribute done for the Limber kernels
-    std::bitset<96> fused_attr_set;  // ... and per instance of the one-kernel emulator
+    std::bitset<192> fused_attr_set;  // ... and per instance of the one-kernel emulator
     // BF16 tile / fused launch-shape choice per (kind, M, N, K, networks), measured at first use
     // or read from the on-disk cache (tune_path, entries of this GPU architecture only)
     std::map<std::tuple<int, int64_t, int, int, int>, int> tune;
@@ -233,6 +234,15 @@ bool fused_shape(const std::vector<int>& dims);
 bool emulator_forward_fused(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t B,
                             void* const* outs, int64_t ldo, const int* is_log, int prec, const int* count,
                             hipStream_t s);
+// Emulator and chi^2 in one launch for the one-network CMB kinds (diagonal
+// Gaussian, cosmic-variance TT) in the BF16-operand forms: logL [B] written;
+// false (nothing launched) for other models or forms, or with
+// NSMI_NO_FUSED_CHI2 or NSMI_NO_FUSED_MLP set.  `part` (chi2_fused_part_bytes)
+// holds the tile partials of the launch shapes that split the output blocks;
+// nullptr: the model's workspace.
+bool emulator_chi2_fused(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl, int prec,
+                         const int* count, hipStream_t s, double* part = nullptr);
+size_t chi2_fused_part_bytes(const ns_model* m, int64_t B);
 
 // Adjoint of the emulator: from delta_out[g] ([rows x n_pad] FP64 for NS_FP64
 // else FP32; derivative of logL w.r.t. the raw network outputs) back to the

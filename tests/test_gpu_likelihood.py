@@ -179,19 +179,24 @@ def test_reduced_precision_forms(built, name, prec):
     assert d.max() <= 1e-2
 
 
-@pytest.mark.parametrize("name,B", [("cmb6", 300), ("cmb4x2500", 333), ("cmbtt_cv", 333), ("shear10", 70),
-                                    ("shear64", 9), ("shear_interp", 5)])
+@pytest.mark.parametrize("name,B", [("cmb6", 300), ("cmb4x2500", 333), ("cmbtt_cv", 333), ("cmbtt_cv", 3100),
+                                    ("shear10", 70), ("shear64", 9), ("shear_interp", 5)])
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
 def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
     """The one-kernel emulator gives bitwise the layer-by-layer result, with
-    the autotuned launch shape and with each candidate shape pinned."""
+    the autotuned launch shape and with each candidate shape pinned (the
+    chi^2 staged after it).  For the one-network CMB models the default path
+    adds the chi^2 in the emulator's epilogue (the diagonal one always, the
+    cosmic-variance one from 3072 rows): its logL is the same for every
+    launch shape, bitwise, and within 1e-12 relative of the staged chi^2
+    (the same terms summed in another order)."""
     say(f"case fused {prec} {name}")
     from paper_2509_13307_amd import Model
     m = W.load_model(name)
     th = torch.tensor(W.prior_draws(m, B, tag=5), device=DEV)
 
     def run(env):
-        for k in ("NSMI_NO_FUSED_MLP", "NSMI_FUSED_CFG"):
+        for k in ("NSMI_NO_FUSED_MLP", "NSMI_FUSED_CFG", "NSMI_NO_FUSED_CHI2"):
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
@@ -202,13 +207,26 @@ def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
         return out, report
 
     ref, _ = run({"NSMI_NO_FUSED_MLP": "1"})
-    got, report = run({})
+    got, report = run({"NSMI_NO_FUSED_CHI2": "1"})
     say(f"{name} {prec}: tuned {report}")
     np.testing.assert_array_equal(got, ref)
     width = m["nets"][0]["W"][0].shape[0]          # hidden width: 128 or 512
-    for c in range(10 if prec == "bf16" or width == 128 else 8):
-        got, _ = run({"NSMI_FUSED_CFG": str(c)})
+    ncfg = 10 if prec == "bf16" or width == 128 else 8
+    for c in range(ncfg):
+        got, _ = run({"NSMI_FUSED_CFG": str(c), "NSMI_NO_FUSED_CHI2": "1"})
         np.testing.assert_array_equal(got, ref)
+    if name != "cmb6" and not (name == "cmbtt_cv" and B >= 3072):   # chi^2 in the epilogue from 3072 rows
+        return
+    fchi, report = run({})
+    say(f"{name} {prec}: chi^2 in the epilogue, tuned {report}; "
+        f"max |fused - staged| {np.max(np.abs(fchi - ref)):.3e}")
+    assert any("chi2" in k for k in report)
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(fchi))
+    np.testing.assert_allclose(fchi[fin], ref[fin], rtol=1e-12, atol=1e-9)
+    for c in range(ncfg):
+        got, _ = run({"NSMI_FUSED_CFG": str(c)})
+        np.testing.assert_array_equal(got, fchi)
 
 
 def test_tuning_cache_round_trip(built, tmp_path, monkeypatch):
