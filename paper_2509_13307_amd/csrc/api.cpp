@@ -463,31 +463,26 @@ static void build_model(ns_model* m, const ns_model_desc* D) {
         upload(m->znodes_d, zn.data(), zn.size());
         upload(m->zsp_idx_d, zi.data(), zi.size());
         upload(m->zsp_coef_d, zc.data(), zc.size());
-        // Slabs of the Limber adjoint's scatter: runs of consecutive nodes
-        // (1 .. n_a - 1) whose z rows zi[j], zi[j] + 1 span at most
-        // lslab_rows rows, the rows of the gradient tables one workgroup
-        // holds in LDS (64 KiB; at least the two rows of one node).  The
-        // nodes' z only grows along the a-grid, so the row ranges of
-        // successive slabs never go back.
+        // Slabs of the Limber adjoint's scatter: the z rows cut into runs of at
+        // most lslab_rows rows, the rows of the gradient tables one workgroup
+        // holds in LDS (64 KiB; at least the two rows of one node), each with
+        // the nodes (1 .. n_a - 1) whose rows zi[j], zi[j] + 1 meet it.  The
+        // nodes' z only grows along the a-grid, so those nodes are a run.
         {
             const int tables = m->z_linear ? 1 : 2;
             const size_t row_bytes = (size_t)tables * D->n_k * sizeof(unsigned long long);
             const int rmax = std::max(2, (int)((64 * 1024) / row_bytes));
-            std::vector<int> sl;
-            int j0 = 1, lo = na > 1 ? zi[1] : 0, hi = lo + 1;
-            for (int j = 1; j < na; ++j) {
+            for (int j = 2; j < na; ++j)
                 NS_CHECK(zi[j] >= zi[j - 1], NS_E_INVALID, "z-spline intervals not monotone along the a-grid");
-                const int nhi = std::max(hi, zi[j] + 1);
-                if (j > j0 && nhi - lo + 1 > rmax) {
-                    sl.insert(sl.end(), {j0, j, lo, hi});
-                    j0 = j;
-                    lo = zi[j];
-                    hi = zi[j] + 1;
-                } else {
-                    hi = nhi;
-                }
+            std::vector<int> sl;
+            int j0 = 1;
+            for (int lo = 0; lo < nz; lo += rmax) {
+                const int hi = std::min(nz - 1, lo + rmax - 1);
+                while (j0 < na && zi[j0] + 1 < lo) ++j0;
+                int j1 = j0;
+                while (j1 < na && zi[j1] <= hi) ++j1;
+                sl.insert(sl.end(), {j0, j1, lo, hi});
             }
-            if (na > 1) sl.insert(sl.end(), {j0, na, lo, hi});
             m->n_lslab = (int)(sl.size() / 4);
             m->lslab_rows = rmax;
             upload(m->lslab_d, sl.data(), sl.size());

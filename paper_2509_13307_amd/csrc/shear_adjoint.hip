@@ -23,16 +23,15 @@
 // g log10 P_bj of the walker and their largest magnitude G; then
 // limber_scatter_kernel adds each contribution c w g log10 P (|c w| < 2:
 // spline and Catmull-Rom weights) rounded to the grid 2^(e - FX_BITS),
-// G < 2^e, as integers: slab by slab (runs of nodes whose z rows fit in LDS)
-// with LDS atomics, each slab's rows then stored to (or, for the row it
-// shares with the slab before, added to) the walker's table.  At most
+// G < 2^e, as integers: slab by slab (runs of z rows that fit in LDS, each
+// taking the parts of the contributions that fall on its rows) with LDS
+// atomics, then each row once as a double.  At most
 // n_a n_ell <= 2^16 contributions reach one entry, so every partial sum stays
 // below 2^(FX_BITS + 17) < 2^63; the grid step is below G 2^-44 (about
 // 6e-14 G), well under the FP64 gradient's error against the complex step.
 // The spline-curvature table g M takes contributions smaller by the factor
 // max |c2|, |c3| <= 0.385 h^2 / 6 (h the z-node spacing) and has a grid finer
-// by 2^mshift, mshift = floor(log2(6 / (0.385 h^2))).  The spline adjoint
-// converts the integers back to doubles.
+// by 2^mshift, mshift = floor(log2(6 / (0.385 h^2))).
 #include "devutil.h"
 #include "nsmi.h"
 #include "shear_common.h"
@@ -471,20 +470,20 @@ __global__ __launch_bounds__(256) void limber_adjoint_kernel(
 }
 
 // Fixed-point scatter of g log10 P_bj (limber_adjoint_kernel's glp_buf and
-// grid step gstep) into gYi (and gMi for the cubic z-spline), one workgroup
-// per walker.  Slab s = (first node, end node, first row, last row) of
-// `slabs`: the contributions of its nodes go to LDS tables of its rows
-// (integer atomics), which are then written to the walker's tables; a row the
-// slab shares with earlier slabs is added to, rows no slab reaches are set to
-// zero.  Every entry of the walker's tables is written, so they need no
-// clearing before.  A walker whose grid step is NaN (a non-finite gradient)
-// gets zero tables.
+// grid step gstep) into the tables gY (and gM for the cubic z-spline), one
+// workgroup per walker.  Slab s = (first node, end node, first row, last row)
+// of `slabs`: the z rows partitioned into runs, each with the nodes whose two
+// rows meet it.  A slab adds the contributions of its nodes to its own rows
+// only, as integers in LDS (atomics); every row's sum is then complete, and
+// the slab writes its rows as doubles (integer x grid step, 2^-mshift finer
+// for gM).  Every entry of the walker's tables is written.  A walker whose
+// grid step is NaN (a non-finite gradient) gets NaN tables.
 template <bool LINZ>
 __global__ __launch_bounds__(256) void limber_scatter_kernel(
     int64_t B, ShearGeom G, const int* __restrict__ zidx, const double* __restrict__ zcoef,
     const double* __restrict__ ell, const double* __restrict__ tg, const double* __restrict__ glp_buf,
     const int4* __restrict__ slabs, int n_slabs, int rmax, const double* __restrict__ gstep, int mshift,
-    unsigned long long* __restrict__ gYi, unsigned long long* __restrict__ gMi) {
+    double* __restrict__ gY, double* __restrict__ gM) {
     extern __shared__ unsigned long long sl[];          // [tables][rmax][n_k]
     const int64_t w = blockIdx.x;
     if (w >= B) return;
@@ -494,21 +493,15 @@ __global__ __launch_bounds__(256) void limber_scatter_kernel(
     const double step = gstep[w];
     const bool ok = !isnan(step);
     const double scale = 1.0 / step, mscale = ldexp(scale, mshift);     // powers of two: exact
+    const double mstep = ldexp(step, -mshift);
     const int tab = rmax * nk;
-    unsigned long long* gYw = gYi + w * (int64_t)nz * nk;
-    unsigned long long* gMw = LINZ ? gYw : gMi + w * (int64_t)nz * nk;
+    double* gYw = gY + w * (int64_t)nz * nk;
+    double* gMw = LINZ ? gYw : gM + w * (int64_t)nz * nk;
     const double* glw = glp_buf + w * (int64_t)ne * na;
     const double* chiw = tg + ((int64_t)w * S + TG_CHI) * na;
-    auto zero_rows = [&](int r0, int r1) {
-        for (int64_t e = (int64_t)r0 * nk + t; e < (int64_t)r1 * nk; e += 256) {
-            gYw[e] = 0ull;
-            if (!LINZ) gMw[e] = 0ull;
-        }
-    };
     auto fx_add = [&](unsigned long long* p, double v, double sc) {
         if (v != 0.0) atomicAdd(p, (unsigned long long)llrint(v * sc));
     };
-    int rnext = 0;                                      // rows below are written
     for (int s = 0; s < n_slabs; ++s) {
         const int4 sb = slabs[s];
         const int lo = sb.z, nr = sb.w - sb.z + 1, nj = sb.y - sb.x;
@@ -525,7 +518,9 @@ __global__ __launch_bounds__(256) void limber_scatter_kernel(
                 if (!(k >= G.k_min && k <= G.k_max)) continue;
                 const double glp = glw[(int64_t)b * na + j];
                 if (glp == 0.0) continue;
-                const int nn = zidx[j] - lo;
+                // the node's rows zi[j], zi[j] + 1 as rows of this slab (either may lie outside it)
+                const int r0 = zidx[j] - lo, r1 = r0 + 1;
+                const bool in0 = r0 >= 0, in1 = r1 < nr;
                 const double c0 = zcoef[4 * j], c1 = zcoef[4 * j + 1];
                 const double c2 = LINZ ? 0.0 : zcoef[4 * j + 2], c3 = LINZ ? 0.0 : zcoef[4 * j + 3];
                 const KPos kp = k_position(k, G);
@@ -538,12 +533,13 @@ __global__ __launch_bounds__(256) void limber_scatter_kernel(
                 if (kp.hi_ghost) { w1c += 2.0 * w2; w0c -= w2; w2 = 0.0; }
                 auto scatter = [&](int col, double wgt) {
                     const double gy = glp * wgt;
-                    const int o0 = nn * nk + col, o1 = o0 + nk;
-                    fx_add(&sl[o0], c0 * gy, scale);
-                    fx_add(&sl[o1], c1 * gy, scale);
-                    if (!LINZ) {
-                        fx_add(&sl[tab + o0], c2 * gy, mscale);
-                        fx_add(&sl[tab + o1], c3 * gy, mscale);
+                    if (in0) {
+                        fx_add(&sl[r0 * nk + col], c0 * gy, scale);
+                        if (!LINZ) fx_add(&sl[tab + r0 * nk + col], c2 * gy, mscale);
+                    }
+                    if (in1) {
+                        fx_add(&sl[r1 * nk + col], c1 * gy, scale);
+                        if (!LINZ) fx_add(&sl[tab + r1 * nk + col], c3 * gy, mscale);
                     }
                 };
                 if (!kp.lo_ghost) scatter(kp.i0 - 1, wm);
@@ -552,31 +548,24 @@ __global__ __launch_bounds__(256) void limber_scatter_kernel(
                 if (!kp.hi_ghost) scatter(kp.i0 + 2, w2);
             }
         __syncthreads();
-        if (rnext < lo) zero_rows(rnext, lo);
         const int64_t g0 = (int64_t)lo * nk;
         for (int e = t; e < nr * nk; e += 256) {
-            const bool seen = lo + e / nk < rnext;
-            gYw[g0 + e] = (seen ? gYw[g0 + e] : 0ull) + sl[e];
-            if (!LINZ) gMw[g0 + e] = (seen ? gMw[g0 + e] : 0ull) + sl[tab + e];
+            gYw[g0 + e] = ok ? (double)(long long)sl[e] * step : NAN;
+            if (!LINZ) gMw[g0 + e] = ok ? (double)(long long)sl[tab + e] * mstep : NAN;
         }
-        rnext = max(rnext, sb.w + 1);
         __syncthreads();                                // LDS reused by the next slab
     }
-    zero_rows(rnext, nz);
 }
 
 // ------------------------------------------------------------ spline adjoint
-// gY, gM arrive as the fixed-point integers of limber_adjoint_kernel (grid
-// gstep[w], and gstep[w] 2^-mshift for gM) and are turned into doubles in
-// place; then gY += S^T gM for the not-a-knot spline of each (walker, k)
-// column, and delta_out[row = w n_z + n][c] = gY[n][c] sigma_out[c] (padded to
-// n_pad).
+// gY, gM (doubles, from limber_scatter_kernel): gY += S^T gM for the
+// not-a-knot spline of each (walker, k) column, and
+// delta_out[row = w n_z + n][c] = gY[n][c] sigma_out[c] (padded to n_pad).
 template <class T>
 __global__ __launch_bounds__(256) void zspline_adjoint_kernel(double* __restrict__ gY, double* __restrict__ gM,
                                                               int64_t B, int nz, int nk, double h,
                                                               const double* __restrict__ sigma_out, int n_pad,
-                                                              T* __restrict__ delta, int linear,
-                                                              const double* __restrict__ gstep, int mshift) {
+                                                              T* __restrict__ delta, int linear) {
     __shared__ double cps[256];
     if (threadIdx.x == 0) {
         double c = 0.0;
@@ -595,21 +584,14 @@ __global__ __launch_bounds__(256) void zspline_adjoint_kernel(double* __restrict
         return;
     }
     double* gy = gY + w * nz * nk + c;
-    const double step = gstep[w];
-    auto fx = [](double bits, double st) { return (double)__builtin_bit_cast(long long, bits) * st; };
     if (linear) {                               // no spline: delta = g Y sigma_out
         const double sg = sigma_out[c];
-        for (int n = 0; n < nz; ++n) delta[(w * nz + n) * n_pad + c] = (T)(fx(gy[(int64_t)n * nk], step) * sg);
+        for (int n = 0; n < nz; ++n) delta[(w * nz + n) * n_pad + c] = (T)(gy[(int64_t)n * nk] * sg);
         return;
     }
     double* gm = gM + w * nz * nk + c;
     auto Y = [&](int n) -> double& { return gy[(int64_t)n * nk]; };
     auto Mg = [&](int n) -> double& { return gm[(int64_t)n * nk]; };
-    const double mstep = ldexp(step, -mshift);
-    for (int n = 0; n < nz; ++n) {
-        Y(n) = fx(Y(n), step);
-        Mg(n) = fx(Mg(n), mstep);
-    }
     const double ih2 = 1.0 / (h * h);
     // M_0 = 2 M_1 - M_2 and M_{N-1} = 2 M_{N-2} - M_{N-3}: fold their adjoints
     // into the other nodes first (valid for every nz >= 4)
@@ -720,8 +702,7 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
             NS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
         hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(256), smem, s, B, G, m->zsp_idx_d.as<int>(),
                            m->zsp_coef_d.as<double>(), m->ell_d.as<double>(), tg, glp, m->lslab_d.as<int4>(),
-                           m->n_lslab, m->lslab_rows, gstep, mshift, reinterpret_cast<unsigned long long*>(gY),
-                           reinterpret_cast<unsigned long long*>(gM));
+                           m->n_lslab, m->lslab_rows, gstep, mshift, gY, gM);
         NS_HIP(hipGetLastError());
     }
     // spline adjoint -> delta for the emulator's raw outputs
@@ -737,12 +718,10 @@ void shear_grad(ns_model* m, const double* theta, int64_t ld, int64_t B, double*
         const dim3 gz((unsigned)((B * n_pad + 255) / 256));
         if (f64)
             hipLaunchKernelGGL(zspline_adjoint_kernel<double>, gz, dim3(256), 0, s, gY, gM, B, nz, nk, hz,
-                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<double>(), (int)lin, gstep,
-                               mshift);
+                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<double>(), (int)lin);
         else
             hipLaunchKernelGGL(zspline_adjoint_kernel<float>, gz, dim3(256), 0, s, gY, gM, B, nz, nk, hz,
-                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<float>(), (int)lin, gstep,
-                               mshift);
+                               net.out_sigma64.as<double>(), n_pad, m->ws_gact[0].as<float>(), (int)lin);
         NS_HIP(hipGetLastError());
     }
     emulator_backward(m, &id0, 1, B, f64 ? NS_FP64 : NS_FP32, s);
