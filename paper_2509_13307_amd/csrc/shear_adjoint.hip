@@ -284,11 +284,11 @@ __device__ __forceinline__ KPos k_position(double k, const ShearGeom& G) {
 
 // One workgroup (256 threads) per walker, thread = a-node j (chunks of 256):
 // g(P wq), g W_i(j), g wq_j and g chi_j (through k = (l+1/2)/chi_j) from the
-// Limber sums; g log10 P_bj goes to glp [B x n_ell x n_a] and, in a second pass
-// over the nodes, into the fixed-point tables gYi (and gMi for the cubic
-// z-spline; integer atomics, see above; they start at zero), with the walker's
-// grid step in gstep [B]; the node terms are contracted with the tangents of
-// shear_tangent_kernel into the direct gradient gdir [B x d] (fully written).
+// Limber sums; g log10 P_bj goes to glp [B x n_ell x n_a] and the walker's
+// fixed-point grid step to gstep [B] (limber_scatter_kernel then sums them
+// into the tables g Y, g M); the node terms are contracted with the tangents
+// of shear_tangent_kernel into the direct gradient gdir [B x d] (fully
+// written).
 template <class T, bool LINZ>
 __global__ __launch_bounds__(256) void limber_adjoint_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, int d, ShearGeom G,
