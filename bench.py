@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--settle-ms", type=float, default=100.0,
+                    help="before each form's warmup steps, run that form's calls back to back (untimed) for this "
+                         "long, so that the timed steps see the clocks of sustained work (0: off)")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--workload", default="cmb4x2500")
     ap.add_argument("--forms", default="bf16,bf16x3,fp32,fp64")
@@ -179,7 +182,20 @@ def main():
     forms = args.forms.split(",")
     res = {}
     traces = {}
+    settle = {}
     for prec in forms:
+        # the GPU's clocks fall within milliseconds of idling and take some
+        # tens of milliseconds of steady work to come back; a sampler keeps the
+        # GPU busy, so the timed steps follow a stretch of back-to-back calls
+        g.loglike(theta, prec, out=logl)             # first call: autotuning of the form
+        torch.cuda.synchronize()
+        t_s, n_s = time.perf_counter(), 0
+        while (time.perf_counter() - t_s) * 1e3 < args.settle_ms:
+            for _ in range(8):
+                g.loglike(theta, prec, out=logl)
+            n_s += 8
+            torch.cuda.synchronize()
+        settle[prec] = dict(calls=n_s, ms=round((time.perf_counter() - t_s) * 1e3, 1))
         for _ in range(args.warmup):
             g.loglike(theta, prec, out=logl)
         torch.cuda.synchronize()
@@ -235,6 +251,8 @@ def main():
         "bf16_evals_per_s": round(res["bf16"]["evals_per_s"], 1) if "bf16" in res else None,
         "kernels": {p: {k: [n, round(t / n * 1e3, 2)] for k, (n, t) in tr_.items()} for p, tr_ in traces.items()},
         "roofline": roofline,
+        "settle": dict(ms_requested=args.settle_ms, per_form=settle,
+                       note="untimed back-to-back calls of each form before its warmup steps"),
         "bf16_tiles": g.tuning_report(),
     }
     if "fp64" in traces and head != "fp64":

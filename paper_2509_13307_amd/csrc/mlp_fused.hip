@@ -167,9 +167,23 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     }
     if (CHI)
         for (int e = tid; e < R * NTILE; e += NT) csl[e] = 0.0;
+    // layer-1 weights of this thread's unit (see first_layer), requested
+    // before the barrier so that they arrive with the inputs
+    const int c1 = tid % H;
+    float w1[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w1[k] = k < n_in ? N.W1[c1 * n_in + k] : 0.0f;
+    const float b1 = N.b1[c1], be1 = N.be1[c1], ga1 = N.ga1[c1];
+    // chi^2 mode, one output group: whether the row's walker lies in the
+    // prior's support (the first threads, one row each), while the last
+    // threads bring in the inputs below
+    bool row_ok = true;
+    if (CHI && A.qg == 1 && tid < nvalid)
+        row_ok = in_support(A.theta_s + (r0 + tid) / rows_per_walker * A.ld_s, A.d, A.pk, A.pa, A.pb);
 
-    // ---- layer-1 inputs (normalised parameters) into LDS
-    for (int e = tid; e < R * n_in; e += NT) {
+    // ---- layer-1 inputs (normalised parameters) into LDS, element e by
+    // thread NT - 1 - e
+    for (int e = NT - 1 - tid; e < R * n_in; e += NT) {
         const int rr = e / n_in, k = e % n_in;
         const int64_t r = r0 + rr;
         float v = 0.0f;
@@ -185,22 +199,30 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
 
     // ---- layer 1 (FP32 VALU, the arithmetic of the layer-by-layer path).  NT
     // is a multiple of H: each thread keeps one unit c (weights in registers)
-    // for rows tid / H, tid / H + NT / H, ...
+    // for rows tid / H, tid / H + NT / H, ..., FU of them at a time, so that
+    // their LDS reads, sums and activations overlap (one row after the other
+    // would wait on each row's reads and exp in turn)
     auto first_layer = [&]() {
-        const int c = tid % H;
-        float w1[16];
+        constexpr int RS = NT / H, NR = R / RS, FU = NR < 8 ? NR : 8;
+        static_assert(R % RS == 0 && NR % FU == 0, "rows per thread");
+        const int c = c1, rr0 = tid / H;
+        for (int j0 = 0; j0 < NR; j0 += FU) {
+            float acc[FU];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) w1[k] = k < n_in ? N.W1[c * n_in + k] : 0.0f;
-        const float b1 = N.b1[c], be1 = N.be1[c], ga1 = N.ga1[c];
-        for (int rr = tid / H; rr < R; rr += NT / H) {
-            float acc = b1;
+            for (int j = 0; j < FU; ++j) acc[j] = b1;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (k < n_in) acc += w1[k] * xs[rr][k];
-            const float v = gated<float>(acc, be1, ga1);
-            const uint16_t hi = f2bf(v);
-            hs[rr * HS + c] = hi;
-            if (X3) hl[rr * HS + c] = bf16_lo(v, hi);
+                if (k < n_in)
+#pragma unroll
+                    for (int j = 0; j < FU; ++j) acc[j] += w1[k] * xs[rr0 + (j0 + j) * RS][k];
+#pragma unroll
+            for (int j = 0; j < FU; ++j) {
+                const int rr = rr0 + (j0 + j) * RS;
+                const float v = gated<float>(acc[j], be1, ga1);
+                const uint16_t hi = f2bf(v);
+                hs[rr * HS + c] = hi;
+                if (X3) hl[rr * HS + c] = bf16_lo(v, hi);
+            }
         }
     };
 
@@ -283,6 +305,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         }
     };
     float e0[CT], e1[CT], e2[CT];
+    double cd[CT], cv[CT];                 // chi^2 mode: data and weight of the wave's output units
     // start of segment v: the next segment's fragments (the stage P steps past
     // the last K step is in the next segment, or, after the last segment, the
     // last stage again) and the epilogue vectors, loaded while the K steps run
@@ -302,6 +325,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
             } else {
                 const int cc = min(c, N_out - 1);
                 e0[j] = bo[cc]; e1[j] = N.sigma[cc]; e2[j] = N.mu[cc];
+                if (CHI) { cd[j] = A.cdata[cc]; cv[j] = A.cw[cc]; }
             }
         }
     };
@@ -381,21 +405,33 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
         for (int j = 0; j < CT; ++j) {
             const int c = nb + j * 32 + (lane & 31);
             const bool live_c = c < N_out;
-            const int cc = min(c, N_out - 1);
             const float bb = e0[j], sg = e1[j], mu0 = e2[j];
-            const double dat = A.cdata[cc], cw = A.cw[cc];
+            const double dat = cd[j], cw = cv[j];
             const int tile = (wave * WC + j * 32) / 32;
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
                 for (int hf = 0; hf < 2; ++hf) {                // accumulator rows r = 8 hf .. 8 hf + 7
-                    double v[8];
+                    // the eight terms side by side: one uniform branch per
+                    // kind of term, and the dead units' terms (computed on
+                    // the last unit's data) dropped by a select, so that the
+                    // exponentials and FP64 products of the rows overlap
+                    float y[8];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        float y = mu0 + sg * (acc[i][j][8 * hf + k] + bb);
-                        if (is_log) y = exp10_of<float>(y);
-                        v[k] = live_c ? chi2_term(A.chi, (double)y, dat, cw) : 0.0;
+                    for (int k = 0; k < 8; ++k) y[k] = mu0 + sg * (acc[i][j][8 * hf + k] + bb);
+                    if (is_log)
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) y[k] = exp10_of<float>(y[k]);
+                    double v[8];
+                    if (A.chi == 1) {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) v[k] = chi2_term(1, (double)y[k], dat, cw);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) v[k] = chi2_term(2, (double)y[k], dat, cw);
                     }
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) v[k] = live_c ? v[k] : 0.0;
                     const double sum = tile_row_sums(v, lane);
                     if ((lane & 3) == 0) {
                         const int rr = 8 * hf + ((lane & 31) >> 2);
@@ -494,9 +530,7 @@ __global__ __launch_bounds__(2 * H / CT) void mlp_fused_kernel(
     if (A.qg == 1 && tid < nvalid) {
         double sum = csl[tid * NTILE];
         for (int tile = 1; tile < NTILE; ++tile) sum += csl[tid * NTILE + tile];
-        const int64_t w = (r0 + tid) / rows_per_walker;
-        const bool ok = in_support(A.theta_s + w * A.ld_s, A.d, A.pk, A.pa, A.pb);
-        A.logl[r0 + tid] = !ok ? -INFINITY : (A.chi == 1 ? -0.5 * sum + A.cst : A.cst - sum);
+        A.logl[r0 + tid] = !row_ok ? -INFINITY : (A.chi == 1 ? -0.5 * sum + A.cst : A.cst - sum);
     }
 }
 

@@ -303,9 +303,14 @@ __device__ __forceinline__ double prior_map(double x, int kind, double a, double
 // theta outside a uniform prior's [a, b] -> false (NaN compares false: kept)
 __device__ __forceinline__ bool in_support(const double* th, int d, const int* kind, const double* a,
                                            const double* b) {
+    // every load unconditional and the tests combined without short
+    // circuits, so that the loads of all parameters are in flight together
     bool ok = true;
-    for (int i = 0; i < d; ++i)
-        if (kind[i] == NS_PRIOR_UNIFORM && (th[i] < a[i] || th[i] > b[i])) ok = false;
+    for (int i = 0; i < d; ++i) {
+        const int k = kind[i];
+        const double t = th[i], lo = a[i], hi = b[i];
+        ok = ok & !((k == NS_PRIOR_UNIFORM) & ((t < lo) | (t > hi)));
+    }
     return ok;
 }
 

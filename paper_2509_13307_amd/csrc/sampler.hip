@@ -114,7 +114,7 @@ __global__ void slice_init_kernel(SliceState S, int64_t k, int64_t* iter_p, uint
 // written after the state machine has run, with compact slots taken by one
 // atomic per wave.  NORMAL: some prior is normal (its map needs erfinv, whose
 // FP64 form alone takes more than half the registers; without it the kernel
-// fits four waves per SIMD).
+// fits three waves per SIMD instead of one).
 template <int GS, bool NORMAL>
 __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_t k, int d,
                                                             const double* __restrict__ lstar_p,
@@ -135,29 +135,36 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
         S.ccount[next] = 0;
         S.active[next] = 0;
     }
-    if (S.active[prev] == 0) return;
-    const uint64_t iter = (uint64_t)*iter_p;
-    // the walker's state is requested first (groups past the last walker read
-    // walker k - 1 and take no part); the direction factor goes to LDS
-    // meanwhile, so that the row products of a new direction read LDS
-    // instead of waiting on one global load per column
+    // the walker's state is requested first, together with the flag that says
+    // whether the round has work (groups past the last walker read walker
+    // k - 1 and take no part); the direction factor goes to LDS meanwhile, so
+    // that the row products of a new direction read LDS instead of waiting on
+    // one global load per column
     const bool live = w < k;
     const int64_t wr = live ? w : k - 1;
     const bool act = lg < d;
+    const int busy_prev = S.active[prev];
+    const uint64_t iter = (uint64_t)*iter_p;
     const double lstar = *lstar_p;
     int st = S.st[wr], step = S.step[wr], q = S.q[wr], ne = S.ne[wr], ne2 = S.ne2[wr];
     int pend = S.pend[wr], npl = S.npl[wr], npr = S.npr[wr];
     int nev = S.n_evals[wr], nst = S.n_stalls[wr];
     double tl = S.tl[wr], tr = S.tr[wr], logl = S.logl[wr];
     double ui = act ? S.u[wr * d + lg] : 0.0, vi = act ? S.v[wr * d + lg] : 0.0;
+    if (busy_prev == 0) return;
     __shared__ double Ls[MAX_DIM * MAX_DIM];
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) Ls[e] = L[e];
-    __syncthreads();
     if (!live) {                        // walker k - 1's state was read: none of it is this group's
         st = ST_DONE;
         pend = -1;
         npl = npr = 0;
     }
+    // last round's results for this walker (at most 2 spec <= GS of them):
+    // lane i of the group loads result i, all in one load
+    static_assert(GS >= 2 * MAX_SPEC, "a group holds a walker's pending results");
+    const double llv = (pend >= 0 && lg < npl + npr) ? S.llc[pend + lg] : 0.0;
+    auto ll_at = [&](int i) { return __shfl(llv, gb + i, 64); };
+    __syncthreads();
     const uint64_t gmask = GS == 64 ? ~0ull : (((1ull << GS) - 1) << gb);
     bool moved = false;
     // the point at t along the direction lies in the unit cube (outside it
@@ -166,21 +173,33 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
         const double xi = __dadd_rn(ui, __dmul_rn(t, vi));
         return (__ballot(act && !((xi >= 0.0) && (xi <= 1.0))) & gmask) == 0;
     };
+    // draws of the current step, GS at a time: lane i of the group computes
+    // draw qb + i (one Philox latency for the batch instead of one per draw);
+    // a draw outside the batch starts a new one at that draw
+    double ub = 0.0;
+    int qb = -(1 << 30);
+    auto draw = [&](int qq) {
+        if (qq < qb || qq >= qb + GS) {
+            qb = qq;
+            ub = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)(qq + lg));
+        }
+        return __shfl(ub, gb + (qq - qb), 64);
+    };
     // shrink point from the bracket and draw qq
     auto shrink_point = [&](double a, double b, int qq) {
-        const double U = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)qq);
+        const double U = draw(qq);
         return __dadd_rn(a, __dmul_rn(U, __dsub_rn(b, a)));
     };
     // last round's evaluations, in the serial order
     if (pend >= 0) {
         if (st == ST_OUT) {
             for (int i = 0; i < npl; ++i) {            // left end at t_L, t_L - 1, ...
-                const double ll = S.llc[pend + i];
+                const double ll = ll_at(i);
                 nev += 1;
                 if (ll > lstar) { tl -= 1.0; ne += 1; } else { ne = -1; break; }
             }
             for (int i = 0; i < npr; ++i) {            // right end at t_R, t_R + 1, ...
-                const double ll = S.llc[pend + npl + i];
+                const double ll = ll_at(npl + i);
                 nev += 1;
                 if (ll > lstar) { tr += 1.0; ne2 += 1; } else { ne2 = -1; break; }
             }
@@ -192,7 +211,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
                 const double t = shrink_point(tl, tr, q);
                 ++q;
                 if (inbox(t)) {
-                    const double ll = S.llc[pend + kk];
+                    const double ll = ll_at(kk);
                     ++kk;
                     nev += 1;
                     if (ll > lstar) {
@@ -222,19 +241,21 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
         if (st == ST_NEWSTEP) {
             if (step >= n_inner) { st = ST_DONE; break; }
             const int s = ++step;
-            double z = 0.0;
-            if (act) {
-                double u1, u2;
-                philox_uniform_pair(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)lg, u1, u2);
-                z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
-            }
+            qb = -(1 << 30);                // the draws of the step before are gone
+            // lane i < d: the pair of draws 2i, 2i + 1 for Box-Muller; lane d
+            // (when the group has one more lane) the pair 2d, 2d + 1, whose
+            // first member is the offset r
+            double z = 0.0, u1 = 0.0, u2 = 0.0;
+            if (lg <= d) philox_uniform_pair(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)lg, u1, u2);
+            if (act) z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
             double acc = 0.0;
             for (int j = 0; j < d; ++j) {
                 const double zj = __shfl(z, gb + j, 64);
                 if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
             }
             vi = act ? acc : 0.0;
-            const double r = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)d);
+            const double r = d < GS ? __shfl(u1, gb + d, 64)
+                                    : philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)d);
             tl = -r;
             tr = 1.0 - r;
             q = 2 * d + 1;
