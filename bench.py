@@ -56,6 +56,27 @@ def measured_traffic(dom, B, workload):
     return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
 
 
+def measured_mfma_busy(dom, B, workload):
+    """MFMA-busy fraction and clock of kernel `dom` from the committed
+    rocprofv3 counter summary (SQ_VALU_MFMA_BUSY_CYCLES over the SIMDs' active
+    cycles, GRBM_GUI_ACTIVE per XCD over the launch time); None when no summary
+    exists for this workload and batch or the kernel sources changed since."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"{dom}_mfma_busy.json")
+    key = next((k for k in KERNEL_SOURCES if dom.startswith(k)), None)
+    if key is None or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[key]:
+        h.update(open(os.path.join(here, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest() or rec.get("batch") != B or rec.get("workload") != workload:
+        return None
+    return dict(frac=round(rec["mfma_busy_frac"], 4), clock_ghz=round(rec["clock_ghz"], 3),
+                launch_us=round(rec["launch_s_median"] * 1e6, 2), source="profiles/" + os.path.basename(path))
+
+
 def roofline_of(dom, avg_s, prec, m, B, workload):
     """Roofline entry of kernel `dom` from its average launch time: algorithmic
     work of one launch over the form's published MI355X peak."""
@@ -90,6 +111,9 @@ def roofline_of(dom, avg_s, prec, m, B, workload):
              work_per_launch=work)
     if issued is not None:
         r["mfma_issued_frac"] = round(issued / avg_s / 1e12 / peak, 4)
+        busy = measured_mfma_busy(dom, B, workload)
+        if busy is not None:
+            r["mfma_busy_profiled"] = busy
     return r
 
 
