@@ -164,21 +164,62 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     static_assert(GS >= 2 * MAX_SPEC, "a group holds a walker's pending results");
     const double llv = (pend >= 0 && lg < npl + npr) ? S.llc[pend + lg] : 0.0;
     auto ll_at = [&](int i) { return __shfl(llv, gb + i, 64); };
+    // This round's random numbers, one Philox4x64 block per lane of the
+    // group, computed once for the whole wave (instead of on each state's
+    // path in turn) and kept in LDS (pw: the block of the thread's lane, as
+    // uniforms): lanes [0, nd) hold blocks 0 .. nd - 1 of step s0 + 1 (s0 the
+    // walker's step at the start of the round), whose draws 0 .. 2d are the
+    // next direction's Box-Muller pairs and offset; lanes [nd, GS) hold the
+    // blocks of step s0 from draw q's block on, the shrink draws that follow.
+    // A draw outside these comes from draw()'s own batches.
+    __shared__ double pw[256][4];
+    const int nd = (2 * d + 4) >> 2;
+    const int step0 = step, qb0 = (q >> 2) << 2, qend0 = qb0 + 4 * (GS - nd);
+    const int wl0 = threadIdx.x - lane + gb;        // this group's lane 0 in pw
+    {
+        const bool dlane = lg < nd;
+        const u64x4 b = philox4x64(dlane ? (uint64_t)lg : (uint64_t)((q >> 2) + lg - nd), (uint64_t)w,
+                                   (uint64_t)(dlane ? step + 1 : step), iter, seed, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pw[threadIdx.x][j] = u01(b.x[j]);
+    }
     __syncthreads();
     const uint64_t gmask = GS == 64 ? ~0ull : (((1ull << GS) - 1) << gb);
     bool moved = false;
+    // the direction of step s0 + 1, v' = L z (z by Box-Muller from the draws
+    // above), and its offset r', formed once for the wave here rather than on
+    // the path of the walkers that begin a step this round
+    double vnext = 0.0;
+    {
+        double z = 0.0;
+        if (act) {
+            const double u1 = pw[wl0 + (lg >> 1)][2 * (lg & 1)], u2 = pw[wl0 + (lg >> 1)][2 * (lg & 1) + 1];
+            z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
+        }
+        double acc = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const double zj = __shfl(z, gb + j, 64);
+            if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
+        }
+        vnext = act ? acc : 0.0;
+    }
+    const double rnext = pw[wl0 + (d >> 1)][2 * (d & 1)];
     // the point at t along the direction lies in the unit cube (outside it
     // needs no evaluation: it is outside the constraint)
     auto inbox = [&](double t) {
         const double xi = __dadd_rn(ui, __dmul_rn(t, vi));
         return (__ballot(act && !((xi >= 0.0) && (xi <= 1.0))) & gmask) == 0;
     };
-    // draws of the current step, GS at a time: lane i of the group computes
-    // draw qb + i (one Philox latency for the batch instead of one per draw);
-    // a draw outside the batch starts a new one at that draw
+    // draws of the current step: the precomputed ones, else GS at a time
+    // (lane i of the group computes draw qb + i; a draw outside the batch
+    // starts a new one at that draw)
     double ub = 0.0;
     int qb = -(1 << 30);
     auto draw = [&](int qq) {
+        if (step == step0 && qq >= qb0 && qq < qend0) {
+            const int o = qq - qb0;
+            return pw[wl0 + nd + (o >> 2)][o & 3];
+        }
         if (qq < qb || qq >= qb + GS) {
             qb = qq;
             ub = philox_uniform(seed, 0, (uint64_t)w, (uint64_t)step, iter, (uint64_t)(qq + lg));
@@ -242,20 +283,26 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             if (step >= n_inner) { st = ST_DONE; break; }
             const int s = ++step;
             qb = -(1 << 30);                // the draws of the step before are gone
-            // lane i < d: the pair of draws 2i, 2i + 1 for Box-Muller; lane d
-            // (when the group has one more lane) the pair 2d, 2d + 1, whose
-            // first member is the offset r
-            double z = 0.0, u1 = 0.0, u2 = 0.0;
-            if (lg <= d) philox_uniform_pair(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)lg, u1, u2);
-            if (act) z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
-            double acc = 0.0;
-            for (int j = 0; j < d; ++j) {
-                const double zj = __shfl(z, gb + j, 64);
-                if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
+            double r;
+            if (s == step0 + 1) {
+                vi = vnext;
+                r = rnext;
+            } else {
+                // a second new step in one round: lane i < d draws the pair
+                // 2i, 2i + 1 for Box-Muller, lane d (when the group has one
+                // more lane) the pair 2d, 2d + 1, whose first member is r
+                double z = 0.0, u1 = 0.0, u2 = 0.0;
+                if (lg <= d) philox_uniform_pair(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)lg, u1, u2);
+                r = d < GS ? __shfl(u1, gb + d, 64)
+                           : philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)d);
+                if (act) z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
+                double acc = 0.0;
+                for (int j = 0; j < d; ++j) {
+                    const double zj = __shfl(z, gb + j, 64);
+                    if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
+                }
+                vi = act ? acc : 0.0;
             }
-            vi = act ? acc : 0.0;
-            const double r = d < GS ? __shfl(u1, gb + d, 64)
-                                    : philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)d);
             tl = -r;
             tr = 1.0 - r;
             q = 2 * d + 1;
