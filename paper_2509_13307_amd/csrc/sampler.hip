@@ -174,11 +174,14 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     // A draw outside these comes from draw()'s own batches.
     __shared__ double pw[256][4];
     const int nd = (2 * d + 4) >> 2;
-    const int step0 = step, qb0 = (q >> 2) << 2, qend0 = qb0 + 4 * (GS - nd);
+    // q is only meaningful once the walker has begun a step (a walker between
+    // steps has none; the initial state leaves it unset)
+    const int qs = (st == ST_OUT || st == ST_SHRINK) ? q : 0;
+    const int step0 = step, qb0 = (qs >> 2) << 2, qend0 = qb0 + 4 * (GS - nd);
     const int wl0 = threadIdx.x - lane + gb;        // this group's lane 0 in pw
     {
         const bool dlane = lg < nd;
-        const u64x4 b = philox4x64(dlane ? (uint64_t)lg : (uint64_t)((q >> 2) + lg - nd), (uint64_t)w,
+        const u64x4 b = philox4x64(dlane ? (uint64_t)lg : (uint64_t)((qs >> 2) + lg - nd), (uint64_t)w,
                                    (uint64_t)(dlane ? step + 1 : step), iter, seed, 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) pw[threadIdx.x][j] = u01(b.x[j]);
