@@ -30,64 +30,97 @@ struct SeedNet {
     int is_log;
 };
 
-template <class T>
+// ROWS walkers per workgroup: the data, whitening blocks and output scales of
+// a multipole are loaded once for all of them (one walker per workgroup read
+// them again for every walker).  Each walker's chi^2 is summed per thread over
+// l = t, t + 256, ..., then over the waves in wave order.
+template <class T, int ROWS>
 __global__ __launch_bounds__(256) void cmb_seed_kernel(
     const double* __restrict__ theta, int64_t ld, int64_t B, int d, const int* __restrict__ pk,
     const double* __restrict__ pa, const double* __restrict__ pb, const T* __restrict__ mvec, int kind, int n,
     int n_ell, const double* __restrict__ data, const double* __restrict__ isig, const double* __restrict__ linv,
     const double* __restrict__ isig_pp, double cst, SeedNet s0, SeedNet s1, SeedNet s2, SeedNet s3, int n_pad,
     size_t gstride, T* __restrict__ delta, double* __restrict__ logl) {
-    __shared__ double red[4];
-    const int64_t row = blockIdx.x;
-    if (row >= B) return;
-    const bool ok = in_support_row(theta + row * ld, d, pk, pa, pb);
-    const T* mv = mvec + row * (int64_t)n;
+    __shared__ double red[ROWS][4];
+    __shared__ int okr[ROWS];
+    const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+    if (r0 >= B) return;
+    const int nr = (int)min<int64_t>(ROWS, B - r0);
+    if (threadIdx.x < ROWS)
+        okr[threadIdx.x] = threadIdx.x < nr && in_support_row(theta + (r0 + threadIdx.x) * ld, d, pk, pa, pb);
+    __syncthreads();
     const SeedNet sn[4] = {s0, s1, s2, s3};
-    double chi2 = 0.0;
-    auto put = [&](int g, int i, double gc) {
-        const double C = (double)mv[(int64_t)g * (kind == NS_MODEL_CMB_BLOCK ? n_ell : 0) + i];
-        double dv = gc * sn[g].sigma_out[i] * (sn[g].is_log ? C * 2.302585092994045684 : 1.0);
-        delta[g * gstride + row * n_pad + i] = ok ? (T)dv : T(0);
+    double chi2[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) chi2[r] = 0.0;
+    // d logL / d o of output i of network g for walker r from d logL / d C
+    auto put = [&](int r, int g, int i, int64_t moff, double gc, double so) {
+        const int64_t row = r0 + r;
+        const double C = (double)mvec[row * (int64_t)n + moff];
+        const double dv = gc * so * (sn[g].is_log ? C * 2.302585092994045684 : 1.0);
+        delta[g * gstride + row * n_pad + i] = okr[r] ? (T)dv : T(0);
     };
     if (kind == NS_MODEL_CMB_DIAG) {
         for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
             if (i < n) {
-                const double r = data[i] - (double)mv[i];
-                const double w = r * isig[i];
-                chi2 += w * w;
-                put(0, i, w * isig[i]);
+                const double di = data[i], is = isig[i], so = sn[0].sigma_out[i];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    if (r >= nr) break;
+                    const double rr = di - (double)mvec[(r0 + r) * (int64_t)n + i];
+                    const double w = rr * is;
+                    chi2[r] += w * w;
+                    put(r, 0, i, i, w * is, so);
+                }
             } else {
-                delta[row * n_pad + i] = T(0);
+                for (int r = 0; r < nr; ++r) delta[(r0 + r) * n_pad + i] = T(0);
             }
         }
     } else {
         for (int l = threadIdx.x; l < n_pad; l += blockDim.x) {
             if (l < n_ell) {
                 const double* Lq = linv + 6 * (int64_t)l;
-                const double rtt = data[l] - (double)mv[l], rte = data[n_ell + l] - (double)mv[n_ell + l];
-                const double ree = data[2 * n_ell + l] - (double)mv[2 * n_ell + l];
-                const double rpp = data[3 * n_ell + l] - (double)mv[3 * n_ell + l];
-                const double y0 = Lq[0] * rtt, y1 = Lq[1] * rtt + Lq[2] * rte;
-                const double y2 = Lq[3] * rtt + Lq[4] * rte + Lq[5] * ree;
-                const double wp = rpp * isig_pp[l];
-                chi2 += y0 * y0 + y1 * y1 + y2 * y2 + wp * wp;
-                put(0, l, Lq[0] * y0 + Lq[1] * y1 + Lq[3] * y2);
-                put(1, l, Lq[2] * y1 + Lq[4] * y2);
-                put(2, l, Lq[5] * y2);
-                put(3, l, wp * isig_pp[l]);
+                const double q0 = Lq[0], q1 = Lq[1], q2 = Lq[2], q3 = Lq[3], q4 = Lq[4], q5 = Lq[5];
+                const double dtt = data[l], dte = data[n_ell + l], dee = data[2 * n_ell + l];
+                const double dpp = data[3 * n_ell + l], ip = isig_pp[l];
+                const double so0 = sn[0].sigma_out[l], so1 = sn[1].sigma_out[l], so2 = sn[2].sigma_out[l];
+                const double so3 = sn[3].sigma_out[l];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    if (r >= nr) break;
+                    const T* mv = mvec + (r0 + r) * (int64_t)n;
+                    const double rtt = dtt - (double)mv[l], rte = dte - (double)mv[n_ell + l];
+                    const double ree = dee - (double)mv[2 * n_ell + l];
+                    const double rpp = dpp - (double)mv[3 * n_ell + l];
+                    const double y0 = q0 * rtt, y1 = q1 * rtt + q2 * rte;
+                    const double y2 = q3 * rtt + q4 * rte + q5 * ree;
+                    const double wp = rpp * ip;
+                    chi2[r] += y0 * y0 + y1 * y1 + y2 * y2 + wp * wp;
+                    put(r, 0, l, l, q0 * y0 + q1 * y1 + q3 * y2, so0);
+                    put(r, 1, l, n_ell + l, q2 * y1 + q4 * y2, so1);
+                    put(r, 2, l, 2 * n_ell + l, q5 * y2, so2);
+                    put(r, 3, l, 3 * n_ell + l, wp * ip, so3);
+                }
             } else {
-                for (int g = 0; g < 4; ++g) delta[g * gstride + row * n_pad + l] = T(0);
+                for (int r = 0; r < nr; ++r)
+                    for (int g = 0; g < 4; ++g) delta[g * gstride + (r0 + r) * n_pad + l] = T(0);
             }
         }
     }
-    chi2 = wave_sum(chi2);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = chi2;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const double v = wave_sum(chi2[r]);
+        if (lane == 0) red[r][wid] = v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double c2 = red[0] + red[1] + red[2] + red[3];
-        logl[row] = ok ? -0.5 * c2 + cst : -INFINITY;
+    if (threadIdx.x < nr) {
+        const double c2 = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        logl[r0 + threadIdx.x] = okr[threadIdx.x] ? -0.5 * c2 + cst : -INFINITY;
     }
 }
+
+constexpr int SEED_ROWS = 8;
 
 // Cosmic-variance seeds: y = log10 C_l, logL = c - sum (k/2)(ln 10 y + Ch 10^-y),
 // d logL / d y_l = -(k/2) ln 10 (1 - Ch_l / C_l); delta = that times sigma_out.
@@ -226,13 +259,15 @@ void loglike_grad_batch(ns_model* m, const double* theta, int64_t ld, int64_t B,
         {
             TraceScope ts(m, s, "adj_seed_chi2");
             if (f64)
-                hipLaunchKernelGGL(cmb_seed_kernel<double>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, m->d,
+                hipLaunchKernelGGL((cmb_seed_kernel<double, SEED_ROWS>), dim3((unsigned)((B + SEED_ROWS - 1) / SEED_ROWS)),
+                                   dim3(256), 0, s, theta, ld, B, m->d,
                                    pk, pa, pb, m->ws_out.as<double>(), m->kind, (int)n, m->n_ell_cmb,
                                    m->data.as<double>(), m->inv_sigma.as<double>(), m->blk_linv.as<double>(),
                                    m->inv_sigma_pp.as<double>(), m->logl_const, sn[0], sn[1], sn[2], sn[3], n_pad,
                                    gstride, m->ws_gact[0].as<double>(), logl);
             else
-                hipLaunchKernelGGL(cmb_seed_kernel<float>, dim3((unsigned)B), dim3(256), 0, s, theta, ld, B, m->d,
+                hipLaunchKernelGGL((cmb_seed_kernel<float, SEED_ROWS>), dim3((unsigned)((B + SEED_ROWS - 1) / SEED_ROWS)),
+                                   dim3(256), 0, s, theta, ld, B, m->d,
                                    pk, pa, pb, m->ws_out.as<float>(), m->kind, (int)n, m->n_ell_cmb,
                                    m->data.as<double>(), m->inv_sigma.as<double>(), m->blk_linv.as<double>(),
                                    m->inv_sigma_pp.as<double>(), m->logl_const, sn[0], sn[1], sn[2], sn[3], n_pad,
