@@ -150,6 +150,14 @@ __global__ __launch_bounds__(256, 2) void mlp_f64_kernel(const double* __restric
     if (r0 >= nrows) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_in = A.n_in, N_out = A.N_out;
+    // chi^2 mode: whether each row's walker lies in the prior's support, found
+    // now (the first threads, one row each) so that its loads overlap the
+    // inputs' instead of closing the kernel
+    __shared__ int okr[MF_R];
+    if (CHI2 && tid < MF_R) {
+        const int64_t row = r0 + tid;
+        okr[tid] = row < nrows && in_support(theta + row * ld, A.d, A.pk, A.pa, A.pb);
+    }
     for (int e = tid; e < MF_R * 16; e += 256) {
         const int rr = e / 16, k = e % 16;
         const int64_t r = r0 + rr;
@@ -163,21 +171,25 @@ __global__ __launch_bounds__(256, 2) void mlp_f64_kernel(const double* __restric
     }
     __syncthreads();
     {
-        const int c = tid % H;
+        // each thread's unit c for its rows tid / H, tid / H + 256 / H, ...,
+        // all of them side by side (one row after the other would wait on
+        // each row's exponential and division in turn)
+        constexpr int RS = 256 / H, NR = MF_R / RS;
+        const int c = tid % H, rr0 = tid / H;
         double w1[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) w1[k] = k < n_in ? A.W1[c * n_in + k] : 0.0;
         const double b1 = A.b1[c], be1 = A.be1[c], ga1 = A.ga1[c];
-        for (int rr = tid / H; rr < MF_R; rr += 256 / H) {
-            double x[16];                              // the row's inputs in registers first
+        double acc[NR];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) x[k] = xs[rr][k];
-            double acc = b1;
+        for (int j = 0; j < NR; ++j) acc[j] = b1;
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k < n_in) acc += w1[k] * x[k];
-            act[rr * LDA + c] = gated<double>(acc, be1, ga1);
-        }
+        for (int k = 0; k < 16; ++k)
+            if (k < n_in)
+#pragma unroll
+                for (int j = 0; j < NR; ++j) acc[j] += w1[k] * xs[rr0 + j * RS][k];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) act[(rr0 + j * RS) * LDA + c] = gated<double>(acc[j], be1, ga1);
     }
     __syncthreads();
     size_t foff = 0;
@@ -191,21 +203,29 @@ __global__ __launch_bounds__(256, 2) void mlp_f64_kernel(const double* __restric
         else mf_layer<4, H, CHI2>(act, ys, A, Wl, l, hid, NT, r0, nrows, wave, lane);
     }
     if (CHI2) {
+        // wave w sums rows w, w + 4, w + 8, w + 12, side by side (each row's
+        // terms in the order of the staged chi^2 kernel, then a wave sum)
         __syncthreads();
-        for (int rr = wave; rr < MF_R; rr += 4) {
-            const int64_t row = r0 + rr;
-            if (row >= nrows) break;
-            double s = 0.0;
-            for (int i = lane; i < N_out; i += 64) {
-                const double r = (A.data[i] - ys[rr * MF_MAXOUT + i]) * A.isig[i];
-                s = fma(r, r, s);
-            }
-            s = wave_sum(s);
-            if (lane == 0) {
-                const bool ok = in_support(theta + row * ld, A.d, A.pk, A.pa, A.pb);
-                A.logl[row] = ok ? -0.5 * s + A.cst : -INFINITY;
+        constexpr int RW = MF_R / 4;
+        double s[RW];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) s[j] = 0.0;
+        for (int i = lane; i < N_out; i += 64) {
+            const double di = A.data[i], wi = A.isig[i];
+#pragma unroll
+            for (int j = 0; j < RW; ++j) {
+                const double r = (di - ys[(wave + 4 * j) * MF_MAXOUT + i]) * wi;
+                s[j] = fma(r, r, s[j]);
             }
         }
+#pragma unroll
+        for (int j = 0; j < RW; ++j) s[j] = wave_sum(s[j]);
+        if (lane == 0)
+#pragma unroll
+            for (int j = 0; j < RW; ++j) {
+                const int rr = wave + 4 * j;
+                if (r0 + rr < nrows) A.logl[r0 + rr] = okr[rr] ? -0.5 * s[j] + A.cst : -INFINITY;
+            }
     }
 }
 
