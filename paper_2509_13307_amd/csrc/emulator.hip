@@ -422,44 +422,51 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Group<Epi> G, int64_t lda
 // ------------------------------------------------------ MFMA GEMM, FP64
 // v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
 // register r of lane l returns D[l / 16 + 4 r][l % 16].
-// WG tile 64 x 64, four waves in 2 x 2, each wave 32 x 32 = 2 x 2 tiles of
-// 16 x 16; BK = 32, LDS row stride 33 doubles.  The next K block's tiles are
-// fetched into registers while the current one feeds the MFMAs (the K order of
-// every accumulator is unchanged: k = 0, 4, 8, ...).  Bounded to 128 registers
-// so that four waves share each SIMD (left free the compiler takes 164 and
-// three fit; four hide the barrier and LDS latency better, 4-7% faster).
+// WG tile BM x 64 (BM = 64: four waves in 2 x 2, each 32 x 32 = 2 x 2 tiles of
+// 16 x 16; BM = 32, for grids too small to fill the GPU: four waves in 1 x 4,
+// each 32 x 16); BK = 32, LDS row stride 33 doubles.  The next K block's tiles
+// are fetched into registers while the current one feeds the MFMAs (the K
+// order of every accumulator is the same for both tiles: k = 0, 4, 8, ...).
+// Bounded to 128 registers so that four waves share each SIMD (left free the
+// compiler takes 164 and three fit; four hide the barrier and LDS latency
+// better, 4-7% faster).
 constexpr int GD_M = 64, GD_N = 64, GD_K = 32, GD_LDS = GD_K + 1;
 
-template <class Epi>
+template <class Epi, int BM>
 __global__ __launch_bounds__(256, 4) void gemm_f64_kernel(Group<Epi> G, int64_t lda, int64_t M, int N, int K,
                                                        const int* __restrict__ count, int rows_per_count) {
-    __shared__ double As[GD_M * GD_LDS];
+    constexpr int WN = 4 / (BM / 32);                  // waves across N
+    constexpr int TN = GD_N / 16 / WN;                 // 16-wide tiles per wave across N
+    constexpr int LA = BM * GD_K / 256;                // A elements per thread and K block
+    __shared__ double As[BM * GD_LDS];
     __shared__ double Bs[GD_N * GD_LDS];
     const int g = blockIdx.z;
     const double* A = static_cast<const double*>(G.A[g]);
     const double* W = static_cast<const double*>(G.W[g]);
     const Epi& epi = G.epi[g];
     if (count) M = min<int64_t>(M, (int64_t)(*count) * rows_per_count);
-    const int64_t m0 = (int64_t)blockIdx.y * GD_M;
+    const int64_t m0 = (int64_t)blockIdx.y * BM;
     const int n0 = blockIdx.x * GD_N;
     if (m0 >= M) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    f64x4_t acc[2][2];
+    const int wr = wave / WN, wc = wave % WN;
+    f64x4_t acc[2][TN];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
-    double ra[8], rb[8];
+    double ra[LA], rb[8];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int it = 0; it < 8; ++it) {
-            const int c = tid + it * 256;          // 64 rows x 32 k
+            const int c = tid + it * 256;          // rows x 32 k
             const int row = c >> 5, kk = c & 31;
-            const int64_t gr = m0 + row;
-            ra[it] = (gr < M && k0 + kk < K) ? A[gr * lda + k0 + kk] : 0.0;
+            if (it < LA) {
+                const int64_t gr = m0 + row;
+                ra[it] = (gr < M && k0 + kk < K) ? A[gr * lda + k0 + kk] : 0.0;
+            }
             const int gn = n0 + row;
             rb[it] = (gn < N && k0 + kk < K) ? W[(int64_t)gn * K + k0 + kk] : 0.0;
         }
@@ -468,7 +475,7 @@ __global__ __launch_bounds__(256, 4) void gemm_f64_kernel(Group<Epi> G, int64_t 
 #pragma unroll
         for (int it = 0; it < 8; ++it) {
             const int c = tid + it * 256;
-            As[(c >> 5) * GD_LDS + (c & 31)] = ra[it];
+            if (it < LA) As[(c >> 5) * GD_LDS + (c & 31)] = ra[it];
             Bs[(c >> 5) * GD_LDS + (c & 31)] = rb[it];
         }
     };
@@ -480,22 +487,22 @@ __global__ __launch_bounds__(256, 4) void gemm_f64_kernel(Group<Epi> G, int64_t 
 #pragma unroll
         for (int kq = 0; kq < GD_K; kq += 4) {
             const int koff = kq + (lane >> 4);
-            double a[2], b[2];
+            double a[2], b[TN];
 #pragma unroll
             for (int i = 0; i < 2; ++i) a[i] = As[(wr * 32 + i * 16 + (lane & 15)) * GD_LDS + koff];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[(wc * 32 + j * 16 + (lane & 15)) * GD_LDS + koff];
+            for (int j = 0; j < TN; ++j) b[j] = Bs[(wc * 16 * TN + j * 16 + (lane & 15)) * GD_LDS + koff];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int c = n0 + wc * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < TN; ++j) {
+        const int c = n0 + wc * 16 * TN + j * 16 + (lane & 15);
         if (c >= N) continue;
         const auto p = epi.col(c);
 #pragma unroll
@@ -603,6 +610,32 @@ static inline dim3 grid3(int64_t M, int N, int bm, int bn, int G) {
     return dim3((unsigned)((N + bn - 1) / bn), (unsigned)((M + bm - 1) / bm), (unsigned)G);
 }
 
+// Compute units of device dev (queried once per device).
+static int device_cus(int dev) {
+    static int cus[64] = {0};
+    if (dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+// One FP64 GEMM launch: 64-row tiles, or 32-row tiles when the 64-row grid
+// has fewer than two workgroups per CU (a sampler round's few thousand rows);
+// the two give identical results (gemm_f64_kernel).
+template <class Epi>
+static void launch_gemm_f64(const ns_model* m, const Group<Epi>& P, int64_t lda, int64_t rows, int N, int K, int G,
+                            const int* count, int rpw, hipStream_t s) {
+    const dim3 gr = grid3(rows, N, GD_M, GD_N, G);
+    if ((int64_t)gr.x * gr.y * gr.z < 2 * (int64_t)device_cus(m->device))
+        hipLaunchKernelGGL((gemm_f64_kernel<Epi, 32>), grid3(rows, N, 32, GD_N, G), dim3(256), 0, s, P, lda, rows, N,
+                           K, count, rpw);
+    else
+        hipLaunchKernelGGL((gemm_f64_kernel<Epi, 64>), gr, dim3(256), 0, s, P, lda, rows, N, K, count, rpw);
+}
+
 template <class T, class OutT>
 static void launch_first(ns_model* m, const int* nets, int G, const double* theta, int64_t ld, int64_t rows,
                          int rpw, OutT* act0, size_t act_stride, T* tsave, size_t save_stride, const int* count,
@@ -697,7 +730,6 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
         auto A_of = [&](int g) { return (const void*)(A0 + g * act_stride * act_elem); };
         auto D_of = [&](int g) { return last ? outs[g] : (void*)(D0 + g * act_stride * act_elem); };
         if (prec == NS_FP64) {
-            const dim3 gr = grid3(rows, N, GD_M, GD_N, G);
             if (!last) {
                 Group<EpiHidden<double, double>> P{};
                 for (int g = 0; g < G; ++g) {
@@ -706,8 +738,7 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
                     P.epi[g] = {ly.b64.as<double>(), ly.beta64.as<double>(), ly.gamma64.as<double>(),
                                 (double*)D_of(g), (int64_t)N, (double*)tslot(g, l)};
                 }
-                hipLaunchKernelGGL((gemm_f64_kernel<EpiHidden<double, double>>), gr, dim3(256), 0, s, P, (int64_t)K,
-                                   rows, N, K, count, rpw);
+                launch_gemm_f64(m, P, (int64_t)K, rows, N, K, G, count, rpw, s);
             } else {
                 Group<EpiOut<double>> P{};
                 for (int g = 0; g < G; ++g) {
@@ -717,8 +748,7 @@ void emulator_forward(ns_model* m, const int* nets, int G, const double* theta, 
                     P.epi[g] = {ly.b64.as<double>(), net.out_mu64.as<double>(), net.out_sigma64.as<double>(),
                                 (double*)D_of(g), ldo, net.out_mu_rows, N, is_log[g]};
                 }
-                hipLaunchKernelGGL((gemm_f64_kernel<EpiOut<double>>), gr, dim3(256), 0, s, P, (int64_t)K, rows, N,
-                                   K, count, rpw);
+                launch_gemm_f64(m, P, (int64_t)K, rows, N, K, G, count, rpw, s);
             }
         } else if (prec == NS_FP32) {
             NS_CHECK(K % GF_K == 0, NS_E_UNSUPPORTED, "FP32 MFMA layers need K % 32 == 0");
@@ -856,8 +886,7 @@ static void backward_impl(ns_model* m, const int* nets, int G, int64_t B, const 
                         (int64_t)Nout};
         }
         if constexpr (sizeof(T) == 8)
-            hipLaunchKernelGGL((gemm_f64_kernel<EpiBack<T>>), grid3(rows, Nout, GD_M, GD_N, G), dim3(256), 0, s, P,
-                               (int64_t)Kred, rows, Nout, Kred, count, rpw);
+            launch_gemm_f64(m, P, (int64_t)Kred, rows, Nout, Kred, G, count, rpw, s);
         else
             hipLaunchKernelGGL((gemm_f32_kernel<EpiBack<T>>), grid3(rows, Nout, GB_M, GB_N, G), dim3(256), 0, s, P,
                                (int64_t)Kred, rows, Nout, Kred, count, rpw);
