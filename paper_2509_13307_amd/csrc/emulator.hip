@@ -60,6 +60,21 @@ __global__ __launch_bounds__(256) void first_layer_kernel(
     const int64_t r0 = (int64_t)blockIdx.x * FL_ROWS;
     if (r0 >= nrows) return;
     const int tid = threadIdx.x;
+    const int groups = n_out / CPT;
+    const int rpi = 256 / groups;                      // rows per pass of the workgroup
+    // this thread's CPT units: weights requested before the barrier, so that
+    // they arrive with the inputs
+    const int c0 = (tid % groups) * CPT;
+    T wr[CPT][NI], bb[CPT], be[CPT], ga[CPT];
+    const T* W = P.W[g];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        bb[j] = P.b[g][c0 + j];
+        be[j] = P.beta[g][c0 + j];
+        ga[j] = P.gamma[g][c0 + j];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) wr[j][k] = k < n_in ? W[(c0 + j) * n_in + k] : T(0);
+    }
     for (int e = tid; e < FL_ROWS * NI; e += 256) {
         const int rr = e / NI, k = e % NI;
         const int64_t r = r0 + rr;
@@ -74,33 +89,40 @@ __global__ __launch_bounds__(256) void first_layer_kernel(
         xs[rr][k] = v;
     }
     __syncthreads();
-    const int groups = n_out / CPT;
-    const int rpi = 256 / groups;                      // rows per pass of the workgroup
     if (tid >= groups * rpi) return;
-    const int c0 = (tid % groups) * CPT;
-    T wr[CPT][NI], bb[CPT], be[CPT], ga[CPT];
-    const T* W = P.W[g];
+    // the thread's rows tid / groups, + rpi, ..., FR at a time with their CPT
+    // units side by side (the FP64 activations' exponentials and divisions of
+    // one row after another would each wait on the last; in FP32, with twice
+    // the units per thread, more rows at a time cost occupancy instead)
+    constexpr int FR = sizeof(T) == 8 ? 4 : 1;
+    for (int rr0 = tid / groups; rr0 < FL_ROWS; rr0 += FR * rpi) {
+        T acc[FR][CPT];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        bb[j] = P.b[g][c0 + j];
-        be[j] = P.beta[g][c0 + j];
-        ga[j] = P.gamma[g][c0 + j];
+        for (int q = 0; q < FR; ++q)
 #pragma unroll
-        for (int k = 0; k < NI; ++k) wr[j][k] = k < n_in ? W[(c0 + j) * n_in + k] : T(0);
-    }
-    for (int rr = tid / groups; rr < FL_ROWS; rr += rpi) {
-        const int64_t r = r0 + rr;
-        if (r >= nrows) break;
-        OutT* out = P.out[g] + r * n_out + c0;
-        T* ts = P.tsave[g] ? P.tsave[g] + r * n_out + c0 : nullptr;
+            for (int j = 0; j < CPT; ++j) acc[q][j] = bb[j];
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            T acc = bb[j];
+        for (int k = 0; k < NI; ++k)
+            if (k < n_in)
 #pragma unroll
-            for (int k = 0; k < NI; ++k)
-                if (k < n_in) acc += wr[j][k] * xs[rr][k];
-            if (ts) ts[j] = acc;
-            out[j] = cvt_out<T, OutT>(gated<T>(acc, be[j], ga[j]));
+                for (int q = 0; q < FR; ++q) {
+                    const int rr = min(rr0 + q * rpi, FL_ROWS - 1);
+                    const T x = xs[rr][k];
+#pragma unroll
+                    for (int j = 0; j < CPT; ++j) acc[q][j] += wr[j][k] * x;
+                }
+#pragma unroll
+        for (int q = 0; q < FR; ++q) {
+            const int rr = rr0 + q * rpi;
+            const int64_t r = r0 + rr;
+            if (rr >= FL_ROWS || r >= nrows) break;
+            OutT* out = P.out[g] + r * n_out + c0;
+            T* ts = P.tsave[g] ? P.tsave[g] + r * n_out + c0 : nullptr;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                if (ts) ts[j] = acc[q][j];
+                out[j] = cvt_out<T, OutT>(gated<T>(acc[q][j], be[j], ga[j]));
+            }
         }
     }
 }
