@@ -645,13 +645,14 @@ static int device_cus(int dev) {
 }
 
 // One FP64 GEMM launch: 64-row tiles, or 32-row tiles when the 64-row grid
-// has fewer than two workgroups per CU (a sampler round's few thousand rows);
-// the two give identical results (gemm_f64_kernel).
+// has fewer than eight workgroups per CU (a sampler round's few thousand
+// rows: twice the workgroups fill the CUs more evenly); the two give
+// identical results (gemm_f64_kernel).
 template <class Epi>
 static void launch_gemm_f64(const ns_model* m, const Group<Epi>& P, int64_t lda, int64_t rows, int N, int K, int G,
                             const int* count, int rpw, hipStream_t s) {
     const dim3 gr = grid3(rows, N, GD_M, GD_N, G);
-    if ((int64_t)gr.x * gr.y * gr.z < 2 * (int64_t)device_cus(m->device))
+    if ((int64_t)gr.x * gr.y * gr.z < 8 * (int64_t)device_cus(m->device))
         hipLaunchKernelGGL((gemm_f64_kernel<Epi, 32>), grid3(rows, N, 32, GD_N, G), dim3(256), 0, s, P, lda, rows, N,
                            K, count, rpw);
     else
