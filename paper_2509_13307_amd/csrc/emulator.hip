@@ -633,7 +633,7 @@ static inline dim3 grid3(int64_t M, int N, int bm, int bn, int G) {
 }
 
 // Compute units of device dev (queried once per device).
-static int device_cus(int dev) {
+int device_cus(int dev) {
     static int cus[64] = {0};
     if (dev < 0 || dev >= 64) return 256;
     if (cus[dev] == 0) {

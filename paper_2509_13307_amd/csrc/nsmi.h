@@ -317,6 +317,8 @@ __device__ __forceinline__ bool in_support(const double* th, int d, const int* k
 // Networks the one-kernel FP64 forward supports: 3..8 layers, <= 16 inputs,
 // every hidden width 128, <= 256 outputs.
 bool narrow_f64_shape(const std::vector<int>& dims);
+// Compute units of HIP device dev (queried once per device).
+int device_cus(int dev);
 // One-kernel FP64 forward of a model's single narrow network (rows = B,
 // outputs [B x ldo] in out), or with logl != nullptr the diagonal-Gaussian
 // logL of a CMB_DIAG model instead of the outputs; false without launching

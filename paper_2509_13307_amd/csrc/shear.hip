@@ -546,39 +546,50 @@ __global__ void limber_reduce_kernel(const double* __restrict__ theta, int64_t l
 // range.  Each tile writes its walkers' partial sums of (w_n - Y_bn)^2 over its
 // 64 columns, w = L^{-1} d; dense_chi2_finish_kernel adds the column tiles in
 // a fixed order (deterministic).
-constexpr int DG_M = 64, DG_N = 64, DG_KB = 32;
-constexpr size_t DG_SMEM = (2 * DG_KB * DG_M + 2 * DG_KB * DG_N + 2 * DG_M) * sizeof(double);
+// BM walkers per tile: 64 (four waves of 32 walkers x 32 columns), or 32 (four
+// waves of 16 x 32) when the 64-walker grid has fewer than eight workgroups
+// per CU: the column tiles of a triangular L^{-T} differ in length up to n / 64
+// fold, and with few workgroups the longest ones run alone.  Both pair the
+// same columns within a lane and reduce them in the same order, so a walker's
+// chi^2 is the same for either.
+constexpr int DG_N = 64, DG_KB = 32;
+template <int BM>
+constexpr size_t dg_smem() { return (2 * DG_KB * BM + 2 * DG_KB * DG_N + 2 * BM) * sizeof(double); }
 // MODE 0: Y = C L^{-T} (Bm = L^{-T}, K range [0, 64 (ct + 1))), partial sums of
 //         (w - Y)^2; with R != nullptr also the residuals R = w - Y.
 // MODE 1: out = R L^{-1} (Bm = L^{-1} row-major, K range [64 ct, np)), the
 //         chi^2 adjoint g_C = L^{-T} L^{-1} (d - C), written to `out`.
-template <int MODE>
+template <int MODE, int BM>
 __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __restrict__ C, int64_t B, int n, int np,
                                                               const double* __restrict__ Lt,
                                                               const double* __restrict__ wv,
                                                               double* __restrict__ part, int64_t pstride,
                                                               double* __restrict__ R, const int* __restrict__ count) {
     extern __shared__ double dg_lds[];
-    auto As = reinterpret_cast<double (*)[DG_KB][DG_M]>(dg_lds);                      // [2][k][walker]
-    auto Bs = reinterpret_cast<double (*)[DG_KB][DG_N]>(dg_lds + 2 * DG_KB * DG_M);   // [2][k][column]
-    auto red = reinterpret_cast<double (*)[DG_M]>(dg_lds + 2 * DG_KB * (DG_M + DG_N)); // [2][walker]
+    constexpr int TI = BM / 32;                        // 16-walker MFMA tiles per wave
+    constexpr int LA = BM * DG_KB / 256;               // A elements per thread and K block
+    auto As = reinterpret_cast<double (*)[DG_KB][BM]>(dg_lds);                        // [2][k][walker]
+    auto Bs = reinterpret_cast<double (*)[DG_KB][DG_N]>(dg_lds + 2 * DG_KB * BM);     // [2][k][column]
+    auto red = reinterpret_cast<double (*)[BM]>(dg_lds + 2 * DG_KB * (BM + DG_N));    // [2][walker]
     if (count) B = min<int64_t>(B, *count);
-    const int64_t b0 = (int64_t)blockIdx.x * DG_M;
+    const int64_t b0 = (int64_t)blockIdx.x * BM;
     if (b0 >= B) return;
     const int ct = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);
+    const int wr = (BM / 2) * (wave >> 1), wc = 32 * (wave & 1);
     const int kbeg = MODE == 0 ? 0 : DG_N * ct;
     const int kend = MODE == 0 ? min(np, DG_N * (ct + 1)) : np;
-    double ra[8], rb[8];
+    double ra[LA], rb[8];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int e = tid + 256 * q;                  // 0 .. 2047
-            const int row = e >> 5, k = e & 31;           // A: 32 consecutive k of one walker
-            const int64_t b = b0 + row;
-            const int kk = k0 + k;
-            ra[q] = (b < B && kk < n) ? C[b * n + kk] : 0.0;
+            if (q < LA) {
+                const int row = e >> 5, k = e & 31;       // A: 32 consecutive k of one walker
+                const int64_t b = b0 + row;
+                const int kk = k0 + k;
+                ra[q] = (b < B && kk < n) ? C[b * n + kk] : 0.0;
+            }
             const int kb = e >> 6, col = e & 63;          // B: one row of the column tile
             rb[q] = Lt[(size_t)(k0 + kb) * np + DG_N * ct + col];
         }
@@ -587,13 +598,13 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int e = tid + 256 * q;
-            As[bf][e & 31][e >> 5] = ra[q];
+            if (q < LA) As[bf][e & 31][e >> 5] = ra[q];
             Bs[bf][e >> 6][e & 63] = rb[q];
         }
     };
-    f64x4_t acc[2][2];
+    f64x4_t acc[TI][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -607,13 +618,13 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
         if (more) gload(k0 + DG_KB);
 #pragma unroll
         for (int kk = 0; kk < DG_KB; kk += 4) {
-            double a[2], bv[2];
+            double a[TI], bv[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[bf][kk + (lane >> 4)][wr + 16 * i + (lane & 15)];
+            for (int i = 0; i < TI; ++i) a[i] = As[bf][kk + (lane >> 4)][wr + 16 * i + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < 2; ++j) bv[j] = Bs[bf][kk + (lane >> 4)][wc + 16 * j + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
         }
@@ -624,7 +635,7 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
     // D row (lane >> 4) + 4 r, column lane & 15 of MFMA tile (i, j)
     if (MODE == 1) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -636,9 +647,9 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
         return;
     }
     // (w_n - Y_bn)^2 summed over this wave's columns
-    double srow[2][4];
+    double srow[TI][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             double sacc = 0.0;
@@ -655,18 +666,18 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
             srow[i][r] = sacc;
         }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int o = 1; o < 16; o <<= 1) srow[i][r] += __shfl_xor(srow[i][r], o, 64);
     if ((lane & 15) == 0)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) red[wave & 1][wr + 16 * i + (lane >> 4) + 4 * r] = srow[i][r];
     __syncthreads();
-    if (tid < DG_M && b0 + tid < B) part[(int64_t)ct * pstride + b0 + tid] = red[0][tid] + red[1][tid];
+    if (tid < BM && b0 + tid < B) part[(int64_t)ct * pstride + b0 + tid] = red[0][tid] + red[1][tid];
 }
 
 __global__ void dense_chi2_finish_kernel(const double* __restrict__ theta, int64_t ld, int64_t B, int d,
@@ -787,10 +798,10 @@ double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, i
                              (const void*)limber_sum_kernel<float, true, 32>};
         for (const void* f : fns)
             NS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)DG_SMEM));
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)DG_SMEM));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0, 64>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64>()));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1, 64>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64>()));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    150 * 1024));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -833,6 +844,22 @@ double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, i
     return Cv;
 }
 
+// One dense chi^2 GEMM launch of mode MODE over B walkers: 64-walker tiles, or
+// 32-walker tiles when the 64-walker grid has fewer than eight workgroups per
+// CU (identical results; dense_chi2_gemm_kernel)
+template <int MODE>
+static void launch_dense_gemm(const ns_model* m, const double* C, int64_t B, int n, int np, int n_ct,
+                              const double* Lm, const double* wv, double* part, double* R, const int* count,
+                              hipStream_t s) {
+    const int64_t g64 = (B + 63) / 64 * n_ct;
+    if (g64 < 8 * (int64_t)device_cus(m->device))
+        hipLaunchKernelGGL((dense_chi2_gemm_kernel<MODE, 32>), dim3((unsigned)((B + 31) / 32), (unsigned)n_ct),
+                           dim3(256), dg_smem<32>(), s, C, B, n, np, Lm, wv, part, B, R, count);
+    else
+        hipLaunchKernelGGL((dense_chi2_gemm_kernel<MODE, 64>), dim3((unsigned)((B + 63) / 64), (unsigned)n_ct),
+                           dim3(256), dg_smem<64>(), s, C, B, n, np, Lm, wv, part, B, R, count);
+}
+
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
                               int prec, const int* count, hipStream_t s) {
     const int n = m->n_data;
@@ -842,9 +869,8 @@ void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int6
     double* part = Cv + (size_t)B * n;
     {
         TraceScope ts(m, s, "dense_chi2");
-        hipLaunchKernelGGL(dense_chi2_gemm_kernel<0>, dim3((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct),
-                           dim3(256), DG_SMEM, s, Cv, B, n, np, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part,
-                           B, (double*)nullptr, count);
+        launch_dense_gemm<0>(m, Cv, B, n, np, n_ct, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part,
+                             (double*)nullptr, count, s);
         NS_HIP(hipGetLastError());
         hipLaunchKernelGGL(dense_chi2_finish_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld,
                            B, m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), part, B,
@@ -860,16 +886,15 @@ void dense_chi2_adjoint(ns_model* m, const double* theta, int64_t ld, int64_t B,
                         double* part, double* logl, double* gC, hipStream_t s) {
     const int n = m->n_data;
     const int np = (n + DG_N - 1) / DG_N * DG_N, n_ct = np / DG_N;
-    const dim3 grid((unsigned)((B + DG_M - 1) / DG_M), (unsigned)n_ct);
-    hipLaunchKernelGGL(dense_chi2_gemm_kernel<0>, grid, dim3(256), DG_SMEM, s, Cv, B, n, np,
-                       m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part, B, R, (const int*)nullptr);
+    launch_dense_gemm<0>(m, Cv, B, n, np, n_ct, m->cov_lt_pad.as<double>(), m->cov_w.as<double>(), part, R,
+                         (const int*)nullptr, s);
     NS_HIP(hipGetLastError());
     hipLaunchKernelGGL(dense_chi2_finish_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, ld, B,
                        m->d, m->prior_kind.as<int>(), m->prior_a.as<double>(), m->prior_b.as<double>(), part, B, n_ct,
                        m->logl_const, logl, (const int*)nullptr);
     NS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(dense_chi2_gemm_kernel<1>, grid, dim3(256), DG_SMEM, s, R, B, n, np,
-                       m->cov_l_pad.as<double>(), (const double*)nullptr, (double*)nullptr, B, gC, (const int*)nullptr);
+    launch_dense_gemm<1>(m, R, B, n, np, n_ct, m->cov_l_pad.as<double>(), (const double*)nullptr, (double*)nullptr,
+                         gC, (const int*)nullptr, s);
     NS_HIP(hipGetLastError());
 }
 
