@@ -189,6 +189,26 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
     __syncthreads();
     const uint64_t gmask = GS == 64 ? ~0ull : (((1ull << GS) - 1) << gb);
     bool moved = false;
+    // lane i of the group: row i of L z (L lower triangular), summed over
+    // j = 0 .. i in order; the z_j come from the group's lanes four shuffles
+    // at a time
+    auto lz = [&](double z) {
+        double acc = 0.0;
+        int j = 0;
+        for (; j + 4 <= d; j += 4) {
+            double zq[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) zq[t] = __shfl(z, gb + j + t, 64);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (act && j + t <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j + t], zq[t]));
+        }
+        for (; j < d; ++j) {
+            const double zj = __shfl(z, gb + j, 64);
+            if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
+        }
+        return act ? acc : 0.0;
+    };
     // the direction of step s0 + 1, v' = L z (z by Box-Muller from the draws
     // above), and its offset r', formed once for the wave here rather than on
     // the path of the walkers that begin a step this round
@@ -199,12 +219,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
             const double u1 = pw[wl0 + (lg >> 1)][2 * (lg & 1)], u2 = pw[wl0 + (lg >> 1)][2 * (lg & 1) + 1];
             z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
         }
-        double acc = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const double zj = __shfl(z, gb + j, 64);
-            if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
-        }
-        vnext = act ? acc : 0.0;
+        vnext = lz(z);
     }
     const double rnext = pw[wl0 + (d >> 1)][2 * (d & 1)];
     // the point at t along the direction lies in the unit cube (outside it
@@ -299,12 +314,7 @@ __global__ __launch_bounds__(256) void slice_advance_kernel(SliceState S, int64_
                 r = d < GS ? __shfl(u1, gb + d, 64)
                            : philox_uniform(seed, 0, (uint64_t)w, (uint64_t)s, iter, 2 * (uint64_t)d);
                 if (act) z = sqrt(-2.0 * log1p(-u1)) * cos(2.0 * M_PI * u2);
-                double acc = 0.0;
-                for (int j = 0; j < d; ++j) {
-                    const double zj = __shfl(z, gb + j, 64);
-                    if (act && j <= lg) acc = __dadd_rn(acc, __dmul_rn(Ls[lg * d + j], zj));
-                }
-                vi = act ? acc : 0.0;
+                vi = lz(z);
             }
             tl = -r;
             tr = 1.0 - r;
