@@ -14,14 +14,6 @@
 
 namespace nsmi {
 
-__device__ __forceinline__ bool in_support_row(const double* th, int d, const int* kind, const double* a,
-                                               const double* b) {
-    bool ok = true;
-    for (int i = 0; i < d; ++i)
-        if (kind[i] == NS_PRIOR_UNIFORM && (th[i] < a[i] || th[i] > b[i])) ok = false;
-    return ok;
-}
-
 // CMB seeds: model vector mvec [B x n] (T) -> logL and delta[g][row][n_pad]
 // (T) for each of the G networks.  Diagonal: dlogL/dC_i = r_i / sigma_i^2.
 // Block: per multipole g3 = Linv^T (Linv r3); PP: r / sigma_pp^2.
@@ -47,7 +39,7 @@ __global__ __launch_bounds__(256) void cmb_seed_kernel(
     if (r0 >= B) return;
     const int nr = (int)min<int64_t>(ROWS, B - r0);
     if (threadIdx.x < ROWS)
-        okr[threadIdx.x] = threadIdx.x < nr && in_support_row(theta + (r0 + threadIdx.x) * ld, d, pk, pa, pb);
+        okr[threadIdx.x] = threadIdx.x < nr && in_support(theta + (r0 + threadIdx.x) * ld, d, pk, pa, pb);
     __syncthreads();
     const SeedNet sn[4] = {s0, s1, s2, s3};
     double chi2[ROWS];
@@ -133,7 +125,7 @@ __global__ __launch_bounds__(256) void cv_seed_kernel(
     __shared__ double red[4];
     const int64_t row = blockIdx.x;
     if (row >= B) return;
-    const bool ok = in_support_row(theta + row * ld, d, pk, pa, pb);
+    const bool ok = in_support(theta + row * ld, d, pk, pa, pb);
     const T* yr = y + row * (int64_t)n;
     double s = 0.0;
     for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
@@ -180,7 +172,7 @@ __global__ void gauss_grad_kernel(const double* __restrict__ theta, int64_t ld, 
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= B) return;
     const double* th = theta + row * ld;
-    const bool ok = in_support_row(th, d, pk, pa, pb);
+    const bool ok = in_support(th, d, pk, pa, pb);
     double s = 0.0;
     for (int i = 0; i < d; ++i) {
         const double r = (th[i] - mu[i]) * isig[i];

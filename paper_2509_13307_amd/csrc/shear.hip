@@ -688,12 +688,9 @@ __global__ void dense_chi2_finish_kernel(const double* __restrict__ theta, int64
     if (count) B = min<int64_t>(B, *count);
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= B) return;
+    const bool ok = in_support(theta + w * ld, d, pk, pa, pb);
     double chi2 = 0.0;
     for (int c = 0; c < n_ct; ++c) chi2 += part[(int64_t)c * pstride + w];
-    bool ok = true;
-    const double* th = theta + w * ld;
-    for (int i = 0; i < d; ++i)
-        if (pk[i] == NS_PRIOR_UNIFORM && (th[i] < pa[i] || th[i] > pb[i])) ok = false;
     logl[w] = ok ? -0.5 * chi2 + cst : -INFINITY;
 }
 
