@@ -229,6 +229,27 @@ def test_fused_mlp_matches_layer_by_layer(built, name, B, prec, monkeypatch):
         np.testing.assert_array_equal(got, fchi)
 
 
+@pytest.mark.parametrize("name,prec,B", [("cmbtt_cv", "fp64", 16384), ("shear_cmp_lcdm", "fp64", 8192),
+                                         ("shear_cmp_lcdm", "bf16x3", 8192)])
+def test_logl_does_not_depend_on_the_batch(built, name, prec, B):
+    """A walker's logL is the same, bitwise, in a batch of 96 and in a batch of
+    B: the launch shapes that the batch size selects (FP64 GEMM tiles of 32 or
+    64 rows, dense-chi^2 tiles of 32 or 64 walkers, the autotuned one-kernel
+    emulator shape) all keep every sum in the same order.  At 96 walkers the
+    small tiles run, at B the large ones."""
+    say(f"case batch independence {name} {prec} B={B}")
+    from paper_2509_13307_amd import Model
+    m = W.load_model(name)
+    g = Model(m)
+    th = torch.tensor(W.prior_draws(m, B, tag=11), device=DEV)
+    big = g.loglike(th, prec).cpu().numpy()
+    small = g.loglike(th[:96].contiguous(), prec).cpu().numpy()
+    g.close()
+    say(f"  {int(np.isfinite(small).sum())} of 96 finite; max |small - big| "
+        f"{np.nanmax(np.abs(small - big[:96])):.3e}")
+    np.testing.assert_array_equal(small, big[:96])
+
+
 def test_tuning_cache_round_trip(built, tmp_path, monkeypatch):
     """The autotuner's choices go to the on-disk cache; a new model on the same
     GPU architecture starts with them (no timing runs, same results), and
