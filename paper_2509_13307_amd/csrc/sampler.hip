@@ -489,35 +489,95 @@ __device__ double block_max(double v, double* buf) {
     return r;
 }
 
-// Bitonic sort of (logl, index) for n <= 4096 by one workgroup: key [N2]
-// doubles and idx [N2] ints in LDS, N2 = n rounded up to a power of two
-// (padding +inf, index 2^31 - 1); ties by index, NaN after +inf.
+// Integer image of a double that orders as the doubles do, with -0 as +0
+// and every NaN after +inf.
+__device__ inline uint64_t order_bits(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x == 0.0 ? 0.0 : x);
+    return isnan(x) ? ~0ull : ((b >> 63) ? ~b : (b | 0x8000000000000000ull));
+}
+
+// (a, ia) comes before (b, ib) in the order of (logL, index)
+__device__ inline bool before(uint64_t a, int ia, uint64_t b, int ib) {
+    return (a < b) | ((a == b) & (ia < ib));
+}
+
+// Sort of the live points by (logl, index) -- NaN after +inf, ties by index --
+// for n <= 4096 by one workgroup of at least N2 / 4 threads: a bitonic network
+// over N2 = max(256, n rounded up to a power of two) entries, the padding
+// after every point.  Entry e = 256 w + 4 lane + r lives in register r of that
+// lane of wave w: strides 1 and 2 compare registers of one lane, strides 4 to
+// 128 lanes of one wave (shuffles), larger strides go through LDS.  On return
+// key[j] is the logl of the j-th point in that order and idx[j] its index,
+// j < n (key: N2 doubles of LDS, idx: N2 ints).
 __device__ void sort_live(const double* __restrict__ logl, int n, double* key, int* idx) {
-    int N2 = 1;
+    int N2 = 256;
     while (N2 < n) N2 <<= 1;
-    for (int i = threadIdx.x; i < N2; i += blockDim.x) {
-        key[i] = i < n ? logl[i] : INFINITY;
-        idx[i] = i < n ? i : 0x7fffffff;
+    uint64_t* kb = reinterpret_cast<uint64_t*>(key);
+    const int lane = threadIdx.x & 63;
+    const int e0 = (threadIdx.x >> 6) * 256 + lane * 4;
+    const bool act = e0 < N2;                          // wave-uniform
+    uint64_t k[4];
+    int x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = e0 + r;
+        k[r] = e < n ? order_bits(logl[e]) : ~0ull;
+        x[r] = e < n ? e : 0x7fffffff;
     }
-    __syncthreads();
-    for (int size = 2; size <= N2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < N2; i += blockDim.x) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const bool up = (i & size) == 0;
-                    const double ki = key[i], kj = key[j];
-                    const int ii = idx[i], ij = idx[j];
-                    const bool gt = (ki > kj) || (ki == kj && ii > ij) || (isnan(ki) && !isnan(kj));
-                    if (gt == up) {
-                        key[i] = kj; key[j] = ki;
-                        idx[i] = ij; idx[j] = ii;
+    // the entry of register a goes first (ascending) or last, of a < b
+    auto regs = [&](int a, int b, bool up) {
+        if (before(k[b], x[b], k[a], x[a]) == up) {
+            const uint64_t tk = k[a]; k[a] = k[b]; k[b] = tk;
+            const int tx = x[a]; x[a] = x[b]; x[b] = tx;
+        }
+    };
+    for (int S = 2; S <= N2; S <<= 1) {
+        if (S >= 512) {
+            __syncthreads();                           // the last loads from LDS are done
+            if (act)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { kb[e0 + r] = k[r]; idx[e0 + r] = x[r]; }
+            __syncthreads();
+            for (int s = S >> 1; s >= 256; s >>= 1) {
+                for (int p = threadIdx.x; p < (N2 >> 1); p += blockDim.x) {
+                    const int a = ((p & ~(s - 1)) << 1) | (p & (s - 1)), b = a + s;
+                    const uint64_t ka = kb[a], kbb = kb[b];
+                    const int ia = idx[a], ib = idx[b];
+                    if (before(kbb, ib, ka, ia) == ((a & S) == 0)) {
+                        kb[a] = kbb; kb[b] = ka;
+                        idx[a] = ib; idx[b] = ia;
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
+            if (act)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { k[r] = kb[e0 + r]; x[r] = idx[e0 + r]; }
         }
+        if (!act) continue;
+        const bool up = (e0 & S) == 0;                 // for S >= 4 the same for the four registers
+        for (int s = S >= 256 ? 128 : S >> 1; s >= 4; s >>= 1) {
+            const int m = s >> 2;
+            const int src = (lane ^ m) << 2;
+            const bool keep_first = ((lane & m) == 0) == up;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int plo = __builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)k[r]);
+                const int phi = __builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(k[r] >> 32));
+                const int px = __builtin_amdgcn_ds_bpermute(src, x[r]);
+                const uint64_t pk = ((uint64_t)(uint32_t)phi << 32) | (uint32_t)plo;
+                if (before(pk, px, k[r], x[r]) == keep_first) { k[r] = pk; x[r] = px; }
+            }
+        }
+        if (S >= 4) { regs(0, 2, up); regs(1, 3, up); regs(0, 1, up); regs(2, 3, up); }
+        else { regs(0, 1, true); regs(2, 3, false); }
     }
+    __syncthreads();                                   // the last loads from LDS are done
+    if (act)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (e0 + r < n) { idx[e0 + r] = x[r]; key[e0 + r] = logl[x[r]]; }
+    __syncthreads();
 }
 
 constexpr int CTL_NT = 1024;

@@ -113,6 +113,9 @@ class Model:
                 D.z_interp = 1 if desc.get("z_interp", "cubic") == "linear" else 0
                 D.pidx = self._p(_i32(desc["pidx"]), C.c_int32_p)
                 D.pfix = self._p(_f64(desc["pfix"]), C.c_double_p)
+        # torch ships its own HIP runtime: it has to open the GPU before the
+        # library's runtime does, or torch finds no device afterwards.
+        torch.cuda.init()
         h = ctypes.c_void_p()
         C.check(C.lib().ns_model_create(ctypes.byref(D), device, ctypes.byref(h)))
         self._h = h

@@ -438,3 +438,25 @@ def test_fp64_one_kernel_narrow_emulator_matches_layer_by_layer(built, monkeypat
         np.testing.assert_array_equal(a, b)
     assert outs[0][0][5] == -np.inf
     check_fp64(oracle_loglike(th, m, chunk=64), outs[0][0], "cmb6 one-kernel fp64")
+
+
+def test_model_made_before_torch_opens_the_gpu():
+    """A process whose first GPU call is the library's (a Model made before any
+    torch tensor on the GPU) still has a working torch device afterwards."""
+    import os
+    import subprocess
+    say("case Model before torch's first GPU call (child process)")
+    code = ("import torch, workloads as W\n"
+            "from paper_2509_13307_amd import Model\n"
+            "g = Model(W.gauss_structure(d=3, mu=[0.1, 0.5, 0.8], sigma=[0.05, 0.1, 0.08]))\n"
+            "th = torch.tensor([[0.1, 0.5, 0.8], [0.2, 0.4, 0.7]], dtype=torch.float64, device='cuda:0')\n"
+            "print(repr(g.loglike(th, 'fp64').tolist()))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=100)
+    say(r.stdout.strip(), r.stderr.strip()[-400:])
+    assert r.returncode == 0
+    from paper_2509_13307_amd import Model
+    g = Model(W.gauss_structure(d=3, mu=[0.1, 0.5, 0.8], sigma=[0.05, 0.1, 0.08]))
+    th = torch.tensor([[0.1, 0.5, 0.8], [0.2, 0.4, 0.7]], dtype=torch.float64, device=DEV)
+    assert r.stdout.strip().splitlines()[-1] == repr(g.loglike(th, "fp64").tolist())
+    g.close()
