@@ -658,24 +658,31 @@ __device__ void dircov_block(const double* __restrict__ u, int n, int d, double*
         X[a * d + b] = X[b * d + a] = v / (n - 1);
     }
     __syncthreads();
-    if (t == 0) {
+    // Cholesky by the first wave, lane i for row i (d <= 64), one column at a
+    // time: entry (i, j) subtracts L_ip L_jp for p = 0 .. j-1 in that order.
+    if (t < 64) {
         double tr = 0.0;
         for (int a = 0; a < d; ++a) tr += X[a * d + a];
         const double jit = 1e-12 * tr / d;
-        for (int a = 0; a < d; ++a) X[a * d + a] += jit;
+        const int i = t;
+        if (i < d) X[i * d + i] += jit;
         for (int j = 0; j < d; ++j) {
-            double s = X[j * d + j];
-            for (int p = 0; p < j; ++p) s -= X[j * d + p] * X[j * d + p];
-            const double djj = sqrt(fmax(s, 0.0));
-            X[j * d + j] = djj;
-            for (int i = j + 1; i < d; ++i) {
-                double v = X[i * d + j];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // column j - 1 is in LDS for every lane
+            __builtin_amdgcn_wave_barrier();
+            double v = 0.0;
+            if (i >= j && i < d) {
+                v = X[i * d + j];
                 for (int p = 0; p < j; ++p) v -= X[i * d + p] * X[j * d + p];
-                X[i * d + j] = djj > 0.0 ? v / djj : 0.0;
             }
+            const double djj = sqrt(fmax(__shfl(v, j, 64), 0.0));
+            if (i == j) X[j * d + j] = djj;
+            else if (i > j && i < d) X[i * d + j] = djj > 0.0 ? v / djj : 0.0;
         }
-        for (int a = 0; a < d; ++a)
-            for (int b = 0; b < d; ++b) L[a * d + b] = b <= a ? X[a * d + b] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < d * d; e += NT) {
+        const int a = e / d, b = e - a * d;
+        L[e] = b <= a ? X[e] : 0.0;
     }
 }
 
