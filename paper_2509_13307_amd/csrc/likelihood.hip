@@ -107,6 +107,11 @@ __global__ __launch_bounds__(256) void cv_loglike_kernel(
     if (count) B = min<int64_t>(B, *count);
     if (row >= B) return;                                 // whole workgroups
     const T* yr = y + row * ldm;
+    // support check, lane i of each wave for parameter i (d <= 64): vector
+    // loads, in flight under the sum, tested after it
+    const int si = min((int)(threadIdx.x & 63), d - 1);
+    const int sk = pk[si];
+    const double st = theta[row * ld + si], slo = pa[si], shi = pb[si];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
         const double lc = 2.302585092994045684 * (double)yr[i];     // ln C_l
@@ -114,10 +119,10 @@ __global__ __launch_bounds__(256) void cv_loglike_kernel(
     }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    const bool ok = __all(!((sk == NS_PRIOR_UNIFORM) & ((st < slo) | (st > shi))));
     __syncthreads();
     if (threadIdx.x == 0) {
         const double tot = red[0] + red[1] + red[2] + red[3];
-        const bool ok = in_support(theta + row * ld, d, pk, pa, pb);
         logl[row] = ok ? cst - tot : -INFINITY;
     }
 }

@@ -303,15 +303,48 @@ __device__ __forceinline__ double prior_map(double x, int kind, double a, double
 // theta outside a uniform prior's [a, b] -> false (NaN compares false: kept)
 __device__ __forceinline__ bool in_support(const double* th, int d, const int* kind, const double* a,
                                            const double* b) {
-    // every load unconditional and the tests combined without short
-    // circuits, so that the loads of all parameters are in flight together
+    // parameters in groups of 8, every load of a group unconditional (places
+    // past d repeat the last parameter, whose test is idempotent) and the
+    // tests combined without short circuits: a group's loads are in flight
+    // together instead of one parameter's after another's
     bool ok = true;
-    for (int i = 0; i < d; ++i) {
-        const int k = kind[i];
-        const double t = th[i], lo = a[i], hi = b[i];
-        ok = ok & !((k == NS_PRIOR_UNIFORM) & ((t < lo) | (t > hi)));
+    for (int i0 = 0; i0 < d; i0 += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = min(i0 + j, d - 1);
+            const int k = kind[i];
+            const double t = th[i], lo = a[i], hi = b[i];
+            ok = ok & !((k == NS_PRIOR_UNIFORM) & ((t < lo) | (t > hi)));
+        }
     }
     return ok;
+}
+
+// in_support in two halves, for a check whose loads should be in flight
+// while other work runs: support_load issues the loads of the first eight
+// parameters (places past d repeat the last one), support_test forms the
+// same result from them and the remaining parameters.
+struct SupportLoads {
+    double t[8], lo[8], hi[8];
+    int k[8];
+};
+__device__ __forceinline__ void support_load(SupportLoads& s, const double* th, int d, const int* kind,
+                                             const double* a, const double* b) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = min(j, d - 1);
+        s.k[j] = kind[i];
+        s.t[j] = th[i];
+        s.lo[j] = a[i];
+        s.hi[j] = b[i];
+    }
+}
+__device__ __forceinline__ bool support_test(const SupportLoads& s, const double* th, int d, const int* kind,
+                                             const double* a, const double* b) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ok = ok & !((s.k[j] == NS_PRIOR_UNIFORM) & ((s.t[j] < s.lo[j]) | (s.t[j] > s.hi[j])));
+    return d > 8 ? ok & in_support(th + 8, d - 8, kind + 8, a + 8, b + 8) : ok;
 }
 
 // Networks the one-kernel FP64 forward supports: 3..8 layers, <= 16 inputs,

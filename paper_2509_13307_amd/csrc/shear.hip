@@ -688,10 +688,19 @@ __global__ void dense_chi2_finish_kernel(const double* __restrict__ theta, int64
     if (count) B = min<int64_t>(B, *count);
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= B) return;
-    const bool ok = in_support(theta + w * ld, d, pk, pa, pb);
+    SupportLoads sup;                                  // in flight with the partials
+    support_load(sup, theta + w * ld, d, pk, pa, pb);
+    // the column tiles' partials added in tile order, loaded eight at a time
     double chi2 = 0.0;
-    for (int c = 0; c < n_ct; ++c) chi2 += part[(int64_t)c * pstride + w];
-    logl[w] = ok ? -0.5 * chi2 + cst : -INFINITY;
+    for (int c0 = 0; c0 < n_ct; c0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = c0 + j < n_ct ? part[(int64_t)(c0 + j) * pstride + w] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (c0 + j < n_ct) chi2 += v[j];
+    }
+    logl[w] = support_test(sup, theta + w * ld, d, pk, pa, pb) ? -0.5 * chi2 + cst : -INFINITY;
 }
 
 ShearGeom shear_geom(const ns_model* m) {
