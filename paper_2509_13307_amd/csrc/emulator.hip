@@ -602,7 +602,8 @@ static void launch_bf16_tuned(ns_model* m, int kind, const Group<Epi>& P, int64_
     bf16_candidate<Epi>(best)(P, M, N, K, G, count, rpw, s);
 }
 
-// kinds 2 .. 9: one-kernel forward, 2 + split + 2 wide + 4 chi^2 mode
+// kinds 2 .. 17: one-kernel forward, 2 + split + 2 wide + 4 chi^2 mode + 8
+// rounds of the sampler (rows a device count below the launch's maximum)
 int tune_ncfg(int kind) { return kind < 2 ? BF16_NCFG : fused_ncfg_of(((kind - 2) >> 1) & 1, (kind - 2) & 1); }
 const char* tune_cfg_name(int kind, int c) {
     return kind < 2 ? BF16_CFG_NAMES[c] : fused_cfg_name(((kind - 2) >> 1) & 1, (kind - 2) & 1, c);
@@ -614,9 +615,11 @@ std::string bf16_tuning_report(const ns_model* m) {
     for (const auto& kv : m->tune) {
         char tmp[256];
         const int kind = std::get<0>(kv.first);
-        static const char* kinds[10] = {"bf16_hidden", "bf16_out", "fused_bf16", "fused_bf16x3", "fused_bf16",
-                                        "fused_bf16x3", "fused_chi2_bf16", "fused_chi2_bf16x3", "fused_chi2_bf16",
-                                        "fused_chi2_bf16x3"};
+        static const char* kinds[18] = {
+            "bf16_hidden", "bf16_out", "fused_bf16", "fused_bf16x3", "fused_bf16", "fused_bf16x3",
+            "fused_chi2_bf16", "fused_chi2_bf16x3", "fused_chi2_bf16", "fused_chi2_bf16x3",
+            "fused_bf16 rounds", "fused_bf16x3 rounds", "fused_bf16 rounds", "fused_bf16x3 rounds",
+            "fused_chi2_bf16 rounds", "fused_chi2_bf16x3 rounds", "fused_chi2_bf16 rounds", "fused_chi2_bf16x3 rounds"};
         const char* cfg = tune_cfg_name(kind, kv.second);
         snprintf(tmp, sizeof tmp, "%s\"%s M=%lld N=%d K=%d networks=%d\": \"%s\"", first ? "" : ", ", kinds[kind],
                  (long long)std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),

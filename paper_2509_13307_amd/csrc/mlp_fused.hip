@@ -693,7 +693,10 @@ static void fused_run(ns_model* m, const FusedArgs& A, int H, bool x3, int G, co
                                (const double*)Ac.part, ncb, H / 32, nr, Ac, cnt);
     };
     auto run = [&](int c) { run_rows(c, rows, count); };
-    const auto key = std::make_tuple(2 + (int)x3 + 2 * h512 + (A.chi ? 4 : 0), rows, A.N_out, H, G);
+    // a sampler round's launch (rows a device count) is tuned apart from an
+    // exact batch of the same maximum: the initial live points and the rounds
+    // of 2 x speculation x k walkers can share one row count
+    const auto key = std::make_tuple(2 + (int)x3 + 2 * h512 + (A.chi ? 4 : 0) + (count ? 8 : 0), rows, A.N_out, H, G);
     int best = 0;
     auto it = m->tune.find(key);
     const char* forced = getenv("NSMI_FUSED_CFG");      // pin one candidate (tests of every shape)
@@ -712,11 +715,22 @@ static void fused_run(ns_model* m, const FusedArgs& A, int H, bool x3, int G, co
             // (clock and cache state drift between candidates of one pass).  A
             // launch whose live rows are a device count (the sampler's rounds,
             // whose batches vary from round to round below the maximum `rows`)
-            // is timed at a quarter, half and all of `rows` and ranked by the
-            // sum: the rows those launches carry are rarely the maximum.
+            // is timed at an eighth, a quarter and half of `rows` and ranked by
+            // the sum: the maximum needs every walker to propose its full
+            // speculation at both bracket ends, and most rounds carry a few
+            // tenths of it (cosmic shear, 500 walkers: 2 600 of 10 000 rows
+            // on average).  It is also timed one launch at a time, each after
+            // 64 MiB of writes that push the weights out of L2, as the
+            // round's other kernels do: with the weights left in L2 by the
+            // launch before, the 64-row tiles won at shear sizes where the
+            // 32-row tiles take 25 us less per call in the likelihood.
+            DevBuf flush;
+            constexpr size_t FLUSH_BYTES = size_t(64) << 20;
+            if (count) flush.ensure(FLUSH_BYTES);
             const int ncfg = fused_ncfg(h512, x3);
-            const int64_t sizes[3] = {std::max<int64_t>(rpw, rows / 4 / rpw * rpw),
-                                      std::max<int64_t>(rpw, rows / 2 / rpw * rpw), rows};
+            const int64_t sizes[3] = {std::max<int64_t>(rpw, rows / 8 / rpw * rpw),
+                                      std::max<int64_t>(rpw, rows / 4 / rpw * rpw),
+                                      std::max<int64_t>(rpw, rows / 2 / rpw * rpw)};
             const int nsz = count ? 3 : 1;
             float tot_ms[FUSED_NCFG];
             for (int c = 0; c < ncfg; ++c) tot_ms[c] = 0.f;
@@ -726,13 +740,26 @@ static void fused_run(ns_model* m, const FusedArgs& A, int H, bool x3, int G, co
                 for (int c = 0; c < ncfg; ++c) best_ms[c] = 1e30f;
                 for (int pass = 0; pass < 2; ++pass)
                     for (int c = 0; c < ncfg; ++c) {
-                        run_rows(c, nr, count ? nullptr : count);
-                        NS_HIP(hipEventRecord(e0, s));
-                        for (int r = 0; r < 4; ++r) run_rows(c, nr, count ? nullptr : count);
-                        NS_HIP(hipEventRecord(e1, s));
-                        NS_HIP(hipEventSynchronize(e1));
+                        run_rows(c, nr, nullptr);
                         float ms = 0.f;
-                        NS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        if (count) {
+                            for (int r = 0; r < 4; ++r) {
+                                NS_HIP(hipMemsetAsync(flush.p, r, FLUSH_BYTES, s));
+                                NS_HIP(hipEventRecord(e0, s));
+                                run_rows(c, nr, nullptr);
+                                NS_HIP(hipEventRecord(e1, s));
+                                NS_HIP(hipEventSynchronize(e1));
+                                float t = 0.f;
+                                NS_HIP(hipEventElapsedTime(&t, e0, e1));
+                                ms += t;
+                            }
+                        } else {
+                            NS_HIP(hipEventRecord(e0, s));
+                            for (int r = 0; r < 4; ++r) run_rows(c, nr, nullptr);
+                            NS_HIP(hipEventRecord(e1, s));
+                            NS_HIP(hipEventSynchronize(e1));
+                            NS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        }
                         best_ms[c] = std::min(best_ms[c], ms);
                     }
                 for (int c = 0; c < ncfg; ++c) tot_ms[c] += best_ms[c];

@@ -368,7 +368,8 @@ int fused_ncfg_of(int h512, int x3);
 std::string bf16_tuning_report(const ns_model* m);
 
 // Autotuner tables: candidates of tuning kind `kind` (0 BF16 hidden GEMM,
-// 1 BF16 output GEMM, 2 + split + 2 wide: one-kernel emulator) and their names.
+// 1 BF16 output GEMM, 2 + split + 2 wide + 4 chi^2 mode + 8 sampler rounds:
+// one-kernel emulator) and their names.
 int tune_ncfg(int kind);
 const char* tune_cfg_name(int kind, int c);
 // On-disk tuning cache: load the entries of the model's GPU architecture into

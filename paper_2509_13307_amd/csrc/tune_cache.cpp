@@ -80,7 +80,7 @@ void tune_cache_load(ns_model* m) {
     while (std::fgets(line, sizeof line, f)) {
         if (std::sscanf(line, "%255s %llx %d %lld %d %d %d %d", arch, &sig, &kind, &M, &N, &K, &G, &cfg) != 8)
             continue;
-        if (m->arch != arch || kind < 0 || kind > 9 || sig != tune_table_sig(kind)) continue;
+        if (m->arch != arch || kind < 0 || kind > 17 || sig != tune_table_sig(kind)) continue;
         if (cfg < 0 || cfg >= tune_ncfg(kind)) continue;
         m->tune[std::make_tuple(kind, (int64_t)M, N, K, G)] = cfg;
     }
