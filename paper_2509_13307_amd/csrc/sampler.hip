@@ -1280,7 +1280,7 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
              "checkpoint_every and resume need a checkpoint_path");
     EventPair tev(hipEventDefault);
     NS_HIP(hipEventRecord(tev.e[0], s));
-    DevBuf live_u, live_l, order, wu, wl, wne, wns, L, state, ctlb, dbuf, th, ev;
+    DevBuf live_u, live_l, order, wu, wl, wne, wns, L, snapd, dbuf, th, ev;
     DevBuf dl, dn, du;
     live_u.ensure((size_t)n * d * 8);
     live_l.ensure((size_t)n * 8);
@@ -1290,12 +1290,11 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
     wne.ensure((size_t)k * 4);
     wns.ensure((size_t)k * 4);
     L.ensure((size_t)d * d * 8);
-    state.ensure(sizeof(NSState));
-    ctlb.ensure(sizeof(NSCtl));
+    snapd.ensure(sizeof(RunSnap));                    // control and state side by side: one copy reads both
     dbuf.ensure(sizeof(DeadBuf));
     th.ensure((size_t)n * d * 8);
-    NSState* S = state.as<NSState>();
-    NSCtl* ctl = ctlb.as<NSCtl>();
+    NSState* S = &snapd.as<RunSnap>()->st;
+    NSCtl* ctl = &snapd.as<RunSnap>()->ctl;
     int64_t dcap = 0;
     // (re)allocate the dead-point storage for at least `need` points, keeping the first n_keep
     auto grow_dead = [&](int64_t need, int64_t n_keep, hipStream_t st) {
@@ -1396,8 +1395,7 @@ void run(ns_model* m, const ns_run_opts* o, ns_run_result* res, double* dl_h, in
         else block(st);
     };
     auto snapshot = [&](int i) {
-        NS_HIP(hipMemcpyAsync(&snap[i].ctl, ctl, sizeof(NSCtl), hipMemcpyDeviceToHost, st));
-        NS_HIP(hipMemcpyAsync(&snap[i].st, S, sizeof(NSState), hipMemcpyDeviceToHost, st));
+        NS_HIP(hipMemcpyAsync(&snap[i], snapd.p, sizeof(RunSnap), hipMemcpyDeviceToHost, st));
         NS_HIP(hipEventRecord(sev.e[i], st));
     };
     // the first launch runs eagerly: it sizes every workspace and tunes the
