@@ -719,14 +719,8 @@ static void fused_run(ns_model* m, const FusedArgs& A, int H, bool x3, int G, co
             // the sum: the maximum needs every walker to propose its full
             // speculation at both bracket ends, and most rounds carry a few
             // tenths of it (cosmic shear, 500 walkers: 2 600 of 10 000 rows
-            // on average).  It is also timed one launch at a time, each after
-            // 64 MiB of writes that push the weights out of L2, as the
-            // round's other kernels do: with the weights left in L2 by the
-            // launch before, the 64-row tiles won at shear sizes where the
-            // 32-row tiles take 25 us less per call in the likelihood.
-            DevBuf flush;
-            constexpr size_t FLUSH_BYTES = size_t(64) << 20;
-            if (count) flush.ensure(FLUSH_BYTES);
+            // on average, where 32-row tiles take 57 us per call and the
+            // 64-row tiles that win at the maximum 83 us).
             const int ncfg = fused_ncfg(h512, x3);
             const int64_t sizes[3] = {std::max<int64_t>(rpw, rows / 8 / rpw * rpw),
                                       std::max<int64_t>(rpw, rows / 4 / rpw * rpw),
@@ -741,25 +735,12 @@ static void fused_run(ns_model* m, const FusedArgs& A, int H, bool x3, int G, co
                 for (int pass = 0; pass < 2; ++pass)
                     for (int c = 0; c < ncfg; ++c) {
                         run_rows(c, nr, nullptr);
+                        NS_HIP(hipEventRecord(e0, s));
+                        for (int r = 0; r < 4; ++r) run_rows(c, nr, nullptr);
+                        NS_HIP(hipEventRecord(e1, s));
+                        NS_HIP(hipEventSynchronize(e1));
                         float ms = 0.f;
-                        if (count) {
-                            for (int r = 0; r < 4; ++r) {
-                                NS_HIP(hipMemsetAsync(flush.p, r, FLUSH_BYTES, s));
-                                NS_HIP(hipEventRecord(e0, s));
-                                run_rows(c, nr, nullptr);
-                                NS_HIP(hipEventRecord(e1, s));
-                                NS_HIP(hipEventSynchronize(e1));
-                                float t = 0.f;
-                                NS_HIP(hipEventElapsedTime(&t, e0, e1));
-                                ms += t;
-                            }
-                        } else {
-                            NS_HIP(hipEventRecord(e0, s));
-                            for (int r = 0; r < 4; ++r) run_rows(c, nr, nullptr);
-                            NS_HIP(hipEventRecord(e1, s));
-                            NS_HIP(hipEventSynchronize(e1));
-                            NS_HIP(hipEventElapsedTime(&ms, e0, e1));
-                        }
+                        NS_HIP(hipEventElapsedTime(&ms, e0, e1));
                         best_ms[c] = std::min(best_ms[c], ms);
                     }
                 for (int c = 0; c < ncfg; ++c) tot_ms[c] += best_ms[c];

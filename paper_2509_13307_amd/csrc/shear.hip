@@ -552,9 +552,14 @@ __global__ void limber_reduce_kernel(const double* __restrict__ theta, int64_t l
 // fold, and with few workgroups the longest ones run alone.  Both pair the
 // same columns within a lane and reduce them in the same order, so a walker's
 // chi^2 is the same for either.
-constexpr int DG_N = 64, DG_KB = 32;
+// K blocks of 32, or 64 for the 32-walker tiles: those run where the grid
+// leaves most CUs idle, and each K block costs a global-load latency that
+// the MFMA work of a block does not cover, so half as many blocks
+constexpr int DG_N = 64;
 template <int BM>
-constexpr size_t dg_smem() { return (2 * DG_KB * BM + 2 * DG_KB * DG_N + 2 * BM) * sizeof(double); }
+constexpr int dg_kb() { return BM == 32 ? 64 : 32; }
+template <int BM>
+constexpr size_t dg_smem() { return (2 * dg_kb<BM>() * BM + 2 * dg_kb<BM>() * DG_N + 2 * BM) * sizeof(double); }
 // MODE 0: Y = C L^{-T} (Bm = L^{-T}, K range [0, 64 (ct + 1))), partial sums of
 //         (w - Y)^2; with R != nullptr also the residuals R = w - Y.
 // MODE 1: out = R L^{-1} (Bm = L^{-1} row-major, K range [64 ct, np)), the
@@ -566,11 +571,14 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
                                                               double* __restrict__ part, int64_t pstride,
                                                               double* __restrict__ R, const int* __restrict__ count) {
     extern __shared__ double dg_lds[];
+    constexpr int KB = dg_kb<BM>();
     constexpr int TI = BM / 32;                        // 16-walker MFMA tiles per wave
-    constexpr int LA = BM * DG_KB / 256;               // A elements per thread and K block
-    auto As = reinterpret_cast<double (*)[DG_KB][BM]>(dg_lds);                        // [2][k][walker]
-    auto Bs = reinterpret_cast<double (*)[DG_KB][DG_N]>(dg_lds + 2 * DG_KB * BM);     // [2][k][column]
-    auto red = reinterpret_cast<double (*)[BM]>(dg_lds + 2 * DG_KB * (BM + DG_N));    // [2][walker]
+    constexpr int LA = BM * KB / 256;                  // A elements per thread and K block
+    constexpr int LB = KB * DG_N / 256;                // B elements per thread and K block
+    constexpr int LQ = LA > LB ? LA : LB;
+    auto As = reinterpret_cast<double (*)[KB][BM]>(dg_lds);                           // [2][k][walker]
+    auto Bs = reinterpret_cast<double (*)[KB][DG_N]>(dg_lds + 2 * KB * BM);           // [2][k][column]
+    auto red = reinterpret_cast<double (*)[BM]>(dg_lds + 2 * KB * (BM + DG_N));       // [2][walker]
     if (count) B = min<int64_t>(B, *count);
     const int64_t b0 = (int64_t)blockIdx.x * BM;
     if (b0 >= B) return;
@@ -579,27 +587,29 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
     const int wr = (BM / 2) * (wave >> 1), wc = 32 * (wave & 1);
     const int kbeg = MODE == 0 ? 0 : DG_N * ct;
     const int kend = MODE == 0 ? min(np, DG_N * (ct + 1)) : np;
-    double ra[LA], rb[8];
+    double ra[LA], rb[LB];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int e = tid + 256 * q;                  // 0 .. 2047
+        for (int q = 0; q < LQ; ++q) {
+            const int e = tid + 256 * q;
             if (q < LA) {
-                const int row = e >> 5, k = e & 31;       // A: 32 consecutive k of one walker
+                const int row = e / KB, k = e % KB;       // A: KB consecutive k of one walker
                 const int64_t b = b0 + row;
                 const int kk = k0 + k;
                 ra[q] = (b < B && kk < n) ? C[b * n + kk] : 0.0;
             }
-            const int kb = e >> 6, col = e & 63;          // B: one row of the column tile
-            rb[q] = Lt[(size_t)(k0 + kb) * np + DG_N * ct + col];
+            if (q < LB) {
+                const int kb = e >> 6, col = e & 63;      // B: one row of the column tile
+                rb[q] = Lt[(size_t)(k0 + kb) * np + DG_N * ct + col];
+            }
         }
     };
     auto sstore = [&](int bf) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < LQ; ++q) {
             const int e = tid + 256 * q;
-            if (q < LA) As[bf][e & 31][e >> 5] = ra[q];
-            Bs[bf][e >> 6][e & 63] = rb[q];
+            if (q < LA) As[bf][e % KB][e / KB] = ra[q];
+            if (q < LB) Bs[bf][e >> 6][e & 63] = rb[q];
         }
     };
     f64x4_t acc[TI][2];
@@ -613,11 +623,11 @@ __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __re
     sstore(0);
     __syncthreads();
     int bf = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += DG_KB) {
-        const bool more = k0 + DG_KB < kend;
-        if (more) gload(k0 + DG_KB);
+    for (int k0 = kbeg; k0 < kend; k0 += KB) {
+        const bool more = k0 + KB < kend;
+        if (more) gload(k0 + KB);
 #pragma unroll
-        for (int kk = 0; kk < DG_KB; kk += 4) {
+        for (int kk = 0; kk < KB; kk += 4) {
             double a[TI], bv[2];
 #pragma unroll
             for (int i = 0; i < TI; ++i) a[i] = As[bf][kk + (lane >> 4)][wr + 16 * i + (lane & 15)];
@@ -808,6 +818,10 @@ double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, i
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64>()));
         NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1, 64>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64>()));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0, 32>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<32>()));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1, 32>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<32>()));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    150 * 1024));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
