@@ -144,11 +144,13 @@ def test_ns_run_replays_oracle_gauss():
     assert abs(res["logz"] - exact) < 3 * res["sigma"]
 
 
-@pytest.mark.parametrize("n_live,n_delete", [(1000, 500), (2400, 1200)])
+@pytest.mark.parametrize("n_live,n_delete", [(300, 150), (1000, 500), (2400, 1200), (4096, 2048)])
 def test_ns_run_replays_oracle_gauss_large(n_live, n_delete):
     """The configured (1000/500) and the sigma <= 0.1 (2400/1200) live-point
-    counts: the selection sorts several points per thread (n > 1024) and the
-    running evidence runs in blocks of ranks (k > 512)."""
+    counts, a count that is no power of two with fewer entries than its sort's
+    padded width (300: 512 entries over two waves, one cross-wave stage) and
+    the largest (4096: sixteen full waves, strides up to 2048 through LDS);
+    the running evidence runs in blocks of ranks for k > 512."""
     say(f"case ns_run gauss {n_live}/{n_delete}")
     desc = W.gauss_structure(d=3, mu=[0.1, 0.5, 0.8], sigma=[0.05, 0.1, 0.08])
     ref = nested.run(lambda u: loglike_u(u, desc), 3, n_live, n_delete, 15, seed=11, n_rep=100)
