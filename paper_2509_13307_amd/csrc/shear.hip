@@ -552,26 +552,24 @@ __global__ void limber_reduce_kernel(const double* __restrict__ theta, int64_t l
 // fold, and with few workgroups the longest ones run alone.  Both pair the
 // same columns within a lane and reduce them in the same order, so a walker's
 // chi^2 is the same for either.
-// K blocks of 32, or 64 for the 32-walker tiles: those run where the grid
-// leaves most CUs idle, and each K block costs a global-load latency that
-// the MFMA work of a block does not cover, so half as many blocks
+// K blocks of KB = 32, or 64 when the 32-walker grid has no more workgroups
+// than the GPU has CUs: there each K block costs a global-load latency that
+// the MFMA work of a block does not cover, so half as many blocks (its 99 KB
+// of LDS allow one workgroup per CU, which a larger grid would queue behind)
 constexpr int DG_N = 64;
-template <int BM>
-constexpr int dg_kb() { return BM == 32 ? 64 : 32; }
-template <int BM>
-constexpr size_t dg_smem() { return (2 * dg_kb<BM>() * BM + 2 * dg_kb<BM>() * DG_N + 2 * BM) * sizeof(double); }
+template <int BM, int KB>
+constexpr size_t dg_smem() { return (2 * KB * BM + 2 * KB * DG_N + 2 * BM) * sizeof(double); }
 // MODE 0: Y = C L^{-T} (Bm = L^{-T}, K range [0, 64 (ct + 1))), partial sums of
 //         (w - Y)^2; with R != nullptr also the residuals R = w - Y.
 // MODE 1: out = R L^{-1} (Bm = L^{-1} row-major, K range [64 ct, np)), the
 //         chi^2 adjoint g_C = L^{-T} L^{-1} (d - C), written to `out`.
-template <int MODE, int BM>
+template <int MODE, int BM, int KB>
 __global__ __launch_bounds__(256) void dense_chi2_gemm_kernel(const double* __restrict__ C, int64_t B, int n, int np,
                                                               const double* __restrict__ Lt,
                                                               const double* __restrict__ wv,
                                                               double* __restrict__ part, int64_t pstride,
                                                               double* __restrict__ R, const int* __restrict__ count) {
     extern __shared__ double dg_lds[];
-    constexpr int KB = dg_kb<BM>();
     constexpr int TI = BM / 32;                        // 16-walker MFMA tiles per wave
     constexpr int LA = BM * KB / 256;                  // A elements per thread and K block
     constexpr int LB = KB * DG_N / 256;                // B elements per thread and K block
@@ -814,14 +812,14 @@ double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, i
                              (const void*)limber_sum_kernel<float, true, 32>};
         for (const void* f : fns)
             NS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0, 64>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64>()));
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1, 64>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64>()));
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0, 32>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<32>()));
-        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1, 32>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<32>()));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0, 64, 32>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64, 32>()));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1, 64, 32>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<64, 32>()));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<0, 32, 64>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<32, 64>()));
+        NS_HIP(hipFuncSetAttribute((const void*)dense_chi2_gemm_kernel<1, 32, 64>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dg_smem<32, 64>()));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    150 * 1024));
         NS_HIP(hipFuncSetAttribute((const void*)zspline_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -866,18 +864,24 @@ double* shear_spectra_from_table(ns_model* m, const double* theta, int64_t ld, i
 
 // One dense chi^2 GEMM launch of mode MODE over B walkers: 64-walker tiles, or
 // 32-walker tiles when the 64-walker grid has fewer than eight workgroups per
-// CU (identical results; dense_chi2_gemm_kernel)
+// CU, with K blocks of 64 when that grid has at most one workgroup per CU
+// (identical results; dense_chi2_gemm_kernel)
 template <int MODE>
 static void launch_dense_gemm(const ns_model* m, const double* C, int64_t B, int n, int np, int n_ct,
                               const double* Lm, const double* wv, double* part, double* R, const int* count,
                               hipStream_t s) {
-    const int64_t g64 = (B + 63) / 64 * n_ct;
-    if (g64 < 8 * (int64_t)device_cus(m->device))
-        hipLaunchKernelGGL((dense_chi2_gemm_kernel<MODE, 32>), dim3((unsigned)((B + 31) / 32), (unsigned)n_ct),
-                           dim3(256), dg_smem<32>(), s, C, B, n, np, Lm, wv, part, B, R, count);
+    const int64_t cus = device_cus(m->device);
+    const int64_t g64 = (B + 63) / 64 * n_ct, g32 = (B + 31) / 32 * n_ct;
+    const dim3 grid32((unsigned)((B + 31) / 32), (unsigned)n_ct);
+    if (g32 <= cus)
+        hipLaunchKernelGGL((dense_chi2_gemm_kernel<MODE, 32, 64>), grid32, dim3(256), (dg_smem<32, 64>()), s, C, B, n,
+                           np, Lm, wv, part, B, R, count);
+    else if (g64 < 8 * cus)
+        hipLaunchKernelGGL((dense_chi2_gemm_kernel<MODE, 32, 32>), grid32, dim3(256), (dg_smem<32, 32>()), s, C, B, n,
+                           np, Lm, wv, part, B, R, count);
     else
-        hipLaunchKernelGGL((dense_chi2_gemm_kernel<MODE, 64>), dim3((unsigned)((B + 63) / 64), (unsigned)n_ct),
-                           dim3(256), dg_smem<64>(), s, C, B, n, np, Lm, wv, part, B, R, count);
+        hipLaunchKernelGGL((dense_chi2_gemm_kernel<MODE, 64, 32>), dim3((unsigned)((B + 63) / 64), (unsigned)n_ct),
+                           dim3(256), (dg_smem<64, 32>()), s, C, B, n, np, Lm, wv, part, B, R, count);
 }
 
 void shear_loglike_from_table(ns_model* m, const double* theta, int64_t ld, int64_t B, double* logl,
